@@ -1,0 +1,177 @@
+"""Throughput of the acquisition hot path on one MI355X.
+
+One step = one acq_detect call on one resident block: block power, segment
+spectra, correlation of every tag x bin x lag, peak keys, FP64 refinement and
+the copy of the detections to the host.  Default workload: 64 tags with
+8192-chip codes at 2 samples/chip, 11 carrier-offset bins over +/-5 kHz,
+2^20-sample blocks at 8 Msps, overlap-save segments of 2^15 samples, ten
+transmissions per block at -15..-5 dB (synthetic, seeded).
+
+Prints one JSON line on stdout.  Reported beside the throughput:
+  roofline     : the correlation kernel's algorithmic FLOP rate (5 M log2 M per
+                 inverse transform + 6 M per spectrum product + 4 per valid
+                 lag, per tag x bin x segment) over its mean duration from HIP
+                 events recorded on the plan's stream during the timed steps,
+                 against the FP32 vector peak;
+  cpu_baseline : the FP64 CPU oracle (direct definition) on a bounded sample
+                 of tag x bin pairs of the same block, on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "correlate_tagbank_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_10445_amd", "csrc", f) for f in ("kernels.hip", "device_fft.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def correlate_flops(T, K, S, M, V) -> float:
+    return float(T) * K * S * (5.0 * M * math.log2(M) + 6.0 * M + 4.0 * V)
+
+
+def traffic_per_launch():
+    """HBM bytes per correlation launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(x, chips, spc, freqs, fs, budget_s: float):
+    """Direct FP64 oracle over (tag, bin) pairs of the full block until the time budget is used."""
+    import numpy as np
+    import oracle
+    oracle.build_library(force=False)
+    T, K, N = chips.shape[0], len(freqs), x.size
+    done = 0
+    t0 = time.perf_counter()
+    for t in range(T):
+        for k in range(K):
+            oracle.corr_power(x, chips[t:t + 1], spc, [freqs[k]], fs)
+            done += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done * N / dt / 1e6, "unit": "tag*freq*Msample/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{done} (tag, bin) pairs x {N} samples, direct FP64 correlation, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tagbank_fp32")
+    ap.add_argument("--fft-len", type=int, default=0, help="override the workload's segment length")
+    ap.add_argument("--tag-tile", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              f"(the path is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import siggen
+    from paper_2005_10445_amd import Plan
+
+    w = siggen.workload(args.workload)
+    T, C, spc, N, K = w["num_tags"], w["num_chips"], w["spc"], w["block_len"], w["num_bins"]
+    fs = w["fs_hz"]
+    seed = w["seeds"][0]
+    fft_len = args.fft_len or w["fft_len"]
+    dev = torch.device("cuda:0")
+    chips = siggen.make_codes(seed, T, C)
+    plan = Plan(chips, spc, fs, num_bins=K, bin_center_hz=w["bin_center_hz"], bin_step_hz=w["bin_step_hz"],
+                max_block_len=N, fft_len=fft_len, tag_tile=args.tag_tile)
+    freqs = plan.freqs_hz
+    x, txs = siggen.make_block(seed, N, chips, spc, fs, freqs, w["n_tx"], snr_db=w["snr_db"])
+    xd = torch.from_numpy(x).to(dev)
+    g = plan.geometry
+    M, V, L = g["fft_len"], g["valid_per_segment"], g["template_len"]
+    S = -(-(N - L + 1) // V)
+    log(f"[bench] workload={args.workload} T={T} K={K} N={N} L={L} M={M} V={V} S={S}")
+
+    for _ in range(args.warmup):
+        plan.detect_raw(xd)
+    plan.set_profiling(True)
+    corr_ms, fwd_ms, total_kernel_ms = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ndet = 0
+    for _ in range(args.steps):
+        ndet = plan.detect_raw(xd)
+        kt = plan.last_kernel_times()
+        corr_ms.append(kt["correlate"])
+        fwd_ms.append(kt["forward"])
+        total_kernel_ms.append(sum(kt.values()))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_profiling(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = T * K * N / (ms_per_step * 1e-3) / 1e6
+    corr_avg = float(np.mean(corr_ms))
+    flops = correlate_flops(T, K, S, M, V)
+    achieved = flops / (corr_avg * 1e-3) / 1e12
+    log(f"[bench] {ms_per_step:.3f} ms/step, correlate {corr_avg:.3f} ms (min {min(corr_ms):.3f}), "
+        f"forward {np.mean(fwd_ms):.3f} ms, kernels {np.mean(total_kernel_ms):.3f} ms, detections {ndet}")
+
+    out = {
+        "metric": "acquisition tag*freq*Msample/s",
+        "value": value,
+        "unit": "tag*freq*Msample/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded BPSK tags in AWGN)",
+        "config": {"workload": args.workload, "tags": T, "bins": K, "block_len": N, "template_len": L,
+                   "fft_len": M, "segments": S, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_per_launch(),
+                     "kernel": "k_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},
+    }
+    if args.cpu_budget > 0:
+        log("[bench] cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(x, chips, spc, freqs, fs, args.cpu_budget)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

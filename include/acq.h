@@ -1,0 +1,200 @@
+/*
+ * acq.h -- acquisition-mode correlation search on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper, Section 2 and Section 3 steps 7-8): given a block of
+ * received complex baseband samples, decide which known tags transmitted in it
+ * and estimate each detected transmission's sub-sample time of arrival, its
+ * power and a quantity correlated with its SNR.  Searching correlates the one
+ * block with the replicas of many tags (Section 2.1, searching mode), each over
+ * a grid of carrier-offset hypotheses.
+ *
+ * What the library computes for every tag t, bin k and valid lag tau:
+ *
+ *     c[t,k,tau] = sum_{n<L} x[tau+n] * s_t[n] * exp(-j 2 pi f_k (tau+n) / Fs)
+ *     P = |c|^2,  z = P / (L * Pxhat),   Pxhat = mean |x|^2 over the block,
+ *
+ * tau = 0 .. N-L (only lags where the whole replica lies inside the block);
+ * s_t[n] = chip_t[n / spc] is the +/-1 BPSK replica held spc samples per chip
+ * (the stored replica of Section 3, step 6).  The correlation is evaluated by
+ * overlap-save FFT correlation (the identity of Section 4.1, with the
+ * conjugate on the replica spectrum) whose replica spectra are computed once at
+ * plan time and kept on the GPU (Section 4.2).  For each tag the peak
+ * (Section 3, step 8) is the argmax of P over all bins and lags (ties: smaller
+ * lag, then smaller bin); it is detected when z >= threshold.  The peak
+ * neighbourhood is re-correlated in FP64, re-maximised within +/- refine_radius
+ * lags, and the time of arrival is the vertex of the parabola through the
+ * powers at the peak lag and its two neighbours (the interpolation of
+ * Section 3, step 8).
+ *
+ * Carrier-offset bins are snapped to multiples of q = Fs / M_min with
+ * M_min = 2^ceil(log2(L+1)): f_k = centre + (k - (K-1)/2) * step, where centre
+ * and step are the requested values rounded to multiples of q (step at least
+ * q when K > 1); K must be odd.  On this grid the frequency shift of a bin is an
+ * exact circular rotation of the segment spectrum at any power-of-two FFT
+ * length M >= M_min, so results do not depend on M.
+ *
+ * Conventions for every entry point:
+ *   - return value: ACQ_OK (0) or a negative acq_status; no exceptions cross
+ *     the boundary; acq_last_error() gives a message for the calling thread;
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory;
+ *   - the caller owns every buffer it passes; a plan owns only the memory it
+ *     allocated itself, and acq_release frees exactly that;
+ *   - a plan is bound to one HIP stream and is not thread-safe: use one plan
+ *     per stream and per host thread.
+ */
+#ifndef ACQ_H_
+#define ACQ_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACQ_API_VERSION 1
+
+typedef enum acq_status {
+    ACQ_OK = 0,
+    ACQ_ERR_INVALID_ARG = -1,        /* bad pointer, size or configuration          */
+    ACQ_ERR_OOM = -2,                /* device or pinned host allocation failed     */
+    ACQ_ERR_DEVICE = -3,             /* a HIP call or kernel launch failed          */
+    ACQ_ERR_TRUNCATED = -4,          /* more detections than capacity; see n_found */
+    ACQ_ERR_BLOCK_TOO_LONG = -5,     /* n > max_block_len of the plan              */
+    ACQ_ERR_UNSUPPORTED = -7         /* valid request outside what this build does */
+} acq_status;
+
+typedef enum acq_precision {
+    ACQ_FP32 = 0,   /* spectra stored and multiplied in FP32                       */
+    ACQ_FP16 = 1,   /* spectra stored in FP16 (RNE), arithmetic in FP32            */
+    ACQ_BF16 = 2    /* spectra stored in BF16 (RNE), arithmetic in FP32            */
+} acq_precision;
+
+/* acq_detection.flags */
+#define ACQ_DET_NEAR_EDGE    0x1u  /* peak at lag 0 or N-L: no parabola, delta = 0    */
+#define ACQ_DET_WINDOW_EDGE  0x2u  /* FP64 re-maximisation ended on its window edge */
+
+/*
+ * Plan configuration.  All fields are read during acq_plan() only; `chips` is
+ * copied, so the caller may free it afterwards.
+ */
+typedef struct acq_config {
+    double        sample_rate_hz;    /* Fs > 0                                          */
+    double        bin_center_hz;     /* requested centre of the offset grid              */
+    double        bin_step_hz;       /* requested bin spacing (ignored when K == 1)      */
+    double        threshold;         /* detection threshold on z; <= 0 selects, per
+                                        block, ln(T*K*(N-L+1) / 1e-3)                    */
+    const int8_t* chips;             /* host [num_tags][num_chips], each +1 or -1        */
+    int64_t       max_block_len;     /* largest N accepted by acq_detect                  */
+    int32_t       num_tags;          /* T >= 1                                           */
+    int32_t       num_chips;         /* C >= 1                                           */
+    int32_t       samples_per_chip;  /* spc in {1, 2, 4, 8}                              */
+    int32_t       num_bins;          /* K >= 1, odd                                      */
+    int32_t       fft_len;           /* M: power of two >= M_min; 0 = library's choice   */
+    int32_t       precision;         /* acq_precision                                    */
+    int32_t       refine_radius;     /* FP64 re-maximisation radius in lags, 0 -> 1, <= 8 */
+    int32_t       tag_tile;          /* tags per correlation work item; 0 = default      */
+    uint32_t      flags;             /* reserved, must be 0                              */
+    int32_t       reserved;          /* must be 0                                        */
+} acq_config;
+
+/* Derived plan geometry (filled by acq_plan_geometry without touching the GPU). */
+typedef struct acq_geometry {
+    int64_t template_len;        /* L = C * spc                                   */
+    int64_t min_fft_len;         /* M_min = 2^ceil(log2(L+1))                     */
+    int64_t fft_len;             /* M, the overlap-save segment length            */
+    int64_t sub_fft_len;         /* M / spc, the per-tag inverse transform length */
+    int64_t valid_per_segment;   /* V = M - L + 1 lags produced per segment       */
+    int64_t max_segments;        /* ceil((max_block_len - L + 1) / V)              */
+    double  freq_quantum_hz;     /* q = Fs / M_min                                 */
+    double  bin_center_hz;       /* snapped centre                                  */
+    double  bin_step_hz;         /* snapped step (0 when K == 1)                    */
+    int64_t device_bytes;        /* device memory a plan allocates                  */
+} acq_geometry;
+
+/* One detection.  lag and bin identify the peak; values are FP64 re-correlations. */
+typedef struct acq_detection {
+    int32_t  tag;           /* tag index t                                           */
+    int32_t  bin;           /* bin index k*                                          */
+    int64_t  lag;           /* tau*: peak lag in samples from the block start        */
+    double   toa_samples;   /* tau* + delta, delta the parabola vertex in [-1/2,1/2]  */
+    double   freq_hz;       /* snapped frequency of bin k*                           */
+    double   peak_power;    /* P at (k*, tau*)                                       */
+    double   z;             /* P / (L * Pxhat)                                       */
+    double   energy;        /* sum_{n<L} |x[tau*+n]|^2                               */
+    double   block_power;   /* Pxhat                                                 */
+    int32_t  block;         /* index of the block in a batch call, else 0            */
+    uint32_t flags;         /* ACQ_DET_*                                             */
+} acq_detection;
+
+typedef struct acq_plan_s* acq_plan_t;
+
+/*
+ * Validate `cfg` and derive the plan geometry without any GPU call.
+ * Returns ACQ_OK, ACQ_ERR_INVALID_ARG (malformed) or ACQ_ERR_UNSUPPORTED.
+ */
+int acq_plan_geometry(const acq_config* cfg, acq_geometry* out);
+
+/*
+ * The K snapped bin frequencies (Hz) of `cfg`, written to host `freqs_hz[0..K)`.
+ * No GPU call.  n must be >= num_bins.
+ */
+int acq_bin_frequencies(const acq_config* cfg, double* freqs_hz, int32_t n);
+
+/*
+ * Create a plan: allocate the plan's device memory, build the replica spectra
+ * (Section 4.2: computed once, kept for the plan's lifetime) and the transform
+ * tables.  `stream` is a hipStream_t (NULL: the null stream).  Synchronises the
+ * stream before returning.  On failure *out is NULL and nothing is leaked.
+ */
+int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out);
+
+/*
+ * Search one block.  `block`: device, n complex64 samples (interleaved re, im,
+ * 8-byte aligned), read only.  Detections (at most one per tag, sorted by tag)
+ * go to host `out[0..capacity)`; *n_found receives the number of detections.
+ * If that exceeds capacity, the first `capacity` are written and
+ * ACQ_ERR_TRUNCATED is returned.  n < L is valid and yields 0 detections.
+ * Synchronous: returns after the results are on the host.
+ */
+int acq_detect(acq_plan_t plan, const void* block, int64_t n,
+               acq_detection* out, int32_t capacity, int32_t* n_found);
+
+/*
+ * Test hook: the FFT-path power P[t][k][tau] for every valid lag, written to
+ * device `power` laid out [T][K][n-L+1] as FP32 (the values the peak search
+ * compares, before any FP64 re-correlation).  Synchronous.
+ */
+int acq_correlate_power(acq_plan_t plan, const void* block, int64_t n, float* power);
+
+/*
+ * Kernel timing.  With profiling on, acq_detect and acq_correlate_power record
+ * HIP events on the plan's stream around each kernel they launch; after the
+ * call, acq_last_kernel_times writes the durations (milliseconds) in the order
+ * ACQ_KERNEL_* below to host `ms[0..n)` and the number of kernels to *count.
+ * Kernels a call did not launch report 0.  Off by default.
+ */
+#define ACQ_KERNEL_BLOCK_POWER 0
+#define ACQ_KERNEL_FORWARD     1
+#define ACQ_KERNEL_CORRELATE   2
+#define ACQ_KERNEL_REFINE      3
+#define ACQ_KERNEL_COMPACT     4
+#define ACQ_NUM_KERNELS        5
+int acq_set_profiling(acq_plan_t plan, int on);
+int acq_last_kernel_times(acq_plan_t plan, double* ms, int32_t n, int32_t* count);
+
+/* Release a plan and the memory it allocated.  NULL is a no-op. */
+int acq_release(acq_plan_t plan);
+
+/* Static description of a status code. */
+const char* acq_strerror(int status);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* acq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACQ_H_ */

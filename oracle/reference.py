@@ -60,17 +60,13 @@ def library_path() -> str:
 
 
 def build_library(force: bool = True) -> str:
-    """Compile direct.c -> _direct.so with gcc (OpenMP, -O3, IEEE arithmetic)."""
+    """Compile direct.c -> _direct.so with gcc (OpenMP, -O3, IEEE arithmetic, baseline
+    x86-64 so the same object runs on any host)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+        cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                "-o", tmp, _SRC, "-lm"]
-        try:
-            subprocess.run(cmd, check=True, capture_output=True, text=True)
-        except subprocess.CalledProcessError:
-            # a host whose gcc lacks -march=native support for this CPU
-            cmd.remove("-march=native")
-            subprocess.run(cmd, check=True, capture_output=True, text=True)
+        subprocess.run(cmd, check=True, capture_output=True, text=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -299,7 +295,7 @@ def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, metho
             pv = {q: float(Pt[k, q]) for q in trip_taus if 0 <= q < lags}
         edge = tau == 0 or tau == lags - 1
         d = parabola(pv.get(tau - 1, 0.0), P0, pv.get(tau + 1, 0.0), at_edge=edge)
-        z = P0 / (L * Px) if Px > 0 else math.inf
+        z = P0 / (L * Px) if Px > 0 else 0.0
         out.append(dict(
             tag=int(t), detected=bool(z >= theta), bin=int(k), lag=int(tau), delta=float(d),
             toa=float(tau + d), peak_power=float(P0), z=float(z), energy=energy_at(x64, tau, L),

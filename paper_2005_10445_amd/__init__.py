@@ -1,0 +1,177 @@
+"""Acquisition-mode correlation search on AMD Instinct MI355X.
+
+Python face of libacq.so (include/acq.h).  It marshals arguments only: the
+block power, segment spectra, replica bank, correlation, peak search and FP64
+refinement all run in the library's HIP kernels.  PyTorch provides device
+memory and the stream.  There is no CPU fallback: constructing a Plan without
+the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+
+from . import _capi
+from ._capi import AcqConfig, AcqDetection, AcqGeometry, AcqError, check
+
+__all__ = ["Plan", "Detection", "geometry", "bin_frequencies", "AcqError", "make_config"]
+
+_PRECISION = {"fp32": _capi.ACQ_FP32, "fp16": _capi.ACQ_FP16, "bf16": _capi.ACQ_BF16}
+
+
+@dataclass
+class Detection:
+    tag: int
+    bin: int
+    lag: int
+    toa: float
+    freq_hz: float
+    peak_power: float
+    z: float
+    energy: float
+    block_power: float
+    block: int
+    flags: int
+
+
+def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
+                bin_center_hz: float = 0.0, bin_step_hz: float = 0.0, max_block_len: int = 1 << 20,
+                fft_len: int = 0, threshold: float = 0.0, precision: str = "fp32",
+                refine_radius: int = 1, tag_tile: int = 0):
+    """Build an AcqConfig; returns (config, chips array that must outlive the call)."""
+    ch = np.ascontiguousarray(np.asarray(chips, dtype=np.int8))
+    if ch.ndim != 2:
+        raise ValueError("chips must be [num_tags][num_chips]")
+    cfg = AcqConfig()
+    cfg.sample_rate_hz = float(fs_hz)
+    cfg.bin_center_hz = float(bin_center_hz)
+    cfg.bin_step_hz = float(bin_step_hz)
+    cfg.threshold = float(threshold)
+    cfg.chips = ch.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+    cfg.max_block_len = int(max_block_len)
+    cfg.num_tags, cfg.num_chips = int(ch.shape[0]), int(ch.shape[1])
+    cfg.samples_per_chip = int(spc)
+    cfg.num_bins = int(num_bins)
+    cfg.fft_len = int(fft_len)
+    cfg.precision = _PRECISION[precision]
+    cfg.refine_radius = int(refine_radius)
+    cfg.tag_tile = int(tag_tile)
+    cfg.flags = 0
+    cfg.reserved = 0
+    return cfg, ch
+
+
+def geometry(**kw) -> dict:
+    """acq_plan_geometry for a configuration (no GPU involved)."""
+    cfg, _keep = make_config(**kw)
+    g = AcqGeometry()
+    check(_capi.lib().acq_plan_geometry(ctypes.byref(cfg), ctypes.byref(g)), "acq_plan_geometry")
+    return {name: getattr(g, name) for name, _ in AcqGeometry._fields_}
+
+
+def bin_frequencies(**kw) -> np.ndarray:
+    cfg, _keep = make_config(**kw)
+    out = np.zeros(cfg.num_bins, dtype=np.float64)
+    check(_capi.lib().acq_bin_frequencies(ctypes.byref(cfg),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          cfg.num_bins), "acq_bin_frequencies")
+    return out
+
+
+def _device_ptr(block):
+    import torch
+    if not isinstance(block, torch.Tensor) or not block.is_cuda:
+        raise TypeError("block must be a CUDA (HIP) torch tensor")
+    if block.dtype != torch.complex64 or not block.is_contiguous() or block.dim() != 1:
+        raise TypeError("block must be a contiguous 1-D complex64 tensor")
+    return block.data_ptr(), block.numel()
+
+
+class Plan:
+    """An acquisition plan bound to one HIP stream (default: torch's current stream)."""
+
+    def __init__(self, chips, spc: int, fs_hz: float, *, num_bins: int = 1, bin_center_hz: float = 0.0,
+                 bin_step_hz: float = 0.0, max_block_len: int = 1 << 20, fft_len: int = 0,
+                 threshold: float = 0.0, precision: str = "fp32", refine_radius: int = 1,
+                 tag_tile: int = 0, stream=None):
+        import torch
+        self._lib = _capi.lib()
+        cfg, ch = make_config(chips, spc, fs_hz, num_bins, bin_center_hz, bin_step_hz, max_block_len,
+                              fft_len, threshold, precision, refine_radius, tag_tile)
+        self.num_tags, self.num_chips = ch.shape
+        self.spc = int(spc)
+        self.num_bins = int(num_bins)
+        self.template_len = self.num_chips * self.spc
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        g = AcqGeometry()
+        check(self._lib.acq_plan_geometry(ctypes.byref(cfg), ctypes.byref(g)), "acq_plan_geometry")
+        self.geometry = {name: getattr(g, name) for name, _ in AcqGeometry._fields_}
+        self.freqs_hz = np.zeros(self.num_bins)
+        check(self._lib.acq_bin_frequencies(ctypes.byref(cfg),
+                                            self.freqs_hz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            self.num_bins), "acq_bin_frequencies")
+        self._h = ctypes.c_void_p()
+        check(self._lib.acq_plan(ctypes.byref(cfg), ctypes.c_void_p(handle), ctypes.byref(self._h)), "acq_plan")
+        self._out = (AcqDetection * self.num_tags)()
+
+    def detect(self, block) -> List[Detection]:
+        ptr, n = _device_ptr(block)
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_detect(self._h, ctypes.c_void_p(ptr), n, self._out, self.num_tags,
+                                   ctypes.byref(nf)), "acq_detect")
+        return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
+                          d.block_power, d.block, d.flags) for d in self._out[:nf.value]]
+
+    def detect_raw(self, block) -> int:
+        """acq_detect without building Python records (for timing); returns the count."""
+        ptr, n = _device_ptr(block)
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_detect(self._h, ctypes.c_void_p(ptr), n, self._out, self.num_tags,
+                                   ctypes.byref(nf)), "acq_detect")
+        return nf.value
+
+    def correlate_power(self, block, out=None):
+        """FFT-path power P[t][k][tau] (FP32, device tensor [T][K][n-L+1])."""
+        import torch
+        ptr, n = _device_ptr(block)
+        lags = max(n - self.template_len + 1, 0)
+        if out is None:
+            out = torch.empty((self.num_tags, self.num_bins, lags), dtype=torch.float32, device=block.device)
+        if lags > 0:
+            check(self._lib.acq_correlate_power(self._h, ctypes.c_void_p(ptr), n,
+                                                ctypes.c_void_p(out.data_ptr())), "acq_correlate_power")
+        return out
+
+    def set_profiling(self, on: bool = True):
+        check(self._lib.acq_set_profiling(self._h, 1 if on else 0), "acq_set_profiling")
+
+    def last_kernel_times(self) -> dict:
+        """Durations (ms) of the kernels of the last call, from HIP events on the plan's stream."""
+        ms = (ctypes.c_double * len(_capi.KERNELS))()
+        cnt = ctypes.c_int32(0)
+        check(self._lib.acq_last_kernel_times(self._h, ms, len(_capi.KERNELS), ctypes.byref(cnt)),
+              "acq_last_kernel_times")
+        return dict(zip(_capi.KERNELS, list(ms)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.acq_release(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,129 @@
+"""ctypes mirror of include/acq.h.
+
+Argument marshalling only: every computation happens in libacq.so.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libacq.so")
+
+ACQ_OK = 0
+ACQ_ERR_INVALID_ARG = -1
+ACQ_ERR_OOM = -2
+ACQ_ERR_DEVICE = -3
+ACQ_ERR_TRUNCATED = -4
+ACQ_ERR_BLOCK_TOO_LONG = -5
+ACQ_ERR_UNSUPPORTED = -7
+
+ACQ_FP32, ACQ_FP16, ACQ_BF16 = 0, 1, 2
+ACQ_DET_NEAR_EDGE = 0x1
+ACQ_DET_WINDOW_EDGE = 0x2
+
+# every symbol include/acq.h declares
+EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect",
+            "acq_correlate_power", "acq_set_profiling", "acq_last_kernel_times", "acq_release",
+            "acq_strerror", "acq_last_error")
+KERNELS = ("block_power", "forward", "correlate", "refine", "compact")
+
+
+class AcqConfig(ctypes.Structure):
+    _fields_ = [
+        ("sample_rate_hz", ctypes.c_double),
+        ("bin_center_hz", ctypes.c_double),
+        ("bin_step_hz", ctypes.c_double),
+        ("threshold", ctypes.c_double),
+        ("chips", ctypes.POINTER(ctypes.c_int8)),
+        ("max_block_len", ctypes.c_int64),
+        ("num_tags", ctypes.c_int32),
+        ("num_chips", ctypes.c_int32),
+        ("samples_per_chip", ctypes.c_int32),
+        ("num_bins", ctypes.c_int32),
+        ("fft_len", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("refine_radius", ctypes.c_int32),
+        ("tag_tile", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class AcqGeometry(ctypes.Structure):
+    _fields_ = [
+        ("template_len", ctypes.c_int64),
+        ("min_fft_len", ctypes.c_int64),
+        ("fft_len", ctypes.c_int64),
+        ("sub_fft_len", ctypes.c_int64),
+        ("valid_per_segment", ctypes.c_int64),
+        ("max_segments", ctypes.c_int64),
+        ("freq_quantum_hz", ctypes.c_double),
+        ("bin_center_hz", ctypes.c_double),
+        ("bin_step_hz", ctypes.c_double),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+class AcqDetection(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_int32),
+        ("bin", ctypes.c_int32),
+        ("lag", ctypes.c_int64),
+        ("toa_samples", ctypes.c_double),
+        ("freq_hz", ctypes.c_double),
+        ("peak_power", ctypes.c_double),
+        ("z", ctypes.c_double),
+        ("energy", ctypes.c_double),
+        ("block_power", ctypes.c_double),
+        ("block", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Load libacq.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libacq.so not built ({path}); run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.acq_plan_geometry.argtypes = [P(AcqConfig), P(AcqGeometry)]
+    L.acq_bin_frequencies.argtypes = [P(AcqConfig), P(ctypes.c_double), ctypes.c_int32]
+    L.acq_plan.argtypes = [P(AcqConfig), ctypes.c_void_p, P(ctypes.c_void_p)]
+    L.acq_detect.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, P(AcqDetection),
+                             ctypes.c_int32, P(ctypes.c_int32)]
+    L.acq_correlate_power.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    L.acq_release.argtypes = [ctypes.c_void_p]
+    L.acq_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.acq_last_kernel_times.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int32,
+                                        P(ctypes.c_int32)]
+    for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect",
+                 "acq_correlate_power", "acq_release", "acq_set_profiling", "acq_last_kernel_times"):
+        getattr(L, name).restype = ctypes.c_int
+    L.acq_strerror.argtypes = [ctypes.c_int]
+    L.acq_strerror.restype = ctypes.c_char_p
+    L.acq_last_error.argtypes = []
+    L.acq_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+class AcqError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        msg = L.acq_last_error().decode() or L.acq_strerror(status).decode()
+        super().__init__(f"{where}: {L.acq_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> int:
+    if status != ACQ_OK:
+        raise AcqError(status, where)
+    return status

@@ -1,0 +1,465 @@
+// HIP kernels of the acquisition path (gfx950).
+//
+//   k_block_power  : FP64 partial sums of |x|^2 (mean block power Pxhat)
+//   k_forward      : overlap-save segment j, X_j = DFT_M(x[jV .. jV+M)) with a zero
+//                    tail, as spc decimated Msub-point transforms combined by one
+//                    radix-spc decimation-in-time step
+//   k_bank         : replica spectra conj(DFT_Msub(chip code)) / M, plan time
+//   k_correlate    : the hot loop, see below
+//   k_refine       : FP64 re-correlation around each tag's peak, re-maximisation,
+//                    parabolic vertex, z and energy
+//   k_compact      : detections in tag order
+//
+// Correlation by overlap-save (the FFT identity of Section 4.1 with the
+// conjugate on the replica; segmented processing as in Section 4.1's
+// overlap-add remark, here overlap-save so each segment yields V = M-L+1 lags):
+//
+//   c_j[tau] = (1/M) sum_i X_j[(i + m_k) mod M] conj(S_t[i]) exp(+j 2 pi i tau / M)
+//
+// equals c[t,k,jV+tau] up to a unit-modulus factor for tau < V (the bin's
+// frequency shift is the rotation by m_k = f_k M / Fs).  The replica is a
+// +/-1 code held spc samples per chip, so its spectrum factors as
+// S_t[i] = Chat_t[i mod Msub] * Rect[i], Msub = M / spc, with Chat_t the
+// Msub-point spectrum of the chip code and Rect the spectrum of a run of spc
+// ones.  Splitting i = i' + Msub*a and the output lag tau = spc*u + rho turns
+// the M-point inverse transform into a radix-spc first step that does not
+// depend on the tag,
+//
+//   G_rho[i'] = exp(+j 2 pi i' rho / M) sum_a X_j[(i'+Msub a + m_k) mod M]
+//               conj(Rect[i'+Msub a]) exp(+j 2 pi a rho / spc),
+//
+// followed per tag by an Msub-point inverse transform of conj(Chat_t) G_rho,
+// whose output u is the lag spc*u + rho.  One work item is (segment j, bin k,
+// phase rho, tile of tags): it forms G_rho once in registers, then for each tag
+// multiplies by the stored conj(Chat_t)/M, runs the LDS-resident inverse
+// transform, squares, masks invalid lags and max-reduces a 64-bit key per tag:
+// key = float_bits(P) << 32 | ~(tau*K + k), so the largest key is the largest
+// power with ties going to the smaller lag and then the smaller bin (the
+// argmax of Section 3, step 8).  P >= 0, so its bit pattern orders like its
+// value.
+#include <hip/hip_runtime.h>
+
+#include "device_fft.h"
+#include "host_logic.h"
+#include "kernels.h"
+
+namespace acq {
+
+using dev::cadd;
+using dev::cmul;
+using dev::cmulc;
+using dev::Fft;
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ block power
+__global__ __launch_bounds__(256) void k_block_power(const float2* __restrict__ x, int64_t n,
+                                                     double* __restrict__ parts) {
+    const int64_t chunk = (n + kPowerParts - 1) / kPowerParts;
+    const int64_t beg = int64_t(blockIdx.x) * chunk;
+    const int64_t end = beg + chunk < n ? beg + chunk : n;
+    double acc = 0.0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
+        const float2 v = x[i];
+        acc += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+    }
+    acc = wave_sum(acc);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) parts[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t count) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0ull;
+}
+
+// ------------------------------------------------------------------ forward spectra
+template <int LOGN>
+__global__ __launch_bounds__(Fft<LOGN>::NT) void k_forward(FwdArgs a) {
+    using F = Fft<LOGN>;
+    constexpr int NT = F::NT;
+    __shared__ float2 lds[F::LDS];
+    const int t = threadIdx.x;
+    const int j = blockIdx.x;
+    const int64_t base = int64_t(j) * a.V;
+    float2* Xj = a.X + size_t(j) * size_t(a.M);
+    const int mmask = a.M - 1;
+    for (int r = 0; r < a.spc; ++r) {
+        int tq = t;                       // see k_correlate: no hoisted addresses
+        const float2* roots = a.rootsSub;
+        asm volatile("" : "+v"(tq), "+s"(roots));
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int64_t idx = base + int64_t(a.spc) * (tq + m * NT) + r;
+            v[m] = idx < a.n ? a.x[idx] : make_float2(0.f, 0.f);
+        }
+        F::template transform<-1>(v, lds, roots, tq);
+        // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub]
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int ip = tq + m * NT;
+            for (int q = 0; q < a.spc; ++q) {
+                const int i = ip + q * a.Msub;
+                float2 c = v[m];
+                if (r) c = cmulc(c, a.rootsM[(int)((int64_t(i) * r) & mmask)]);
+                Xj[i] = r ? cadd(Xj[i], c) : c;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ replica bank
+template <int LOGN>
+__global__ __launch_bounds__(Fft<LOGN>::NT) void k_bank(const int8_t* __restrict__ chips, int C,
+                                                        float2* __restrict__ bank,
+                                                        const float2* __restrict__ rootsSub, int M) {
+    using F = Fft<LOGN>;
+    constexpr int NT = F::NT;
+    __shared__ float2 lds[F::LDS];
+    const int t = threadIdx.x;
+    const int tag = blockIdx.x;
+    float2 v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int ip = t + m * NT;
+        v[m] = make_float2(ip < C ? float(chips[size_t(tag) * C + ip]) : 0.f, 0.f);
+    }
+    F::template transform<-1>(v, lds, rootsSub, t);
+    const float s = 1.0f / float(M);   // exact: M is a power of two
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int ip = t + m * NT;
+        bank[size_t(tag) * F::N + ip] = make_float2(v[m].x * s, -v[m].y * s);
+    }
+}
+
+// ------------------------------------------------------------------ correlation
+template <int LOGN, bool DUMP>
+__global__ __launch_bounds__(Fft<LOGN>::NT) void k_correlate(CorrArgs a) {
+    using F = Fft<LOGN>;
+    constexpr int NT = F::NT;
+    constexpr int NW = NT / 64;
+    __shared__ float2 lds[F::LDS];
+    __shared__ unsigned long long red[kMaxTagTile * NW];
+
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // range of work items so items sharing a segment and a tag tile share its L2.
+    const int per = int(gridDim.x) >> 3;
+    const int w = int(blockIdx.x & 7u) * per + int(blockIdx.x >> 3);
+    if (w >= a.nwork) return;
+    int rem = w;
+    const int rho = rem % a.spc;
+    rem /= a.spc;
+    const int k = rem % a.K;
+    rem /= a.K;
+    const int j = rem % a.S;
+    const int tile = rem / a.S;
+    const int tag0 = tile * a.tile;
+    const int ntag = min(a.tile, a.T - tag0);
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+
+    // tag-independent first step of the inverse transform
+    float2 G[16];
+    {
+        const float2* Xj = a.X + size_t(j) * size_t(a.M);
+        const int rot = a.rot[k];
+        const int mmask = a.M - 1;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int ip = t + m * NT;
+            float2 acc = make_float2(0.f, 0.f);
+            for (int q = 0; q < a.spc; ++q) {
+                const int i = ip + q * a.Msub;
+                float2 xv = cmul(Xj[(i + rot) & mmask], a.rect[i]);
+                const int e = (a.Msub * q * rho) & mmask;
+                if (e) xv = cmul(xv, a.rootsM[e]);
+                acc = cadd(acc, xv);
+            }
+            if (rho) acc = cmul(acc, a.rootsM[ip * rho]);
+            G[m] = acc;
+        }
+    }
+
+    const int64_t seg0 = int64_t(j) * a.V;
+    for (int tt = 0; tt < ntag; ++tt) {
+        const int tag = tag0 + tt;
+        const float2* B = a.bank + size_t(tag) * F::N;
+        // Every address and twiddle below is the same for each tag.  Hiding the
+        // thread index and the table pointer from the optimiser per iteration
+        // keeps it from holding all of them in registers across the tag loop
+        // (which spills at 1024 threads); recomputing them is a few integer ops.
+        int tq = t;
+        const float2* roots = a.rootsSub;
+        asm volatile("" : "+v"(tq), "+s"(roots));
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], B[tq + m * NT]);
+        F::template transform<+1>(v, lds, roots, tq);
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int u = tq + m * NT;
+            const int64_t ts = int64_t(a.spc) * u + rho;
+            const int64_t tau = seg0 + ts;
+            if (ts < a.V && tau < a.lags) {
+                const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
+                const unsigned idx = unsigned(tau * a.K + k);
+                const unsigned long long key =
+                    (static_cast<unsigned long long>(__float_as_uint(p)) << 32) |
+                    static_cast<unsigned long long>(~idx);
+                best = key > best ? key : best;
+                if constexpr (DUMP) a.dump[(size_t(tag) * a.K + k) * size_t(a.lags) + size_t(tau)] = p;
+            }
+        }
+        best = wave_max(best);
+        if (lane == 0) red[tt * NW + wave] = best;
+    }
+    __syncthreads();
+    for (int i = t; i < ntag; i += NT) {
+        unsigned long long m = 0ull;
+        for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
+        if (m) atomicMax(&a.keys[tag0 + i], m);
+    }
+}
+
+// ------------------------------------------------------------------ refine
+constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
+
+__global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
+    const int tag = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    __shared__ double s_px;
+    __shared__ double red[4][kMaxWin][3];
+    __shared__ long long s_center;
+    __shared__ int s_again;
+
+    const unsigned long long key = a.keys[tag];
+    if (key == 0ull) {               // no valid lag was searched for this tag
+        if (t == 0) a.found[tag] = 0;
+        return;
+    }
+    if (t == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kPowerParts; ++i) s += a.parts[i];
+        s_px = s / double(a.n);
+    }
+    const unsigned idx = ~unsigned(key & 0xffffffffull);
+    const int k = int(idx % unsigned(a.K));
+    int64_t center = int64_t(idx / unsigned(a.K));
+    const int R = a.radius;
+    const int W = 2 * R + 3;
+    const int64_t mrot = a.rot_signed[k];
+    const int8_t* ch = a.chips + size_t(tag) * size_t(a.C);
+
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t lam0 = center - R - 1;
+        double cr[kMaxWin], ci[kMaxWin], en[kMaxWin];
+#pragma unroll
+        for (int w = 0; w < kMaxWin; ++w) cr[w] = ci[w] = en[w] = 0.0;
+        for (int64_t e = t; e < a.L + W - 1; e += 256) {
+            const int64_t i = lam0 + e;
+            if (i < 0 || i >= a.n) continue;
+            const float2 xv = a.x[i];
+            const double xr = xv.x, xi = xv.y;
+            int64_t ph = (mrot * i) % a.M;
+            if (ph < 0) ph += a.M;
+            double sn, cs;
+            sincospi(2.0 * double(ph) / double(a.M), &sn, &cs);
+            const double mr = xr * cs + xi * sn;      // x * exp(-j 2 pi m i / M)
+            const double mi = xi * cs - xr * sn;
+            const double pw = xr * xr + xi * xi;
+#pragma unroll
+            for (int w = 0; w < kMaxWin; ++w) {
+                const int64_t nn = e - w;
+                if (w < W && nn >= 0 && nn < a.L) {
+                    const double sg = double(ch[nn / a.spc]);
+                    cr[w] += mr * sg;
+                    ci[w] += mi * sg;
+                    en[w] += pw;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < kMaxWin; ++w) {
+            const double r0 = wave_sum(cr[w]), r1 = wave_sum(ci[w]), r2 = wave_sum(en[w]);
+            if (lane == 0 && w < W) {
+                red[wave][w][0] = r0;
+                red[wave][w][1] = r1;
+                red[wave][w][2] = r2;
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            double P[kMaxWin], E[kMaxWin];
+            for (int w = 0; w < W; ++w) {
+                const double re = (red[0][w][0] + red[1][w][0]) + (red[2][w][0] + red[3][w][0]);
+                const double im = (red[0][w][1] + red[1][w][1]) + (red[2][w][1] + red[3][w][1]);
+                E[w] = (red[0][w][2] + red[1][w][2]) + (red[2][w][2] + red[3][w][2]);
+                const int64_t lam = lam0 + w;
+                P[w] = (lam >= 0 && lam < a.lags) ? re * re + im * im : -1.0;
+            }
+            int wb = R + 1;
+            for (int w = 1; w <= W - 2; ++w)
+                if (P[w] > P[wb] || (P[w] == P[wb] && w < wb)) wb = w;
+            const int64_t lam = lam0 + wb;
+            const bool hit = (wb == 1 && lam > 0) || (wb == W - 2 && lam < a.lags - 1);
+            if (hit && pass == 0) {
+                s_center = lam;
+                s_again = 1;
+            } else {
+                s_again = 0;
+                unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
+                const double p0 = P[wb];
+                const double pm = P[wb - 1] < 0.0 ? 0.0 : P[wb - 1];
+                const double pp = P[wb + 1] < 0.0 ? 0.0 : P[wb + 1];
+                double delta = 0.0;
+                if (lam == 0 || lam == a.lags - 1) {
+                    flags |= ACQ_DET_NEAR_EDGE;
+                } else {
+                    const double den = pm - 2.0 * p0 + pp;
+                    if (den < 0.0) {
+                        delta = 0.5 * (pm - pp) / den;
+                        delta = delta > 0.5 ? 0.5 : (delta < -0.5 ? -0.5 : delta);
+                    }
+                }
+                const double px = s_px;
+                const double z = px > 0.0 ? p0 / (double(a.L) * px) : 0.0;
+                acq_detection d;
+                d.tag = tag;
+                d.bin = k;
+                d.lag = lam;
+                d.toa_samples = double(lam) + delta;
+                d.freq_hz = a.freqs[k];
+                d.peak_power = p0;
+                d.z = z;
+                d.energy = E[wb];
+                d.block_power = px;
+                d.block = 0;
+                d.flags = flags;
+                a.dets[tag] = d;
+                a.found[tag] = z >= a.theta ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (!s_again) break;
+        center = s_center;
+    }
+}
+
+__global__ void k_compact(const acq_detection* __restrict__ dets, const int32_t* __restrict__ found,
+                          int T, acq_detection* __restrict__ out, int32_t* __restrict__ count) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int c = 0;
+    for (int i = 0; i < T; ++i)
+        if (found[i]) out[c++] = dets[i];
+    *count = c;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_block_power(const float2* x, int64_t n, double* parts, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_power, dim3(kPowerParts), dim3(256), 0, st, x, n, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u64, dim3(unsigned(blocks)), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+template <int LOGN>
+static hipError_t fwd_n(const FwdArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((k_forward<LOGN>), dim3(a.S), dim3(Fft<LOGN>::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const FwdArgs& a, int log2_sub, hipStream_t st) {
+    if (a.S <= 0) return hipSuccess;
+    switch (log2_sub) {
+        case 10: return fwd_n<10>(a, st);
+        case 11: return fwd_n<11>(a, st);
+        case 12: return fwd_n<12>(a, st);
+        case 13: return fwd_n<13>(a, st);
+        case 14: return fwd_n<14>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LOGN>
+static hipError_t bank_n(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub, int M,
+                         hipStream_t st) {
+    hipLaunchKernelGGL((k_bank<LOGN>), dim3(T), dim3(Fft<LOGN>::NT), 0, st, chips, C, bank, rootsSub, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_bank(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub, int Msub,
+                       int M, int log2_sub, hipStream_t st) {
+    if ((1 << log2_sub) != Msub || C > Msub) return hipErrorInvalidValue;
+    switch (log2_sub) {
+        case 10: return bank_n<10>(chips, T, C, bank, rootsSub, M, st);
+        case 11: return bank_n<11>(chips, T, C, bank, rootsSub, M, st);
+        case 12: return bank_n<12>(chips, T, C, bank, rootsSub, M, st);
+        case 13: return bank_n<13>(chips, T, C, bank, rootsSub, M, st);
+        case 14: return bank_n<14>(chips, T, C, bank, rootsSub, M, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int LOGN>
+static hipError_t corr_n(const CorrArgs& a, hipStream_t st) {
+    const int grid = ((a.nwork + 7) / 8) * 8;
+    if (a.dump)
+        hipLaunchKernelGGL((k_correlate<LOGN, true>), dim3(grid), dim3(Fft<LOGN>::NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_correlate<LOGN, false>), dim3(grid), dim3(Fft<LOGN>::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_correlate(const CorrArgs& a, int log2_sub, hipStream_t st) {
+    if (a.nwork <= 0) return hipSuccess;
+    if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile) return hipErrorInvalidValue;
+    switch (log2_sub) {
+        case 10: return corr_n<10>(a, st);
+        case 11: return corr_n<11>(a, st);
+        case 12: return corr_n<12>(a, st);
+        case 13: return corr_n<13>(a, st);
+        case 14: return corr_n<14>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_refine(const RefineArgs& a, hipStream_t st) {
+    if (a.radius < 0 || a.radius > kMaxRefineRadius) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_refine, dim3(a.T), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const acq_detection* dets, const int32_t* found, int T, acq_detection* out,
+                          int32_t* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, dets, found, T, out, count);
+    return hipGetLastError();
+}
+
+}  // namespace acq

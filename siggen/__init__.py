@@ -138,11 +138,11 @@ def make_block(seed: int, n: int, chips: np.ndarray, spc: int, fs_hz: float,
     x = np.zeros(n, dtype=np.complex128)
     txs = []
     if n_tx > 0:
-        if n < L + 1:
+        if n < L:
             raise ValueError("block shorter than a transmission")
         tag_list = list(tags) if tags is not None else list(g.choice(T, size=n_tx, replace=False))
         for i in range(n_tx):
-            D = int(delays[i]) if delays is not None else int(g.integers(0, n - L))
+            D = int(delays[i]) if delays is not None else int(g.integers(0, max(n - L, 1)))
             phi = float(fracs[i]) if fracs is not None else float(g.random())
             if D + phi > n - L:
                 raise ValueError("transmission does not fit in the block")

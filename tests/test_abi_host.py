@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI: the library loads, exports what the header
+declares, and validates configurations before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import siggen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2005_10445_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_2005_10445_amd.build import build
+        build()
+    return _capi
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "acq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(acq_\w+)\s*\(", src, flags=re.M))
+
+
+def test_header_symbols_exported(capi):
+    declared = _declared_functions()
+    assert declared == set(capi.EXPORTED)
+    L = capi.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def _cfg(capi, **over):
+    from paper_2005_10445_amd import make_config
+    kw = dict(chips=siggen.make_codes(1, 4, 8192), spc=2, fs_hz=8e6, num_bins=11, bin_step_hz=1000.0,
+              max_block_len=1 << 20, fft_len=1 << 15)
+    kw.update(over)
+    return make_config(**kw)
+
+
+def _status(capi, cfg):
+    g = capi.AcqGeometry()
+    return capi.lib().acq_plan_geometry(ctypes.byref(cfg), ctypes.byref(g)), g
+
+
+def test_geometry_of_the_tag_bank_workload(capi):
+    cfg, keep = _cfg(capi)
+    rc, g = _status(capi, cfg)
+    assert rc == 0
+    assert (g.template_len, g.min_fft_len, g.fft_len, g.sub_fft_len) == (16384, 32768, 32768, 16384)
+    assert g.valid_per_segment == 16385
+    assert g.max_segments == 63
+    assert g.freq_quantum_hz == 244.140625 and g.bin_step_hz == 976.5625
+
+
+def test_bins_agree_with_oracle_reading(capi):
+    from paper_2005_10445_amd import bin_frequencies
+    for K, step, centre in ((11, 1000.0, 0.0), (21, 1000.0, 0.0), (5, 3333.0, 1234.0), (1, 0.0, 0.0)):
+        f = bin_frequencies(chips=siggen.make_codes(1, 2, 8192), spc=2, fs_hz=8e6, num_bins=K,
+                            bin_step_hz=step, bin_center_hz=centre, max_block_len=1 << 20)
+        ref, _ = oracle.snap_bins(8e6, 16384, K, centre, step)
+        np.testing.assert_array_equal(f, ref)
+
+
+def test_default_segment_length_choice(capi):
+    from paper_2005_10445_amd import geometry
+    g = geometry(chips=siggen.make_codes(1, 1, 1024), spc=4, fs_hz=8e6, max_block_len=1 << 17)
+    assert g["template_len"] == 4096 and g["min_fft_len"] == 8192
+    assert g["fft_len"] >= 8192 and g["fft_len"] // 4 <= 16384
+    assert g["max_segments"] * g["valid_per_segment"] >= (1 << 17) - 4096 + 1
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(num_bins=4), -1),
+    (dict(spc=3), -7),
+    (dict(fft_len=3 << 14), -1),
+    (dict(fft_len=1 << 14), -1),
+    (dict(fft_len=1 << 16), -7),
+    (dict(precision="fp16"), -7),
+    (dict(refine_radius=9), -1),
+    (dict(fs_hz=0.0), -1),
+    (dict(max_block_len=0), -1),
+    (dict(bin_step_hz=0.0), -1),
+])
+def test_invalid_configs_rejected(capi, over, status):
+    cfg, keep = _cfg(capi, **over)
+    rc, _ = _status(capi, cfg)
+    assert rc == status, capi.lib().acq_last_error()
+
+
+def test_chips_must_be_pm1(capi):
+    chips = siggen.make_codes(1, 2, 64)
+    chips[1, 5] = 0
+    cfg, keep = _cfg(capi, chips=chips, fft_len=0)
+    rc, _ = _status(capi, cfg)
+    assert rc == -1 and b"chips" in capi.lib().acq_last_error()
+
+
+def test_null_handles_rejected_without_gpu(capi):
+    L = capi.lib()
+    n = ctypes.c_int32(5)
+    out = (capi.AcqDetection * 1)()
+    assert L.acq_detect(None, None, 10, out, 1, ctypes.byref(n)) == -1
+    assert L.acq_correlate_power(None, None, 10, None) == -1
+    assert L.acq_release(None) == 0
+    assert L.acq_plan(None, None, None) == -1
+    assert L.acq_strerror(-4) == b"output truncated"
+    assert L.acq_strerror(0) == b"ok"
+
+
+def test_oracle_is_not_imported_by_the_product():
+    pkg = os.path.join(ROOT, "paper_2005_10445_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "direct.c" not in text, f
