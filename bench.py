@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--fft-len", type=int, default=0, help="override the workload's segment length")
     ap.add_argument("--tag-tile", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0: skip)")
+    ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
+                    help="copy: a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -102,6 +104,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.mode == "copy":
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")   # 256 MiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
 
     import siggen
     from paper_2005_10445_amd import Plan

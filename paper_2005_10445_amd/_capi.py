@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libacq.so")
+# ACQ_LIBRARY selects another build of the same library (e.g. to compare variants)
+LIB_PATH = os.environ.get("ACQ_LIBRARY") or os.path.join(_PKG, "libacq.so")
 
 ACQ_OK = 0
 ACQ_ERR_INVALID_ARG = -1

@@ -80,6 +80,15 @@ __device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2&
     x3 = csub(a1, b1);
 }
 
+// outputs 0 and 1 of dft4 only (x2, x3 are left unspecified)
+template <int S>
+__device__ __forceinline__ void dft4_low(float2& x0, float2& x1, float2& x2, float2& x3) {
+    const float2 a0 = cadd(x0, x2), a1 = csub(x0, x2);
+    const float2 b0 = cadd(x1, x3), b1 = mul_sj<S>(csub(x1, x3));
+    x0 = cadd(a0, b0);
+    x1 = cadd(a1, b1);
+}
+
 template <int S>
 __device__ __forceinline__ void dft8(float2 (&u)[8]) {
     float2 e0 = u[0], e1 = u[2], e2 = u[4], e3 = u[6];

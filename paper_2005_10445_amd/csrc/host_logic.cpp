@@ -183,6 +183,21 @@ std::vector<float> unit_roots(int64_t n) {
     return out;
 }
 
+std::vector<float> fft14_b1_table() {
+    const int64_t n = 16384;
+    const std::vector<float> roots = unit_roots(n);
+    std::vector<float> out(size_t(2 * 16 * 16 * 64));
+    size_t o = 0;
+    for (int64_t w = 0; w < 16; ++w)
+        for (int64_t k2a = 0; k2a < 16; ++k2a)
+            for (int64_t l = 0; l < 64; ++l) {
+                const int64_t e = (l * (w + 16 * k2a)) % n;
+                out[o++] = roots[size_t(2 * e)];
+                out[o++] = roots[size_t(2 * e + 1)];
+            }
+    return out;
+}
+
 std::vector<float> rect_spectrum_conj(int64_t M, int spc) {
     std::vector<float> out(size_t(2 * M));
     const double two_pi = 6.283185307179586476925286766559;

@@ -51,6 +51,10 @@ double default_threshold(int64_t num_tags, int64_t num_bins, int64_t n, int64_t 
 // symmetry and rounded to FP32; interleaved (re, im).
 std::vector<float> unit_roots(int64_t n);
 
+// Twiddles of the 2^14-point workgroup transform, laid out [w][k2a][l] with
+// entry exp(+j 2 pi l (w + 16 k2a) / 2^14), w, k2a < 16, l < 64.
+std::vector<float> fft14_b1_table();
+
 // conj of the spectrum of a length-spc run of ones at M points:
 // sum_{r<spc} exp(+j 2 pi i r / M), i in [0, M); interleaved FP32 from FP64.
 std::vector<float> rect_spectrum_conj(int64_t M, int spc);

@@ -17,6 +17,7 @@ struct CorrArgs {
     const float2* rect;         // [M] sum_{r<spc} exp(+j 2 pi i r / M)
     const float2* rootsM;       // [M] exp(+j 2 pi m / M)
     const float2* rootsSub;     // [Msub] exp(+j 2 pi m / Msub)
+    const float2* b1tab;        // 2^14-point engine twiddle table (else unused)
     const int32_t* rot;         // [K] rotation of bin k, in [0, M)
     unsigned long long* keys;   // [T] packed (power bits, ~(lag*K + k)), max-reduced
     float* dump;                // optional [T][K][lags] power
@@ -31,6 +32,7 @@ struct FwdArgs {
     float2* X;                  // [S][M]
     const float2* rootsM;
     const float2* rootsSub;
+    const float2* b1tab;
     int64_t n, V;
     int32_t S, spc, M, Msub;
 };
@@ -53,7 +55,7 @@ hipError_t launch_block_power(const float2* x, int64_t n, double* parts, hipStre
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st);
 hipError_t launch_forward(const FwdArgs& a, int log2_sub, hipStream_t st);
 hipError_t launch_bank(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub,
-                       int Msub, int M, int log2_sub, hipStream_t st);
+                       const float2* b1tab, int Msub, int M, int log2_sub, hipStream_t st);
 hipError_t launch_correlate(const CorrArgs& a, int log2_sub, hipStream_t st);
 hipError_t launch_refine(const RefineArgs& a, hipStream_t st);
 hipError_t launch_compact(const acq_detection* dets, const int32_t* found, int T,

@@ -40,6 +40,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_fft.h"
+#include "fft14.h"
 #include "host_logic.h"
 #include "kernels.h"
 
@@ -49,6 +50,7 @@ using dev::cadd;
 using dev::cmul;
 using dev::cmulc;
 using dev::Fft;
+using dev::dft16;
 
 namespace {
 
@@ -90,32 +92,71 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t count) {
     if (i < count) p[i] = 0ull;
 }
 
+// ------------------------------------------------------------------ transform engines
+// Both engines take v[m] = a[in_index(m)] and leave output index
+// out_base() + out_off(r) in v[r].
+
+// Stockham passes (2^10 .. 2^13 points), see device_fft.h.
+template <int LOGN_>
+struct StockhamEngine {
+    using F = Fft<LOGN_>;
+    static constexpr int LOGN = LOGN_;
+    static constexpr int N = F::N;
+    static constexpr int NT = F::NT;
+    static constexpr int LDS = F::LDS;
+    static constexpr int EXTRA = 1;
+    static constexpr int B1_TABLE = 1;
+    int t;
+    const float2* roots;
+    __device__ __forceinline__ void init(const float2* __restrict__ r, float2*) {
+        t = int(threadIdx.x);
+        roots = r;
+    }
+    __device__ __forceinline__ int in_index(int m) const { return t + m * NT; }
+    __device__ __forceinline__ int out_base() const { return t; }
+    // smallest / largest out_base() over the wave (wave-uniform)
+    __device__ __forceinline__ int out_min() const { return __builtin_amdgcn_readfirstlane(t & ~63); }
+    __device__ __forceinline__ int out_max() const { return out_min() + 63; }
+    static constexpr int out_off(int r) { return r * NT; }
+    static constexpr int HI_OFF = 1 << 30;      // no output is ever pruned
+    template <int S>
+    __device__ __forceinline__ void transform(float2 (&v)[16], float2* lds, __amdgpu_buffer_rsrc_t,
+                                              const float2*, bool = true) const {
+        int tq = t;
+        asm volatile("" : "+v"(tq));            // recompute addressing per call, no hoisting
+        F::template transform<S>(v, lds, roots, tq);
+    }
+};
+
+using dev::bload;
+using dev::Fft14;
+using dev::make_rsrc;
+
 // ------------------------------------------------------------------ forward spectra
-template <int LOGN>
-__global__ __launch_bounds__(Fft<LOGN>::NT) void k_forward(FwdArgs a) {
-    using F = Fft<LOGN>;
-    constexpr int NT = F::NT;
-    __shared__ float2 lds[F::LDS];
-    const int t = threadIdx.x;
+template <class E>
+__global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
+    __shared__ float2 lds[E::LDS];
+    __shared__ float2 extra[E::EXTRA];
+    E eng;
+    eng.init(a.rootsSub, extra);
+    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     const int j = blockIdx.x;
     const int64_t base = int64_t(j) * a.V;
     float2* Xj = a.X + size_t(j) * size_t(a.M);
     const int mmask = a.M - 1;
     for (int r = 0; r < a.spc; ++r) {
-        int tq = t;                       // see k_correlate: no hoisted addresses
-        const float2* roots = a.rootsSub;
-        asm volatile("" : "+v"(tq), "+s"(roots));
         float2 v[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-            const int64_t idx = base + int64_t(a.spc) * (tq + m * NT) + r;
+            const int64_t idx = base + int64_t(a.spc) * eng.in_index(m) + r;
             v[m] = idx < a.n ? a.x[idx] : make_float2(0.f, 0.f);
         }
-        F::template transform<-1>(v, lds, roots, tq);
+        eng.template transform<-1>(v, lds, b1, extra);
         // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub]
+        const int ob = eng.out_base();
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-            const int ip = tq + m * NT;
+            const int ip = ob + E::out_off(m);
             for (int q = 0; q < a.spc; ++q) {
                 const int i = ip + q * a.Msub;
                 float2 c = v[m];
@@ -123,49 +164,51 @@ __global__ __launch_bounds__(Fft<LOGN>::NT) void k_forward(FwdArgs a) {
                 Xj[i] = r ? cadd(Xj[i], c) : c;
             }
         }
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ replica bank
-template <int LOGN>
-__global__ __launch_bounds__(Fft<LOGN>::NT) void k_bank(const int8_t* __restrict__ chips, int C,
-                                                        float2* __restrict__ bank,
-                                                        const float2* __restrict__ rootsSub, int M) {
-    using F = Fft<LOGN>;
-    constexpr int NT = F::NT;
-    __shared__ float2 lds[F::LDS];
-    const int t = threadIdx.x;
+template <class E>
+__global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips, int C,
+                                                float2* __restrict__ bank,
+                                                const float2* __restrict__ rootsSub,
+                                                const float2* __restrict__ b1tab, int M) {
+    __shared__ float2 lds[E::LDS];
+    __shared__ float2 extra[E::EXTRA];
+    E eng;
+    eng.init(rootsSub, extra);
+    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(b1tab, E::B1_TABLE * 8);
     const int tag = blockIdx.x;
     float2 v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-        const int ip = t + m * NT;
+        const int ip = eng.in_index(m);
         v[m] = make_float2(ip < C ? float(chips[size_t(tag) * C + ip]) : 0.f, 0.f);
     }
-    F::template transform<-1>(v, lds, rootsSub, t);
+    eng.template transform<-1>(v, lds, b1, extra);
     const float s = 1.0f / float(M);   // exact: M is a power of two
+    const int ob = eng.out_base();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int ip = t + m * NT;
-        bank[size_t(tag) * F::N + ip] = make_float2(v[m].x * s, -v[m].y * s);
-    }
+    for (int m = 0; m < 16; ++m)
+        bank[size_t(tag) * E::N + ob + E::out_off(m)] = make_float2(v[m].x * s, -v[m].y * s);
 }
 
 // ------------------------------------------------------------------ correlation
-template <int LOGN, bool DUMP>
-__global__ __launch_bounds__(Fft<LOGN>::NT) void k_correlate(CorrArgs a) {
-    using F = Fft<LOGN>;
-    constexpr int NT = F::NT;
-    constexpr int NW = NT / 64;
-    __shared__ float2 lds[F::LDS];
+template <class E, bool DUMP>
+__global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
+    constexpr int N = E::N;
+    constexpr int NW = E::NT / 64;
+    __shared__ float2 lds[E::LDS];
+    __shared__ float2 extra[E::EXTRA];
     __shared__ unsigned long long red[kMaxTagTile * NW];
 
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
     // range of work items so items sharing a segment and a tag tile share its L2.
     const int per = int(gridDim.x) >> 3;
-    const int w = int(blockIdx.x & 7u) * per + int(blockIdx.x >> 3);
-    if (w >= a.nwork) return;
-    int rem = w;
+    const int wi = int(blockIdx.x & 7u) * per + int(blockIdx.x >> 3);
+    if (wi >= a.nwork) return;
+    int rem = wi;
     const int rho = rem % a.spc;
     rem /= a.spc;
     const int k = rem % a.K;
@@ -174,8 +217,12 @@ __global__ __launch_bounds__(Fft<LOGN>::NT) void k_correlate(CorrArgs a) {
     const int tile = rem / a.S;
     const int tag0 = tile * a.tile;
     const int ntag = min(a.tile, a.T - tag0);
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+
+    E eng;
+    eng.init(a.rootsSub, extra);
+    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
+    const __amdgpu_buffer_rsrc_t bank = make_rsrc(a.bank + size_t(tag0) * N, uint32_t(ntag) * N * 8);
 
     // tag-independent first step of the inverse transform
     float2 G[16];
@@ -185,7 +232,7 @@ __global__ __launch_bounds__(Fft<LOGN>::NT) void k_correlate(CorrArgs a) {
         const int mmask = a.M - 1;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-            const int ip = t + m * NT;
+            const int ip = eng.in_index(m);
             float2 acc = make_float2(0.f, 0.f);
             for (int q = 0; q < a.spc; ++q) {
                 const int i = ip + q * a.Msub;
@@ -199,42 +246,50 @@ __global__ __launch_bounds__(Fft<LOGN>::NT) void k_correlate(CorrArgs a) {
         }
     }
 
+    // valid outputs: segment lag spc*u + rho < min(V, lags - jV)  <=>  u < ulim
     const int64_t seg0 = int64_t(j) * a.V;
+    const int64_t vlim64 = a.lags - seg0 < a.V ? a.lags - seg0 : a.V;
+    const int vlim = int(vlim64);
+    const int ulim = vlim > rho ? (vlim - rho + a.spc - 1) / a.spc : 0;
+    // key index tau*K + k = kbase + u*kstep (fits in 32 bits for valid lags)
+    const unsigned kbase = unsigned((seg0 + rho) * a.K + k);
+    const unsigned kstep = unsigned(a.spc * a.K);
+    const int ob = eng.out_base();
+    const unsigned idx0 = kbase + unsigned(ob) * kstep;
+    const int omin = eng.out_min(), omax = eng.out_max();   // wave-uniform
+    const bool hi = omin + E::HI_OFF < ulim;               // any output of the upper half needed
+
+    const int voff = eng.in_index(0) * 8;       // bank element of register m: in_index(0) + m*NT
+
     for (int tt = 0; tt < ntag; ++tt) {
-        const int tag = tag0 + tt;
-        const float2* B = a.bank + size_t(tag) * F::N;
-        // Every address and twiddle below is the same for each tag.  Hiding the
-        // thread index and the table pointer from the optimiser per iteration
-        // keeps it from holding all of them in registers across the tag loop
-        // (which spills at 1024 threads); recomputing them is a few integer ops.
-        int tq = t;
-        const float2* roots = a.rootsSub;
-        asm volatile("" : "+v"(tq), "+s"(roots));
         float2 v[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], B[tq + m * NT]);
-        F::template transform<+1>(v, lds, roots, tq);
+        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], bload(bank, voff, (tt * N + m * E::NT) * 8));
+        eng.template transform<+1>(v, lds, b1, extra, hi);
         unsigned long long best = 0ull;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int u = tq + m * NT;
-            const int64_t ts = int64_t(a.spc) * u + rho;
-            const int64_t tau = seg0 + ts;
-            if (ts < a.V && tau < a.lags) {
-                const float p = fmaf(v[m].x, v[m].x, v[m].y * v[m].y);
-                const unsigned idx = unsigned(tau * a.K + k);
-                const unsigned long long key =
-                    (static_cast<unsigned long long>(__float_as_uint(p)) << 32) |
-                    static_cast<unsigned long long>(~idx);
+        for (int r = 0; r < 16; ++r) {
+            const int off = E::out_off(r);
+            if (omin + off < ulim) {               // wave-uniform: some lane of this register is valid
+                const float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
+                const unsigned idx = idx0 + unsigned(off) * kstep;
+                unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(p)) << 32) |
+                                         static_cast<unsigned long long>(~idx);
+                if (omax + off >= ulim && ob + off >= ulim) key = 0ull;
                 best = key > best ? key : best;
-                if constexpr (DUMP) a.dump[(size_t(tag) * a.K + k) * size_t(a.lags) + size_t(tau)] = p;
+                if constexpr (DUMP) {
+                    if (ob + off < ulim) {
+                        const int64_t tau = seg0 + int64_t(a.spc) * (ob + off) + rho;
+                        a.dump[(size_t(tag0 + tt) * a.K + k) * size_t(a.lags) + size_t(tau)] = p;
+                    }
+                }
             }
         }
         best = wave_max(best);
         if (lane == 0) red[tt * NW + wave] = best;
     }
     __syncthreads();
-    for (int i = t; i < ntag; i += NT) {
+    for (int i = int(threadIdx.x); i < ntag; i += E::NT) {
         unsigned long long m = 0ull;
         for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
         if (m) atomicMax(&a.keys[tag0 + i], m);
@@ -389,51 +444,52 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int LOGN>
-static hipError_t fwd_n(const FwdArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((k_forward<LOGN>), dim3(a.S), dim3(Fft<LOGN>::NT), 0, st, a);
+template <class E>
+static hipError_t fwd_e(const FwdArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((k_forward<E>), dim3(a.S), dim3(E::NT), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_forward(const FwdArgs& a, int log2_sub, hipStream_t st) {
     if (a.S <= 0) return hipSuccess;
+    if ((1 << log2_sub) != a.Msub) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return fwd_n<10>(a, st);
-        case 11: return fwd_n<11>(a, st);
-        case 12: return fwd_n<12>(a, st);
-        case 13: return fwd_n<13>(a, st);
-        case 14: return fwd_n<14>(a, st);
+        case 10: return fwd_e<StockhamEngine<10>>(a, st);
+        case 11: return fwd_e<StockhamEngine<11>>(a, st);
+        case 12: return fwd_e<StockhamEngine<12>>(a, st);
+        case 13: return fwd_e<StockhamEngine<13>>(a, st);
+        case 14: return fwd_e<Fft14>(a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int LOGN>
-static hipError_t bank_n(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub, int M,
-                         hipStream_t st) {
-    hipLaunchKernelGGL((k_bank<LOGN>), dim3(T), dim3(Fft<LOGN>::NT), 0, st, chips, C, bank, rootsSub, M);
+template <class E>
+static hipError_t bank_e(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub,
+                         const float2* b1tab, int M, hipStream_t st) {
+    hipLaunchKernelGGL((k_bank<E>), dim3(T), dim3(E::NT), 0, st, chips, C, bank, rootsSub, b1tab, M);
     return hipGetLastError();
 }
 
-hipError_t launch_bank(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub, int Msub,
-                       int M, int log2_sub, hipStream_t st) {
+hipError_t launch_bank(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub,
+                       const float2* b1tab, int Msub, int M, int log2_sub, hipStream_t st) {
     if ((1 << log2_sub) != Msub || C > Msub) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return bank_n<10>(chips, T, C, bank, rootsSub, M, st);
-        case 11: return bank_n<11>(chips, T, C, bank, rootsSub, M, st);
-        case 12: return bank_n<12>(chips, T, C, bank, rootsSub, M, st);
-        case 13: return bank_n<13>(chips, T, C, bank, rootsSub, M, st);
-        case 14: return bank_n<14>(chips, T, C, bank, rootsSub, M, st);
+        case 10: return bank_e<StockhamEngine<10>>(chips, T, C, bank, rootsSub, b1tab, M, st);
+        case 11: return bank_e<StockhamEngine<11>>(chips, T, C, bank, rootsSub, b1tab, M, st);
+        case 12: return bank_e<StockhamEngine<12>>(chips, T, C, bank, rootsSub, b1tab, M, st);
+        case 13: return bank_e<StockhamEngine<13>>(chips, T, C, bank, rootsSub, b1tab, M, st);
+        case 14: return bank_e<Fft14>(chips, T, C, bank, rootsSub, b1tab, M, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int LOGN>
-static hipError_t corr_n(const CorrArgs& a, hipStream_t st) {
+template <class E>
+static hipError_t corr_e(const CorrArgs& a, hipStream_t st) {
     const int grid = ((a.nwork + 7) / 8) * 8;
     if (a.dump)
-        hipLaunchKernelGGL((k_correlate<LOGN, true>), dim3(grid), dim3(Fft<LOGN>::NT), 0, st, a);
+        hipLaunchKernelGGL((k_correlate<E, true>), dim3(grid), dim3(E::NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_correlate<LOGN, false>), dim3(grid), dim3(Fft<LOGN>::NT), 0, st, a);
+        hipLaunchKernelGGL((k_correlate<E, false>), dim3(grid), dim3(E::NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -441,11 +497,11 @@ hipError_t launch_correlate(const CorrArgs& a, int log2_sub, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return corr_n<10>(a, st);
-        case 11: return corr_n<11>(a, st);
-        case 12: return corr_n<12>(a, st);
-        case 13: return corr_n<13>(a, st);
-        case 14: return corr_n<14>(a, st);
+        case 10: return corr_e<StockhamEngine<10>>(a, st);
+        case 11: return corr_e<StockhamEngine<11>>(a, st);
+        case 12: return corr_e<StockhamEngine<12>>(a, st);
+        case 13: return corr_e<StockhamEngine<13>>(a, st);
+        case 14: return corr_e<Fft14>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

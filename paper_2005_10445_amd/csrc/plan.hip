@@ -30,6 +30,7 @@ struct acq_plan_s {
     float2* d_rect = nullptr;           // [M]
     float2* d_rootsM = nullptr;         // [M]
     float2* d_rootsSub = nullptr;       // [Msub]
+    float2* d_b1tab = nullptr;          // 2^14-point engine table (or a 1-entry stub)
     int8_t* d_chips = nullptr;          // [T][C]
     int32_t* d_rot = nullptr;           // [K]
     int64_t* d_rot_signed = nullptr;    // [K]
@@ -70,7 +71,7 @@ hipError_t dalloc(T** p, size_t count) {
 
 void free_plan(acq_plan_s* p) {
     if (!p) return;
-    void* dev[] = {p->d_X, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_chips,
+    void* dev[] = {p->d_X, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_dets,
                    p->d_out, p->d_found, p->d_count};
     for (void* d : dev)
@@ -93,6 +94,8 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_rect, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsM, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
+    const std::vector<float> b1 = g.log2_sub == 14 ? acq::fft14_b1_table() : std::vector<float>(2, 0.f);
+    ACQ_HIP(dalloc(&p->d_b1tab, b1.size() / 2));
     ACQ_HIP(dalloc(&p->d_chips, T * C));
     ACQ_HIP(dalloc(&p->d_rot, K));
     ACQ_HIP(dalloc(&p->d_rot_signed, K));
@@ -113,12 +116,13 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(hipMemcpyAsync(p->d_rootsM, rootsM.data(), rootsM.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rootsSub, rootsSub.data(), rootsSub.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rect, rect.data(), rect.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    ACQ_HIP(hipMemcpyAsync(p->d_b1tab, b1.data(), b1.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_chips, c.chips, T * C, hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rot, g.rot.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rot_signed, g.rot_signed.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_freqs, g.freqs_hz.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
-    ACQ_HIP(acq::launch_bank(p->d_chips, int(T), int(C), p->d_bank, p->d_rootsSub, int(g.Msub), int(g.M),
-                             g.log2_sub, st));
+    ACQ_HIP(acq::launch_bank(p->d_chips, int(T), int(C), p->d_bank, p->d_rootsSub, p->d_b1tab, int(g.Msub),
+                             int(g.M), g.log2_sub, st));
     ACQ_HIP(hipStreamSynchronize(st));
     return ACQ_OK;
 }
@@ -162,6 +166,7 @@ int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
     fa.X = p->d_X;
     fa.rootsM = p->d_rootsM;
     fa.rootsSub = p->d_rootsSub;
+    fa.b1tab = p->d_b1tab;
     fa.n = n;
     fa.V = g.V;
     fa.S = S;
@@ -179,6 +184,7 @@ int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
     ca.rect = p->d_rect;
     ca.rootsM = p->d_rootsM;
     ca.rootsSub = p->d_rootsSub;
+    ca.b1tab = p->d_b1tab;
     ca.rot = p->d_rot;
     ca.keys = p->d_keys;
     ca.dump = dump;
