@@ -19,7 +19,6 @@ Prints one JSON line on stdout.  Reported beside the throughput:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -31,19 +30,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "correlate_tagbank_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_10445_amd", "csrc", f) for f in ("kernels.hip", "device_fft.h")]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def correlate_flops(T, K, S, M, V) -> float:
@@ -58,6 +48,7 @@ def traffic_per_launch():
             t = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2005_10445_amd.profiling import kernel_source_hash
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")

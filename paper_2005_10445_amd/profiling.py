@@ -1,0 +1,129 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+  python -m paper_2005_10445_amd.profiling trace  <trace_dir> <out.txt> --cmd "<command>"
+  python -m paper_2005_10445_amd.profiling traffic <fetch_dir> <write_dir> <copy_fetch_dir>
+         <copy_write_dir> <out.json> --kernel k_correlate --copy-bytes 268435456 --cmd "<command>"
+
+FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
+counters read for a plain device copy of known size, so that the reported
+figure is HBM bytes per launch of the kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_10445_amd", "csrc", f)
+                  for f in ("kernels.hip", "device_fft.h", "fft14.h")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def counters(d: str):
+    """{kernel name: {counter: [value per dispatch]}} from a --pmc run."""
+    out = defaultdict(lambda: defaultdict(list))
+    with open(_find(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def _pick(table, substr):
+    names = [k for k in table if substr in k]
+    if not names:
+        raise KeyError(substr)
+    return names[0]
+
+
+def mean_counter(d: str, kernel_substr: str, counter: str) -> float:
+    t = counters(d)
+    vals = t[_pick(t, kernel_substr)][counter]
+    return sum(vals) / len(vals)
+
+
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_bytes, cmd):
+    copy_name = "copyBuffer"
+    f_copy = mean_counter(copy_fetch_dir, copy_name, "FETCH_SIZE")
+    w_copy = mean_counter(copy_write_dir, copy_name, "WRITE_SIZE")
+    f_scale = copy_bytes / f_copy          # bytes per counted KiB
+    w_scale = copy_bytes / w_copy
+    f_k = mean_counter(fetch_dir, kernel, "FETCH_SIZE")
+    w_k = mean_counter(write_dir, kernel, "WRITE_SIZE")
+    return {
+        "kernel": kernel,
+        "fetch_kib_counted": f_k, "write_kib_counted": w_k,
+        "copy_bytes": copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+        "fetch_scale_bytes_per_kib": f_scale, "write_scale_bytes_per_kib": w_scale,
+        "bytes_read_per_launch": f_k * f_scale, "bytes_written_per_launch": w_k * w_scale,
+        "bytes_per_launch": f_k * f_scale + w_k * w_scale,
+        "kernel_source_hash": kernel_source_hash(),
+        "command": cmd,
+    }
+
+
+def trace_summary(trace_dir: str, cmd: str, top: int = 12) -> str:
+    path = _find(trace_dir, "kernel_stats.csv")
+    with open(path) as f:
+        rows = list(csv.DictReader(f))
+    lines = [f"# rocprofv3 kernel trace summary", f"# command: {cmd}",
+             f"# kernel source hash: {kernel_source_hash()}", "",
+             f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+    for r in rows[:top]:
+        name = r["Name"].replace("void ", "")[:60]
+        lines.append(f"{name:60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                     f"{float(r['Percentage']):6.2f}")
+    return "\n".join(lines) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("trace_dir")
+    t.add_argument("out")
+    t.add_argument("--cmd", required=True)
+    c = sub.add_parser("traffic")
+    c.add_argument("fetch_dir")
+    c.add_argument("write_dir")
+    c.add_argument("copy_fetch_dir")
+    c.add_argument("copy_write_dir")
+    c.add_argument("out")
+    c.add_argument("--kernel", default="k_correlate")
+    c.add_argument("--copy-bytes", type=int, default=256 << 20)
+    c.add_argument("--cmd", required=True)
+    a = ap.parse_args(argv)
+    if a.what == "trace":
+        with open(a.out, "w") as f:
+            f.write(trace_summary(a.trace_dir, a.cmd))
+    else:
+        res = traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir, a.kernel,
+                      a.copy_bytes, a.cmd)
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+            f.write("\n")
+    print(open(a.out).read())
+
+
+if __name__ == "__main__":
+    main()
