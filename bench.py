@@ -115,8 +115,10 @@ def main():
     fft_len = args.fft_len or w["fft_len"]
     dev = torch.device("cuda:0")
     chips = siggen.make_codes(seed, T, C)
+    prec = w.get("precision", "fp32")
     plan = Plan(chips, spc, fs, num_bins=K, bin_center_hz=w["bin_center_hz"], bin_step_hz=w["bin_step_hz"],
-                max_block_len=N, fft_len=fft_len, tag_tile=args.tag_tile)
+                max_block_len=N, fft_len=fft_len, tag_tile=args.tag_tile, precision=prec,
+                refine_radius=w.get("refine_radius", 1))
     freqs = plan.freqs_hz
     x, txs = siggen.make_block(seed, N, chips, spc, fs, freqs, w["n_tx"], snr_db=w["snr_db"])
     xd = torch.from_numpy(x).to(dev)
@@ -160,10 +162,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == "fp32" else f"f32 ({prec} storage)",
         "data": "synthetic (seeded BPSK tags in AWGN)",
         "config": {"workload": args.workload, "tags": T, "bins": K, "block_len": N, "template_len": L,
-                   "fft_len": M, "segments": S, "parallelism": "single GPU"},
+                   "fft_len": M, "segments": S, "precision": prec, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_per_launch(),
                      "kernel": "k_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},

@@ -64,8 +64,6 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
         return fail(ACQ_ERR_INVALID_ARG, "bin_step_hz must be > 0 when num_bins > 1");
     if (cfg->precision != ACQ_FP32 && cfg->precision != ACQ_FP16 && cfg->precision != ACQ_BF16)
         return fail(ACQ_ERR_INVALID_ARG, "unknown precision");
-    if (cfg->precision != ACQ_FP32)
-        return fail(ACQ_ERR_UNSUPPORTED, "FP16/BF16 spectra are not built yet");
     if (cfg->refine_radius < 0 || cfg->refine_radius > kMaxRefineRadius)
         return fail(ACQ_ERR_INVALID_ARG, "refine_radius must be in [0, 8]");
     if (cfg->tag_tile < 0) return fail(ACQ_ERR_INVALID_ARG, "tag_tile must be >= 0");
@@ -142,8 +140,10 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
 
     // device memory: spectra of segments, replica bank, tables, small buffers
     int64_t bytes = 0;
-    bytes += G.max_segments * G.M * 8;        // forward spectra X[S][M]
-    bytes += T * G.Msub * 8;                  // replica bank [T][M/spc]
+    const int64_t sbytes = cfg->precision == ACQ_FP32 ? 8 : 4;
+    bytes += G.max_segments * G.M * 8;        // forward spectra X[S][M] (FP32)
+    if (sbytes == 4) bytes += G.max_segments * G.M * 4;   // their 16-bit copy
+    bytes += T * G.Msub * sbytes;             // replica bank [T][M/spc]
     bytes += G.M * 8 * 2 + G.Msub * 8;        // rect spectrum, roots at M and M/spc
     bytes += T * C;                           // chips
     bytes += K * (4 + 8);                     // rotations, frequencies

@@ -41,6 +41,7 @@
 
 #include "device_fft.h"
 #include "fft14.h"
+#include "storage.h"
 #include "host_logic.h"
 #include "kernels.h"
 
@@ -133,8 +134,23 @@ using dev::Fft14;
 using dev::make_rsrc;
 
 // ------------------------------------------------------------------ forward spectra
-template <class E>
+// Power-of-two prescale of the stored segment spectra for 16-bit storage:
+// 2^-e with e = round(log2(sqrt(M * Pxhat))), so typical |X| is near 1.
+__device__ __forceinline__ int spectrum_exponent(const double* __restrict__ parts, int64_t n, int M) {
+    __shared__ int s_e;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kPowerParts; ++i) s += parts[i];
+        const double px = s / double(n);
+        s_e = px > 0.0 ? int(rint(0.5 * log2(double(M) * px))) : 0;
+    }
+    __syncthreads();
+    return s_e;
+}
+
+template <class E, int PREC>
 __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
+    using St = dev::Storage<PREC>;
     __shared__ float2 lds[E::LDS];
     __shared__ float2 extra[E::EXTRA];
     E eng;
@@ -144,6 +160,8 @@ __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
     const int64_t base = int64_t(j) * a.V;
     float2* Xj = a.X + size_t(j) * size_t(a.M);
     const int mmask = a.M - 1;
+    float xs = 1.0f;
+    if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -spectrum_exponent(a.parts, a.n, a.M));
     for (int r = 0; r < a.spc; ++r) {
         float2 v[16];
 #pragma unroll
@@ -152,8 +170,9 @@ __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
             v[m] = idx < a.n ? a.x[idx] : make_float2(0.f, 0.f);
         }
         eng.template transform<-1>(v, lds, b1, extra);
-        // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub]
+        // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub], accumulated in FP32
         const int ob = eng.out_base();
+        const bool last = r == a.spc - 1;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int ip = ob + E::out_off(m);
@@ -161,7 +180,16 @@ __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
                 const int i = ip + q * a.Msub;
                 float2 c = v[m];
                 if (r) c = cmulc(c, a.rootsM[(int)((int64_t(i) * r) & mmask)]);
-                Xj[i] = r ? cadd(Xj[i], c) : c;
+                if (r) c = cadd(Xj[i], c);
+                if constexpr (PREC == ACQ_FP32) {
+                    Xj[i] = c;
+                } else {
+                    if (last)
+                        reinterpret_cast<typename St::T*>(a.Xh)[size_t(j) * size_t(a.M) + i] =
+                            St::pack(make_float2(c.x * xs, c.y * xs));
+                    else
+                        Xj[i] = c;
+                }
             }
         }
         __syncthreads();
@@ -169,11 +197,13 @@ __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
 }
 
 // ------------------------------------------------------------------ replica bank
-template <class E>
+// bank[t][i] = 2^bank_exp * conj(DFT_Msub(chips_t))[i] / M in the storage format
+template <class E, int PREC>
 __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips, int C,
-                                                float2* __restrict__ bank,
+                                                void* __restrict__ bank,
                                                 const float2* __restrict__ rootsSub,
-                                                const float2* __restrict__ b1tab, int M) {
+                                                const float2* __restrict__ b1tab, int M, int bank_exp) {
+    using St = dev::Storage<PREC>;
     __shared__ float2 lds[E::LDS];
     __shared__ float2 extra[E::EXTRA];
     E eng;
@@ -187,16 +217,17 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
         v[m] = make_float2(ip < C ? float(chips[size_t(tag) * C + ip]) : 0.f, 0.f);
     }
     eng.template transform<-1>(v, lds, b1, extra);
-    const float s = 1.0f / float(M);   // exact: M is a power of two
+    const float s = ldexpf(1.0f, bank_exp) / float(M);   // exact: powers of two
     const int ob = eng.out_base();
+    typename St::T* out = reinterpret_cast<typename St::T*>(bank) + size_t(tag) * E::N;
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
-        bank[size_t(tag) * E::N + ob + E::out_off(m)] = make_float2(v[m].x * s, -v[m].y * s);
+    for (int m = 0; m < 16; ++m) out[ob + E::out_off(m)] = St::pack(make_float2(v[m].x * s, -v[m].y * s));
 }
 
 // ------------------------------------------------------------------ correlation
-template <class E, bool DUMP>
+template <class E, int PREC, bool DUMP>
 __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
+    using St = dev::Storage<PREC>;
     constexpr int N = E::N;
     constexpr int NW = E::NT / 64;
     __shared__ float2 lds[E::LDS];
@@ -222,12 +253,16 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
     E eng;
     eng.init(a.rootsSub, extra);
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const __amdgpu_buffer_rsrc_t bank = make_rsrc(a.bank + size_t(tag0) * N, uint32_t(ntag) * N * 8);
+    const __amdgpu_buffer_rsrc_t bank =
+        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag0) * N * St::BYTES, uint32_t(ntag) * N * St::BYTES);
+    // stored spectra carry 2^-x_exp (segments) and 2^bank_exp (bank): undo both in G
+    float gscale = 1.0f;
+    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, spectrum_exponent(a.parts, a.n, a.M) - a.bank_exp);
 
     // tag-independent first step of the inverse transform
     float2 G[16];
     {
-        const float2* Xj = a.X + size_t(j) * size_t(a.M);
+        const typename St::T* Xj = static_cast<const typename St::T*>(a.X) + size_t(j) * size_t(a.M);
         const int rot = a.rot[k];
         const int mmask = a.M - 1;
 #pragma unroll
@@ -236,12 +271,13 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
             float2 acc = make_float2(0.f, 0.f);
             for (int q = 0; q < a.spc; ++q) {
                 const int i = ip + q * a.Msub;
-                float2 xv = cmul(Xj[(i + rot) & mmask], a.rect[i]);
+                float2 xv = cmul(St::unpack(Xj[(i + rot) & mmask]), a.rect[i]);
                 const int e = (a.Msub * q * rho) & mmask;
                 if (e) xv = cmul(xv, a.rootsM[e]);
                 acc = cadd(acc, xv);
             }
             if (rho) acc = cmul(acc, a.rootsM[ip * rho]);
+            if constexpr (PREC != ACQ_FP32) acc = make_float2(acc.x * gscale, acc.y * gscale);
             G[m] = acc;
         }
     }
@@ -259,12 +295,12 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
     const int omin = eng.out_min(), omax = eng.out_max();   // wave-uniform
     const bool hi = omin + E::HI_OFF < ulim;               // any output of the upper half needed
 
-    const int voff = eng.in_index(0) * 8;       // bank element of register m: in_index(0) + m*NT
+    const int voff = eng.in_index(0) * St::BYTES;   // bank element of register m: in_index(0) + m*NT
 
     for (int tt = 0; tt < ntag; ++tt) {
         float2 v[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], bload(bank, voff, (tt * N + m * E::NT) * 8));
+        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], St::bload(bank, voff, (tt * N + m * E::NT) * St::BYTES));
         eng.template transform<+1>(v, lds, b1, extra, hi);
         unsigned long long best = 0ull;
 #pragma unroll
@@ -445,63 +481,93 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st)
 }
 
 template <class E>
-static hipError_t fwd_e(const FwdArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((k_forward<E>), dim3(a.S), dim3(E::NT), 0, st, a);
+static hipError_t fwd_e(const FwdArgs& a, int prec, hipStream_t st) {
+    switch (prec) {
+        case ACQ_FP32: hipLaunchKernelGGL((k_forward<E, ACQ_FP32>), dim3(a.S), dim3(E::NT), 0, st, a); break;
+        case ACQ_FP16: hipLaunchKernelGGL((k_forward<E, ACQ_FP16>), dim3(a.S), dim3(E::NT), 0, st, a); break;
+        case ACQ_BF16: hipLaunchKernelGGL((k_forward<E, ACQ_BF16>), dim3(a.S), dim3(E::NT), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs& a, int log2_sub, hipStream_t st) {
+hipError_t launch_forward(const FwdArgs& a, int log2_sub, int prec, hipStream_t st) {
     if (a.S <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return fwd_e<StockhamEngine<10>>(a, st);
-        case 11: return fwd_e<StockhamEngine<11>>(a, st);
-        case 12: return fwd_e<StockhamEngine<12>>(a, st);
-        case 13: return fwd_e<StockhamEngine<13>>(a, st);
-        case 14: return fwd_e<Fft14>(a, st);
+        case 10: return fwd_e<StockhamEngine<10>>(a, prec, st);
+        case 11: return fwd_e<StockhamEngine<11>>(a, prec, st);
+        case 12: return fwd_e<StockhamEngine<12>>(a, prec, st);
+        case 13: return fwd_e<StockhamEngine<13>>(a, prec, st);
+        case 14: return fwd_e<Fft14>(a, prec, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <class E>
-static hipError_t bank_e(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub,
-                         const float2* b1tab, int M, hipStream_t st) {
-    hipLaunchKernelGGL((k_bank<E>), dim3(T), dim3(E::NT), 0, st, chips, C, bank, rootsSub, b1tab, M);
+static hipError_t bank_e(const int8_t* chips, int T, int C, void* bank, const float2* rootsSub,
+                         const float2* b1tab, int M, int bank_exp, int prec, hipStream_t st) {
+    switch (prec) {
+        case ACQ_FP32:
+            hipLaunchKernelGGL((k_bank<E, ACQ_FP32>), dim3(T), dim3(E::NT), 0, st, chips, C, bank, rootsSub, b1tab, M,
+                               bank_exp);
+            break;
+        case ACQ_FP16:
+            hipLaunchKernelGGL((k_bank<E, ACQ_FP16>), dim3(T), dim3(E::NT), 0, st, chips, C, bank, rootsSub, b1tab, M,
+                               bank_exp);
+            break;
+        case ACQ_BF16:
+            hipLaunchKernelGGL((k_bank<E, ACQ_BF16>), dim3(T), dim3(E::NT), 0, st, chips, C, bank, rootsSub, b1tab, M,
+                               bank_exp);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_bank(const int8_t* chips, int T, int C, float2* bank, const float2* rootsSub,
-                       const float2* b1tab, int Msub, int M, int log2_sub, hipStream_t st) {
+hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const float2* rootsSub,
+                       const float2* b1tab, int Msub, int M, int bank_exp, int log2_sub, int prec,
+                       hipStream_t st) {
     if ((1 << log2_sub) != Msub || C > Msub) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return bank_e<StockhamEngine<10>>(chips, T, C, bank, rootsSub, b1tab, M, st);
-        case 11: return bank_e<StockhamEngine<11>>(chips, T, C, bank, rootsSub, b1tab, M, st);
-        case 12: return bank_e<StockhamEngine<12>>(chips, T, C, bank, rootsSub, b1tab, M, st);
-        case 13: return bank_e<StockhamEngine<13>>(chips, T, C, bank, rootsSub, b1tab, M, st);
-        case 14: return bank_e<Fft14>(chips, T, C, bank, rootsSub, b1tab, M, st);
+        case 10: return bank_e<StockhamEngine<10>>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
+        case 11: return bank_e<StockhamEngine<11>>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
+        case 12: return bank_e<StockhamEngine<12>>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
+        case 13: return bank_e<StockhamEngine<13>>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
+        case 14: return bank_e<Fft14>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <class E>
-static hipError_t corr_e(const CorrArgs& a, hipStream_t st) {
-    const int grid = ((a.nwork + 7) / 8) * 8;
+template <class E, int PREC>
+static void corr_ep(const CorrArgs& a, int grid, hipStream_t st) {
     if (a.dump)
-        hipLaunchKernelGGL((k_correlate<E, true>), dim3(grid), dim3(E::NT), 0, st, a);
+        hipLaunchKernelGGL((k_correlate<E, PREC, true>), dim3(grid), dim3(E::NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_correlate<E, false>), dim3(grid), dim3(E::NT), 0, st, a);
+        hipLaunchKernelGGL((k_correlate<E, PREC, false>), dim3(grid), dim3(E::NT), 0, st, a);
+}
+
+template <class E>
+static hipError_t corr_e(const CorrArgs& a, int prec, hipStream_t st) {
+    const int grid = ((a.nwork + 7) / 8) * 8;
+    switch (prec) {
+        case ACQ_FP32: corr_ep<E, ACQ_FP32>(a, grid, st); break;
+        case ACQ_FP16: corr_ep<E, ACQ_FP16>(a, grid, st); break;
+        case ACQ_BF16: corr_ep<E, ACQ_BF16>(a, grid, st); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_correlate(const CorrArgs& a, int log2_sub, hipStream_t st) {
+hipError_t launch_correlate(const CorrArgs& a, int log2_sub, int prec, hipStream_t st) {
     if (a.nwork <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return corr_e<StockhamEngine<10>>(a, st);
-        case 11: return corr_e<StockhamEngine<11>>(a, st);
-        case 12: return corr_e<StockhamEngine<12>>(a, st);
-        case 13: return corr_e<StockhamEngine<13>>(a, st);
-        case 14: return corr_e<Fft14>(a, st);
+        case 10: return corr_e<StockhamEngine<10>>(a, prec, st);
+        case 11: return corr_e<StockhamEngine<11>>(a, prec, st);
+        case 12: return corr_e<StockhamEngine<12>>(a, prec, st);
+        case 13: return corr_e<StockhamEngine<13>>(a, prec, st);
+        case 14: return corr_e<Fft14>(a, prec, st);
         default: return hipErrorInvalidValue;
     }
 }

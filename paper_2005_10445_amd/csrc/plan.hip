@@ -8,6 +8,7 @@
 // kernels on the plan's stream and copies the detections back.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -25,8 +26,10 @@ struct acq_plan_s {
     hipStream_t stream = nullptr;
     int device = 0;
 
-    float2* d_X = nullptr;              // [S][M]
-    float2* d_bank = nullptr;           // [T][Msub]
+    float2* d_X = nullptr;              // [S][M] FP32 segment spectra
+    void* d_Xh = nullptr;               // [S][M] 16-bit segment spectra (FP16/BF16 plans)
+    void* d_bank = nullptr;             // [T][Msub] in the plan's storage format
+    int bank_exp = 0;                   // power-of-two prescale of the stored bank
     float2* d_rect = nullptr;           // [M]
     float2* d_rootsM = nullptr;         // [M]
     float2* d_rootsSub = nullptr;       // [Msub]
@@ -71,7 +74,7 @@ hipError_t dalloc(T** p, size_t count) {
 
 void free_plan(acq_plan_s* p) {
     if (!p) return;
-    void* dev[] = {p->d_X, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_chips,
+    void* dev[] = {p->d_X, p->d_Xh, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_dets,
                    p->d_out, p->d_found, p->d_count};
     for (void* d : dev)
@@ -89,8 +92,12 @@ int build_plan(acq_plan_s* p) {
     const acq_config& c = p->cfg;
     const size_t T = size_t(c.num_tags), C = size_t(c.num_chips), K = size_t(c.num_bins);
     const size_t S = size_t(g.max_segments > 0 ? g.max_segments : 1);
+    const bool half = c.precision != ACQ_FP32;
     ACQ_HIP(dalloc(&p->d_X, S * size_t(g.M)));
-    ACQ_HIP(dalloc(&p->d_bank, T * size_t(g.Msub)));
+    if (half) ACQ_HIP(hipMalloc(&p->d_Xh, S * size_t(g.M) * 4));
+    ACQ_HIP(hipMalloc(&p->d_bank, T * size_t(g.Msub) * (half ? 4 : 8)));
+    // 16-bit banks are stored with rms magnitude near 1: 2^round(log2(M / sqrt(C)))
+    p->bank_exp = half ? int(std::lrint(std::log2(double(g.M) / std::sqrt(double(C))))) : 0;
     ACQ_HIP(dalloc(&p->d_rect, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsM, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
@@ -122,7 +129,7 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(hipMemcpyAsync(p->d_rot_signed, g.rot_signed.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_freqs, g.freqs_hz.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
     ACQ_HIP(acq::launch_bank(p->d_chips, int(T), int(C), p->d_bank, p->d_rootsSub, p->d_b1tab, int(g.Msub),
-                             int(g.M), g.log2_sub, st));
+                             int(g.M), p->bank_exp, g.log2_sub, c.precision, st));
     ACQ_HIP(hipStreamSynchronize(st));
     return ACQ_OK;
 }
@@ -164,6 +171,8 @@ int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
     acq::FwdArgs fa{};
     fa.x = x;
     fa.X = p->d_X;
+    fa.Xh = p->d_Xh;
+    fa.parts = p->d_parts;
     fa.rootsM = p->d_rootsM;
     fa.rootsSub = p->d_rootsSub;
     fa.b1tab = p->d_b1tab;
@@ -175,12 +184,14 @@ int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
     fa.Msub = int(g.Msub);
     {
         KernelTimer kt(p, ACQ_KERNEL_FORWARD);
-        ACQ_HIP(acq::launch_forward(fa, g.log2_sub, st));
+        ACQ_HIP(acq::launch_forward(fa, g.log2_sub, c.precision, st));
     }
 
     acq::CorrArgs ca{};
-    ca.X = p->d_X;
+    ca.X = c.precision == ACQ_FP32 ? static_cast<const void*>(p->d_X) : p->d_Xh;
     ca.bank = p->d_bank;
+    ca.parts = p->d_parts;
+    ca.bank_exp = p->bank_exp;
     ca.rect = p->d_rect;
     ca.rootsM = p->d_rootsM;
     ca.rootsSub = p->d_rootsSub;
@@ -204,7 +215,7 @@ int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
     ca.nwork = int(nwork);
     {
         KernelTimer kt(p, ACQ_KERNEL_CORRELATE);
-        ACQ_HIP(acq::launch_correlate(ca, g.log2_sub, st));
+        ACQ_HIP(acq::launch_correlate(ca, g.log2_sub, c.precision, st));
     }
     return ACQ_OK;
 }

@@ -82,7 +82,6 @@ def test_default_segment_length_choice(capi):
     (dict(fft_len=3 << 14), -1),
     (dict(fft_len=1 << 14), -1),
     (dict(fft_len=1 << 16), -7),
-    (dict(precision="fp16"), -7),
     (dict(refine_radius=9), -1),
     (dict(fs_hz=0.0), -1),
     (dict(max_block_len=0), -1),

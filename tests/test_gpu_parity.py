@@ -215,17 +215,13 @@ def test_plain_workload_over_seeds(dev):
 
 
 @pytest.mark.timeout(500)
-def test_tag_bank_full_size(dev):
+def test_tag_bank_full_size(dev, tagbank_case):
     """The 64-tag x 11-bin x 2^20-sample workload at its own sizes and launch
     configuration: detections against the oracle's FFT-identity search, and
     FFT-path power at sampled points against the direct definition."""
-    w = siggen.workload("tagbank_fp32")
+    w, chips, freqs, x, txs, ref = tagbank_case
     T, C, spc, N, K = w["num_tags"], w["num_chips"], w["spc"], w["block_len"], w["num_bins"]
     L = C * spc
-    seed = w["seeds"][0]
-    chips = siggen.make_codes(seed, T, C)
-    freqs, _ = oracle.snap_bins(w["fs_hz"], L, K, 0.0, w["bin_step_hz"])
-    x, txs = siggen.make_block(seed, N, chips, spc, w["fs_hz"], freqs, w["n_tx"], snr_db=w["snr_db"])
     xt = torch.from_numpy(x).to(dev)
     print("[tagbank] GPU", flush=True)
     with _plan(chips, spc, K, w["bin_step_hz"], N, w["fft_len"]) as plan:
@@ -250,8 +246,6 @@ def test_tag_bank_full_size(dev):
     Px = oracle.block_power(x)
     err = np.abs(Ps - ref_pts) / np.maximum(ref_pts, L * Px)
     assert err.max() <= 1e-4, float(err.max())
-    print("[tagbank] oracle search", flush=True)
-    ref = oracle.acquire(x, chips, spc, freqs, w["fs_hz"], method="fft")
     got, want = _compare_detections(dets, ref, L)
     strong = [tx for tx in txs if tx.snr_db > -12.0]
     for tx in strong:
