@@ -2,7 +2,9 @@
 
 One step = one acq_detect call on one resident block: block power, segment
 spectra, correlation of every tag x bin x lag, peak keys, FP64 refinement and
-the copy of the detections to the host.  Default workload: 64 tags with
+the copy of the detections to the host (--workload batched_stream: one
+acq_detect_batch call over 64 resident blocks of uneven length, 256 tags x 21
+bins, optionally replayed from a captured hipGraph).  Default workload: 64 tags with
 8192-chip codes at 2 samples/chip, 11 carrier-offset bins over +/-5 kHz,
 2^20-sample blocks at 8 Msps, overlap-save segments of 2^15 samples, ten
 transmissions per block at -15..-5 dB (synthetic, seeded).
@@ -84,6 +86,8 @@ def main():
     ap.add_argument("--workload", default="tagbank_fp32")
     ap.add_argument("--fft-len", type=int, default=0, help="override the workload's segment length")
     ap.add_argument("--tag-tile", type=int, default=0)
+    ap.add_argument("--tune", action="store_true", help="time every launch configuration first, keep the fastest")
+    ap.add_argument("--graph", action="store_true", help="batched workloads: replay one captured hipGraph per step")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: a plain 256 MiB device copy, the reference for HBM byte counters")
@@ -106,50 +110,80 @@ def main():
         return
 
     import siggen
-    from paper_2005_10445_amd import Plan
+    from paper_2005_10445_amd import Plan, bin_frequencies
 
     w = siggen.workload(args.workload)
-    T, C, spc, N, K = w["num_tags"], w["num_chips"], w["spc"], w["block_len"], w["num_bins"]
+    batched = "num_blocks" in w
+    T, C, spc, K = w["num_tags"], w["num_chips"], w["spc"], w["num_bins"]
     fs = w["fs_hz"]
     seed = w["seeds"][0]
-    fft_len = args.fft_len or w["fft_len"]
     dev = torch.device("cuda:0")
     chips = siggen.make_codes(seed, T, C)
     prec = w.get("precision", "fp32")
-    plan = Plan(chips, spc, fs, num_bins=K, bin_center_hz=w["bin_center_hz"], bin_step_hz=w["bin_step_hz"],
-                max_block_len=N, fft_len=fft_len, tag_tile=args.tag_tile, precision=prec,
-                refine_radius=w.get("refine_radius", 1))
-    freqs = plan.freqs_hz
-    x, txs = siggen.make_block(seed, N, chips, spc, fs, freqs, w["n_tx"], snr_db=w["snr_db"])
-    xd = torch.from_numpy(x).to(dev)
+    L = C * spc
+    bins = dict(num_bins=K, bin_center_hz=w["bin_center_hz"], bin_step_hz=w["bin_step_hz"])
+    if batched:
+        fft_len = args.fft_len or w["fft_len"] or (1 << 15)
+        freqs = bin_frequencies(chips=chips, spc=spc, fs_hz=fs, max_block_len=1 << 21, fft_len=fft_len, **bins)
+        log(f"[bench] generating {w['num_blocks']} blocks")
+        blocks = siggen.make_stream_batch(seed, chips, spc, fs, freqs, w["num_blocks"], w["block_len_log2"],
+                                          w["receivers"], w["n_tx"], w["snr_db"])
+        lens = [x.size for x, _ in blocks]
+        xds = [torch.from_numpy(x).to(dev) for x, _ in blocks]
+        plan = Plan(chips, spc, fs, max_block_len=max(lens), fft_len=fft_len, tag_tile=args.tag_tile,
+                    precision=prec, refine_radius=w.get("refine_radius", 1), max_batch_blocks=len(lens),
+                    max_batch_samples=sum(lens), graph=args.graph, **bins)
+        x = blocks[0][0]
+        run = lambda: len(plan.detect_batch(xds))      # noqa: E731
+    else:
+        N = w["block_len"]
+        fft_len = args.fft_len or w["fft_len"]
+        plan = Plan(chips, spc, fs, max_block_len=N, fft_len=fft_len, tag_tile=args.tag_tile, precision=prec,
+                    refine_radius=w.get("refine_radius", 1), **bins)
+        freqs = plan.freqs_hz
+        x, txs = siggen.make_block(seed, N, chips, spc, fs, freqs, w["n_tx"], snr_db=w["snr_db"])
+        xd = torch.from_numpy(x).to(dev)
+        lens = [N]
+        run = lambda: plan.detect_raw(xd)              # noqa: E731
     g = plan.geometry
-    M, V, L = g["fft_len"], g["valid_per_segment"], g["template_len"]
-    S = -(-(N - L + 1) // V)
-    log(f"[bench] workload={args.workload} T={T} K={K} N={N} L={L} M={M} V={V} S={S}")
+    M, V = g["fft_len"], g["valid_per_segment"]
+    S = sum(-(-(n - L + 1) // V) for n in lens if n >= L)
+    samples = sum(lens)
+    if args.tune:
+        table = plan.tune(xds[int(np.argmax(lens))] if batched else xd, reps=3)
+        log(f"[bench] tuning table {table} -> {plan.tuning}")
+    log(f"[bench] workload={args.workload} T={T} K={K} blocks={len(lens)} samples={samples} L={L} "
+        f"M={M} V={V} S={S} tuning={plan.tuning}")
 
     for _ in range(args.warmup):
-        plan.detect_raw(xd)
-    plan.set_profiling(True)
+        run()
+    profiled = not (batched and args.graph)
+    plan.set_profiling(profiled)
     corr_ms, fwd_ms, total_kernel_ms = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ndet = 0
     for _ in range(args.steps):
-        ndet = plan.detect_raw(xd)
-        kt = plan.last_kernel_times()
-        corr_ms.append(kt["correlate"])
-        fwd_ms.append(kt["forward"])
-        total_kernel_ms.append(sum(kt.values()))
+        ndet = run()
+        if profiled:
+            kt = plan.last_kernel_times()
+            corr_ms.append(kt["correlate"])
+            fwd_ms.append(kt["forward"])
+            total_kernel_ms.append(sum(kt.values()))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plan.set_profiling(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = T * K * N / (ms_per_step * 1e-3) / 1e6
-    corr_avg = float(np.mean(corr_ms))
+    value = T * K * samples / (ms_per_step * 1e-3) / 1e6
     flops = correlate_flops(T, K, S, M, V)
-    achieved = flops / (corr_avg * 1e-3) / 1e12
-    log(f"[bench] {ms_per_step:.3f} ms/step, correlate {corr_avg:.3f} ms (min {min(corr_ms):.3f}), "
-        f"forward {np.mean(fwd_ms):.3f} ms, kernels {np.mean(total_kernel_ms):.3f} ms, detections {ndet}")
+    if profiled:
+        corr_avg = float(np.mean(corr_ms))
+        achieved = flops / (corr_avg * 1e-3) / 1e12
+        log(f"[bench] {ms_per_step:.3f} ms/step, correlate {corr_avg:.3f} ms (min {min(corr_ms):.3f}), "
+            f"forward {np.mean(fwd_ms):.3f} ms, kernels {np.mean(total_kernel_ms):.3f} ms, detections {ndet}")
+    else:
+        corr_avg, achieved = None, None
+        log(f"[bench] {ms_per_step:.3f} ms/step (graph replays, no per-kernel events), detections {ndet}")
 
     out = {
         "metric": "acquisition tag*freq*Msample/s",
@@ -164,10 +198,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == "fp32" else f"f32 ({prec} storage)",
         "data": "synthetic (seeded BPSK tags in AWGN)",
-        "config": {"workload": args.workload, "tags": T, "bins": K, "block_len": N, "template_len": L,
-                   "fft_len": M, "segments": S, "precision": prec, "parallelism": "single GPU"},
+        "config": {"workload": args.workload, "tags": T, "bins": K, "blocks": len(lens), "samples": samples,
+                   "template_len": L, "fft_len": M, "segments": S, "precision": prec, "tuning": plan.tuning,
+                   "graph": bool(batched and args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_per_launch(),
+                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None,
+                     "traffic": traffic_per_launch() if args.workload == "tagbank_fp32" else None,
                      "kernel": "k_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},
     }
     if args.cpu_budget > 0:

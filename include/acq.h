@@ -71,6 +71,9 @@ typedef enum acq_precision {
     ACQ_BF16 = 2    /* spectra stored in BF16 (RNE), arithmetic in FP32            */
 } acq_precision;
 
+/* acq_config.flags */
+#define ACQ_FLAG_GRAPH       0x1u  /* acq_detect_batch replays one captured hipGraph  */
+
 /* acq_detection.flags */
 #define ACQ_DET_NEAR_EDGE    0x1u  /* peak at lag 0 or N-L: no parabola, delta = 0    */
 #define ACQ_DET_WINDOW_EDGE  0x2u  /* FP64 re-maximisation ended on its window edge */
@@ -95,8 +98,9 @@ typedef struct acq_config {
     int32_t       precision;         /* acq_precision                                    */
     int32_t       refine_radius;     /* FP64 re-maximisation radius in lags, 0 -> 1, <= 8 */
     int32_t       tag_tile;          /* tags per correlation work item; 0 = default      */
-    uint32_t      flags;             /* reserved, must be 0                              */
-    int32_t       reserved;          /* must be 0                                        */
+    uint32_t      flags;             /* ACQ_FLAG_*                                       */
+    int32_t       max_batch_blocks;  /* blocks per acq_detect_batch call; 0 -> 1         */
+    int64_t       max_batch_samples; /* samples per acq_detect_batch call; 0 -> blocks * max_block_len */
 } acq_config;
 
 /* Derived plan geometry (filled by acq_plan_geometry without touching the GPU). */
@@ -160,6 +164,50 @@ int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out);
  */
 int acq_detect(acq_plan_t plan, const void* block, int64_t n,
                acq_detection* out, int32_t capacity, int32_t* n_found);
+
+/*
+ * Search a batch of blocks of uneven lengths (a stream of blocks from several
+ * receivers): blocks[b] is a device pointer to lens[b] complex64 samples, both
+ * arrays on the host, 1 <= nblocks <= max_batch_blocks, every lens[b] <=
+ * max_block_len and their sum <= max_batch_samples.  Each block is searched
+ * independently, exactly as acq_detect would (same kernels, same results);
+ * the work items of all blocks share one persistent correlation launch.
+ * Detections are sorted by (block, tag) and carry their block index.  With
+ * ACQ_FLAG_GRAPH the launch sequence is captured once as a hipGraph (on a
+ * private stream) and replayed on the plan's stream for every later call;
+ * block descriptors travel through pinned memory that the graph copies.
+ * Synchronous; capacity and truncation as in acq_detect.
+ */
+int acq_detect_batch(acq_plan_t plan, const void* const* blocks, const int64_t* lens, int32_t nblocks,
+                     acq_detection* out, int32_t capacity, int32_t* n_found);
+
+/*
+ * Launch configuration of the correlation kernel.  engine: 0 = the default
+ * transform engine for the plan's inverse-transform length, 1 = Stockham
+ * passes through padded LDS (available for every length).  tag_tile: tags per
+ * work item, 1..64.  Results do not depend on the tuning.
+ */
+typedef struct acq_tuning {
+    int32_t engine;
+    int32_t tag_tile;
+} acq_tuning;
+
+typedef struct acq_tune_entry {
+    acq_tuning tuning;
+    double     ms;              /* mean correlation-kernel time over the repetitions */
+} acq_tune_entry;
+
+int acq_get_tuning(acq_plan_t plan, acq_tuning* out);
+int acq_set_tuning(acq_plan_t plan, const acq_tuning* tuning);
+
+/*
+ * Autotune: time every candidate tuning (engines x tag tiles 4..64 that divide
+ * the work sensibly) on the device block `block` of n samples, `reps` runs
+ * each (HIP events around the correlation kernel), keep the fastest in the
+ * plan and write the candidates to host out[0..capacity) (*n_out = count).
+ */
+int acq_tune(acq_plan_t plan, const void* block, int64_t n, int32_t reps,
+             acq_tune_entry* out, int32_t capacity, int32_t* n_out);
 
 /*
  * Test hook: the FFT-path power P[t][k][tau] for every valid lag, written to

@@ -40,7 +40,8 @@ class Detection:
 def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
                 bin_center_hz: float = 0.0, bin_step_hz: float = 0.0, max_block_len: int = 1 << 20,
                 fft_len: int = 0, threshold: float = 0.0, precision: str = "fp32",
-                refine_radius: int = 1, tag_tile: int = 0):
+                refine_radius: int = 1, tag_tile: int = 0, max_batch_blocks: int = 0,
+                max_batch_samples: int = 0, graph: bool = False):
     """Build an AcqConfig; returns (config, chips array that must outlive the call)."""
     ch = np.ascontiguousarray(np.asarray(chips, dtype=np.int8))
     if ch.ndim != 2:
@@ -59,8 +60,9 @@ def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
     cfg.precision = _PRECISION[precision]
     cfg.refine_radius = int(refine_radius)
     cfg.tag_tile = int(tag_tile)
-    cfg.flags = 0
-    cfg.reserved = 0
+    cfg.flags = _capi.ACQ_FLAG_GRAPH if graph else 0
+    cfg.max_batch_blocks = int(max_batch_blocks)
+    cfg.max_batch_samples = int(max_batch_samples)
     return cfg, ch
 
 
@@ -96,12 +98,16 @@ class Plan:
     def __init__(self, chips, spc: int, fs_hz: float, *, num_bins: int = 1, bin_center_hz: float = 0.0,
                  bin_step_hz: float = 0.0, max_block_len: int = 1 << 20, fft_len: int = 0,
                  threshold: float = 0.0, precision: str = "fp32", refine_radius: int = 1,
-                 tag_tile: int = 0, stream=None):
+                 tag_tile: int = 0, max_batch_blocks: int = 0, max_batch_samples: int = 0,
+                 graph: bool = False, stream=None):
         import torch
         self._lib = _capi.lib()
         cfg, ch = make_config(chips, spc, fs_hz, num_bins, bin_center_hz, bin_step_hz, max_block_len,
-                              fft_len, threshold, precision, refine_radius, tag_tile)
+                              fft_len, threshold, precision, refine_radius, tag_tile, max_batch_blocks,
+                              max_batch_samples, graph)
+        self.max_batch_blocks = max(int(max_batch_blocks), 1)
         self.num_tags, self.num_chips = ch.shape
+        self.precision = precision
         self.spc = int(spc)
         self.num_bins = int(num_bins)
         self.template_len = self.num_chips * self.spc
@@ -127,6 +133,40 @@ class Plan:
                                    ctypes.byref(nf)), "acq_detect")
         return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
                           d.block_power, d.block, d.flags) for d in self._out[:nf.value]]
+
+    def detect_batch(self, blocks) -> List[Detection]:
+        """acq_detect_batch over a list of 1-D complex64 device tensors of any lengths."""
+        n = len(blocks)
+        ptrs = (ctypes.c_void_p * n)()
+        lens = (ctypes.c_int64 * n)()
+        for i, b in enumerate(blocks):
+            ptr, m = _device_ptr(b)
+            ptrs[i], lens[i] = ptr, m
+        cap = n * self.num_tags
+        out = (AcqDetection * cap)()
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_detect_batch(self._h, ptrs, lens, n, out, cap, ctypes.byref(nf)), "acq_detect_batch")
+        return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
+                          d.block_power, d.block, d.flags) for d in out[:nf.value]]
+
+    @property
+    def tuning(self) -> dict:
+        t = _capi.AcqTuning()
+        check(self._lib.acq_get_tuning(self._h, ctypes.byref(t)), "acq_get_tuning")
+        return {"engine": t.engine, "tag_tile": t.tag_tile}
+
+    def set_tuning(self, engine: int, tag_tile: int):
+        t = _capi.AcqTuning(int(engine), int(tag_tile))
+        check(self._lib.acq_set_tuning(self._h, ctypes.byref(t)), "acq_set_tuning")
+
+    def tune(self, block, reps: int = 3) -> list:
+        """acq_tune: time every candidate tuning on `block`, keep the fastest; returns the table."""
+        ptr, n = _device_ptr(block)
+        out = (_capi.AcqTuneEntry * 32)()
+        cnt = ctypes.c_int32(0)
+        check(self._lib.acq_tune(self._h, ctypes.c_void_p(ptr), n, int(reps), out, 32, ctypes.byref(cnt)),
+              "acq_tune")
+        return [{"engine": e.tuning.engine, "tag_tile": e.tuning.tag_tile, "ms": e.ms} for e in out[:cnt.value]]
 
     def detect_raw(self, block) -> int:
         """acq_detect without building Python records (for timing); returns the count."""

@@ -23,11 +23,12 @@ ACQ_ERR_UNSUPPORTED = -7
 ACQ_FP32, ACQ_FP16, ACQ_BF16 = 0, 1, 2
 ACQ_DET_NEAR_EDGE = 0x1
 ACQ_DET_WINDOW_EDGE = 0x2
+ACQ_FLAG_GRAPH = 0x1
 
 # every symbol include/acq.h declares
-EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect",
-            "acq_correlate_power", "acq_set_profiling", "acq_last_kernel_times", "acq_release",
-            "acq_strerror", "acq_last_error")
+EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
+            "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
+            "acq_last_kernel_times", "acq_release", "acq_strerror", "acq_last_error")
 KERNELS = ("block_power", "forward", "correlate", "refine", "compact")
 
 
@@ -48,7 +49,8 @@ class AcqConfig(ctypes.Structure):
         ("refine_radius", ctypes.c_int32),
         ("tag_tile", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("max_batch_blocks", ctypes.c_int32),
+        ("max_batch_samples", ctypes.c_int64),
     ]
 
 
@@ -83,6 +85,14 @@ class AcqDetection(ctypes.Structure):
     ]
 
 
+class AcqTuning(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("tag_tile", ctypes.c_int32)]
+
+
+class AcqTuneEntry(ctypes.Structure):
+    _fields_ = [("tuning", AcqTuning), ("ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -101,12 +111,19 @@ def lib(path: str = LIB_PATH):
     L.acq_detect.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, P(AcqDetection),
                              ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_correlate_power.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    L.acq_detect_batch.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_int64), ctypes.c_int32,
+                                   P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32)]
+    L.acq_get_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
+    L.acq_set_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
+    L.acq_tune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, P(AcqTuneEntry),
+                           ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_release.argtypes = [ctypes.c_void_p]
     L.acq_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.acq_last_kernel_times.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int32,
                                         P(ctypes.c_int32)]
-    for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect",
-                 "acq_correlate_power", "acq_release", "acq_set_profiling", "acq_last_kernel_times"):
+    for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
+                 "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
+                 "acq_set_profiling", "acq_last_kernel_times"):
         getattr(L, name).restype = ctypes.c_int
     L.acq_strerror.argtypes = [ctypes.c_int]
     L.acq_strerror.restype = ctypes.c_char_p

@@ -67,8 +67,9 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     if (cfg->refine_radius < 0 || cfg->refine_radius > kMaxRefineRadius)
         return fail(ACQ_ERR_INVALID_ARG, "refine_radius must be in [0, 8]");
     if (cfg->tag_tile < 0) return fail(ACQ_ERR_INVALID_ARG, "tag_tile must be >= 0");
-    if (cfg->flags != 0 || cfg->reserved != 0)
-        return fail(ACQ_ERR_INVALID_ARG, "flags and reserved must be 0");
+    if ((cfg->flags & ~ACQ_FLAG_GRAPH) != 0) return fail(ACQ_ERR_INVALID_ARG, "unknown flags");
+    if (cfg->max_batch_blocks < 0 || cfg->max_batch_samples < 0)
+        return fail(ACQ_ERR_INVALID_ARG, "negative batch capacity");
 
     const int64_t T = cfg->num_tags, C = cfg->num_chips, K = cfg->num_bins;
     for (int64_t i = 0; i < T * C; ++i)
@@ -134,6 +135,16 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
         G.rot[size_t(k)] = int32_t(r);
     }
 
+    // batch capacity: segments of a batch are bounded by sum(n_b)/V + blocks
+    G.max_blocks = cfg->max_batch_blocks > 0 ? cfg->max_batch_blocks : 1;
+    G.max_batch_samples = cfg->max_batch_samples > 0 ? cfg->max_batch_samples
+                                                     : int64_t(G.max_blocks) * cfg->max_block_len;
+    if (G.max_batch_samples < cfg->max_block_len) G.max_batch_samples = cfg->max_block_len;
+    G.max_total_segments = G.max_batch_samples / G.V + G.max_blocks;
+    if (G.max_total_segments < G.max_segments) G.max_total_segments = G.max_segments;
+    if (double(G.max_total_segments) * double(K) * double(spc) * double(T) >= 2147483000.0)
+        return fail(ACQ_ERR_UNSUPPORTED, "batch too large for 32-bit work-item indices");
+
     G.tag_tile = cfg->tag_tile > 0 ? cfg->tag_tile : 16;
     if (G.tag_tile > kMaxTagTile) G.tag_tile = kMaxTagTile;
     if (G.tag_tile > T) G.tag_tile = int(T);
@@ -141,13 +152,13 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     // device memory: spectra of segments, replica bank, tables, small buffers
     int64_t bytes = 0;
     const int64_t sbytes = cfg->precision == ACQ_FP32 ? 8 : 4;
-    bytes += G.max_segments * G.M * 8;        // forward spectra X[S][M] (FP32)
-    if (sbytes == 4) bytes += G.max_segments * G.M * 4;   // their 16-bit copy
+    bytes += G.max_total_segments * G.M * 8;  // forward spectra X[S][M] (FP32)
+    if (sbytes == 4) bytes += G.max_total_segments * G.M * 4;   // their 16-bit copy
     bytes += T * G.Msub * sbytes;             // replica bank [T][M/spc]
     bytes += G.M * 8 * 2 + G.Msub * 8;        // rect spectrum, roots at M and M/spc
     bytes += T * C;                           // chips
     bytes += K * (4 + 8);                     // rotations, frequencies
-    bytes += T * (8 + 4 + 2 * int64_t(sizeof(acq_detection))) + 4096;
+    bytes += int64_t(G.max_blocks) * (T * (8 + 4 + 2 * int64_t(sizeof(acq_detection))) + 2048 + 64) + 4096;
     G.device_bytes = bytes;
     *g = std::move(G);
     clear_error();

@@ -29,6 +29,9 @@ struct Geometry {
     int64_t centre_q = 0;   // snapped centre in quanta
     int64_t step_q = 0;     // snapped step in quanta
     int     tag_tile = 0;
+    int     max_blocks = 1;         // blocks per batch call
+    int64_t max_batch_samples = 0;  // samples per batch call
+    int64_t max_total_segments = 0; // segment spectra allocated
     std::vector<double>  freqs_hz;   // K snapped frequencies
     std::vector<int32_t> rot;        // per-bin rotation of the M-point spectrum, in [0, M)
     std::vector<int64_t> rot_signed; // per-bin signed rotation at M

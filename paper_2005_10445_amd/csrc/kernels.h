@@ -8,61 +8,98 @@
 
 namespace acq {
 
-// Workgroups of the block-power partial sums.
+// Workgroups of the block-power partial sums, per block.
 constexpr int kPowerParts = 256;
+// Persistent correlation launch: work-item counters, one per XCD.
+constexpr int kXcds = 8;
+
+// One block of a launch.
+struct BlockDesc {
+    const float2* x;            // device, n complex64 samples
+    int64_t n;
+    int64_t lags;               // n - L + 1 (<= 0: nothing to search)
+    int32_t seg0;               // first global segment index
+    int32_t nseg;               // overlap-save segments of this block
+    double theta;               // detection threshold for this block
+};
+
+// The blocks of one launch: a single inline descriptor (single-block calls), or
+// a device array of descriptors whose count and total segment count are read
+// on the device, so one captured graph serves any batch within capacity.
+struct BlockTable {
+    const BlockDesc* descs;     // device [nblocks] or nullptr (use `one`)
+    const int32_t* counts;      // device [2] = {nblocks, total segments} when descs != nullptr
+    BlockDesc one;
+
+    __device__ __forceinline__ int nblocks() const { return descs ? counts[0] : 1; }
+    __device__ __forceinline__ int total_seg() const { return descs ? counts[1] : one.nseg; }
+    __device__ __forceinline__ BlockDesc get(int b) const { return descs ? descs[b] : one; }
+    // block holding global segment g (segments are numbered block by block)
+    __device__ __forceinline__ int block_of_segment(int g) const {
+        if (!descs) return 0;
+        int lo = 0, hi = counts[0] - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (descs[mid].seg0 <= g) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+};
 
 struct CorrArgs {
-    const void* X;              // [S][M] forward spectra of the segments (storage format)
+    BlockTable blocks;
+    const void* X;              // [segments][M] spectra (storage format)
     const void* bank;           // [T][Msub] 2^bank_exp conj(DFT_Msub(chips)) / M (storage format)
-    const double* parts;        // [kPowerParts] partial sums of |x|^2 (16-bit storage scale)
+    const double* parts;        // [block][kPowerParts] partial sums of |x|^2
     const float2* rect;         // [M] sum_{r<spc} exp(+j 2 pi i r / M)
     const float2* rootsM;       // [M] exp(+j 2 pi m / M)
     const float2* rootsSub;     // [Msub] exp(+j 2 pi m / Msub)
     const float2* b1tab;        // 2^14-point engine twiddle table (else unused)
     const int32_t* rot;         // [K] rotation of bin k, in [0, M)
-    unsigned long long* keys;   // [T] packed (power bits, ~(lag*K + k)), max-reduced
-    float* dump;                // optional [T][K][lags] power
-    int64_t n;                  // block length N
-    int64_t lags;               // N - L + 1
+    unsigned long long* keys;   // [block][T] packed (power bits, ~(lag*K + k)), max-reduced
+    float* dump;                // optional [T][K][lags] power (single-block calls)
+    int* counters;              // [kXcds] work-item counters (persistent launches)
     int64_t V;                  // valid lags per segment
-    int32_t S, K, spc, M, Msub, T, tile, ntiles, nwork, bank_exp;
+    int32_t K, spc, M, Msub, T, tile, ntiles, bank_exp;
+    int32_t persistent;         // 1: loop over work items from the counters
 };
 
 struct FwdArgs {
-    const float2* x;            // [N] block
-    float2* X;                  // [S][M] FP32 spectra (accumulator)
-    void* Xh;                   // [S][M] 16-bit copy (FP16/BF16 plans only)
-    const double* parts;        // [kPowerParts] partial sums of |x|^2
+    BlockTable blocks;
+    float2* X;                  // [segments][M] FP32 spectra (accumulator)
+    void* Xh;                   // [segments][M] 16-bit copy (FP16/BF16 plans only)
+    const double* parts;        // [block][kPowerParts]
     const float2* rootsM;
     const float2* rootsSub;
     const float2* b1tab;
-    int64_t n, V;
-    int32_t S, spc, M, Msub;
+    int64_t V;
+    int32_t spc, M, Msub;
 };
 
 struct RefineArgs {
-    const float2* x;
+    BlockTable blocks;
     const int8_t* chips;        // [T][C]
     const int64_t* rot_signed;  // [K] signed rotation at M
     const double* freqs;        // [K]
-    const unsigned long long* keys;
-    const double* parts;        // [kPowerParts] partial sums of |x|^2
-    acq_detection* dets;        // [T]
-    int32_t* found;             // [T] 1 if detected
-    int64_t n, L, lags;
-    double theta;
+    const unsigned long long* keys;   // [block][T]
+    const double* parts;        // [block][kPowerParts]
+    acq_detection* dets;        // [block][T]
+    int32_t* found;             // [block][T] 1 if detected
+    int64_t L;
     int32_t T, C, K, spc, M, radius;
 };
 
-hipError_t launch_block_power(const float2* x, int64_t n, double* parts, hipStream_t st);
+hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st);
-hipError_t launch_forward(const FwdArgs& a, int log2_sub, int prec, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t count, hipStream_t st);
+hipError_t launch_forward(const FwdArgs& a, int grid, int log2_sub, int prec, hipStream_t st);
 hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const float2* rootsSub,
                        const float2* b1tab, int Msub, int M, int bank_exp, int log2_sub, int prec,
                        hipStream_t st);
-hipError_t launch_correlate(const CorrArgs& a, int log2_sub, int prec, hipStream_t st);
-hipError_t launch_refine(const RefineArgs& a, hipStream_t st);
-hipError_t launch_compact(const acq_detection* dets, const int32_t* found, int T,
+// engine: 0 = the library's choice for the size, 1 = Stockham passes (any size)
+hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec, int engine, hipStream_t st);
+hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st);
+hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T,
                           acq_detection* out, int32_t* count, hipStream_t st);
 
 }  // namespace acq

@@ -71,26 +71,41 @@ __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
 }
 
 // ------------------------------------------------------------------ block power
-__global__ __launch_bounds__(256) void k_block_power(const float2* __restrict__ x, int64_t n,
-                                                     double* __restrict__ parts) {
-    const int64_t chunk = (n + kPowerParts - 1) / kPowerParts;
-    const int64_t beg = int64_t(blockIdx.x) * chunk;
-    const int64_t end = beg + chunk < n ? beg + chunk : n;
+// grid = max_blocks * kPowerParts; partial sums of block b in parts[b][*]
+__global__ __launch_bounds__(256) void k_block_power(BlockTable bt, double* __restrict__ parts) {
+    const int b = int(blockIdx.x) / kPowerParts, part = int(blockIdx.x) % kPowerParts;
+    if (b >= bt.nblocks()) return;
+    const BlockDesc d = bt.get(b);
+    const int64_t chunk = (d.n + kPowerParts - 1) / kPowerParts;
+    const int64_t beg = int64_t(part) * chunk;
+    const int64_t end = beg + chunk < d.n ? beg + chunk : d.n;
     double acc = 0.0;
     for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
-        const float2 v = x[i];
+        const float2 v = d.x[i];
         acc += double(v.x) * double(v.x) + double(v.y) * double(v.y);
     }
     acc = wave_sum(acc);
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) parts[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) parts[size_t(b) * kPowerParts + part] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t count) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0ull;
+}
+
+__global__ void k_fill_i32(int* p, int64_t count) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// mean block power from the fixed-order partial sums
+__device__ __forceinline__ double block_mean_power(const double* __restrict__ parts, int64_t n) {
+    double s = 0.0;
+    for (int i = 0; i < kPowerParts; ++i) s += parts[i];
+    return n > 0 ? s / double(n) : 0.0;
 }
 
 // ------------------------------------------------------------------ transform engines
@@ -139,15 +154,17 @@ using dev::make_rsrc;
 __device__ __forceinline__ int spectrum_exponent(const double* __restrict__ parts, int64_t n, int M) {
     __shared__ int s_e;
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < kPowerParts; ++i) s += parts[i];
-        const double px = s / double(n);
+        const double px = block_mean_power(parts, n);
         s_e = px > 0.0 ? int(rint(0.5 * log2(double(M) * px))) : 0;
     }
     __syncthreads();
-    return s_e;
+    const int e = s_e;
+    __syncthreads();
+    return e;
 }
 
+// One workgroup per global segment g (looping when the grid is smaller):
+// X_g = DFT_M of segment j = g - seg0 of its block.
 template <class E, int PREC>
 __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
     using St = dev::Storage<PREC>;
@@ -156,43 +173,48 @@ __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
     E eng;
     eng.init(a.rootsSub, extra);
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const int j = blockIdx.x;
-    const int64_t base = int64_t(j) * a.V;
-    float2* Xj = a.X + size_t(j) * size_t(a.M);
     const int mmask = a.M - 1;
-    float xs = 1.0f;
-    if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -spectrum_exponent(a.parts, a.n, a.M));
-    for (int r = 0; r < a.spc; ++r) {
-        float2 v[16];
+    const int total = a.blocks.total_seg();
+    for (int g = int(blockIdx.x); g < total; g += int(gridDim.x)) {
+        const int bi = a.blocks.block_of_segment(g);
+        const BlockDesc d = a.blocks.get(bi);
+        const int64_t base = int64_t(g - d.seg0) * a.V;
+        float2* Xg = a.X + size_t(g) * size_t(a.M);
+        float xs = 1.0f;
+        if constexpr (PREC != ACQ_FP32)
+            xs = ldexpf(1.0f, -spectrum_exponent(a.parts + size_t(bi) * kPowerParts, d.n, a.M));
+        for (int r = 0; r < a.spc; ++r) {
+            float2 v[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int64_t idx = base + int64_t(a.spc) * eng.in_index(m) + r;
-            v[m] = idx < a.n ? a.x[idx] : make_float2(0.f, 0.f);
-        }
-        eng.template transform<-1>(v, lds, b1, extra);
-        // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub], accumulated in FP32
-        const int ob = eng.out_base();
-        const bool last = r == a.spc - 1;
+            for (int m = 0; m < 16; ++m) {
+                const int64_t idx = base + int64_t(a.spc) * eng.in_index(m) + r;
+                v[m] = idx < d.n ? d.x[idx] : make_float2(0.f, 0.f);
+            }
+            eng.template transform<-1>(v, lds, b1, extra);
+            // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub], accumulated in FP32
+            const int ob = eng.out_base();
+            const bool last = r == a.spc - 1;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int ip = ob + E::out_off(m);
-            for (int q = 0; q < a.spc; ++q) {
-                const int i = ip + q * a.Msub;
-                float2 c = v[m];
-                if (r) c = cmulc(c, a.rootsM[(int)((int64_t(i) * r) & mmask)]);
-                if (r) c = cadd(Xj[i], c);
-                if constexpr (PREC == ACQ_FP32) {
-                    Xj[i] = c;
-                } else {
-                    if (last)
-                        reinterpret_cast<typename St::T*>(a.Xh)[size_t(j) * size_t(a.M) + i] =
-                            St::pack(make_float2(c.x * xs, c.y * xs));
-                    else
-                        Xj[i] = c;
+            for (int m = 0; m < 16; ++m) {
+                const int ip = ob + E::out_off(m);
+                for (int q = 0; q < a.spc; ++q) {
+                    const int i = ip + q * a.Msub;
+                    float2 c = v[m];
+                    if (r) c = cmulc(c, a.rootsM[(int)((int64_t(i) * r) & mmask)]);
+                    if (r) c = cadd(Xg[i], c);
+                    if constexpr (PREC == ACQ_FP32) {
+                        Xg[i] = c;
+                    } else {
+                        if (last)
+                            reinterpret_cast<typename St::T*>(a.Xh)[size_t(g) * size_t(a.M) + i] =
+                                St::pack(make_float2(c.x * xs, c.y * xs));
+                        else
+                            Xg[i] = c;
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -225,44 +247,41 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
 }
 
 // ------------------------------------------------------------------ correlation
+// One work item: (tile of tags, global segment g, bin k, phase rho), item index
+// wi = ((tile * segments + g) * K + k) * spc + rho.
 template <class E, int PREC, bool DUMP>
-__global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
+__device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, int wi, int total_seg,
+                                               float2* lds, const float2* extra, unsigned long long* red) {
     using St = dev::Storage<PREC>;
     constexpr int N = E::N;
     constexpr int NW = E::NT / 64;
-    __shared__ float2 lds[E::LDS];
-    __shared__ float2 extra[E::EXTRA];
-    __shared__ unsigned long long red[kMaxTagTile * NW];
-
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-    // range of work items so items sharing a segment and a tag tile share its L2.
-    const int per = int(gridDim.x) >> 3;
-    const int wi = int(blockIdx.x & 7u) * per + int(blockIdx.x >> 3);
-    if (wi >= a.nwork) return;
     int rem = wi;
     const int rho = rem % a.spc;
     rem /= a.spc;
     const int k = rem % a.K;
     rem /= a.K;
-    const int j = rem % a.S;
-    const int tile = rem / a.S;
+    const int g = rem % total_seg;
+    const int tile = rem / total_seg;
     const int tag0 = tile * a.tile;
     const int ntag = min(a.tile, a.T - tag0);
     const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const int bi = a.blocks.block_of_segment(g);
+    const BlockDesc d = a.blocks.get(bi);
+    const int j = g - d.seg0;
+    const double* parts = a.parts + size_t(bi) * kPowerParts;
+    unsigned long long* keys = a.keys + size_t(bi) * a.T;
 
-    E eng;
-    eng.init(a.rootsSub, extra);
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     const __amdgpu_buffer_rsrc_t bank =
         make_rsrc(static_cast<const char*>(a.bank) + size_t(tag0) * N * St::BYTES, uint32_t(ntag) * N * St::BYTES);
     // stored spectra carry 2^-x_exp (segments) and 2^bank_exp (bank): undo both in G
     float gscale = 1.0f;
-    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, spectrum_exponent(a.parts, a.n, a.M) - a.bank_exp);
+    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, spectrum_exponent(parts, d.n, a.M) - a.bank_exp);
 
     // tag-independent first step of the inverse transform
     float2 G[16];
     {
-        const typename St::T* Xj = static_cast<const typename St::T*>(a.X) + size_t(j) * size_t(a.M);
+        const typename St::T* Xj = static_cast<const typename St::T*>(a.X) + size_t(g) * size_t(a.M);
         const int rot = a.rot[k];
         const int mmask = a.M - 1;
 #pragma unroll
@@ -284,14 +303,14 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
 
     // valid outputs: segment lag spc*u + rho < min(V, lags - jV)  <=>  u < ulim
     const int64_t seg0 = int64_t(j) * a.V;
-    const int64_t vlim64 = a.lags - seg0 < a.V ? a.lags - seg0 : a.V;
+    const int64_t vlim64 = d.lags - seg0 < a.V ? d.lags - seg0 : a.V;
     const int vlim = int(vlim64);
     const int ulim = vlim > rho ? (vlim - rho + a.spc - 1) / a.spc : 0;
     // key index tau*K + k = kbase + u*kstep (fits in 32 bits for valid lags)
     const unsigned kbase = unsigned((seg0 + rho) * a.K + k);
     const unsigned kstep = unsigned(a.spc * a.K);
-    const int ob = eng.out_base();
-    const unsigned idx0 = kbase + unsigned(ob) * kstep;
+    const int ob0 = eng.out_base();
+    const unsigned idx00 = kbase + unsigned(ob0) * kstep;
     const int omin = eng.out_min(), omax = eng.out_max();   // wave-uniform
     const bool hi = omin + E::HI_OFF < ulim;               // any output of the upper half needed
 
@@ -303,6 +322,11 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
         for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], St::bload(bank, voff, (tt * N + m * E::NT) * St::BYTES));
         eng.template transform<+1>(v, lds, b1, extra, hi);
         unsigned long long best = 0ull;
+        // per-register indices and masks are the same for every tag: keep the
+        // optimiser from holding all of them across the loop (recomputing is cheap)
+        int ob = ob0;
+        unsigned idx0 = idx00;
+        asm volatile("" : "+v"(ob), "+v"(idx0));
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int off = E::out_off(r);
@@ -316,7 +340,7 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
                 if constexpr (DUMP) {
                     if (ob + off < ulim) {
                         const int64_t tau = seg0 + int64_t(a.spc) * (ob + off) + rho;
-                        a.dump[(size_t(tag0 + tt) * a.K + k) * size_t(a.lags) + size_t(tau)] = p;
+                        a.dump[(size_t(tag0 + tt) * a.K + k) * size_t(d.lags) + size_t(tau)] = p;
                     }
                 }
             }
@@ -328,31 +352,74 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
     for (int i = int(threadIdx.x); i < ntag; i += E::NT) {
         unsigned long long m = 0ull;
         for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
-        if (m) atomicMax(&a.keys[tag0 + i], m);
+        if (m) atomicMax(&keys[tag0 + i], m);
+    }
+    __syncthreads();                             // red[] is rewritten by the next item
+}
+
+// Launch forms of the correlation kernel.  Each is its own instantiation so the
+// persistent loop's live state does not weigh on the one-item-per-workgroup forms.
+enum CorrMode { kCorrGrid = 0, kCorrGridDump = 1, kCorrPersistent = 2 };
+
+template <class E, int PREC, int MODE>
+__global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
+    constexpr int NW = E::NT / 64;
+    constexpr bool DUMP = MODE == kCorrGridDump;
+    __shared__ float2 lds[E::LDS];
+    __shared__ float2 extra[E::EXTRA];
+    __shared__ unsigned long long red[kMaxTagTile * NW];
+    __shared__ int s_item;
+    const int total_seg = a.blocks.total_seg();
+    const int total = a.ntiles * total_seg * a.K * a.spc;
+    // Workgroups are dealt round-robin to the XCDs; each XCD takes a contiguous
+    // range of work items, so items sharing a segment and a tag tile share its L2.
+    const int xcd = int(blockIdx.x) % kXcds;
+    E eng;
+    if constexpr (MODE == kCorrPersistent) {
+        eng.init(a.rootsSub, extra);
+        const int chunk = (total + kXcds - 1) / kXcds;
+        const int begin = xcd * chunk;
+        const int end = min(total, begin + chunk);
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(&a.counters[xcd], 1);
+            __syncthreads();
+            // uniform by construction; saying so keeps every address derived from
+            // the item (bank rows, segment) scalar, with no per-lane resource loops
+            const int it = begin + __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            if (it >= end) break;
+            correlate_item<E, PREC, false>(a, eng, it, total_seg, lds, extra, red);
+        }
+    } else {
+        const int per = int(gridDim.x) / kXcds;
+        const int wi = xcd * per + int(blockIdx.x) / kXcds;
+        if (wi >= total) return;
+        eng.init(a.rootsSub, extra);
+        correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red);
     }
 }
 
 // ------------------------------------------------------------------ refine
 constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
 
+// grid = max_blocks * T: one workgroup per (block, tag)
 __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
-    const int tag = blockIdx.x;
+    const int bi = int(blockIdx.x) / a.T, tag = int(blockIdx.x) % a.T;
+    if (bi >= a.blocks.nblocks()) return;
+    const BlockDesc d = a.blocks.get(bi);
+    const size_t slot = size_t(bi) * a.T + tag;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     __shared__ double s_px;
     __shared__ double red[4][kMaxWin][3];
     __shared__ long long s_center;
     __shared__ int s_again;
 
-    const unsigned long long key = a.keys[tag];
+    const unsigned long long key = d.lags > 0 ? a.keys[slot] : 0ull;
     if (key == 0ull) {               // no valid lag was searched for this tag
-        if (t == 0) a.found[tag] = 0;
+        if (t == 0) a.found[slot] = 0;
         return;
     }
-    if (t == 0) {
-        double s = 0.0;
-        for (int i = 0; i < kPowerParts; ++i) s += a.parts[i];
-        s_px = s / double(a.n);
-    }
+    if (t == 0) s_px = block_mean_power(a.parts + size_t(bi) * kPowerParts, d.n);
     const unsigned idx = ~unsigned(key & 0xffffffffull);
     const int k = int(idx % unsigned(a.K));
     int64_t center = int64_t(idx / unsigned(a.K));
@@ -368,8 +435,8 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
         for (int w = 0; w < kMaxWin; ++w) cr[w] = ci[w] = en[w] = 0.0;
         for (int64_t e = t; e < a.L + W - 1; e += 256) {
             const int64_t i = lam0 + e;
-            if (i < 0 || i >= a.n) continue;
-            const float2 xv = a.x[i];
+            if (i < 0 || i >= d.n) continue;
+            const float2 xv = d.x[i];
             const double xr = xv.x, xi = xv.y;
             int64_t ph = (mrot * i) % a.M;
             if (ph < 0) ph += a.M;
@@ -406,13 +473,13 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
                 const double im = (red[0][w][1] + red[1][w][1]) + (red[2][w][1] + red[3][w][1]);
                 E[w] = (red[0][w][2] + red[1][w][2]) + (red[2][w][2] + red[3][w][2]);
                 const int64_t lam = lam0 + w;
-                P[w] = (lam >= 0 && lam < a.lags) ? re * re + im * im : -1.0;
+                P[w] = (lam >= 0 && lam < d.lags) ? re * re + im * im : -1.0;
             }
             int wb = R + 1;
             for (int w = 1; w <= W - 2; ++w)
                 if (P[w] > P[wb] || (P[w] == P[wb] && w < wb)) wb = w;
             const int64_t lam = lam0 + wb;
-            const bool hit = (wb == 1 && lam > 0) || (wb == W - 2 && lam < a.lags - 1);
+            const bool hit = (wb == 1 && lam > 0) || (wb == W - 2 && lam < d.lags - 1);
             if (hit && pass == 0) {
                 s_center = lam;
                 s_again = 1;
@@ -423,7 +490,7 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
                 const double pm = P[wb - 1] < 0.0 ? 0.0 : P[wb - 1];
                 const double pp = P[wb + 1] < 0.0 ? 0.0 : P[wb + 1];
                 double delta = 0.0;
-                if (lam == 0 || lam == a.lags - 1) {
+                if (lam == 0 || lam == d.lags - 1) {
                     flags |= ACQ_DET_NEAR_EDGE;
                 } else {
                     const double den = pm - 2.0 * p0 + pp;
@@ -434,20 +501,20 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
                 }
                 const double px = s_px;
                 const double z = px > 0.0 ? p0 / (double(a.L) * px) : 0.0;
-                acq_detection d;
-                d.tag = tag;
-                d.bin = k;
-                d.lag = lam;
-                d.toa_samples = double(lam) + delta;
-                d.freq_hz = a.freqs[k];
-                d.peak_power = p0;
-                d.z = z;
-                d.energy = E[wb];
-                d.block_power = px;
-                d.block = 0;
-                d.flags = flags;
-                a.dets[tag] = d;
-                a.found[tag] = z >= a.theta ? 1 : 0;
+                acq_detection r;
+                r.tag = tag;
+                r.bin = k;
+                r.lag = lam;
+                r.toa_samples = double(lam) + delta;
+                r.freq_hz = a.freqs[k];
+                r.peak_power = p0;
+                r.z = z;
+                r.energy = E[wb];
+                r.block_power = px;
+                r.block = bi;
+                r.flags = flags;
+                a.dets[slot] = r;
+                a.found[slot] = z >= d.theta ? 1 : 0;
             }
         }
         __syncthreads();
@@ -456,20 +523,23 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
     }
 }
 
-__global__ void k_compact(const acq_detection* __restrict__ dets, const int32_t* __restrict__ found,
+// detections in (block, tag) order
+__global__ void k_compact(BlockTable bt, const acq_detection* __restrict__ dets, const int32_t* __restrict__ found,
                           int T, acq_detection* __restrict__ out, int32_t* __restrict__ count) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int nb = bt.nblocks();
     int c = 0;
-    for (int i = 0; i < T; ++i)
-        if (found[i]) out[c++] = dets[i];
+    for (int b = 0; b < nb; ++b)
+        for (int i = 0; i < T; ++i)
+            if (found[size_t(b) * T + i]) out[c++] = dets[size_t(b) * T + i];
     *count = c;
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_block_power(const float2* x, int64_t n, double* parts, hipStream_t st) {
-    hipLaunchKernelGGL(k_block_power, dim3(kPowerParts), dim3(256), 0, st, x, n, parts);
+hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_power, dim3(unsigned(max_blocks) * kPowerParts), dim3(256), 0, st, bt, parts);
     return hipGetLastError();
 }
 
@@ -480,26 +550,33 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_i32(int* p, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3(unsigned(blocks)), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
 template <class E>
-static hipError_t fwd_e(const FwdArgs& a, int prec, hipStream_t st) {
+static hipError_t fwd_e(const FwdArgs& a, int grid, int prec, hipStream_t st) {
     switch (prec) {
-        case ACQ_FP32: hipLaunchKernelGGL((k_forward<E, ACQ_FP32>), dim3(a.S), dim3(E::NT), 0, st, a); break;
-        case ACQ_FP16: hipLaunchKernelGGL((k_forward<E, ACQ_FP16>), dim3(a.S), dim3(E::NT), 0, st, a); break;
-        case ACQ_BF16: hipLaunchKernelGGL((k_forward<E, ACQ_BF16>), dim3(a.S), dim3(E::NT), 0, st, a); break;
+        case ACQ_FP32: hipLaunchKernelGGL((k_forward<E, ACQ_FP32>), dim3(grid), dim3(E::NT), 0, st, a); break;
+        case ACQ_FP16: hipLaunchKernelGGL((k_forward<E, ACQ_FP16>), dim3(grid), dim3(E::NT), 0, st, a); break;
+        case ACQ_BF16: hipLaunchKernelGGL((k_forward<E, ACQ_BF16>), dim3(grid), dim3(E::NT), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs& a, int log2_sub, int prec, hipStream_t st) {
-    if (a.S <= 0) return hipSuccess;
+hipError_t launch_forward(const FwdArgs& a, int grid, int log2_sub, int prec, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return fwd_e<StockhamEngine<10>>(a, prec, st);
-        case 11: return fwd_e<StockhamEngine<11>>(a, prec, st);
-        case 12: return fwd_e<StockhamEngine<12>>(a, prec, st);
-        case 13: return fwd_e<StockhamEngine<13>>(a, prec, st);
-        case 14: return fwd_e<Fft14>(a, prec, st);
+        case 10: return fwd_e<StockhamEngine<10>>(a, grid, prec, st);
+        case 11: return fwd_e<StockhamEngine<11>>(a, grid, prec, st);
+        case 12: return fwd_e<StockhamEngine<12>>(a, grid, prec, st);
+        case 13: return fwd_e<StockhamEngine<13>>(a, grid, prec, st);
+        case 14: return fwd_e<Fft14>(a, grid, prec, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -541,15 +618,16 @@ hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const floa
 
 template <class E, int PREC>
 static void corr_ep(const CorrArgs& a, int grid, hipStream_t st) {
-    if (a.dump)
-        hipLaunchKernelGGL((k_correlate<E, PREC, true>), dim3(grid), dim3(E::NT), 0, st, a);
+    if (a.persistent)
+        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrPersistent>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (a.dump)
+        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrGridDump>), dim3(grid), dim3(E::NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_correlate<E, PREC, false>), dim3(grid), dim3(E::NT), 0, st, a);
+        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrGrid>), dim3(grid), dim3(E::NT), 0, st, a);
 }
 
 template <class E>
-static hipError_t corr_e(const CorrArgs& a, int prec, hipStream_t st) {
-    const int grid = ((a.nwork + 7) / 8) * 8;
+static hipError_t corr_e(const CorrArgs& a, int grid, int prec, hipStream_t st) {
     switch (prec) {
         case ACQ_FP32: corr_ep<E, ACQ_FP32>(a, grid, st); break;
         case ACQ_FP16: corr_ep<E, ACQ_FP16>(a, grid, st); break;
@@ -559,28 +637,29 @@ static hipError_t corr_e(const CorrArgs& a, int prec, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_correlate(const CorrArgs& a, int log2_sub, int prec, hipStream_t st) {
-    if (a.nwork <= 0) return hipSuccess;
-    if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile) return hipErrorInvalidValue;
+hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec, int engine, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile || grid % kXcds) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return corr_e<StockhamEngine<10>>(a, prec, st);
-        case 11: return corr_e<StockhamEngine<11>>(a, prec, st);
-        case 12: return corr_e<StockhamEngine<12>>(a, prec, st);
-        case 13: return corr_e<StockhamEngine<13>>(a, prec, st);
-        case 14: return corr_e<Fft14>(a, prec, st);
+        case 10: return corr_e<StockhamEngine<10>>(a, grid, prec, st);
+        case 11: return corr_e<StockhamEngine<11>>(a, grid, prec, st);
+        case 12: return corr_e<StockhamEngine<12>>(a, grid, prec, st);
+        case 13: return corr_e<StockhamEngine<13>>(a, grid, prec, st);
+        case 14:
+            return engine == 1 ? corr_e<StockhamEngine<14>>(a, grid, prec, st) : corr_e<Fft14>(a, grid, prec, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_refine(const RefineArgs& a, hipStream_t st) {
+hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
     if (a.radius < 0 || a.radius > kMaxRefineRadius) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_refine, dim3(a.T), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_refine, dim3(unsigned(max_blocks) * a.T), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const acq_detection* dets, const int32_t* found, int T, acq_detection* out,
-                          int32_t* count, hipStream_t st) {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, dets, found, T, out, count);
+hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T,
+                          acq_detection* out, int32_t* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, bt, dets, found, T, out, count);
     return hipGetLastError();
 }
 

@@ -1,11 +1,13 @@
-// C ABI of the acquisition library: plan lifecycle and the per-block search.
+// C ABI of the acquisition library: plan lifecycle, single-block and batched
+// searches, tuning and kernel timing.
 //
 // A plan owns everything that does not change from block to block (Section
 // 4.2: allocate once, keep the transformed replicas and transform tables on the
 // GPU for the plan's lifetime): the replica spectra, the rectangular-chip
-// spectrum, the unit-root tables, the per-bin rotations, the segment spectra
-// workspace and the small result buffers.  acq_detect then only launches
-// kernels on the plan's stream and copies the detections back.
+// spectrum, the unit-root tables, the per-bin rotations, the segment-spectra
+// workspace (sized for the largest batch), the result buffers and pinned host
+// staging.  A search only launches kernels on the plan's stream and copies the
+// detections back.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,6 +20,8 @@
 #include "host_logic.h"
 #include "kernels.h"
 
+using acq::BlockDesc;
+using acq::BlockTable;
 using acq::Geometry;
 
 struct acq_plan_s {
@@ -25,9 +29,12 @@ struct acq_plan_s {
     Geometry g;
     hipStream_t stream = nullptr;
     int device = 0;
+    int cus = 256;                      // compute units (persistent grid size)
+    int engine = 0;                     // acq_tuning.engine
+    int tile = 16;                      // acq_tuning.tag_tile
 
-    float2* d_X = nullptr;              // [S][M] FP32 segment spectra
-    void* d_Xh = nullptr;               // [S][M] 16-bit segment spectra (FP16/BF16 plans)
+    float2* d_X = nullptr;              // [segments][M] FP32 segment spectra
+    void* d_Xh = nullptr;               // [segments][M] 16-bit segment spectra (FP16/BF16 plans)
     void* d_bank = nullptr;             // [T][Msub] in the plan's storage format
     int bank_exp = 0;                   // power-of-two prescale of the stored bank
     float2* d_rect = nullptr;           // [M]
@@ -38,18 +45,28 @@ struct acq_plan_s {
     int32_t* d_rot = nullptr;           // [K]
     int64_t* d_rot_signed = nullptr;    // [K]
     double* d_freqs = nullptr;          // [K]
-    unsigned long long* d_keys = nullptr;   // [T]
-    double* d_parts = nullptr;          // [kPowerParts]
-    acq_detection* d_dets = nullptr;    // [T]
-    acq_detection* d_out = nullptr;     // [T]
-    int32_t* d_found = nullptr;         // [T]
+    unsigned long long* d_keys = nullptr;   // [blocks][T]
+    double* d_parts = nullptr;          // [blocks][kPowerParts]
+    acq_detection* d_dets = nullptr;    // [blocks][T]
+    acq_detection* d_out = nullptr;     // [blocks][T]
+    int32_t* d_found = nullptr;         // [blocks][T]
     int32_t* d_count = nullptr;         // [1]
-    acq_detection* h_out = nullptr;     // pinned [T]
+    int* d_counters = nullptr;          // [kXcds]
+    BlockDesc* d_descs = nullptr;       // [blocks]
+    int32_t* d_counts = nullptr;        // [2]
+    acq_detection* h_out = nullptr;     // pinned [blocks][T]
     int32_t* h_count = nullptr;         // pinned [1]
+    BlockDesc* h_descs = nullptr;       // pinned [blocks]
+    int32_t* h_counts = nullptr;        // pinned [2]
 
     bool profiling = false;
+    bool capturing = false;
     hipEvent_t ev[ACQ_NUM_KERNELS][2] = {};
     bool ev_used[ACQ_NUM_KERNELS] = {};
+
+    hipStream_t cap_stream = nullptr;   // private stream the batch graph is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -72,18 +89,28 @@ hipError_t dalloc(T** p, size_t count) {
     return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count ? count : 1));
 }
 
+void drop_graph(acq_plan_s* p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+}
+
 void free_plan(acq_plan_s* p) {
     if (!p) return;
+    drop_graph(p);
     void* dev[] = {p->d_X, p->d_Xh, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_dets,
-                   p->d_out, p->d_found, p->d_count};
+                   p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts};
     for (void* d : dev)
         if (d) (void)hipFree(d);
-    if (p->h_out) (void)hipHostFree(p->h_out);
-    if (p->h_count) (void)hipHostFree(p->h_count);
+    void* host[] = {p->h_out, p->h_count, p->h_descs, p->h_counts};
+    for (void* h : host)
+        if (h) (void)hipHostFree(h);
     for (auto& pair : p->ev)
         for (hipEvent_t e : pair)
             if (e) (void)hipEventDestroy(e);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
 }
 
@@ -91,7 +118,8 @@ int build_plan(acq_plan_s* p) {
     const Geometry& g = p->g;
     const acq_config& c = p->cfg;
     const size_t T = size_t(c.num_tags), C = size_t(c.num_chips), K = size_t(c.num_bins);
-    const size_t S = size_t(g.max_segments > 0 ? g.max_segments : 1);
+    const size_t B = size_t(g.max_blocks);
+    const size_t S = size_t(g.max_total_segments > 0 ? g.max_total_segments : 1);
     const bool half = c.precision != ACQ_FP32;
     ACQ_HIP(dalloc(&p->d_X, S * size_t(g.M)));
     if (half) ACQ_HIP(hipMalloc(&p->d_Xh, S * size_t(g.M) * 4));
@@ -107,14 +135,19 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_rot, K));
     ACQ_HIP(dalloc(&p->d_rot_signed, K));
     ACQ_HIP(dalloc(&p->d_freqs, K));
-    ACQ_HIP(dalloc(&p->d_keys, T));
-    ACQ_HIP(dalloc(&p->d_parts, size_t(acq::kPowerParts)));
-    ACQ_HIP(dalloc(&p->d_dets, T));
-    ACQ_HIP(dalloc(&p->d_out, T));
-    ACQ_HIP(dalloc(&p->d_found, T));
+    ACQ_HIP(dalloc(&p->d_keys, B * T));
+    ACQ_HIP(dalloc(&p->d_parts, B * size_t(acq::kPowerParts)));
+    ACQ_HIP(dalloc(&p->d_dets, B * T));
+    ACQ_HIP(dalloc(&p->d_out, B * T));
+    ACQ_HIP(dalloc(&p->d_found, B * T));
     ACQ_HIP(dalloc(&p->d_count, 1));
-    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_detection) * T));
+    ACQ_HIP(dalloc(&p->d_counters, size_t(acq::kXcds)));
+    ACQ_HIP(dalloc(&p->d_descs, B));
+    ACQ_HIP(dalloc(&p->d_counts, 2));
+    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_detection) * B * T));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t)));
+    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_descs), sizeof(BlockDesc) * B));
+    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_counts), sizeof(int32_t) * 2));
 
     const std::vector<float> rootsM = acq::unit_roots(g.M);
     const std::vector<float> rootsSub = acq::unit_roots(g.Msub);
@@ -134,18 +167,19 @@ int build_plan(acq_plan_s* p) {
     return ACQ_OK;
 }
 
-// Event pair around one kernel launch when profiling is on.
+// Event pair around one kernel launch when profiling is on (not while capturing).
 struct KernelTimer {
     acq_plan_s* p;
     int id;
-    KernelTimer(acq_plan_s* plan, int kernel) : p(plan), id(kernel) {
-        if (p->profiling) {
+    bool on;
+    KernelTimer(acq_plan_s* plan, int kernel) : p(plan), id(kernel), on(plan->profiling && !plan->capturing) {
+        if (on) {
             (void)hipEventRecord(p->ev[id][0], p->stream);
             p->ev_used[id] = true;
         }
     }
     ~KernelTimer() {
-        if (p->profiling) (void)hipEventRecord(p->ev[id][1], p->stream);
+        if (on) (void)hipEventRecord(p->ev[id][1], p->stream);
     }
 };
 
@@ -153,45 +187,49 @@ void reset_timers(acq_plan_s* p) {
     for (bool& u : p->ev_used) u = false;
 }
 
-// Kernels shared by acq_detect and acq_correlate_power: block power, segment
-// spectra, correlation (argmax keys, optional power dump).
-int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
+double threshold_for(const acq_plan_s* p, int64_t n) {
+    const acq_config& c = p->cfg;
+    return c.threshold > 0.0 ? c.threshold : acq::default_threshold(c.num_tags, c.num_bins, n, p->g.L);
+}
+
+// Launch sequence of a search on stream st.  `bt` holds one inline block
+// (single-block calls: plain grids sized on the host) or the plan's device
+// block table (batches: persistent grids that do not depend on the batch, so
+// the sequence can be captured once and replayed).
+int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_seg_host, float* dump,
+                   bool refine, hipStream_t st) {
     const Geometry& g = p->g;
     const acq_config& c = p->cfg;
-    hipStream_t st = p->stream;
-    const int64_t lags = n - g.L + 1;
-    const int S = int((lags + g.V - 1) / g.V);
-    reset_timers(p);
+    const int nb_grid = batch ? g.max_blocks : 1;
     {
         KernelTimer kt(p, ACQ_KERNEL_BLOCK_POWER);
-        ACQ_HIP(acq::launch_block_power(x, n, p->d_parts, st));
+        ACQ_HIP(acq::launch_block_power(bt, nb_grid, p->d_parts, st));
     }
-    ACQ_HIP(acq::launch_fill_u64(p->d_keys, c.num_tags, st));
+    ACQ_HIP(acq::launch_fill_u64(p->d_keys, int64_t(nb_grid) * c.num_tags, st));
 
     acq::FwdArgs fa{};
-    fa.x = x;
+    fa.blocks = bt;
     fa.X = p->d_X;
     fa.Xh = p->d_Xh;
     fa.parts = p->d_parts;
     fa.rootsM = p->d_rootsM;
     fa.rootsSub = p->d_rootsSub;
     fa.b1tab = p->d_b1tab;
-    fa.n = n;
     fa.V = g.V;
-    fa.S = S;
     fa.spc = c.samples_per_chip;
     fa.M = int(g.M);
     fa.Msub = int(g.Msub);
     {
         KernelTimer kt(p, ACQ_KERNEL_FORWARD);
-        ACQ_HIP(acq::launch_forward(fa, g.log2_sub, c.precision, st));
+        const int grid = batch ? p->cus : total_seg_host;
+        ACQ_HIP(acq::launch_forward(fa, grid, g.log2_sub, c.precision, st));
     }
 
     acq::CorrArgs ca{};
+    ca.blocks = bt;
     ca.X = c.precision == ACQ_FP32 ? static_cast<const void*>(p->d_X) : p->d_Xh;
     ca.bank = p->d_bank;
     ca.parts = p->d_parts;
-    ca.bank_exp = p->bank_exp;
     ca.rect = p->d_rect;
     ca.rootsM = p->d_rootsM;
     ca.rootsSub = p->d_rootsSub;
@@ -199,24 +237,59 @@ int run_search(acq_plan_s* p, const float2* x, int64_t n, float* dump) {
     ca.rot = p->d_rot;
     ca.keys = p->d_keys;
     ca.dump = dump;
-    ca.n = n;
-    ca.lags = lags;
+    ca.counters = p->d_counters;
     ca.V = g.V;
-    ca.S = S;
     ca.K = c.num_bins;
     ca.spc = c.samples_per_chip;
     ca.M = int(g.M);
     ca.Msub = int(g.Msub);
     ca.T = c.num_tags;
-    ca.tile = g.tag_tile;
-    ca.ntiles = (c.num_tags + g.tag_tile - 1) / g.tag_tile;
-    const int64_t nwork = int64_t(ca.ntiles) * S * c.num_bins * c.samples_per_chip;
-    if (nwork >= (int64_t(1) << 31) - 8) return acq::fail(ACQ_ERR_UNSUPPORTED, "too many work items");
-    ca.nwork = int(nwork);
+    ca.tile = p->tile;
+    ca.ntiles = (c.num_tags + p->tile - 1) / p->tile;
+    ca.bank_exp = p->bank_exp;
+    ca.persistent = batch ? 1 : 0;
+    int grid;
+    if (batch) {
+        ACQ_HIP(acq::launch_fill_i32(p->d_counters, acq::kXcds, st));
+        grid = p->cus;
+    } else {
+        const int64_t nwork = int64_t(ca.ntiles) * total_seg_host * c.num_bins * c.samples_per_chip;
+        if (nwork >= (int64_t(1) << 31) - 8) return acq::fail(ACQ_ERR_UNSUPPORTED, "too many work items");
+        grid = int((nwork + acq::kXcds - 1) / acq::kXcds) * acq::kXcds;
+    }
     {
         KernelTimer kt(p, ACQ_KERNEL_CORRELATE);
-        ACQ_HIP(acq::launch_correlate(ca, g.log2_sub, c.precision, st));
+        ACQ_HIP(acq::launch_correlate(ca, grid, g.log2_sub, c.precision, p->engine, st));
     }
+    if (!refine) return ACQ_OK;
+
+    acq::RefineArgs ra{};
+    ra.blocks = bt;
+    ra.chips = p->d_chips;
+    ra.rot_signed = p->d_rot_signed;
+    ra.freqs = p->d_freqs;
+    ra.keys = p->d_keys;
+    ra.parts = p->d_parts;
+    ra.dets = p->d_dets;
+    ra.found = p->d_found;
+    ra.L = g.L;
+    ra.T = c.num_tags;
+    ra.C = c.num_chips;
+    ra.K = c.num_bins;
+    ra.spc = c.samples_per_chip;
+    ra.M = int(g.M);
+    ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
+    {
+        KernelTimer kt(p, ACQ_KERNEL_REFINE);
+        ACQ_HIP(acq::launch_refine(ra, nb_grid, st));
+    }
+    {
+        KernelTimer kt(p, ACQ_KERNEL_COMPACT);
+        ACQ_HIP(acq::launch_compact(bt, p->d_dets, p->d_found, c.num_tags, p->d_out, p->d_count, st));
+    }
+    ACQ_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    ACQ_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_detection) * size_t(nb_grid) * size_t(c.num_tags),
+                           hipMemcpyDeviceToHost, st));
     return ACQ_OK;
 }
 
@@ -227,6 +300,27 @@ int check_block(acq_plan_s* p, const void* block, int64_t n) {
     if (n > 0 && !block) return acq::fail(ACQ_ERR_INVALID_ARG, "null block");
     if (reinterpret_cast<uintptr_t>(block) % 8 != 0)
         return acq::fail(ACQ_ERR_INVALID_ARG, "block must be 8-byte aligned");
+    return ACQ_OK;
+}
+
+BlockDesc single_desc(const acq_plan_s* p, const void* block, int64_t n) {
+    BlockDesc d{};
+    d.x = static_cast<const float2*>(block);
+    d.n = n;
+    d.lags = n - p->g.L + 1;
+    d.seg0 = 0;
+    d.nseg = d.lags > 0 ? int((d.lags + p->g.V - 1) / p->g.V) : 0;
+    d.theta = threshold_for(p, n);
+    return d;
+}
+
+int deliver(acq_plan_s* p, acq_detection* out, int32_t capacity, int32_t* n_found) {
+    const int32_t found = *p->h_count;
+    *n_found = found;
+    const int32_t ncopy = found < capacity ? found : capacity;
+    if (ncopy > 0) std::memcpy(out, p->h_out, sizeof(acq_detection) * size_t(ncopy));
+    if (found > capacity) return acq::fail(ACQ_ERR_TRUNCATED, "more detections than capacity");
+    acq::clear_error();
     return ACQ_OK;
 }
 
@@ -272,11 +366,15 @@ int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out) {
     if (!p) return acq::fail(ACQ_ERR_OOM, "host allocation failed");
     p->cfg = *cfg;                   // chips are read by build_plan only
     p->g = std::move(g);
+    p->tile = p->g.tag_tile;
     p->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&p->device) != hipSuccess) {
         delete p;
         return acq::fail(ACQ_ERR_DEVICE, "no HIP device");
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus >= 8)
+        p->cus = cus / acq::kXcds * acq::kXcds;
     rc = build_plan(p);
     p->cfg.chips = nullptr;          // copied to the device; the caller keeps its buffer
     if (rc != ACQ_OK) {
@@ -295,54 +393,81 @@ int acq_detect(acq_plan_t p, const void* block, int64_t n, acq_detection* out, i
     if (!n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null n_found");
     if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
     *n_found = 0;
-    const Geometry& g = p->g;
-    if (n < g.L) {
+    if (n < p->g.L) {
         acq::clear_error();
         return ACQ_OK;
     }
-    const float2* x = static_cast<const float2*>(block);
-    rc = run_search(p, x, n, nullptr);
+    reset_timers(p);
+    BlockTable bt{};
+    bt.one = single_desc(p, block, n);
+    rc = enqueue_search(p, bt, false, bt.one.nseg, nullptr, true, p->stream);
     if (rc != ACQ_OK) return rc;
-    const acq_config& c = p->cfg;
-    acq::RefineArgs ra{};
-    ra.x = x;
-    ra.chips = p->d_chips;
-    ra.rot_signed = p->d_rot_signed;
-    ra.freqs = p->d_freqs;
-    ra.keys = p->d_keys;
-    ra.parts = p->d_parts;
-    ra.dets = p->d_dets;
-    ra.found = p->d_found;
-    ra.n = n;
-    ra.L = g.L;
-    ra.lags = n - g.L + 1;
-    ra.theta = c.threshold > 0.0 ? c.threshold : acq::default_threshold(c.num_tags, c.num_bins, n, g.L);
-    ra.T = c.num_tags;
-    ra.C = c.num_chips;
-    ra.K = c.num_bins;
-    ra.spc = c.samples_per_chip;
-    ra.M = int(g.M);
-    ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
-    hipStream_t st = p->stream;
-    {
-        KernelTimer kt(p, ACQ_KERNEL_REFINE);
-        ACQ_HIP(acq::launch_refine(ra, st));
+    ACQ_HIP(hipStreamSynchronize(p->stream));
+    return deliver(p, out, capacity, n_found);
+}
+
+int acq_detect_batch(acq_plan_t p, const void* const* blocks, const int64_t* lens, int32_t nblocks,
+                     acq_detection* out, int32_t capacity, int32_t* n_found) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (!blocks || !lens || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (nblocks < 1 || nblocks > p->g.max_blocks)
+        return acq::fail(ACQ_ERR_INVALID_ARG, "nblocks outside [1, max_batch_blocks]");
+    int64_t total = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const int rc = check_block(p, blocks[b], lens[b]);
+        if (rc != ACQ_OK) return rc;
+        total += lens[b];
     }
-    {
-        KernelTimer kt(p, ACQ_KERNEL_COMPACT);
-        ACQ_HIP(acq::launch_compact(p->d_dets, p->d_found, c.num_tags, p->d_out, p->d_count, st));
+    if (total > p->g.max_batch_samples)
+        return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "batch longer than max_batch_samples");
+    *n_found = 0;
+    int32_t seg = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        BlockDesc d = single_desc(p, blocks[b], lens[b]);
+        d.seg0 = seg;
+        seg += d.nseg;
+        p->h_descs[b] = d;
     }
-    ACQ_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    ACQ_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_detection) * size_t(c.num_tags),
-                           hipMemcpyDeviceToHost, st));
-    ACQ_HIP(hipStreamSynchronize(st));
-    const int32_t found = *p->h_count;
-    *n_found = found;
-    const int32_t ncopy = found < capacity ? found : capacity;
-    if (ncopy > 0) std::memcpy(out, p->h_out, sizeof(acq_detection) * size_t(ncopy));
-    if (found > capacity) return acq::fail(ACQ_ERR_TRUNCATED, "more detections than capacity");
-    acq::clear_error();
-    return ACQ_OK;
+    p->h_counts[0] = nblocks;
+    p->h_counts[1] = seg;
+    reset_timers(p);
+
+    BlockTable bt{};
+    bt.descs = p->d_descs;
+    bt.counts = p->d_counts;
+    const size_t desc_bytes = sizeof(BlockDesc) * size_t(p->g.max_blocks);
+    if (p->cfg.flags & ACQ_FLAG_GRAPH) {
+        if (!p->gexec) {
+            if (!p->cap_stream) ACQ_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            ACQ_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            p->capturing = true;
+            int rc = ACQ_OK;
+            hipError_t e = hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->cap_stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   p->cap_stream);
+            if (e == hipSuccess) rc = enqueue_search(p, bt, true, 0, nullptr, true, p->cap_stream);
+            p->capturing = false;
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+            if (e != hipSuccess || rc != ACQ_OK || e2 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                if (rc != ACQ_OK) return rc;
+                return acq::fail(ACQ_ERR_DEVICE, hip_msg("graph capture", e != hipSuccess ? e : e2));
+            }
+            p->graph = graph;
+            ACQ_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+        }
+        ACQ_HIP(hipGraphLaunch(p->gexec, p->stream));
+    } else {
+        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->stream));
+        ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+        const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream);
+        if (rc != ACQ_OK) return rc;
+    }
+    ACQ_HIP(hipStreamSynchronize(p->stream));
+    return deliver(p, out, capacity, n_found);
 }
 
 int acq_correlate_power(acq_plan_t p, const void* block, int64_t n, float* power) {
@@ -353,9 +478,81 @@ int acq_correlate_power(acq_plan_t p, const void* block, int64_t n, float* power
         return ACQ_OK;
     }
     if (!power) return acq::fail(ACQ_ERR_INVALID_ARG, "null power output");
-    rc = run_search(p, static_cast<const float2*>(block), n, power);
+    reset_timers(p);
+    BlockTable bt{};
+    bt.one = single_desc(p, block, n);
+    rc = enqueue_search(p, bt, false, bt.one.nseg, power, false, p->stream);
     if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+int acq_get_tuning(acq_plan_t p, acq_tuning* out) {
+    if (!p || !out) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    out->engine = p->engine;
+    out->tag_tile = p->tile;
+    return ACQ_OK;
+}
+
+int acq_set_tuning(acq_plan_t p, const acq_tuning* t) {
+    if (!p || !t) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (t->engine < 0 || t->engine > 1 || t->tag_tile < 1 || t->tag_tile > acq::kMaxTagTile)
+        return acq::fail(ACQ_ERR_INVALID_ARG, "engine must be 0 or 1, tag_tile in [1, 64]");
+    const int tile = t->tag_tile < p->cfg.num_tags ? t->tag_tile : p->cfg.num_tags;
+    if (t->engine != p->engine || tile != p->tile) drop_graph(p);   // the captured kernels change
+    p->engine = t->engine;
+    p->tile = tile;
+    return ACQ_OK;
+}
+
+int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_entry* out, int32_t capacity,
+             int32_t* n_out) {
+    int rc = check_block(p, block, n);
+    if (rc != ACQ_OK) return rc;
+    if (!n_out || reps < 1 || capacity < 0 || (capacity > 0 && !out))
+        return acq::fail(ACQ_ERR_INVALID_ARG, "bad arguments");
+    if (n < p->g.L) return acq::fail(ACQ_ERR_INVALID_ARG, "block shorter than a template");
+    const bool was_profiling = p->profiling;
+    rc = acq_set_profiling(p, 1);
+    if (rc != ACQ_OK) return rc;
+    std::vector<acq_tune_entry> cand;
+    const int engines = p->g.log2_sub == 14 ? 2 : 1;
+    for (int e = 0; e < engines; ++e)
+        for (int tile : {4, 8, 16, 32, 64}) {
+            if (tile > p->cfg.num_tags && tile != 4) continue;
+            acq_tune_entry c{};
+            c.tuning.engine = e;
+            c.tuning.tag_tile = tile;
+            cand.push_back(c);
+        }
+    const acq_tuning before{p->engine, p->tile};
+    BlockTable bt{};
+    bt.one = single_desc(p, block, n);
+    size_t best = 0;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        acq_set_tuning(p, &cand[i].tuning);
+        double total = 0.0;
+        for (int r = 0; r <= reps; ++r) {           // one warm-up run
+            reset_timers(p);
+            rc = enqueue_search(p, bt, false, bt.one.nseg, nullptr, false, p->stream);
+            if (rc != ACQ_OK) {
+                acq_set_tuning(p, &before);
+                acq_set_profiling(p, was_profiling ? 1 : 0);
+                return rc;
+            }
+            ACQ_HIP(hipStreamSynchronize(p->stream));
+            float ms = 0.f;
+            ACQ_HIP(hipEventElapsedTime(&ms, p->ev[ACQ_KERNEL_CORRELATE][0], p->ev[ACQ_KERNEL_CORRELATE][1]));
+            if (r > 0) total += ms;
+        }
+        cand[i].ms = total / reps;
+        if (cand[i].ms < cand[best].ms) best = i;
+    }
+    acq_set_tuning(p, &cand[best].tuning);
+    acq_set_profiling(p, was_profiling ? 1 : 0);
+    *n_out = int32_t(cand.size());
+    for (size_t i = 0; i < cand.size() && int32_t(i) < capacity; ++i) out[i] = cand[i];
     acq::clear_error();
     return ACQ_OK;
 }

@@ -34,7 +34,7 @@ import numpy as np
 
 __all__ = [
     "rng", "make_codes", "chip_waveform", "delayed_waveform", "Transmission",
-    "make_block", "add_noise", "WORKLOADS", "workload",
+    "make_block", "add_noise", "WORKLOADS", "workload", "batch_lengths", "make_stream_batch",
 ]
 
 # stream identifiers (second SeedSequence word)
@@ -203,3 +203,24 @@ def batch_lengths(seed: int, num_blocks: int, log2_lo: float, log2_hi: float):
     """Block lengths drawn log-uniform: floor(2^U[lo, hi])."""
     g = rng(seed, _STREAM_LENGTHS)
     return [int(np.floor(2.0 ** (log2_lo + (log2_hi - log2_lo) * g.random()))) for _ in range(num_blocks)]
+
+
+def make_stream_batch(seed: int, chips: np.ndarray, spc: int, fs_hz: float, freqs_hz: Sequence[float],
+                      num_blocks: int, log2_len=(18.0, 21.0), receivers: int = 8, n_tx=(0, 20),
+                      snr_db=(-15.0, -5.0)):
+    """A batch of blocks of uneven length from several receivers.
+
+    Block b comes from receiver b mod receivers (a seed component: blocks are
+    independent); its length is log-uniform in [2^lo, 2^hi]; it carries a
+    uniform integer number of transmissions in [n_tx[0], n_tx[1]] from distinct
+    tags.  Returns a list of (x complex64, list[Transmission]).
+    """
+    lens = batch_lengths(seed, num_blocks, *log2_len)
+    g = rng(seed, _STREAM_LENGTHS, 1)
+    L = np.asarray(chips).shape[1] * spc
+    out = []
+    for b, n in enumerate(lens):
+        k = int(g.integers(n_tx[0], n_tx[1] + 1)) if n >= L + 1 else 0
+        sub = (b % receivers) * 100000 + b
+        out.append(make_block(seed, n, chips, spc, fs_hz, freqs_hz, k, snr_db=snr_db, sub=sub))
+    return out
