@@ -6,7 +6,9 @@ package.  The GPU path (paper_2005_10445_amd) never imports it, and the two
 share no code: no kernels, headers, tables, constants or pre/post-processing.
 
 Everything here is FP64 and written from the definitions (see reference.py
-for the passages followed and the readings taken where the paper is silent).
+for the passages followed and the readings taken where the paper is silent;
+learned.py holds the proposal stage: STFT power map, CNN, loss, optimiser and
+the proposal-to-segment mapping).
 """
 from .reference import *  # noqa: F401,F403
 from .reference import __all__  # noqa: F401
