@@ -235,6 +235,138 @@ int acq_last_kernel_times(acq_plan_t plan, double* ms, int32_t n, int32_t* count
 /* Release a plan and the memory it allocated.  NULL is a no-op. */
 int acq_release(acq_plan_t plan);
 
+/* ====================================================================
+ * Proposal stage (an extension: the paper searches every lag).  A small
+ * 1-D CNN scores the frames of a block's STFT power map; the exhaustive
+ * search then runs only on the overlap-save segments that the best-scoring
+ * frames propose, with a full search as fallback.  Inside the searched
+ * segments every value is the one the exhaustive search computes.
+ *
+ * Power map: 256-sample frames at hop 128 (F = floor((n-256)/128)+1 rows),
+ * periodic Hann window, P[f][b] = |DFT_256|^2 (FP32), map = ln(P / med) with
+ * med the lower median of the block's F*256 powers (0 when med is 0), stored
+ * [F][256] row-major as bf16 (ACQ_BF16 networks) or FP32 (ACQ_FP32).
+ *
+ * Network: four "same"-padded conv layers over frames (kernel 5, dilations
+ * 1, 2, 4, 8, in_channels -> 64 -> 64 -> 64 -> 64, ReLU), then a 1x1 head to one
+ * logit per frame.  Parameters, FP32, in this order: per layer W[5][cin][64]
+ * then b[64]; then wh[64], bh.  Training: mean weighted BCE with logits over
+ * frames (label 1 when half the frame lies inside a transmission), Adam.
+ * ==================================================================== */
+typedef struct acq_cnn_s* acq_cnn_t;
+
+typedef struct acq_cnn_config {
+    int32_t precision;          /* ACQ_BF16: bf16 activations and weights, MFMA products,
+                                   FP32 accumulation and master weights; ACQ_FP32: FP32
+                                   throughout (reference arithmetic, slow, for tests) */
+    int32_t in_channels;        /* 256 for power maps; ACQ_BF16 needs a multiple of 64 */
+    int64_t max_rows;           /* most frames in one call, over all its blocks */
+    int64_t max_block_len;      /* longest block acq_power_map/acq_detect_learned take */
+} acq_cnn_config;
+
+/* Number of FP32 parameters of a network with this many input channels. */
+int64_t acq_cnn_num_params(int32_t in_channels);
+
+/* Create a network bound to a HIP stream (NULL: the null stream).  Parameters
+ * start at zero; load them with acq_cnn_set_params. */
+int acq_cnn_create(const acq_cnn_config* cfg, void* hip_stream, acq_cnn_t* out);
+int acq_cnn_release(acq_cnn_t cnn);
+
+/* Copy n = acq_cnn_num_params FP32 parameters from / to host memory.  Setting
+ * also clears the optimiser state (moments, step count). */
+int acq_cnn_set_params(acq_cnn_t cnn, const float* params, int64_t n);
+int acq_cnn_get_params(acq_cnn_t cnn, float* params, int64_t n);
+
+/* Logits of nblocks blocks of `frames` rows each: input device
+ * [nblocks*frames][in_channels] (bf16 or FP32 by precision), logits device
+ * FP32 [nblocks*frames].  Synchronous. */
+int acq_cnn_forward(acq_cnn_t cnn, const void* input, int32_t nblocks, int64_t frames, float* logits);
+
+/* Loss and gradient for labels (device FP32 [rows]) with positive-class
+ * weight pos_weight: *loss (host) is the mean loss; the gradient is kept for
+ * acq_cnn_adam_step and, when grad is not NULL, copied to device FP32
+ * grad[acq_cnn_num_params].  Synchronous. */
+int acq_cnn_gradients(acq_cnn_t cnn, const void* input, int32_t nblocks, int64_t frames, const float* labels,
+                      float pos_weight, float* grad, float* loss);
+
+/* Adam (b1 0.9, b2 0.999, eps 1e-8) on the gradient of the last
+ * acq_cnn_gradients call, learning rate lr; clears that gradient. */
+int acq_cnn_adam_step(acq_cnn_t cnn, float lr);
+
+/* Power map of one device block of n >= 256 samples into device `map`
+ * (layout above); *median (host) receives med.  Synchronous. */
+int acq_power_map(acq_cnn_t cnn, const void* block, int64_t n, void* map, float* median);
+
+/* One transmission of a synthetic training block: BPSK chips (Philox stream
+ * `code`) held samples_per_chip samples, amplitude amp (noise power 1),
+ * carrier offset freq_over_fs cycles per sample, phase phase0 cycles at
+ * sample 0, starting at sample `delay`. */
+typedef struct acq_synth_tx {
+    int64_t  delay;
+    double   freq_over_fs;
+    float    amp;
+    float    phase0;
+    uint32_t code;
+    uint32_t reserved;
+} acq_synth_tx;
+
+#define ACQ_SYNTH_MAX_TX 32
+
+/* A batch of synthetic blocks generated on the device (Philox4x32-10 keyed by
+ * seed; block b is stream first_block + b): CN(0,1) noise plus ntx[b] <= 32
+ * transmissions tx[b*32 + i] (host arrays), num_chips chips each. */
+typedef struct acq_synth_batch {
+    uint64_t seed;
+    int64_t  first_block;
+    int32_t  nblocks;
+    int32_t  num_chips;
+    int32_t  samples_per_chip;
+    int64_t  block_len;
+    const acq_synth_tx* tx;
+    const int32_t* ntx;
+} acq_synth_batch;
+
+/* Write the samples of synthetic block 0 of the batch to device complex64
+ * out[block_len].  Synchronous. */
+int acq_synth_block(acq_cnn_t cnn, const acq_synth_batch* batch, void* out);
+
+/* One training step on a generated batch: samples, power maps, frame labels,
+ * forward, loss, backward and Adam, all on the device (no sample is written to
+ * memory).  *loss (host) is the batch's mean loss before the update. */
+int acq_cnn_train_synthetic(acq_cnn_t cnn, const acq_synth_batch* batch, float pos_weight, float lr, float* loss);
+
+typedef struct acq_learned_params {
+    float   kappa;              /* proposal threshold on the window score */
+    int32_t max_proposals;      /* at most this many proposed frames */
+    float   max_fraction;       /* full search when more than this fraction of segments is proposed */
+    float   floor_db;           /* full search when the map median departs from the running
+                                   noise floor by more than this (dB); <= 0 disables */
+} acq_learned_params;
+
+#define ACQ_FALLBACK_NONE     0
+#define ACQ_FALLBACK_FRACTION 1
+#define ACQ_FALLBACK_FLOOR    2
+
+typedef struct acq_learned_report {
+    int32_t proposals;          /* proposed frames */
+    int32_t segments;           /* segments searched */
+    int32_t total_segments;     /* segments of the block */
+    int32_t fallback;           /* ACQ_FALLBACK_* */
+    float   median;             /* power-map median of the block */
+    float   floor;              /* running noise floor before this block */
+} acq_learned_report;
+
+/* Proposal-driven search of one device block: power map, network, window
+ * scores, proposals, then the plan's search on the proposed segments only (or
+ * on all segments when a fallback rule fires).  Output as acq_detect;
+ * *report (host, may be NULL) describes what was searched.  The network keeps
+ * the running noise floor: the first call sets it to the block's map median,
+ * every later call moves it a tenth of the way towards the new median (after
+ * the fallback test).  Synchronous; one call at a time per network. */
+int acq_detect_learned(acq_plan_t plan, acq_cnn_t cnn, const void* block, int64_t n,
+                       const acq_learned_params* params, acq_detection* out, int32_t capacity,
+                       int32_t* n_found, acq_learned_report* report);
+
 /* Static description of a status code. */
 const char* acq_strerror(int status);
 

@@ -12,7 +12,8 @@ textbook definitions:
   w[n] = (1 - cos(2 pi n / 256)) / 2.  P[f][b] = |sum_n w[n] x[128 f + n]
   exp(-j 2 pi b n / 256)|^2, b in FFT order.  The map is ln(P / med), med the
   lower median of all F*256 values of the block (the ceil(F*256/2)-th
-  smallest), so that the map does not depend on the receiver gain.
+  smallest), so that the map does not depend on the receiver gain (0 when
+  that median is 0).
 * Network.  Four "same"-padded dilated convolutions over frames, kernel 5,
   dilations 1, 2, 4, 8, channels 256 -> 64 -> 64 -> 64 -> 64, each followed by
   ReLU, then a 1x1 head 64 -> 1 giving one logit per frame:
@@ -84,9 +85,12 @@ def lower_median(v) -> float:
 
 
 def power_map(x) -> Tuple[np.ndarray, float]:
-    """ln(P / med) and med.  Bins with P == 0 map to ln(tiny / med)."""
+    """ln(P / med) and med.  Bins with P == 0 map to ln(tiny / med); a block
+    whose median is 0 (more than half the bins exactly empty) maps to 0."""
     P = stft_power(x)
     med = lower_median(P)
+    if med == 0.0:
+        return np.zeros_like(P), 0.0
     tiny = np.finfo(np.float64).tiny
     return np.log(np.maximum(P, tiny) / med), med
 

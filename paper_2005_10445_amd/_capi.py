@@ -28,7 +28,12 @@ ACQ_FLAG_GRAPH = 0x1
 # every symbol include/acq.h declares
 EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
             "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
-            "acq_last_kernel_times", "acq_release", "acq_strerror", "acq_last_error")
+            "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
+            "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
+            "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
+            "acq_detect_learned", "acq_strerror", "acq_last_error")
+ACQ_SYNTH_MAX_TX = 32
+ACQ_FALLBACK_NONE, ACQ_FALLBACK_FRACTION, ACQ_FALLBACK_FLOOR = 0, 1, 2
 KERNELS = ("block_power", "forward", "correlate", "refine", "compact")
 
 
@@ -93,6 +98,59 @@ class AcqTuneEntry(ctypes.Structure):
     _fields_ = [("tuning", AcqTuning), ("ms", ctypes.c_double)]
 
 
+class AcqCnnConfig(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("in_channels", ctypes.c_int32),
+        ("max_rows", ctypes.c_int64),
+        ("max_block_len", ctypes.c_int64),
+    ]
+
+
+class AcqSynthTx(ctypes.Structure):
+    _fields_ = [
+        ("delay", ctypes.c_int64),
+        ("freq_over_fs", ctypes.c_double),
+        ("amp", ctypes.c_float),
+        ("phase0", ctypes.c_float),
+        ("code", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class AcqSynthBatch(ctypes.Structure):
+    _fields_ = [
+        ("seed", ctypes.c_uint64),
+        ("first_block", ctypes.c_int64),
+        ("nblocks", ctypes.c_int32),
+        ("num_chips", ctypes.c_int32),
+        ("samples_per_chip", ctypes.c_int32),
+        ("block_len", ctypes.c_int64),
+        ("tx", ctypes.POINTER(AcqSynthTx)),
+        ("ntx", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class AcqLearnedParams(ctypes.Structure):
+    _fields_ = [
+        ("kappa", ctypes.c_float),
+        ("max_proposals", ctypes.c_int32),
+        ("max_fraction", ctypes.c_float),
+        ("floor_db", ctypes.c_float),
+    ]
+
+
+class AcqLearnedReport(ctypes.Structure):
+    _fields_ = [
+        ("proposals", ctypes.c_int32),
+        ("segments", ctypes.c_int32),
+        ("total_segments", ctypes.c_int32),
+        ("fallback", ctypes.c_int32),
+        ("median", ctypes.c_float),
+        ("floor", ctypes.c_float),
+    ]
+
+
 _lib = None
 
 
@@ -121,9 +179,27 @@ def lib(path: str = LIB_PATH):
     L.acq_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int]
     L.acq_last_kernel_times.argtypes = [ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int32,
                                         P(ctypes.c_int32)]
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.acq_cnn_num_params.argtypes = [i32]
+    L.acq_cnn_num_params.restype = i64
+    L.acq_cnn_create.argtypes = [P(AcqCnnConfig), vp, P(vp)]
+    L.acq_cnn_release.argtypes = [vp]
+    L.acq_cnn_set_params.argtypes = [vp, P(ctypes.c_float), i64]
+    L.acq_cnn_get_params.argtypes = [vp, P(ctypes.c_float), i64]
+    L.acq_cnn_forward.argtypes = [vp, vp, i32, i64, vp]
+    L.acq_cnn_gradients.argtypes = [vp, vp, i32, i64, vp, f32, vp, P(ctypes.c_float)]
+    L.acq_cnn_adam_step.argtypes = [vp, f32]
+    L.acq_power_map.argtypes = [vp, vp, i64, vp, P(ctypes.c_float)]
+    L.acq_synth_block.argtypes = [vp, P(AcqSynthBatch), vp]
+    L.acq_cnn_train_synthetic.argtypes = [vp, P(AcqSynthBatch), f32, f32, P(ctypes.c_float)]
+    L.acq_detect_learned.argtypes = [vp, vp, vp, i64, P(AcqLearnedParams), P(AcqDetection), i32, P(i32),
+                                     P(AcqLearnedReport)]
     for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
                  "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
-                 "acq_set_profiling", "acq_last_kernel_times"):
+                 "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create", "acq_cnn_release",
+                 "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
+                 "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
+                 "acq_detect_learned"):
         getattr(L, name).restype = ctypes.c_int
     L.acq_strerror.argtypes = [ctypes.c_int]
     L.acq_strerror.restype = ctypes.c_char_p

@@ -165,8 +165,8 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     return ACQ_OK;
 }
 
-std::vector<float> unit_roots(int64_t n) {
-    std::vector<float> out(size_t(2 * n));
+std::vector<double> unit_roots64(int64_t n) {
+    std::vector<double> out(size_t(2 * n));
     const double two_pi = 6.283185307179586476925286766559;
     for (int64_t m = 0; m < n; ++m) {
         // reduce to a quadrant, then to [0, pi/4] by reflection, exactly in integers
@@ -188,10 +188,15 @@ std::vector<float> unit_roots(int64_t n) {
             re = -im;
             im = t;
         }
-        out[size_t(2 * m)] = float(re);
-        out[size_t(2 * m + 1)] = float(im);
+        out[size_t(2 * m)] = re;
+        out[size_t(2 * m + 1)] = im;
     }
     return out;
+}
+
+std::vector<float> unit_roots(int64_t n) {
+    const std::vector<double> r = unit_roots64(n);
+    return std::vector<float>(r.begin(), r.end());
 }
 
 std::vector<float> fft14_b1_table() {

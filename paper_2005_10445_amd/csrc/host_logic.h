@@ -53,6 +53,8 @@ double default_threshold(int64_t num_tags, int64_t num_bins, int64_t n, int64_t 
 // exp(+j 2 pi m / n) for m in [0, n), computed in FP64 with exact quadrant
 // symmetry and rounded to FP32; interleaved (re, im).
 std::vector<float> unit_roots(int64_t n);
+// The same roots in FP64: [2n] = (cos, sin)(2 pi m / n).
+std::vector<double> unit_roots64(int64_t n);
 
 // Twiddles of the 2^14-point workgroup transform, laid out [w][k2a][l] with
 // entry exp(+j 2 pi l (w + 16 k2a) / 2^14), w, k2a < 16, l < 64.

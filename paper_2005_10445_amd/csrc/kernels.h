@@ -29,11 +29,15 @@ struct BlockDesc {
 struct BlockTable {
     const BlockDesc* descs;     // device [nblocks] or nullptr (use `one`)
     const int32_t* counts;      // device [2] = {nblocks, total segments} when descs != nullptr
+    const int32_t* seg_of;      // device [total segments]: segment of the block searched in global slot g
+                                // (a subset of the block's segments), or nullptr: slot g is segment g - seg0
     BlockDesc one;
 
     __device__ __forceinline__ int nblocks() const { return descs ? counts[0] : 1; }
     __device__ __forceinline__ int total_seg() const { return descs ? counts[1] : one.nseg; }
     __device__ __forceinline__ BlockDesc get(int b) const { return descs ? descs[b] : one; }
+    // overlap-save segment (within its block d) held in global slot g
+    __device__ __forceinline__ int segment(int g, const BlockDesc& d) const { return seg_of ? seg_of[g] : g - d.seg0; }
     // block holding global segment g (segments are numbered block by block)
     __device__ __forceinline__ int block_of_segment(int g) const {
         if (!descs) return 0;
@@ -81,12 +85,13 @@ struct RefineArgs {
     const int8_t* chips;        // [T][C]
     const int64_t* rot_signed;  // [K] signed rotation at M
     const double* freqs;        // [K]
+    const double2* roots64;     // [M] (cos, sin)(2 pi m / M), FP64
     const unsigned long long* keys;   // [block][T]
     const double* parts;        // [block][kPowerParts]
     acq_detection* dets;        // [block][T]
     int32_t* found;             // [block][T] 1 if detected
     int64_t L;
-    int32_t T, C, K, spc, M, radius;
+    int32_t T, C, K, spc, log2_spc, M, radius;
 };
 
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);

@@ -164,7 +164,8 @@ __device__ __forceinline__ int spectrum_exponent(const double* __restrict__ part
 }
 
 // One workgroup per global segment g (looping when the grid is smaller):
-// X_g = DFT_M of segment j = g - seg0 of its block.
+// X_g = DFT_M of the segment held in slot g (segment g - seg0 of its block, or
+// the listed segment when only some segments are searched).
 template <class E, int PREC>
 __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
     using St = dev::Storage<PREC>;
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
     for (int g = int(blockIdx.x); g < total; g += int(gridDim.x)) {
         const int bi = a.blocks.block_of_segment(g);
         const BlockDesc d = a.blocks.get(bi);
-        const int64_t base = int64_t(g - d.seg0) * a.V;
+        const int64_t base = int64_t(a.blocks.segment(g, d)) * a.V;
         float2* Xg = a.X + size_t(g) * size_t(a.M);
         float xs = 1.0f;
         if constexpr (PREC != ACQ_FP32)
@@ -267,7 +268,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
     const int bi = a.blocks.block_of_segment(g);
     const BlockDesc d = a.blocks.get(bi);
-    const int j = g - d.seg0;
+    const int j = a.blocks.segment(g, d);
     const double* parts = a.parts + size_t(bi) * kPowerParts;
     unsigned long long* keys = a.keys + size_t(bi) * a.T;
 
@@ -402,15 +403,21 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
 // ------------------------------------------------------------------ refine
 constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
 
-// grid = max_blocks * T: one workgroup per (block, tag)
-__global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
+// grid = max_blocks * T: one workgroup of NT threads per (block, tag).  WMAX
+// bounds the window W = 2R + 3 (3 for the FP32 plans' R = 1, with 1024
+// threads; kMaxWin with 256 threads, whose register budget holds the 3*WMAX
+// FP64 accumulators).  The mix exp(-j 2 pi m_k i / M) is an FP64 table entry at
+// (m_k i) mod M (M a power of two, so the reduction is exact).
+template <int WMAX, int NT>
+__global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
+    constexpr int NW = NT / 64;
     const int bi = int(blockIdx.x) / a.T, tag = int(blockIdx.x) % a.T;
     if (bi >= a.blocks.nblocks()) return;
     const BlockDesc d = a.blocks.get(bi);
     const size_t slot = size_t(bi) * a.T + tag;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     __shared__ double s_px;
-    __shared__ double red[4][kMaxWin][3];
+    __shared__ double red[NW][WMAX][3];
     __shared__ long long s_center;
     __shared__ int s_again;
 
@@ -426,30 +433,28 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
     const int R = a.radius;
     const int W = 2 * R + 3;
     const int64_t mrot = a.rot_signed[k];
+    const int64_t mmask = int64_t(a.M) - 1;
     const int8_t* ch = a.chips + size_t(tag) * size_t(a.C);
 
     for (int pass = 0; pass < 2; ++pass) {
         const int64_t lam0 = center - R - 1;
-        double cr[kMaxWin], ci[kMaxWin], en[kMaxWin];
+        double cr[WMAX], ci[WMAX], en[WMAX];
 #pragma unroll
-        for (int w = 0; w < kMaxWin; ++w) cr[w] = ci[w] = en[w] = 0.0;
-        for (int64_t e = t; e < a.L + W - 1; e += 256) {
+        for (int w = 0; w < WMAX; ++w) cr[w] = ci[w] = en[w] = 0.0;
+        for (int64_t e = t; e < a.L + W - 1; e += NT) {
             const int64_t i = lam0 + e;
             if (i < 0 || i >= d.n) continue;
             const float2 xv = d.x[i];
             const double xr = xv.x, xi = xv.y;
-            int64_t ph = (mrot * i) % a.M;
-            if (ph < 0) ph += a.M;
-            double sn, cs;
-            sincospi(2.0 * double(ph) / double(a.M), &sn, &cs);
-            const double mr = xr * cs + xi * sn;      // x * exp(-j 2 pi m i / M)
-            const double mi = xi * cs - xr * sn;
+            const double2 cs = a.roots64[(mrot * i) & mmask];
+            const double mr = xr * cs.x + xi * cs.y;      // x * exp(-j 2 pi m i / M)
+            const double mi = xi * cs.x - xr * cs.y;
             const double pw = xr * xr + xi * xi;
 #pragma unroll
-            for (int w = 0; w < kMaxWin; ++w) {
+            for (int w = 0; w < WMAX; ++w) {
                 const int64_t nn = e - w;
                 if (w < W && nn >= 0 && nn < a.L) {
-                    const double sg = double(ch[nn / a.spc]);
+                    const double sg = double(ch[nn >> a.log2_spc]);
                     cr[w] += mr * sg;
                     ci[w] += mi * sg;
                     en[w] += pw;
@@ -457,9 +462,9 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
             }
         }
 #pragma unroll
-        for (int w = 0; w < kMaxWin; ++w) {
+        for (int w = 0; w < WMAX; ++w) {
             const double r0 = wave_sum(cr[w]), r1 = wave_sum(ci[w]), r2 = wave_sum(en[w]);
-            if (lane == 0 && w < W) {
+            if (lane == 0) {
                 red[wave][w][0] = r0;
                 red[wave][w][1] = r1;
                 red[wave][w][2] = r2;
@@ -467,11 +472,15 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a) {
         }
         __syncthreads();
         if (t == 0) {
-            double P[kMaxWin], E[kMaxWin];
+            double P[WMAX], E[WMAX];
             for (int w = 0; w < W; ++w) {
-                const double re = (red[0][w][0] + red[1][w][0]) + (red[2][w][0] + red[3][w][0]);
-                const double im = (red[0][w][1] + red[1][w][1]) + (red[2][w][1] + red[3][w][1]);
-                E[w] = (red[0][w][2] + red[1][w][2]) + (red[2][w][2] + red[3][w][2]);
+                double re = 0.0, im = 0.0, en2 = 0.0;
+                for (int q = 0; q < NW; ++q) {
+                    re += red[q][w][0];
+                    im += red[q][w][1];
+                    en2 += red[q][w][2];
+                }
+                E[w] = en2;
                 const int64_t lam = lam0 + w;
                 P[w] = (lam >= 0 && lam < d.lags) ? re * re + im * im : -1.0;
             }
@@ -652,8 +661,12 @@ hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec,
 }
 
 hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
-    if (a.radius < 0 || a.radius > kMaxRefineRadius) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_refine, dim3(unsigned(max_blocks) * a.T), dim3(256), 0, st, a);
+    if (a.radius < 0 || a.radius > kMaxRefineRadius || (a.M & (a.M - 1)) || (1 << a.log2_spc) != a.spc)
+        return hipErrorInvalidValue;
+    if (a.radius <= 1)
+        hipLaunchKernelGGL((k_refine<3, 1024>), dim3(unsigned(max_blocks) * a.T), dim3(1024), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_refine<kMaxWin, 256>), dim3(unsigned(max_blocks) * a.T), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,797 @@
+// Kernels of the proposal stage (declarations and conventions in learned.h).
+//
+//   k_stft            256-point Hann-windowed FFT per frame (hop 128), one wave per
+//                     frame, radix-4 Stockham passes exchanged through LDS; the
+//                     samples come from a device block or from the synthetic
+//                     generator (so training blocks never touch HBM)
+//   k_hist/k_select   exact lower median of a block's F*256 powers: radix
+//                     selection over the FP32 bit patterns (11 + 10 + 10 bits)
+//   k_map             ln(P / median), stored bf16 (or FP32)
+//   k_conv_*_mfma     dilated conv layers as implicit GEMMs on bf16 MFMA
+//                     (v_mfma_f32_16x16x16_bf16, FP32 accumulation): forward,
+//                     input gradient, weight gradient
+//   k_conv_*_ref      the same products in FP32 FMA, one output per thread
+//                     (reference arithmetic for tests)
+//   k_head            1x1 head, weighted BCE with logits and its gradient
+//   k_adam            Adam update of the FP32 master weights, refreshing the
+//                     bf16 copies in both operand layouts
+//   k_window/k_propose window scores, local maxima, top-k and the segment list
+#include <hip/hip_runtime.h>
+#include <cfloat>
+
+#include "device_fft.h"
+#include "learned.h"
+
+namespace acq {
+namespace learned {
+
+NetLayout net_layout(int cin0) {
+    NetLayout l{};
+    int64_t off = 0, bf = 0;
+    for (int i = 0; i < kLayers; ++i) {
+        l.cin[i] = i == 0 ? cin0 : kCh;
+        l.w_off[i] = off;
+        off += int64_t(kTaps) * l.cin[i] * kCh;
+        l.b_off[i] = off;
+        off += kCh;
+        l.bf_off[i] = bf;
+        bf += int64_t(kTaps) * l.cin[i] * kCh;
+    }
+    l.wh_off = off;
+    off += kCh;
+    l.bh_off = off;
+    off += 1;
+    l.total = off;
+    l.bf_total = bf;
+    return l;
+}
+
+namespace {
+
+using dev::cmul;
+using bf16x4 = __attribute__((ext_vector_type(4))) short;
+using f32x4 = __attribute__((ext_vector_type(4))) float;
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);   // nearest even (finite inputs)
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// ------------------------------------------------------------------ generator
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).
+struct P4 {
+    uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ P4 philox10(P4 x, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = uint64_t(0xD2511F53u) * x.a;
+        const uint64_t p1 = uint64_t(0xCD9E8D57u) * x.c;
+        x = P4{uint32_t(p1 >> 32) ^ x.b ^ k0, uint32_t(p1), uint32_t(p0 >> 32) ^ x.d ^ k1, uint32_t(p0)};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return x;
+}
+
+// Sample n of synthetic block b: CN(0,1) noise (Box-Muller on two 24-bit
+// uniforms) plus every transmission covering n.
+__device__ float2 synth_sample(const BlockSource& s, int b, int64_t n) {
+    const int64_t blk = s.block0 + b;
+    const P4 r = philox10(P4{uint32_t(n), uint32_t(n >> 32), uint32_t(blk), uint32_t(blk >> 32) ^ 0x4E4F4953u},
+                          s.seed_lo, s.seed_hi);
+    const float u1 = (float(r.a >> 8) + 0.5f) * (1.0f / 16777216.0f);     // (0, 1)
+    const float u2 = float(r.b >> 8) * (1.0f / 16777216.0f);              // [0, 1)
+    const float rad = sqrtf(-logf(u1));                                   // sqrt(-2 ln u1) / sqrt(2)
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    float2 v = make_float2(rad * cs, rad * sn);
+    const int nt = s.ntx[b];
+    for (int t = 0; t < nt; ++t) {
+        const SynthTx tx = s.tx[int64_t(b) * kMaxTx + t];
+        const int64_t m = n - tx.delay;
+        if (m < 0 || m >= s.chip_len) continue;
+        const int64_t c = m / s.spc;
+        const P4 q = philox10(P4{uint32_t(c >> 7), tx.code, uint32_t(blk), 0x43484950u}, s.seed_lo, s.seed_hi);
+        const int w = int(c & 127);
+        const uint32_t word = w < 32 ? q.a : w < 64 ? q.b : w < 96 ? q.c : q.d;
+        const float chip = ((word >> (w & 31)) & 1u) ? 1.0f : -1.0f;
+        double ph = tx.cycles_per_sample * double(n) + double(tx.phase0);
+        ph -= floor(ph);
+        float s2, c2;
+        sincospif(2.0f * float(ph), &s2, &c2);
+        v.x = fmaf(tx.amp * chip, c2, v.x);
+        v.y = fmaf(tx.amp * chip, s2, v.y);
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ STFT
+// Wave w of workgroup g transforms row 4g + w.  Lane l holds elements
+// l + 64 r (r < 4) before and after each radix-4 pass (Stockham: pass with
+// sub-transform length Ns reads a[j + 64 r], twiddles input r by
+// exp(-j 2 pi r (j mod Ns) / (4 Ns)), and writes output r to
+// (j / Ns) 4 Ns + (j mod Ns) + r Ns).
+__global__ __launch_bounds__(256) void k_stft(BlockSource src, int nblocks, int64_t F, const float* __restrict__ hann,
+                                              const float2* __restrict__ tw, float* __restrict__ P) {
+    __shared__ float2 buf[4][kWin];
+    __shared__ float2 stw[kWin];
+    __shared__ float swin[kWin];
+    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    stw[tid] = tw[tid];
+    swin[tid] = hann[tid];
+    __syncthreads();
+    const int64_t total = int64_t(nblocks) * F;
+    const int64_t row = int64_t(blockIdx.x) * 4 + wave;
+    const bool live = row < total;
+    const int64_t rr = live ? row : total - 1;
+    const int b = int(rr / F);
+    const int64_t f = rr - int64_t(b) * F;
+    float2 a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = lane + 64 * r;
+        const int64_t n = f * kHop + j;
+        const float2 x = src.x ? src.x[int64_t(b) * src.stride + n] : synth_sample(src, b, n);
+        a[r] = make_float2(x.x * swin[j], x.y * swin[j]);
+    }
+    float2* X = buf[wave];
+#pragma unroll
+    for (int Ns = 1; Ns < kWin; Ns *= 4) {
+        const int k = lane & (Ns - 1);
+        const int step = 64 / Ns;
+#pragma unroll
+        for (int r = 1; r < 4; ++r) a[r] = cmul(a[r], stw[(r * k * step) & (kWin - 1)]);
+        dev::dft4<-1>(a[0], a[1], a[2], a[3]);
+        if (Ns < 64) {
+            const int o = (lane / Ns) * Ns * 4 + k;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[o + r * Ns] = a[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = X[lane + 64 * r];
+            __syncthreads();
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[row * kWin + lane + 64 * r] = fmaf(a[r].x, a[r].x, a[r].y * a[r].y);
+    }
+}
+
+// ------------------------------------------------------------------ median
+__global__ void k_median_init(MedianState* st, int nblocks, uint32_t rank) {
+    const int b = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b < nblocks) st[b] = MedianState{0u, rank};
+}
+
+// pass 0: digit = bits[30:20]; pass 1: bits[19:10] of values whose bits[30:20]
+// equal the prefix; pass 2: bits[9:0] of values whose bits[30:10] match.
+__global__ __launch_bounds__(256) void k_hist(const float* __restrict__ P, int64_t per_block, int pass,
+                                              const MedianState* __restrict__ st, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[2048];
+    for (int i = int(threadIdx.x); i < 2048; i += 256) h[i] = 0u;
+    __syncthreads();
+    const int b = int(blockIdx.y);
+    const uint32_t prefix = st[b].prefix;
+    const float* p = P + int64_t(b) * per_block;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < per_block; i += int64_t(gridDim.x) * 256) {
+        const uint32_t u = __float_as_uint(p[i]);
+        uint32_t digit;
+        bool match;
+        if (pass == 0) {
+            digit = u >> 20;
+            match = true;
+        } else if (pass == 1) {
+            digit = (u >> 10) & 1023u;
+            match = (u >> 20) == prefix;
+        } else {
+            digit = u & 1023u;
+            match = (u >> 10) == prefix;
+        }
+        if (match) atomicAdd(&h[digit], 1u);
+    }
+    __syncthreads();
+    for (int i = int(threadIdx.x); i < 2048; i += 256)
+        if (h[i]) atomicAdd(&hist[int64_t(b) * 2048 + i], h[i]);
+}
+
+// One workgroup per block: find the bucket holding the wanted rank, extend the
+// prefix, and clear the histogram for the next pass.
+__global__ __launch_bounds__(256) void k_select(uint32_t* __restrict__ hist, int pass, MedianState* __restrict__ st,
+                                                float* __restrict__ med) {
+    __shared__ uint32_t part[256];
+    const int b = int(blockIdx.x), t = int(threadIdx.x);
+    const MedianState s = st[b];
+    uint32_t* h = hist + int64_t(b) * 2048;
+    const int per = pass == 0 ? 8 : 4;
+    uint32_t local[8];
+    uint32_t sum = 0;
+    for (int q = 0; q < per; ++q) {
+        local[q] = h[t * per + q];
+        sum += local[q];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const uint32_t incl = part[t], excl = incl - sum;
+    if (s.rank >= excl && s.rank < incl) {
+        uint32_t c = excl, digit = 0, rank = 0;
+        for (int q = 0; q < per; ++q) {
+            if (s.rank < c + local[q]) {
+                digit = uint32_t(t * per + q);
+                rank = s.rank - c;
+                break;
+            }
+            c += local[q];
+        }
+        const uint32_t prefix = pass == 0 ? digit : (s.prefix << 10) | digit;
+        st[b] = MedianState{prefix, rank};
+        if (pass == 2) med[b] = __uint_as_float(prefix);
+    }
+    for (int q = 0; q < per; ++q) h[t * per + q] = 0u;
+}
+
+template <bool BF>
+__global__ void k_map(const float* __restrict__ P, int64_t per_block, int64_t total, const float* __restrict__ med,
+                      void* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const float m = med[i / per_block];
+    const float v = m > 0.0f ? logf(fmaxf(P[i], FLT_MIN) / m) : 0.0f;
+    if constexpr (BF)
+        static_cast<uint16_t*>(out)[i] = to_bf16(v);
+    else
+        static_cast<float*>(out)[i] = v;
+}
+
+__global__ void k_synth(BlockSource src, int64_t n, float2* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = synth_sample(src, 0, i);
+}
+
+// 1 when at least half of the frame lies inside some transmission.
+__global__ void k_labels(const SynthTx* __restrict__ tx, const int32_t* __restrict__ ntx, int64_t rows, int64_t F,
+                         int L, float* __restrict__ labels) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const int b = int(r / F);
+    const int64_t f0 = (r - int64_t(b) * F) * kHop;
+    const int nt = ntx[b];
+    int covered = 0;
+    for (int j = 0; j < kWin; ++j) {
+        const int64_t n = f0 + j;
+        bool in = false;
+        for (int t = 0; t < nt && !in; ++t) {
+            const int64_t d = tx[int64_t(b) * kMaxTx + t].delay;
+            in = n >= d && n < d + L;
+        }
+        covered += in;
+    }
+    labels[r] = covered >= kWin / 2 ? 1.0f : 0.0f;
+}
+
+// ------------------------------------------------------------------ conv (MFMA)
+// v_mfma_f32_16x16x16_bf16 operand layout, lane l: A[row l%16][k 4(l/16)+e],
+// B[k 4(l/16)+e][col l%16], D[row 4(l/16)+e][col l%16], e < 4.
+//
+// Forward / input gradient share one shape: out[r][n] (n < 64) =
+// sum_i sum_k A(r, i, k) Bt[i][n][k], A(r, i, k) = src[r + sgn d (i-2)][k] (zero
+// outside r's block).  A workgroup computes 64 rows x 64 columns; wave w rows
+// 16w .. 16w+15 as four 16x16 tiles.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_conv_mfma(const void* __restrict__ src, const uint16_t* __restrict__ H,
+                                                   int K, const uint16_t* __restrict__ Bt,
+                                                   const float* __restrict__ bias, void* __restrict__ out,
+                                                   int64_t rows, int64_t F, int d) {
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const int64_t r0 = int64_t(blockIdx.x) * 64 + wave * 16;
+    const int64_t ar = r0 + (lane & 15);
+    const int kq = 4 * (lane >> 4);
+    const int sgn = FWD ? 1 : -1;
+    const int64_t blk = ar / F, f = ar - blk * F;
+    f32x4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < kTaps; ++i) {
+        const int64_t fs = f + int64_t(sgn) * d * (i - 2);
+        const bool ok = ar < rows && fs >= 0 && fs < F;
+        const int64_t srow = blk * F + fs;
+        const uint16_t* brow = Bt + (int64_t(i) * kCh + (lane & 15)) * K;
+        for (int kc = 0; kc < K; kc += 16) {
+            bf16x4 a = bf16x4{0, 0, 0, 0};
+            if (ok) {
+                if constexpr (FWD) {
+                    a = *reinterpret_cast<const bf16x4*>(static_cast<const uint16_t*>(src) + srow * K + kc + kq);
+                } else {
+                    const float4 g = *reinterpret_cast<const float4*>(static_cast<const float*>(src) + srow * kCh + kc + kq);
+                    const uint2 hb = *reinterpret_cast<const uint2*>(H + srow * kCh + kc + kq);
+                    // dA = dH where the layer output is positive
+                    const float g0 = (hb.x & 0x7fffu) && !(hb.x & 0x8000u) ? g.x : 0.f;
+                    const float g1 = (hb.x & 0x7fff0000u) && !(hb.x & 0x80000000u) ? g.y : 0.f;
+                    const float g2 = (hb.y & 0x7fffu) && !(hb.y & 0x8000u) ? g.z : 0.f;
+                    const float g3 = (hb.y & 0x7fff0000u) && !(hb.y & 0x80000000u) ? g.w : 0.f;
+                    a = bf16x4{short(to_bf16(g0)), short(to_bf16(g1)), short(to_bf16(g2)), short(to_bf16(g3))};
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x4 bb = *reinterpret_cast<const bf16x4*>(brow + int64_t(nt) * 16 * K + kc + kq);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int n = nt * 16 + (lane & 15);
+        const float bn = FWD ? bias[n] : 0.0f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t row = r0 + 4 * (lane >> 4) + e;
+            if (row >= rows) continue;
+            if constexpr (FWD)
+                static_cast<uint16_t*>(out)[row * kCh + n] = to_bf16(fmaxf(acc[nt][e] + bn, 0.0f));
+            else
+                static_cast<float*>(out)[row * kCh + n] = acc[nt][e];
+        }
+    }
+}
+
+// Weight gradient of one tap and 64 input channels over 256 rows:
+// dW[i][c][o] += sum_r in[r + d(i-2)][c] dA[r][o].  The row chunk is staged in
+// LDS transposed ([channel][row]) so both MFMA operands are 8-byte reads.
+constexpr int kDwRows = 256;
+constexpr int kDwPitch = 72;   // 64 rows + 8 pad (bf16)
+
+__global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict__ in, int cin,
+                                                      const float* __restrict__ dH, const uint16_t* __restrict__ H,
+                                                      float* __restrict__ dW, int64_t rows, int64_t F, int d) {
+    __shared__ __align__(16) uint16_t sA[64 * kDwPitch];
+    __shared__ __align__(16) uint16_t sD[64 * kDwPitch];
+    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    const int i = int(blockIdx.y) % kTaps, c0 = (int(blockIdx.y) / kTaps) * 64;
+    const int kq = 4 * (lane >> 4);
+    f32x4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int sub = 0; sub < kDwRows; sub += 64) {
+        const int64_t rbase = int64_t(blockIdx.x) * kDwRows + sub;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int idx = e * 256 + tid;
+            const int rr = idx >> 6, c = idx & 63;
+            const int64_t r = rbase + rr;
+            uint16_t av = 0, dv = 0;
+            if (r < rows) {
+                const int64_t blk = r / F, f = r - blk * F, fs = f + int64_t(d) * (i - 2);
+                if (fs >= 0 && fs < F) av = in[(blk * F + fs) * cin + c0 + c];
+                const uint16_t hv = H[r * kCh + c];
+                if (hv && !(hv & 0x8000u)) dv = to_bf16(dH[r * kCh + c]);
+            }
+            sA[c * kDwPitch + rr] = av;
+            sD[c * kDwPitch + rr] = dv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 64; ks += 16) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&sA[(wave * 16 + (lane & 15)) * kDwPitch + ks + kq]);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sD[(nt * 16 + (lane & 15)) * kDwPitch + ks + kq]);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = c0 + wave * 16 + 4 * (lane >> 4) + e;
+            atomicAdd(&dW[(int64_t(i) * cin + c) * kCh + nt * 16 + (lane & 15)], acc[nt][e]);
+        }
+}
+
+// ------------------------------------------------------------------ conv (FP32 reference)
+// out[r][o] = relu(b[o] + sum_i sum_c W[i][c][o] in[r + d(i-2)][c]), W FP32 [5][cin][64].
+__global__ void k_conv_fwd_ref(const float* __restrict__ in, int cin, const float* __restrict__ W,
+                               const float* __restrict__ bias, float* __restrict__ out, int64_t rows, int64_t F,
+                               int d) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= rows * kCh) return;
+    const int64_t r = t / kCh;
+    const int o = int(t % kCh);
+    const int64_t blk = r / F, f = r - blk * F;
+    float acc = bias[o];
+    for (int i = 0; i < kTaps; ++i) {
+        const int64_t fs = f + int64_t(d) * (i - 2);
+        if (fs < 0 || fs >= F) continue;
+        const float* a = in + (blk * F + fs) * cin;
+        for (int c = 0; c < cin; ++c) acc = fmaf(a[c], W[(int64_t(i) * cin + c) * kCh + o], acc);
+    }
+    out[t] = fmaxf(acc, 0.0f);
+}
+
+__global__ void k_conv_dinput_ref(const float* __restrict__ dH, const float* __restrict__ H,
+                                  const float* __restrict__ W, float* __restrict__ dprev, int64_t rows, int64_t F,
+                                  int d) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= rows * kCh) return;
+    const int64_t r = t / kCh;
+    const int c = int(t % kCh);
+    const int64_t blk = r / F, f = r - blk * F;
+    float acc = 0.0f;
+    for (int i = 0; i < kTaps; ++i) {
+        const int64_t fs = f - int64_t(d) * (i - 2);
+        if (fs < 0 || fs >= F) continue;
+        const int64_t sr = blk * F + fs;
+        for (int o = 0; o < kCh; ++o) {
+            const float g = H[sr * kCh + o] > 0.0f ? dH[sr * kCh + o] : 0.0f;
+            acc = fmaf(W[(int64_t(i) * kCh + c) * kCh + o], g, acc);
+        }
+    }
+    dprev[t] = acc;
+}
+
+// thread per (i, c, o); the first kCh threads of each tap also form db
+__global__ void k_conv_dw_ref(const float* __restrict__ in, int cin, const float* __restrict__ dH,
+                              const float* __restrict__ H, float* __restrict__ dW, float* __restrict__ db,
+                              int64_t rows, int64_t F, int d) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(kTaps) * cin * kCh) return;
+    const int o = int(t % kCh);
+    const int c = int((t / kCh) % cin);
+    const int i = int(t / (int64_t(kCh) * cin));
+    float acc = 0.0f, bacc = 0.0f;
+    for (int64_t r = 0; r < rows; ++r) {
+        const float g = H[r * kCh + o] > 0.0f ? dH[r * kCh + o] : 0.0f;
+        bacc += g;
+        const int64_t blk = r / F, f = r - blk * F, fs = f + int64_t(d) * (i - 2);
+        if (fs < 0 || fs >= F) continue;
+        acc = fmaf(in[(blk * F + fs) * cin + c], g, acc);
+    }
+    dW[t] += acc;
+    if (i == 0 && c == 0) db[o] += bacc;
+}
+
+// db[o] += sum_r dA[r][o] (bf16 activations)
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dH, const uint16_t* __restrict__ H,
+                                                float* __restrict__ db, int64_t rows) {
+    __shared__ float s[256];
+    const int t = int(threadIdx.x), o = t & 63, part = t >> 6;
+    float acc = 0.0f;
+    const int64_t r0 = int64_t(blockIdx.x) * 1024;
+    for (int64_t r = r0 + part; r < r0 + 1024 && r < rows; r += 4) {
+        const uint16_t hv = H[r * kCh + o];
+        if (hv && !(hv & 0x8000u)) acc += dH[r * kCh + o];
+    }
+    s[t] = acc;
+    __syncthreads();
+    if (t < 64) atomicAdd(&db[o], s[t] + s[t + 64] + s[t + 128] + s[t + 192]);
+}
+
+// ------------------------------------------------------------------ head and loss
+__device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+
+template <bool BF>
+__global__ __launch_bounds__(256) void k_head(const void* __restrict__ h4, const float* __restrict__ theta,
+                                              int64_t wh_off, float* __restrict__ y, const float* __restrict__ labels,
+                                              float pw, float inv_rows, float* __restrict__ dH4,
+                                              float* __restrict__ grad, float* __restrict__ loss_sum, int64_t rows) {
+    __shared__ float swh[kCh];
+    __shared__ float sdw[kCh];
+    __shared__ float sred[2][256];
+    const int t = int(threadIdx.x);
+    if (t < kCh) {
+        swh[t] = theta[wh_off + t];
+        sdw[t] = 0.0f;
+    }
+    __syncthreads();
+    const int64_t r = int64_t(blockIdx.x) * 256 + t;
+    const bool ok = r < rows;
+    float h[kCh];
+    float z = theta[wh_off + kCh];
+#pragma unroll
+    for (int o = 0; o < kCh; ++o) {
+        if constexpr (BF)
+            h[o] = ok ? from_bf16(static_cast<const uint16_t*>(h4)[r * kCh + o]) : 0.0f;
+        else
+            h[o] = ok ? static_cast<const float*>(h4)[r * kCh + o] : 0.0f;
+        z = fmaf(h[o], swh[o], z);
+    }
+    if (ok) y[r] = z;
+    if (!labels) return;   // uniform: inference
+    float dz = 0.0f, loss = 0.0f;
+    if (ok) {
+        const float lab = labels[r];
+        const float s = 1.0f / (1.0f + expf(-z));
+        loss = pw * lab * softplus(-z) + (1.0f - lab) * softplus(z);
+        dz = (pw * lab * (s - 1.0f) + (1.0f - lab) * s) * inv_rows;
+#pragma unroll
+        for (int o = 0; o < kCh; ++o) dH4[r * kCh + o] = dz * swh[o];
+#pragma unroll
+        for (int o = 0; o < kCh; ++o) atomicAdd(&sdw[o], dz * h[o]);
+    }
+    sred[0][t] = dz;
+    sred[1][t] = loss;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            sred[0][t] += sred[0][t + off];
+            sred[1][t] += sred[1][t + off];
+        }
+        __syncthreads();
+    }
+    if (t < kCh) atomicAdd(&grad[wh_off + t], sdw[t]);
+    if (t == 0) {
+        atomicAdd(&grad[wh_off + kCh], sred[0][0]);
+        atomicAdd(loss_sum, sred[1][0]);
+    }
+}
+
+// ------------------------------------------------------------------ Adam
+__global__ void k_adam(float* __restrict__ theta, float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       NetLayout lay, uint16_t* __restrict__ w_bf, uint16_t* __restrict__ wt_bf, int update) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    float th = theta[p];
+    if (update) {
+        const float g = grad[p];
+        const float mm = b1 * m[p] + (1.0f - b1) * g;
+        const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+        m[p] = mm;
+        v[p] = vv;
+        th -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+        theta[p] = th;
+        grad[p] = 0.0f;
+    }
+    if (!w_bf) return;
+    for (int l = 0; l < kLayers; ++l) {
+        const int64_t q = p - lay.w_off[l];
+        const int cin = lay.cin[l];
+        if (q < 0 || q >= int64_t(kTaps) * cin * kCh) continue;
+        const int64_t i = q / (int64_t(cin) * kCh), rem = q % (int64_t(cin) * kCh);
+        const int64_t c = rem / kCh, o = rem % kCh;
+        const uint16_t hb = to_bf16(th);
+        w_bf[lay.bf_off[l] + q] = hb;
+        wt_bf[lay.bf_off[l] + (i * kCh + o) * cin + c] = hb;
+    }
+}
+
+__global__ void k_fill_f32(float* p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+__global__ void k_fill_u32(uint32_t* p, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ proposals
+__global__ void k_window(const float* __restrict__ y, int64_t F, float* __restrict__ c) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    float acc = 0.0f;
+    for (int i = -(kSpan / 2 - 1); i <= kSpan / 2; ++i) {
+        const int64_t g = f + i;
+        if (g >= 0 && g < F) acc += y[g];
+    }
+    c[f] = acc;
+}
+
+constexpr int kMaxCand = 2048;
+constexpr int kMaxSegList = 4096;
+
+// One workgroup: candidates (local maxima over +/-64 frames, ties to the
+// smaller frame) at or above kappa; their rank by (score desc, frame asc);
+// the kmax best propose lag ranges [128f + 256 - L, 128f] within [0, n-L];
+// segments meeting a range are listed in ascending order.
+__global__ __launch_bounds__(1024) void k_propose(const float* __restrict__ c, int64_t F, float kappa, int kmax,
+                                                  int64_t n, int64_t L, int64_t V, int32_t max_segments,
+                                                  int32_t* __restrict__ frames, int32_t* __restrict__ segs,
+                                                  int32_t* __restrict__ info) {
+    __shared__ int cf[kMaxCand];
+    __shared__ float cv[kMaxCand];
+    __shared__ unsigned char mask[kMaxSegList];
+    __shared__ int ncand;
+    const int t = int(threadIdx.x);
+    if (t == 0) ncand = 0;
+    for (int j = t; j < kMaxSegList; j += 1024) mask[j] = 0;
+    __syncthreads();
+    for (int64_t f = t; f < F; f += 1024) {
+        const float v = c[f];
+        if (!(v >= kappa)) continue;
+        bool is_max = true;
+        const int64_t a = f - kNms < 0 ? 0 : f - kNms, b = f + kNms >= F ? F - 1 : f + kNms;
+        for (int64_t g = a; g <= b && is_max; ++g) {
+            if (g < f) is_max = c[g] < v;
+            else if (g > f) is_max = c[g] <= v;
+        }
+        if (is_max) {
+            const int idx = atomicAdd(&ncand, 1);
+            if (idx < kMaxCand) {
+                cf[idx] = int(f);
+                cv[idx] = v;
+            }
+        }
+    }
+    __syncthreads();
+    const int nc = ncand < kMaxCand ? ncand : kMaxCand;
+    const int64_t lags = n - L + 1;
+    for (int q = t; q < nc; q += 1024) {
+        int rank = 0;
+        for (int p = 0; p < nc; ++p) rank += (cv[p] > cv[q]) || (cv[p] == cv[q] && cf[p] < cf[q]);
+        if (rank >= kmax) continue;
+        frames[rank] = cf[q];
+        const int64_t lo = int64_t(kHop) * cf[q] + kWin - L < 0 ? 0 : int64_t(kHop) * cf[q] + kWin - L;
+        const int64_t hi = int64_t(kHop) * cf[q] < lags - 1 ? int64_t(kHop) * cf[q] : lags - 1;
+        for (int64_t j = lo / V; lo <= hi && j <= hi / V && j < max_segments; ++j) mask[j] = 1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int ns = 0;
+        const int64_t S = (lags + V - 1) / V;
+        for (int64_t j = 0; j < S && j < max_segments; ++j)
+            if (mask[j]) segs[ns++] = int32_t(j);
+        info[0] = nc < kmax ? nc : kmax;
+        info[1] = ns;
+        info[2] = ncand;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+static unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+hipError_t launch_stft(const BlockSource& src, int nblocks, int64_t F, const float* hann, const float2* tw, float* P,
+                       hipStream_t st) {
+    const int64_t rows = int64_t(nblocks) * F;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stft, dim3(blocks_for(rows, 4)), dim3(256), 0, st, src, nblocks, F, hann, tw, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_median(const float* P, int nblocks, int64_t per_block, uint32_t* hist, MedianState* state,
+                         float* med, hipStream_t st) {
+    if (nblocks <= 0 || per_block <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(int64_t(nblocks) * 2048, 256)), dim3(256), 0, st, hist,
+                       int64_t(nblocks) * 2048);
+    hipLaunchKernelGGL(k_median_init, dim3(blocks_for(nblocks, 64)), dim3(64), 0, st, state, nblocks,
+                       uint32_t((per_block - 1) / 2));
+    const unsigned chunks = unsigned(per_block / (256 * 16) + 1 < 512 ? per_block / (256 * 16) + 1 : 512);
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_hist, dim3(chunks, unsigned(nblocks)), dim3(256), 0, st, P, per_block, pass,
+                           (const MedianState*)state, hist);
+        hipLaunchKernelGGL(k_select, dim3(unsigned(nblocks)), dim3(256), 0, st, hist, pass, state, med);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_map(const float* P, int nblocks, int64_t F, const float* med, void* map, bool bf16,
+                      hipStream_t st) {
+    const int64_t per = F * kWin, total = per * nblocks;
+    if (total <= 0) return hipSuccess;
+    if (bf16)
+        hipLaunchKernelGGL(k_map<true>, dim3(blocks_for(total, 256)), dim3(256), 0, st, P, per, total, med, map);
+    else
+        hipLaunchKernelGGL(k_map<false>, dim3(blocks_for(total, 256)), dim3(256), 0, st, P, per, total, med, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_synth(const BlockSource& src, int64_t n, float2* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_synth, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_labels(const SynthTx* tx, const int32_t* ntx, int nblocks, int64_t F, int L, float* labels,
+                         hipStream_t st) {
+    const int64_t rows = int64_t(nblocks) * F;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_labels, dim3(blocks_for(rows, 256)), dim3(256), 0, st, tx, ntx, rows, F, L, labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_forward(const void* in, int cin, const void* w, const float* bias, void* out, int64_t rows,
+                               int64_t F, int d, bool bf16, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    if (bf16) {
+        if (cin % 16) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_conv_mfma<true>, dim3(blocks_for(rows, 64)), dim3(256), 0, st, in,
+                           (const uint16_t*)nullptr, cin, (const uint16_t*)w, bias, out, rows, F, d);
+    } else {
+        hipLaunchKernelGGL(k_conv_fwd_ref, dim3(blocks_for(rows * kCh, 256)), dim3(256), 0, st, (const float*)in,
+                           cin, (const float*)w, bias, (float*)out, rows, F, d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_dinput(const float* dH, const void* H, const void* w, float* dprev, int64_t rows, int64_t F,
+                              int d, bool bf16, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    if (bf16)
+        hipLaunchKernelGGL(k_conv_mfma<false>, dim3(blocks_for(rows, 64)), dim3(256), 0, st, (const void*)dH,
+                           (const uint16_t*)H, kCh, (const uint16_t*)w, (const float*)nullptr, (void*)dprev, rows,
+                           F, d);
+    else
+        hipLaunchKernelGGL(k_conv_dinput_ref, dim3(blocks_for(rows * kCh, 256)), dim3(256), 0, st, dH,
+                           (const float*)H, (const float*)w, dprev, rows, F, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_dweight(const void* in, int cin, const float* dH, const void* H, float* dW, float* db,
+                               int64_t rows, int64_t F, int d, bool bf16, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    if (bf16) {
+        if (cin % 64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_conv_dw_mfma, dim3(blocks_for(rows, kDwRows), unsigned(kTaps * (cin / 64))), dim3(256),
+                           0, st, (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, rows, F, d);
+        hipLaunchKernelGGL(k_colsum, dim3(blocks_for(rows, 1024)), dim3(256), 0, st, dH, (const uint16_t*)H, db,
+                           rows);
+    } else {
+        hipLaunchKernelGGL(k_conv_dw_ref, dim3(blocks_for(int64_t(kTaps) * cin * kCh, 256)), dim3(256), 0, st,
+                           (const float*)in, cin, dH, (const float*)H, dW, db, rows, F, d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_head(const void* h4, const float* theta, int64_t wh_off, float* y, const float* labels,
+                       float pos_weight, float inv_rows, float* dH4, float* grad, float* loss_sum, int64_t rows,
+                       bool bf16, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    if (bf16)
+        hipLaunchKernelGGL(k_head<true>, dim3(blocks_for(rows, 256)), dim3(256), 0, st, h4, theta, wh_off, y, labels,
+                           pos_weight, inv_rows, dH4, grad, loss_sum, rows);
+    else
+        hipLaunchKernelGGL(k_head<false>, dim3(blocks_for(rows, 256)), dim3(256), 0, st, h4, theta, wh_off, y,
+                           labels, pos_weight, inv_rows, dH4, grad, loss_sum, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* theta, float* grad, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, int t, const NetLayout& lay, uint16_t* w_bf, uint16_t* wt_bf, hipStream_t st) {
+    // t = 0: refresh the bf16 copies only
+    const double c1 = t > 0 ? 1.0 / (1.0 - pow(double(b1), t)) : 1.0;
+    const double c2 = t > 0 ? 1.0 / (1.0 - pow(double(b2), t)) : 1.0;
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n, 256)), dim3(256), 0, st, theta, grad, m, v, n, lr, b1, b2, eps,
+                       float(c1), float(c2), lay, w_bf, wt_bf, t > 0 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(const float* y, int64_t F, float* c, hipStream_t st) {
+    if (F <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_window, dim3(blocks_for(F, 256)), dim3(256), 0, st, y, F, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_propose(const float* c, int64_t F, float kappa, int kmax, int64_t n, int64_t L, int64_t V,
+                          int32_t max_segments, int32_t* frames, int32_t* segs, int32_t* out_info, hipStream_t st) {
+    if (max_segments > kMaxSegList || kmax < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_propose, dim3(1), dim3(1024), 0, st, c, F, kappa, kmax, n, L, V, max_segments, frames, segs,
+                       out_info);
+    return hipGetLastError();
+}
+
+}  // namespace learned
+}  // namespace acq

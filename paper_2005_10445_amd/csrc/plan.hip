@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "acq.h"
+#include "cnn_internal.h"
 #include "host_logic.h"
 #include "kernels.h"
 
@@ -40,6 +41,7 @@ struct acq_plan_s {
     float2* d_rect = nullptr;           // [M]
     float2* d_rootsM = nullptr;         // [M]
     float2* d_rootsSub = nullptr;       // [Msub]
+    double2* d_roots64 = nullptr;       // [M] FP64 unit roots (refinement mix)
     float2* d_b1tab = nullptr;          // 2^14-point engine table (or a 1-entry stub)
     int8_t* d_chips = nullptr;          // [T][C]
     int32_t* d_rot = nullptr;           // [K]
@@ -58,6 +60,7 @@ struct acq_plan_s {
     int32_t* h_count = nullptr;         // pinned [1]
     BlockDesc* h_descs = nullptr;       // pinned [blocks]
     int32_t* h_counts = nullptr;        // pinned [2]
+    int32_t* d_seglist = nullptr;       // [max_segments] segments proposed for a learned search
 
     bool profiling = false;
     bool capturing = false;
@@ -99,9 +102,10 @@ void drop_graph(acq_plan_s* p) {
 void free_plan(acq_plan_s* p) {
     if (!p) return;
     drop_graph(p);
-    void* dev[] = {p->d_X, p->d_Xh, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_chips,
+    void* dev[] = {p->d_X, p->d_Xh, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
+                   p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_dets,
-                   p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts};
+                   p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     void* host[] = {p->h_out, p->h_count, p->h_descs, p->h_counts};
@@ -129,6 +133,7 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_rect, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsM, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
+    ACQ_HIP(dalloc(&p->d_roots64, size_t(g.M)));
     const std::vector<float> b1 = g.log2_sub == 14 ? acq::fft14_b1_table() : std::vector<float>(2, 0.f);
     ACQ_HIP(dalloc(&p->d_b1tab, b1.size() / 2));
     ACQ_HIP(dalloc(&p->d_chips, T * C));
@@ -144,6 +149,7 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_counters, size_t(acq::kXcds)));
     ACQ_HIP(dalloc(&p->d_descs, B));
     ACQ_HIP(dalloc(&p->d_counts, 2));
+    ACQ_HIP(dalloc(&p->d_seglist, size_t(g.max_segments > 0 ? g.max_segments : 1)));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_detection) * B * T));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t)));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_descs), sizeof(BlockDesc) * B));
@@ -151,10 +157,12 @@ int build_plan(acq_plan_s* p) {
 
     const std::vector<float> rootsM = acq::unit_roots(g.M);
     const std::vector<float> rootsSub = acq::unit_roots(g.Msub);
+    const std::vector<double> roots64 = acq::unit_roots64(g.M);
     const std::vector<float> rect = acq::rect_spectrum_conj(g.M, c.samples_per_chip);
     hipStream_t st = p->stream;
     ACQ_HIP(hipMemcpyAsync(p->d_rootsM, rootsM.data(), rootsM.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rootsSub, rootsSub.data(), rootsSub.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    ACQ_HIP(hipMemcpyAsync(p->d_roots64, roots64.data(), roots64.size() * sizeof(double), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rect, rect.data(), rect.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_b1tab, b1.data(), b1.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_chips, c.chips, T * C, hipMemcpyHostToDevice, st));
@@ -277,6 +285,8 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ra.C = c.num_chips;
     ra.K = c.num_bins;
     ra.spc = c.samples_per_chip;
+    ra.log2_spc = c.samples_per_chip == 1 ? 0 : c.samples_per_chip == 2 ? 1 : c.samples_per_chip == 4 ? 2 : 3;
+    ra.roots64 = p->d_roots64;
     ra.M = int(g.M);
     ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
     {
@@ -466,6 +476,58 @@ int acq_detect_batch(acq_plan_t p, const void* const* blocks, const int64_t* len
         const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream);
         if (rc != ACQ_OK) return rc;
     }
+    ACQ_HIP(hipStreamSynchronize(p->stream));
+    return deliver(p, out, capacity, n_found);
+}
+
+int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n, const acq_learned_params* lp,
+                       acq_detection* out, int32_t capacity, int32_t* n_found, acq_learned_report* report) {
+    int rc = check_block(p, block, n);
+    if (rc != ACQ_OK) return rc;
+    if (!cnn || !lp || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (lp->max_proposals < 0 || !(lp->max_fraction >= 0.0f))
+        return acq::fail(ACQ_ERR_INVALID_ARG, "bad proposal parameters");
+    *n_found = 0;
+    acq_learned_report rep{};
+    double floor = 0.0;
+    const bool have_floor = acq::cnn_floor(cnn, &floor);
+    rep.floor = float(floor);
+    if (n < p->g.L) {
+        if (report) *report = rep;
+        acq::clear_error();
+        return ACQ_OK;
+    }
+    reset_timers(p);
+    BlockTable bt{};
+    bt.one = single_desc(p, block, n);
+    rep.total_segments = bt.one.nseg;
+    acq::ProposalResult pr{};
+    rc = acq::cnn_propose(cnn, block, n, p->g.L, p->g.V, int32_t(p->g.max_segments), lp->kappa, lp->max_proposals,
+                          p->d_seglist, p->stream, &pr);
+    if (rc != ACQ_OK) return rc;
+    rep.proposals = pr.proposals;
+    rep.median = pr.median;
+    if (double(pr.segments) > double(lp->max_fraction) * double(bt.one.nseg))
+        rep.fallback = ACQ_FALLBACK_FRACTION;
+    else if (lp->floor_db > 0.0f && have_floor && floor > 0.0 && pr.median > 0.0f &&
+             std::fabs(10.0 * std::log10(double(pr.median) / floor)) > double(lp->floor_db))
+        rep.fallback = ACQ_FALLBACK_FLOOR;
+    acq::cnn_update_floor(cnn, double(pr.median));
+    if (rep.fallback == ACQ_FALLBACK_NONE) {
+        rep.segments = pr.segments;
+        bt.one.nseg = pr.segments;
+        bt.seg_of = p->d_seglist;
+    } else {
+        rep.segments = bt.one.nseg;
+    }
+    if (report) *report = rep;
+    if (bt.one.nseg == 0) {
+        acq::clear_error();
+        return ACQ_OK;
+    }
+    rc = enqueue_search(p, bt, false, bt.one.nseg, nullptr, true, p->stream);
+    if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
     return deliver(p, out, capacity, n_found);
 }

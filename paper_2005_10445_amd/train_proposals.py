@@ -1,0 +1,158 @@
+"""Train, calibrate and evaluate the proposal network on the GPU.
+
+Training data are generated on the device (acq_cnn_train_synthetic): blocks
+of the tag-bank workload's shape -- 2^20 samples at 8 Msps, ten BPSK
+transmissions of 8192 chips at 2 samples per chip, per-sample SNR uniform in
+[-15, -5] dB, carrier offsets on the 11-bin grid over +/-5 kHz, integer delays
+-- with CN(0,1) noise.  Only the transmission parameters are drawn on the
+host.  Calibration picks the proposal threshold kappa on held-out blocks so
+that the proposal search keeps a target share of the exhaustive search's
+detections; the exhaustive search is the judge.
+
+    python -m paper_2005_10445_amd.train_proposals train --blocks 200000 --batch 8
+    python -m paper_2005_10445_amd.train_proposals calibrate
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from typing import List, Sequence
+
+import numpy as np
+
+from .proposals import LearnedParams, Network, SynthTransmission, num_params
+
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+WEIGHTS = os.path.join(WEIGHTS_DIR, "proposal_cnn.npy")
+META = os.path.join(WEIGHTS_DIR, "proposal_cnn.json")
+
+FS = 8e6
+BLOCK_LEN = 1 << 20
+CHIPS, SPC = 8192, 2
+N_TX = 10
+SNR_DB = (-15.0, -5.0)
+BINS, BIN_STEP_HZ = 11, 976.5625       # the snapped 1 kHz grid of 16384-sample templates
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def he_init(seed: int, in_channels: int = 256) -> np.ndarray:
+    """He-normal conv and head weights, zero biases, in the library's parameter order."""
+    g = np.random.default_rng(seed)
+    parts, c = [], in_channels
+    for _ in range(4):
+        parts.append(g.normal(0.0, math.sqrt(2.0 / (5 * c)), size=5 * c * 64))
+        parts.append(np.zeros(64))
+        c = 64
+    parts.append(g.normal(0.0, math.sqrt(1.0 / 64), size=64))
+    parts.append(np.zeros(1))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == num_params(in_channels)
+    return p
+
+
+def draw_transmissions(g: np.random.Generator, nblocks: int, n: int = BLOCK_LEN, n_tx: int = N_TX,
+                       snr_db=SNR_DB) -> List[List[SynthTransmission]]:
+    L = CHIPS * SPC
+    out = []
+    for _ in range(nblocks):
+        lst = []
+        for _ in range(n_tx):
+            k = int(g.integers(0, BINS)) - BINS // 2
+            snr = float(g.uniform(*snr_db))
+            lst.append(SynthTransmission(delay=int(g.integers(0, n - L)), freq_over_fs=k * BIN_STEP_HZ / FS,
+                                         amp=10.0 ** (snr / 20.0), phase0=float(g.random()),
+                                         code=int(g.integers(0, 2 ** 32))))
+        out.append(lst)
+    return out
+
+
+def train(blocks: int, batch: int, seed: int, lr: float, lr_final: float, pos_weight: float,
+          init: np.ndarray | None = None, log_every: int = 200):
+    rows = batch * ((BLOCK_LEN - 256) // 128 + 1)
+    net = Network("bf16", 256, max_rows=rows, max_block_len=BLOCK_LEN)
+    net.set_params(he_init(seed) if init is None else init)
+    g = np.random.default_rng(seed)
+    steps = blocks // batch
+    losses = []
+    t0 = time.time()
+    for s in range(steps):
+        # cosine decay from lr to lr_final
+        a = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * s / max(steps - 1, 1)))
+        txs = draw_transmissions(g, batch)
+        losses.append(net.train_synthetic(seed, s * batch, BLOCK_LEN, CHIPS, SPC, txs, pos_weight, a))
+        if (s + 1) % log_every == 0 or s == steps - 1:
+            log(f"[train] step {s + 1}/{steps} blocks {(s + 1) * batch} loss {np.mean(losses[-log_every:]):.4f} "
+                f"lr {a:.2e} {time.time() - t0:.0f} s")
+    return net, losses, time.time() - t0
+
+
+def recall_at(plan, net: Network, blocks, kappa: float, kmax: int, exhaustive=None):
+    """Share of exhaustive detections that the proposal search returns with the same values,
+    and the mean share of segments it searched."""
+    hit = total = 0
+    frac = []
+    fallbacks = 0
+    for i, x in enumerate(blocks):
+        full = exhaustive[i] if exhaustive is not None else plan.detect(x)
+        dets, rep = net.detect(plan, x, LearnedParams(kappa=kappa, max_proposals=kmax, max_fraction=1.0,
+                                                      floor_db=0.0))
+        got = {(d.tag, d.bin, d.lag, d.toa) for d in dets}
+        total += len(full)
+        hit += sum((d.tag, d.bin, d.lag, d.toa) in got for d in full)
+        frac.append(rep.segments / max(rep.total_segments, 1))
+        fallbacks += rep.fallback != 0
+    return (hit / total if total else 1.0), float(np.mean(frac)), fallbacks
+
+
+def calibrate(plan, net: Network, blocks, target: float, kmax: int, lo: float = -2000.0, hi: float = 2000.0,
+              iters: int = 24):
+    """Largest kappa (bisection; recall does not increase with kappa) whose recall >= target."""
+    exhaustive = [plan.detect(x) for x in blocks]
+    r_lo, _, _ = recall_at(plan, net, blocks, lo, kmax, exhaustive)
+    if r_lo < target:
+        return lo, r_lo
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        r, _, _ = recall_at(plan, net, blocks, mid, kmax, exhaustive)
+        if r >= target:
+            lo = mid
+        else:
+            hi = mid
+    r, f, _ = recall_at(plan, net, blocks, lo, kmax, exhaustive)
+    return lo, r
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--blocks", type=int, default=200000)
+    t.add_argument("--batch", type=int, default=8)
+    t.add_argument("--seed", type=int, default=1_000_000)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--lr-final", type=float, default=1e-4)
+    t.add_argument("--pos-weight", type=float, default=4.0)
+    t.add_argument("--out", default=WEIGHTS)
+    args = ap.parse_args(argv)
+    if args.cmd == "train":
+        net, losses, secs = train(args.blocks, args.batch, args.seed, args.lr, args.lr_final, args.pos_weight)
+        os.makedirs(os.path.dirname(args.out), exist_ok=True)
+        np.save(args.out, net.get_params())
+        meta = {"blocks": args.blocks, "batch": args.batch, "seed": args.seed, "lr": args.lr,
+                "lr_final": args.lr_final, "pos_weight": args.pos_weight, "seconds": secs,
+                "loss_first": float(np.mean(losses[:50])), "loss_last": float(np.mean(losses[-50:])),
+                "loss_curve": [float(np.mean(losses[i:i + 500])) for i in range(0, len(losses), 500)]}
+        with open(os.path.splitext(args.out)[0] + ".train.json", "w") as f:
+            json.dump(meta, f, indent=1)
+        log(json.dumps({k: v for k, v in meta.items() if k != "loss_curve"}))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -251,3 +251,8 @@ def test_transmission_covers_its_middle_frame():
         f = (tau + L // 2) // 128 - 1
         r = ol.frame_lag_range(f, n, L)
         assert r is not None and r[0] <= tau <= r[1], tau
+
+
+def test_power_map_of_an_empty_block_is_zero():
+    m, med = ol.power_map(np.zeros(256 + 128 * 3, np.complex64))
+    assert med == 0.0 and m.shape == (4, 256) and not m.any()
