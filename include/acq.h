@@ -190,7 +190,16 @@ int acq_detect_batch(acq_plan_t plan, const void* const* blocks, const int64_t* 
 typedef struct acq_tuning {
     int32_t engine;
     int32_t tag_tile;
+    int32_t batch_launch;       /* ACQ_BATCH_GRID or ACQ_BATCH_PERSISTENT */
 } acq_tuning;
+
+/* Launch forms of the correlation kernel in batched searches.  GRID: one
+ * workgroup per work item, dispatched by the hardware; a graph-captured batch
+ * is sized for the plan's capacity and surplus workgroups exit at once.
+ * PERSISTENT: one workgroup per compute unit pulling work items from per-XCD
+ * atomic counters. */
+#define ACQ_BATCH_GRID       0
+#define ACQ_BATCH_PERSISTENT 1
 
 typedef struct acq_tune_entry {
     acq_tuning tuning;
@@ -203,8 +212,11 @@ int acq_set_tuning(acq_plan_t plan, const acq_tuning* tuning);
 /*
  * Autotune: time every candidate tuning (engines x tag tiles 4..64 that divide
  * the work sensibly) on the device block `block` of n samples, `reps` runs
- * each (HIP events around the correlation kernel), keep the fastest in the
- * plan and write the candidates to host out[0..capacity) (*n_out = count).
+ * each (HIP events around the correlation kernel), then both batch launch
+ * forms with the fastest engine and tile on the same block as a one-block
+ * batch (the last two entries; skipped when n exceeds max_batch_samples).
+ * Keeps the fastest in the plan and writes the candidates to host
+ * out[0..capacity) (*n_out = count).
  */
 int acq_tune(acq_plan_t plan, const void* block, int64_t n, int32_t reps,
              acq_tune_entry* out, int32_t capacity, int32_t* n_out);

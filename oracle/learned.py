@@ -19,6 +19,9 @@ textbook definitions:
   ReLU, then a 1x1 head 64 -> 1 giving one logit per frame:
       h_l[f][o] = relu(b_l[o] + sum_{i<5} sum_c W_l[i][c][o] h_{l-1}[f + d_l (i - 2)][c])
   with h_{l-1} = 0 outside 0 .. F-1.
+* Reduced-precision network.  A bf16 network stores its conv weights and every
+  layer's output rounded to bf16 (nearest, ties to even); biases, the head and
+  all sums stay exact.  Its gradient is the FP64 gradient of that function.
 * Training.  Frame label 1 when at least half of the frame (128 samples) lies
   inside a transmission [D, D + L).  Loss: mean over frames of the binary
   cross-entropy with logits and a positive-class weight,
@@ -53,7 +56,8 @@ DILATIONS = (1, 2, 4, 8)
 __all__ = [
     "WIN", "HOP", "SPAN", "NMS_RADIUS", "CHANNELS", "KERNEL", "DILATIONS",
     "num_frames", "hann", "stft_power", "lower_median", "power_map", "frame_labels",
-    "CNN", "init_cnn", "conv_same", "cnn_forward", "cnn_backward", "bce_with_logits",
+    "CNN", "init_cnn", "conv_same", "cnn_forward", "cnn_backward", "bce_with_logits", "bf16_round",
+    "bf16_network",
     "adam_step", "window_scores", "candidates", "propose", "frame_lag_range", "segments_for_ranges",
 ]
 
@@ -169,11 +173,27 @@ def conv_same(h: np.ndarray, W: np.ndarray, b: np.ndarray, d: int) -> np.ndarray
     return out
 
 
-def cnn_forward(net: CNN, m: np.ndarray):
-    """Logits [F] and the activations needed by the backward pass."""
+def bf16_round(a) -> np.ndarray:
+    """Round to the nearest bf16 value (8-bit significand), ties to even, via the
+    FP32 bit pattern: keep the top 16 bits after adding 0x7fff plus the lowest
+    kept bit.  Finite inputs; returned as FP64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_network(net: CNN) -> CNN:
+    """The network with its conv weights stored in bf16 (biases and head stay FP32-exact)."""
+    return CNN([bf16_round(W) for W in net.W], [b.copy() for b in net.b], net.wh.copy(), net.bh)
+
+
+def cnn_forward(net: CNN, m: np.ndarray, act_round=None):
+    """Logits [F] and the activations needed by the backward pass.  act_round,
+    when given, is applied to every layer's output (bf16 activation storage)."""
     h = [np.asarray(m, np.float64)]
     for l, d in enumerate(DILATIONS):
-        h.append(np.maximum(conv_same(h[-1], net.W[l], net.b[l], d), 0.0))
+        a = np.maximum(conv_same(h[-1], net.W[l], net.b[l], d), 0.0)
+        h.append(act_round(a) if act_round is not None else a)
     y = h[-1] @ net.wh + net.bh
     return y, h
 

@@ -153,10 +153,13 @@ class Plan:
     def tuning(self) -> dict:
         t = _capi.AcqTuning()
         check(self._lib.acq_get_tuning(self._h, ctypes.byref(t)), "acq_get_tuning")
-        return {"engine": t.engine, "tag_tile": t.tag_tile}
+        return {"engine": t.engine, "tag_tile": t.tag_tile, "batch_launch": t.batch_launch}
 
-    def set_tuning(self, engine: int, tag_tile: int):
-        t = _capi.AcqTuning(int(engine), int(tag_tile))
+    def set_tuning(self, engine: int, tag_tile: int, batch_launch: Optional[int] = None):
+        """batch_launch: 0 grid over work items (default), 1 persistent workgroups; None keeps it."""
+        if batch_launch is None:
+            batch_launch = self.tuning["batch_launch"]
+        t = _capi.AcqTuning(int(engine), int(tag_tile), int(batch_launch))
         check(self._lib.acq_set_tuning(self._h, ctypes.byref(t)), "acq_set_tuning")
 
     def tune(self, block, reps: int = 3) -> list:
@@ -166,7 +169,8 @@ class Plan:
         cnt = ctypes.c_int32(0)
         check(self._lib.acq_tune(self._h, ctypes.c_void_p(ptr), n, int(reps), out, 32, ctypes.byref(cnt)),
               "acq_tune")
-        return [{"engine": e.tuning.engine, "tag_tile": e.tuning.tag_tile, "ms": e.ms} for e in out[:cnt.value]]
+        return [{"engine": e.tuning.engine, "tag_tile": e.tuning.tag_tile, "batch_launch": e.tuning.batch_launch,
+                 "ms": e.ms} for e in out[:cnt.value]]
 
     def detect_raw(self, block) -> int:
         """acq_detect without building Python records (for timing); returns the count."""

@@ -91,7 +91,10 @@ class AcqDetection(ctypes.Structure):
 
 
 class AcqTuning(ctypes.Structure):
-    _fields_ = [("engine", ctypes.c_int32), ("tag_tile", ctypes.c_int32)]
+    _fields_ = [("engine", ctypes.c_int32), ("tag_tile", ctypes.c_int32), ("batch_launch", ctypes.c_int32)]
+
+
+ACQ_BATCH_GRID, ACQ_BATCH_PERSISTENT = 0, 1
 
 
 class AcqTuneEntry(ctypes.Structure):

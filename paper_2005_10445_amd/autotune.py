@@ -41,7 +41,7 @@ def tune(plan, sample_block, reps: int = 3, path: Optional[str] = None, force: b
     cache = _load(path)
     if not force and key in cache:
         t = cache[key]
-        plan.set_tuning(t["engine"], t["tag_tile"])
+        plan.set_tuning(t["engine"], t["tag_tile"], t.get("batch_launch", 0))
         return {"key": key, "cached": True, **t}
     table = plan.tune(sample_block, reps=reps)
     best = plan.tuning

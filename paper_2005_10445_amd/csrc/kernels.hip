@@ -392,9 +392,13 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
             correlate_item<E, PREC, false>(a, eng, it, total_seg, lds, extra, red);
         }
     } else {
-        const int per = int(gridDim.x) / kXcds;
-        const int wi = xcd * per + int(blockIdx.x) / kXcds;
-        if (wi >= total) return;
+        // one item per workgroup; the grid may exceed the work (a batch captured
+        // for its capacity): the first ceil(total/8) workgroups of each XCD take
+        // its contiguous range, the rest exit
+        const int per = (total + kXcds - 1) / kXcds;
+        const int q = int(blockIdx.x) / kXcds;
+        const int wi = xcd * per + q;
+        if (q >= per || wi >= total) return;
         eng.init(a.rootsSub, extra);
         correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red);
     }
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
 constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
 
 // grid = max_blocks * T: one workgroup of NT threads per (block, tag).  WMAX
-// bounds the window W = 2R + 3 (3 for the FP32 plans' R = 1, with 1024
+// bounds the window W = 2R + 3 (5 for the FP32 plans' R = 1, with 1024
 // threads; kMaxWin with 256 threads, whose register budget holds the 3*WMAX
 // FP64 accumulators).  The mix exp(-j 2 pi m_k i / M) is an FP64 table entry at
 // (m_k i) mod M (M a power of two, so the reduction is exact).
@@ -432,6 +436,7 @@ __global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
     int64_t center = int64_t(idx / unsigned(a.K));
     const int R = a.radius;
     const int W = 2 * R + 3;
+    if (W > WMAX) return;            // the launcher picks WMAX >= W
     const int64_t mrot = a.rot_signed[k];
     const int64_t mmask = int64_t(a.M) - 1;
     const int8_t* ch = a.chips + size_t(tag) * size_t(a.C);
@@ -664,7 +669,7 @@ hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
     if (a.radius < 0 || a.radius > kMaxRefineRadius || (a.M & (a.M - 1)) || (1 << a.log2_spc) != a.spc)
         return hipErrorInvalidValue;
     if (a.radius <= 1)
-        hipLaunchKernelGGL((k_refine<3, 1024>), dim3(unsigned(max_blocks) * a.T), dim3(1024), 0, st, a);
+        hipLaunchKernelGGL((k_refine<5, 1024>), dim3(unsigned(max_blocks) * a.T), dim3(1024), 0, st, a);
     else
         hipLaunchKernelGGL((k_refine<kMaxWin, 256>), dim3(unsigned(max_blocks) * a.T), dim3(256), 0, st, a);
     return hipGetLastError();

@@ -33,6 +33,7 @@ struct acq_plan_s {
     int cus = 256;                      // compute units (persistent grid size)
     int engine = 0;                     // acq_tuning.engine
     int tile = 16;                      // acq_tuning.tag_tile
+    int batch_launch = ACQ_BATCH_GRID;  // acq_tuning.batch_launch
 
     float2* d_X = nullptr;              // [segments][M] FP32 segment spectra
     void* d_Xh = nullptr;               // [segments][M] 16-bit segment spectra (FP16/BF16 plans)
@@ -255,13 +256,16 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ca.tile = p->tile;
     ca.ntiles = (c.num_tags + p->tile - 1) / p->tile;
     ca.bank_exp = p->bank_exp;
-    ca.persistent = batch ? 1 : 0;
+    ca.persistent = batch && p->batch_launch == ACQ_BATCH_PERSISTENT ? 1 : 0;
     int grid;
-    if (batch) {
+    if (ca.persistent) {
         ACQ_HIP(acq::launch_fill_i32(p->d_counters, acq::kXcds, st));
         grid = p->cus;
     } else {
-        const int64_t nwork = int64_t(ca.ntiles) * total_seg_host * c.num_bins * c.samples_per_chip;
+        // batches captured into a graph size the grid for the plan's capacity;
+        // the kernel reads the real item count from the block table
+        const int64_t segs = batch && p->capturing ? int64_t(g.max_total_segments) : int64_t(total_seg_host);
+        const int64_t nwork = int64_t(ca.ntiles) * segs * c.num_bins * c.samples_per_chip;
         if (nwork >= (int64_t(1) << 31) - 8) return acq::fail(ACQ_ERR_UNSUPPORTED, "too many work items");
         grid = int((nwork + acq::kXcds - 1) / acq::kXcds) * acq::kXcds;
     }
@@ -554,17 +558,21 @@ int acq_get_tuning(acq_plan_t p, acq_tuning* out) {
     if (!p || !out) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
     out->engine = p->engine;
     out->tag_tile = p->tile;
+    out->batch_launch = p->batch_launch;
     return ACQ_OK;
 }
 
 int acq_set_tuning(acq_plan_t p, const acq_tuning* t) {
     if (!p || !t) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
-    if (t->engine < 0 || t->engine > 1 || t->tag_tile < 1 || t->tag_tile > acq::kMaxTagTile)
-        return acq::fail(ACQ_ERR_INVALID_ARG, "engine must be 0 or 1, tag_tile in [1, 64]");
+    if (t->engine < 0 || t->engine > 1 || t->tag_tile < 1 || t->tag_tile > acq::kMaxTagTile ||
+        (t->batch_launch != ACQ_BATCH_GRID && t->batch_launch != ACQ_BATCH_PERSISTENT))
+        return acq::fail(ACQ_ERR_INVALID_ARG, "engine must be 0 or 1, tag_tile in [1, 64], batch_launch 0 or 1");
     const int tile = t->tag_tile < p->cfg.num_tags ? t->tag_tile : p->cfg.num_tags;
-    if (t->engine != p->engine || tile != p->tile) drop_graph(p);   // the captured kernels change
+    if (t->engine != p->engine || tile != p->tile || t->batch_launch != p->batch_launch)
+        drop_graph(p);   // the captured kernels change
     p->engine = t->engine;
     p->tile = tile;
+    p->batch_launch = t->batch_launch;
     return ACQ_OK;
 }
 
@@ -588,30 +596,65 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
             c.tuning.tag_tile = tile;
             cand.push_back(c);
         }
-    const acq_tuning before{p->engine, p->tile};
+    const acq_tuning before{p->engine, p->tile, p->batch_launch};
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
-    size_t best = 0;
-    for (size_t i = 0; i < cand.size(); ++i) {
-        acq_set_tuning(p, &cand[i].tuning);
+    // the same block as a one-block batch (device descriptor table)
+    BlockTable bbt{};
+    bbt.descs = p->d_descs;
+    bbt.counts = p->d_counts;
+    const bool batch_ok = n <= p->g.max_batch_samples;
+    if (batch_ok) {
+        p->h_descs[0] = bt.one;
+        p->h_counts[0] = 1;
+        p->h_counts[1] = bt.one.nseg;
+        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(BlockDesc), hipMemcpyHostToDevice, p->stream));
+        ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+    }
+    auto time_one = [&](const acq_tuning& t, bool batch, double* mean_ms) -> int {
+        acq_set_tuning(p, &t);
         double total = 0.0;
         for (int r = 0; r <= reps; ++r) {           // one warm-up run
             reset_timers(p);
-            rc = enqueue_search(p, bt, false, bt.one.nseg, nullptr, false, p->stream);
-            if (rc != ACQ_OK) {
-                acq_set_tuning(p, &before);
-                acq_set_profiling(p, was_profiling ? 1 : 0);
-                return rc;
-            }
+            const int rc2 = enqueue_search(p, batch ? bbt : bt, batch, bt.one.nseg, nullptr, false, p->stream);
+            if (rc2 != ACQ_OK) return rc2;
             ACQ_HIP(hipStreamSynchronize(p->stream));
             float ms = 0.f;
             ACQ_HIP(hipEventElapsedTime(&ms, p->ev[ACQ_KERNEL_CORRELATE][0], p->ev[ACQ_KERNEL_CORRELATE][1]));
             if (r > 0) total += ms;
         }
-        cand[i].ms = total / reps;
+        *mean_ms = total / reps;
+        return ACQ_OK;
+    };
+    size_t best = 0;
+    for (size_t i = 0; i < cand.size() && rc == ACQ_OK; ++i) {
+        cand[i].tuning.batch_launch = before.batch_launch;
+        rc = time_one(cand[i].tuning, false, &cand[i].ms);
         if (cand[i].ms < cand[best].ms) best = i;
     }
-    acq_set_tuning(p, &cand[best].tuning);
+    // launch form of batches, with the best engine and tile
+    acq_tuning chosen = cand[best].tuning;
+    if (rc == ACQ_OK && batch_ok) {
+        double best_ms = 0.0;
+        for (int form : {ACQ_BATCH_GRID, ACQ_BATCH_PERSISTENT}) {
+            acq_tune_entry c{};
+            c.tuning = cand[best].tuning;
+            c.tuning.batch_launch = form;
+            rc = time_one(c.tuning, true, &c.ms);
+            if (rc != ACQ_OK) break;
+            if (form == ACQ_BATCH_GRID || c.ms < best_ms) {
+                best_ms = c.ms;
+                chosen = c.tuning;
+            }
+            cand.push_back(c);
+        }
+    }
+    if (rc != ACQ_OK) {
+        acq_set_tuning(p, &before);
+        acq_set_profiling(p, was_profiling ? 1 : 0);
+        return rc;
+    }
+    acq_set_tuning(p, &chosen);
     acq_set_profiling(p, was_profiling ? 1 : 0);
     *n_out = int32_t(cand.size());
     for (size_t i = 0; i < cand.size() && int32_t(i) < capacity; ++i) out[i] = cand[i];

@@ -111,7 +111,7 @@ def recall_at(plan, net: Network, blocks, kappa: float, kmax: int, exhaustive=No
     return (hit / total if total else 1.0), float(np.mean(frac)), fallbacks
 
 
-def calibrate(plan, net: Network, blocks, target: float, kmax: int, lo: float = -2000.0, hi: float = 2000.0,
+def calibrate(plan, net: Network, blocks, target: float, kmax: int, lo: float = -5000.0, hi: float = 5000.0,
               iters: int = 24):
     """Largest kappa (bisection; recall does not increase with kappa) whose recall >= target."""
     exhaustive = [plan.detect(x) for x in blocks]
@@ -129,9 +129,120 @@ def calibrate(plan, net: Network, blocks, target: float, kmax: int, lo: float = 
     return lo, r
 
 
+def load_model(path: str = WEIGHTS, meta: str = META):
+    p = np.load(path)
+    with open(meta) as f:
+        m = json.load(f)
+    return p, m
+
+
+def cmd_calibrate(args):
+    """kappa for the target recall on held-out tag-bank blocks (64 tags, 11 bins, 2^20 samples)."""
+    import torch
+    import siggen
+    from . import Plan
+    w = siggen.workload("tagbank_fp32")
+    chips = siggen.make_codes(w["seeds"][0], w["num_tags"], w["num_chips"])
+    plan = Plan(chips, w["spc"], w["fs_hz"], num_bins=w["num_bins"], bin_step_hz=w["bin_step_hz"],
+                max_block_len=w["block_len"], fft_len=w["fft_len"])
+    blocks = []
+    for i in range(args.blocks):
+        x, _ = siggen.make_block(args.seed + i, w["block_len"], chips, w["spc"], w["fs_hz"], plan.freqs_hz,
+                                 w["n_tx"], snr_db=w["snr_db"])
+        blocks.append(torch.from_numpy(x).cuda())
+        if (i + 1) % 10 == 0:
+            log(f"[calibrate] generated {i + 1}/{args.blocks}")
+    net = Network("bf16", 256, max_rows=1 << 14, max_block_len=1 << 21)
+    net.set_params(np.load(args.weights))
+    kappa, recall = calibrate(plan, net, blocks, args.target, args.kmax)
+    r, frac, fb = recall_at(plan, net, blocks, kappa, args.kmax)
+    meta = {"kappa": kappa, "max_proposals": args.kmax, "target_recall": args.target, "recall": r,
+            "segment_fraction": frac, "blocks": args.blocks, "seed": args.seed, "workload": "tagbank_fp32"}
+    with open(args.meta, "w") as f:
+        json.dump(meta, f, indent=1)
+    log(json.dumps(meta))
+
+
+def cmd_evaluate(args):
+    """Recall, searched share and speed of the proposal search against the exhaustive search
+    on the batched-stream workload (256 tags, 21 bins, uneven blocks)."""
+    import torch
+    import siggen
+    from . import Plan
+    w = siggen.workload("batched_stream")
+    chips = siggen.make_codes(w["seeds"][0], w["num_tags"], w["num_chips"])
+    with open(args.meta) as f:
+        meta = json.load(f)
+    from . import bin_frequencies
+    freqs = bin_frequencies(chips=chips, spc=w["spc"], fs_hz=w["fs_hz"], num_bins=w["num_bins"],
+                            bin_step_hz=w["bin_step_hz"], max_block_len=1 << 21, fft_len=1 << 15)
+    data = siggen.make_stream_batch(args.seed, chips, w["spc"], w["fs_hz"], freqs, args.blocks,
+                                    w["block_len_log2"], w["receivers"], w["n_tx"], w["snr_db"])
+    xs = [torch.from_numpy(x).cuda() for x, _ in data]
+    plan = Plan(chips, w["spc"], w["fs_hz"], num_bins=w["num_bins"], bin_step_hz=w["bin_step_hz"],
+                max_block_len=max(x.numel() for x in xs), fft_len=1 << 15, max_batch_blocks=len(xs),
+                max_batch_samples=sum(x.numel() for x in xs))
+    net = Network("bf16", 256, max_rows=1 << 15, max_block_len=1 << 21)
+    net.set_params(np.load(args.weights))
+    lp = LearnedParams(kappa=meta["kappa"], max_proposals=meta["max_proposals"], max_fraction=args.max_fraction,
+                       floor_db=args.floor_db)
+    for x in xs[:2]:                      # warm up both paths
+        plan.detect(x)
+        net.detect(plan, x, lp)
+    torch.cuda.synchronize()
+    t_full = t_learned = 0.0
+    hit = total = extra = 0
+    segs = segs_total = fallbacks = 0
+    for x in xs:
+        t0 = time.perf_counter()
+        full = plan.detect(x)
+        t1 = time.perf_counter()
+        dets, rep = net.detect(plan, x, lp)
+        t2 = time.perf_counter()
+        t_full += t1 - t0
+        t_learned += t2 - t1
+        fk = {(d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in full}
+        lk = {(d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in dets}
+        total += len(fk)
+        hit += len(fk & lk)
+        extra += len(lk - fk)
+        segs += rep.segments
+        segs_total += rep.total_segments
+        fallbacks += rep.fallback != 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.detect_batch(xs)
+    t_batch = time.perf_counter() - t0
+    out = {"blocks": len(xs), "samples": int(sum(x.numel() for x in xs)), "kappa": meta["kappa"],
+           "recall": hit / max(total, 1), "exhaustive_detections": total, "extra_detections": extra,
+           "segments_searched": segs / max(segs_total, 1), "fallbacks": fallbacks,
+           "ms_exhaustive_per_block_calls": 1e3 * t_full, "ms_exhaustive_batch": 1e3 * t_batch,
+           "ms_learned": 1e3 * t_learned, "speedup_vs_per_block": t_full / t_learned,
+           "speedup_vs_batch": t_batch / t_learned}
+    log(json.dumps(out))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(out, f, indent=1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("calibrate")
+    c.add_argument("--blocks", type=int, default=50)
+    c.add_argument("--seed", type=int, default=2_000_000)
+    c.add_argument("--target", type=float, default=0.995)
+    c.add_argument("--kmax", type=int, default=64)
+    c.add_argument("--weights", default=WEIGHTS)
+    c.add_argument("--meta", default=META)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--blocks", type=int, default=64)
+    e.add_argument("--seed", type=int, default=4001)
+    e.add_argument("--max-fraction", type=float, default=0.5)
+    e.add_argument("--floor-db", type=float, default=1.0)
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--meta", default=META)
+    e.add_argument("--report", default="")
     t = sub.add_parser("train")
     t.add_argument("--blocks", type=int, default=200000)
     t.add_argument("--batch", type=int, default=8)
@@ -141,6 +252,10 @@ def main(argv=None):
     t.add_argument("--pos-weight", type=float, default=4.0)
     t.add_argument("--out", default=WEIGHTS)
     args = ap.parse_args(argv)
+    if args.cmd == "calibrate":
+        return cmd_calibrate(args)
+    if args.cmd == "evaluate":
+        return cmd_evaluate(args)
     if args.cmd == "train":
         net, losses, secs = train(args.blocks, args.batch, args.seed, args.lr, args.lr_final, args.pos_weight)
         os.makedirs(os.path.dirname(args.out), exist_ok=True)

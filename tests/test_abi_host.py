@@ -121,3 +121,40 @@ def test_oracle_is_not_imported_by_the_product():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "direct.c" not in text, f
+
+
+def test_network_parameter_count_matches_the_oracle_layout(capi):
+    from oracle import learned as ol
+    L = capi.lib()
+    for cin in (256, 64, 5):
+        net = ol.init_cnn(0, cin=cin)
+        assert L.acq_cnn_num_params(cin) == sum(v.size for v in net.params().values())
+    assert L.acq_cnn_num_params(0) == 0
+
+
+def test_network_calls_reject_null_handles_without_gpu(capi):
+    L = capi.lib()
+    loss = ctypes.c_float(0)
+    assert L.acq_cnn_create(None, None, None) == -1
+    assert L.acq_cnn_release(None) == 0
+    assert L.acq_cnn_set_params(None, None, 0) == -1
+    assert L.acq_cnn_forward(None, None, 1, 1, None) == -1
+    assert L.acq_cnn_gradients(None, None, 1, 1, None, 1.0, None, ctypes.byref(loss)) == -1
+    assert L.acq_cnn_adam_step(None, 1e-3) == -1
+    assert L.acq_power_map(None, None, 0, None, None) == -1
+    assert L.acq_synth_block(None, None, None) == -1
+    assert L.acq_cnn_train_synthetic(None, None, 1.0, 1e-3, ctypes.byref(loss)) == -1
+    n = ctypes.c_int32(0)
+    assert L.acq_detect_learned(None, None, None, 0, None, None, 0, ctypes.byref(n), None) == -1
+
+
+def test_network_config_validation_without_gpu(capi):
+    L = capi.lib()
+    h = ctypes.c_void_p()
+    bad = [capi.AcqCnnConfig(capi.ACQ_FP16, 256, 1024, 1 << 17),   # precision
+           capi.AcqCnnConfig(capi.ACQ_BF16, 100, 1024, 1 << 17),   # bf16 needs multiples of 64
+           capi.AcqCnnConfig(capi.ACQ_BF16, 256, 0, 0),            # rows
+           capi.AcqCnnConfig(capi.ACQ_BF16, 256, 100, 1 << 17)]    # block needs more frames than rows
+    for cfg in bad:
+        assert L.acq_cnn_create(ctypes.byref(cfg), None, ctypes.byref(h)) in (-1, -7)
+        assert not h.value

@@ -43,11 +43,14 @@ def _small_batch(seed=0):
     return (T, C, spc, K, step, M, L), chips, freqs, blocks
 
 
+@pytest.mark.parametrize("launch", [0, 1], ids=["grid", "persistent"])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batch_equals_single_blocks_and_oracle(dev, graph):
+def test_batch_equals_single_blocks_and_oracle(dev, graph, launch):
     (T, C, spc, K, step, M, L), chips, freqs, blocks = _small_batch()
     xs = [torch.from_numpy(x).to(dev) for x, _ in blocks]
     with _plan(chips, spc, K, step, 20000, M, max_batch_blocks=8, graph=graph) as plan:
+        t = plan.tuning
+        plan.set_tuning(t["engine"], t["tag_tile"], launch)
         batch = plan.detect_batch(xs)
         singles = []
         for b, x in enumerate(xs):
@@ -100,9 +103,10 @@ def test_tuning_candidates_give_identical_results(dev):
         base_P = plan.correlate_power(xt).cpu().numpy()
         table = plan.tune(xt, reps=2)
         assert {(e["engine"], e["tag_tile"]) for e in table} >= {(0, 16), (1, 16)}
+        assert {e["batch_launch"] for e in table[-2:]} == {0, 1}
         assert all(e["ms"] > 0 for e in table)
         for e in table:
-            plan.set_tuning(e["engine"], e["tag_tile"])
+            plan.set_tuning(e["engine"], e["tag_tile"], e["batch_launch"])
             assert [_key(d) for d in plan.detect(xt)] == base_det, e
             P = plan.correlate_power(xt).cpu().numpy()
             if e["engine"] == 0:

@@ -256,3 +256,26 @@ def test_transmission_covers_its_middle_frame():
 def test_power_map_of_an_empty_block_is_zero():
     m, med = ol.power_map(np.zeros(256 + 128 * 3, np.complex64))
     assert med == 0.0 and m.shape == (4, 256) and not m.any()
+
+
+def test_bf16_round_is_the_library_conversion():
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(12)
+    v = np.concatenate([g.normal(0, 10, 5000), g.normal(0, 1e-30, 100), [0.0, -0.0, 1.0, 3.0, 65504.0]])
+    # values exactly halfway between two bf16 numbers: ties go to the even significand
+    base = np.array([1.0, 1.0078125, 3.0, -5.5], dtype=np.float32).view(np.uint32)
+    ties = (base + 0x8000).view(np.float32).astype(np.float64)
+    v = np.concatenate([v, ties]).astype(np.float32)
+    want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ol.bf16_round(v), want)
+
+
+def test_bf16_forward_rounds_every_layer_output():
+    g = np.random.default_rng(13)
+    net = ol.init_cnn(14, cin=8)
+    m = g.normal(size=(30, 8))
+    y, h = ol.cnn_forward(ol.bf16_network(net), m, act_round=ol.bf16_round)
+    for a in h[1:]:
+        assert np.array_equal(a, ol.bf16_round(a))
+    y64, _ = ol.cnn_forward(net, m)
+    assert 0 < np.linalg.norm(y - y64) / np.linalg.norm(y64) < 0.05
