@@ -261,7 +261,9 @@ int acq_release(acq_plan_t plan);
  *
  * Network: four "same"-padded conv layers over frames (kernel 5, dilations
  * 1, 2, 4, 8, in_channels -> 64 -> 64 -> 64 -> 64, ReLU), then a 1x1 head to one
- * logit per frame.  Parameters, FP32, in this order: per layer W[5][cin][64]
+ * logit per frame.  Frame f proposes the lags [128f + 256 - L, 128f] (the
+ * replica covers the whole frame); the searched segments are those meeting a
+ * proposed range.  Parameters, FP32, in this order: per layer W[5][cin][64]
  * then b[64]; then wh[64], bh.  Training: mean weighted BCE with logits over
  * frames (label 1 when half the frame lies inside a transmission), Adam.
  * ==================================================================== */
@@ -348,8 +350,8 @@ int acq_synth_block(acq_cnn_t cnn, const acq_synth_batch* batch, void* out);
 int acq_cnn_train_synthetic(acq_cnn_t cnn, const acq_synth_batch* batch, float pos_weight, float lr, float* loss);
 
 typedef struct acq_learned_params {
-    float   kappa;              /* proposal threshold on the window score */
-    int32_t max_proposals;      /* at most this many proposed frames */
+    float   kappa;              /* a frame is proposed when its window score (the sum of the
+                                   logits of frames f-63 .. f+64) reaches kappa */
     float   max_fraction;       /* full search when more than this fraction of segments is proposed */
     float   floor_db;           /* full search when the map median departs from the running
                                    noise floor by more than this (dB); <= 0 disables */

@@ -30,10 +30,8 @@ textbook definitions:
   p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 * Proposals.  Window score c[f] = sum of the logits of frames f-63 .. f+64
   (128 frames, the span of a 16384-sample transmission at hop 128; frames
-  outside the block count 0).  Candidates are local maxima: c[f] is the
-  largest of frames f-64 .. f+64, ties to the smaller f.  A candidate is
-  proposed when c[f] >= kappa, at most k_max of them, largest first.  Frame f
-  proposes every lag whose replica covers the whole frame,
+  outside the block count 0).  Every frame with c[f] >= kappa is proposed.
+  Frame f proposes every lag whose replica covers the whole frame,
   tau in [128 f + 256 - L, 128 f] intersected with [0, N - L]; the search then
   runs on every overlap-save segment j (lags jV .. jV+V-1) meeting a proposed
   range, so its values are those of the exhaustive search on those lags.
@@ -48,17 +46,16 @@ import numpy as np
 WIN = 256
 HOP = 128
 SPAN = 128              # window-score length, frames
-NMS_RADIUS = 64
 CHANNELS = 64
 KERNEL = 5
 DILATIONS = (1, 2, 4, 8)
 
 __all__ = [
-    "WIN", "HOP", "SPAN", "NMS_RADIUS", "CHANNELS", "KERNEL", "DILATIONS",
+    "WIN", "HOP", "SPAN", "CHANNELS", "KERNEL", "DILATIONS",
     "num_frames", "hann", "stft_power", "lower_median", "power_map", "frame_labels",
     "CNN", "init_cnn", "conv_same", "cnn_forward", "cnn_backward", "bce_with_logits", "bf16_round",
     "bf16_network",
-    "adam_step", "window_scores", "candidates", "propose", "frame_lag_range", "segments_for_ranges",
+    "adam_step", "window_scores", "propose", "frame_lag_range", "segments_for_ranges",
 ]
 
 
@@ -255,25 +252,9 @@ def window_scores(y: np.ndarray) -> np.ndarray:
     return c
 
 
-def candidates(c: np.ndarray) -> np.ndarray:
-    """Frames whose score is the maximum over f-64 .. f+64, ties to the smaller frame."""
-    F = c.size
-    out = []
-    for f in range(F):
-        a, b = max(0, f - NMS_RADIUS), min(F, f + NMS_RADIUS + 1)
-        w = c[a:b]
-        best = a + int(np.argmax(w))                # first maximum = smallest frame
-        if best == f:
-            out.append(f)
-    return np.asarray(out, dtype=np.int64)
-
-
-def propose(c: np.ndarray, kappa: float, k_max: int) -> np.ndarray:
-    """Candidates with c >= kappa, largest first (ties to the smaller frame), at most k_max."""
-    cand = candidates(c)
-    cand = cand[c[cand] >= kappa]
-    order = sorted(cand.tolist(), key=lambda f: (-c[f], f))
-    return np.asarray(order[:k_max], dtype=np.int64)
+def propose(c: np.ndarray, kappa: float) -> np.ndarray:
+    """Frames whose window score reaches kappa, ascending."""
+    return np.flatnonzero(np.asarray(c, np.float64) >= kappa).astype(np.int64)
 
 
 def frame_lag_range(f: int, n: int, L: int):

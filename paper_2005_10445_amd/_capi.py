@@ -137,7 +137,6 @@ class AcqSynthBatch(ctypes.Structure):
 class AcqLearnedParams(ctypes.Structure):
     _fields_ = [
         ("kappa", ctypes.c_float),
-        ("max_proposals", ctypes.c_int32),
         ("max_fraction", ctypes.c_float),
         ("floor_db", ctypes.c_float),
     ]

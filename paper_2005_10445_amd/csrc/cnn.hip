@@ -71,12 +71,11 @@ struct acq_cnn_s {
     SynthTx* d_tx = nullptr;        // [kMaxBatch][kMaxTx]
     int32_t* d_ntx = nullptr;       // [kMaxBatch]
     float* wscore = nullptr;        // [max frames of one block]
-    int32_t* d_frames = nullptr;    // [max frames of one block]
-    int32_t* d_info = nullptr;      // [3]
+    int32_t* d_info = nullptr;      // [2]
 
     SynthTx* h_tx = nullptr;        // pinned staging
     int32_t* h_ntx = nullptr;
-    int32_t* h_info = nullptr;      // pinned [3]
+    int32_t* h_info = nullptr;      // pinned [2]
     float* h_scalar = nullptr;      // pinned [2]: loss, median
 
     bool floor_init = false;
@@ -89,7 +88,7 @@ void free_cnn(acq_cnn_s* c) {
     if (!c) return;
     void* dev[] = {c->theta, c->grad, c->m, c->v, c->w_bf, c->wt_bf, c->act[0], c->act[1], c->act[2], c->act[3],
                    c->act[4], c->dH[0], c->dH[1], c->y, c->labels, c->P, c->hist, c->mstate, c->med, c->hann,
-                   c->tw, c->loss, c->d_tx, c->d_ntx, c->wscore, c->d_frames, c->d_info};
+                   c->tw, c->loss, c->d_tx, c->d_ntx, c->wscore, c->d_info};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     void* host[] = {c->h_tx, c->h_ntx, c->h_info, c->h_scalar};
@@ -126,11 +125,10 @@ int build_cnn(acq_cnn_s* c) {
     CNN_HIP(dalloc(&c->d_tx, size_t(kMaxBatch) * kMaxTx));
     CNN_HIP(dalloc(&c->d_ntx, size_t(kMaxBatch)));
     CNN_HIP(dalloc(&c->wscore, fmax));
-    CNN_HIP(dalloc(&c->d_frames, fmax));
-    CNN_HIP(dalloc(&c->d_info, 3));
+    CNN_HIP(dalloc(&c->d_info, 2));
     CNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_tx), sizeof(SynthTx) * kMaxBatch * kMaxTx));
     CNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_ntx), sizeof(int32_t) * kMaxBatch));
-    CNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_info), sizeof(int32_t) * 3));
+    CNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_info), sizeof(int32_t) * 2));
     CNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->h_scalar), sizeof(float) * 2));
 
     // window and twiddles from FP64
@@ -237,7 +235,7 @@ int synth_source(acq_cnn_s* c, const acq_synth_batch* b, BlockSource* src) {
 namespace acq {
 
 int cnn_propose(acq_cnn_t c, const void* block, int64_t n, int64_t L, int64_t V, int32_t max_segments, float kappa,
-                int32_t kmax, int32_t* d_segs, hipStream_t st, ProposalResult* out) {
+                int32_t* d_segs, hipStream_t st, ProposalResult* out) {
     const int64_t F = num_frames(n);
     if (F < 1) return acq::fail(ACQ_ERR_INVALID_ARG, "block shorter than one frame");
     if (n > c->cfg.max_block_len || F > c->cfg.max_rows)
@@ -250,14 +248,12 @@ int cnn_propose(acq_cnn_t c, const void* block, int64_t n, int64_t L, int64_t V,
     rc = run_forward(c, c->act[0], 1, F, st);
     if (rc != ACQ_OK) return rc;
     CNN_HIP(launch_window(c->y, F, c->wscore, st));
-    const int32_t kcap = int32_t(std::min<int64_t>(kmax, F));
-    CNN_HIP(launch_propose(c->wscore, F, kappa, kcap, n, L, V, max_segments, c->d_frames, d_segs, c->d_info, st));
-    CNN_HIP(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st));
+    CNN_HIP(launch_propose(c->wscore, F, kappa, n, L, V, max_segments, d_segs, c->d_info, st));
+    CNN_HIP(hipMemcpyAsync(c->h_info, c->d_info, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, st));
     CNN_HIP(hipMemcpyAsync(c->h_scalar + 1, c->med, sizeof(float), hipMemcpyDeviceToHost, st));
     CNN_HIP(hipStreamSynchronize(st));
     out->proposals = c->h_info[0];
     out->segments = c->h_info[1];
-    out->candidates = c->h_info[2];
     out->median = c->h_scalar[1];
     return ACQ_OK;
 }
@@ -292,8 +288,6 @@ int acq_cnn_create(const acq_cnn_config* cfg, void* stream, acq_cnn_t* out) {
         return acq::fail(ACQ_ERR_INVALID_ARG, "max_rows outside [1, 2^26]");
     if (cfg->max_block_len < 0 || num_frames(cfg->max_block_len) > cfg->max_rows)
         return acq::fail(ACQ_ERR_INVALID_ARG, "max_block_len needs more frames than max_rows");
-    if (num_frames(cfg->max_block_len) > int64_t(kNms + 1) * 2048)
-        return acq::fail(ACQ_ERR_UNSUPPORTED, "max_block_len above the proposal stage's limit");
     acq_cnn_s* c = new (std::nothrow) acq_cnn_s();
     if (!c) return acq::fail(ACQ_ERR_OOM, "host allocation failed");
     c->cfg = *cfg;

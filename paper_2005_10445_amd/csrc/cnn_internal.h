@@ -12,7 +12,6 @@ namespace acq {
 struct ProposalResult {
     int32_t proposals;          // frames proposed
     int32_t segments;           // segments listed in d_segs
-    int32_t candidates;         // local maxima at or above kappa
     float median;               // power-map median of the block
 };
 
@@ -20,7 +19,7 @@ struct ProposalResult {
 // stream st; the proposed segments (ascending) go to device d_segs.  Waits for
 // the stream.  Returns an ACQ status.
 int cnn_propose(acq_cnn_t cnn, const void* block, int64_t n, int64_t L, int64_t V, int32_t max_segments,
-                float kappa, int32_t kmax, int32_t* d_segs, hipStream_t st, ProposalResult* out);
+                float kappa, int32_t* d_segs, hipStream_t st, ProposalResult* out);
 
 // Running noise floor of the network's blocks: false until the first update.
 bool cnn_floor(acq_cnn_t cnn, double* floor);

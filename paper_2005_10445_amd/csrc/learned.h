@@ -16,7 +16,6 @@ namespace learned {
 constexpr int kWin = 256;          // STFT length
 constexpr int kHop = 128;          // STFT hop
 constexpr int kSpan = 128;         // window-score length (frames)
-constexpr int kNms = 64;           // local-maximum radius (frames)
 constexpr int kCh = 64;            // channels of every conv layer
 constexpr int kTaps = 5;
 constexpr int kLayers = 4;
@@ -101,11 +100,10 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t st);
 
 // Window scores c[f] = sum_{i=-63}^{64} y[f+i] of one block.
 hipError_t launch_window(const float* y, int64_t F, float* c, hipStream_t st);
-// Candidates, ranking, lag ranges and the segment list of one block.
-// out_info = {number of proposals, number of segments}.
-hipError_t launch_propose(const float* c, int64_t F, float kappa, int kmax, int64_t n, int64_t L, int64_t V,
-                          int32_t max_segments, int32_t* frames, int32_t* segs, int32_t* out_info,
-                          hipStream_t st);
+// Frames at or above kappa, their lag ranges and the segment list of one block.
+// out_info = {proposed frames, segments}.
+hipError_t launch_propose(const float* c, int64_t F, float kappa, int64_t n, int64_t L, int64_t V,
+                          int32_t max_segments, int32_t* segs, int32_t* out_info, hipStream_t st);
 
 }  // namespace learned
 }  // namespace acq

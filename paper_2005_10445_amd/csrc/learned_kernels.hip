@@ -15,7 +15,8 @@
 //   k_head            1x1 head, weighted BCE with logits and its gradient
 //   k_adam            Adam update of the FP32 master weights, refreshing the
 //                     bf16 copies in both operand layouts
-//   k_window/k_propose window scores, local maxima, top-k and the segment list
+//   k_window/k_propose window scores, frames at or above the threshold and the
+//                     segment list
 #include <hip/hip_runtime.h>
 #include <cfloat>
 
@@ -587,63 +588,38 @@ __global__ void k_window(const float* __restrict__ y, int64_t F, float* __restri
     c[f] = acc;
 }
 
-constexpr int kMaxCand = 2048;
 constexpr int kMaxSegList = 4096;
 
-// One workgroup: candidates (local maxima over +/-64 frames, ties to the
-// smaller frame) at or above kappa; their rank by (score desc, frame asc);
-// the kmax best propose lag ranges [128f + 256 - L, 128f] within [0, n-L];
-// segments meeting a range are listed in ascending order.
-__global__ __launch_bounds__(1024) void k_propose(const float* __restrict__ c, int64_t F, float kappa, int kmax,
-                                                  int64_t n, int64_t L, int64_t V, int32_t max_segments,
-                                                  int32_t* __restrict__ frames, int32_t* __restrict__ segs,
-                                                  int32_t* __restrict__ info) {
-    __shared__ int cf[kMaxCand];
-    __shared__ float cv[kMaxCand];
+// One workgroup: every frame whose window score reaches kappa proposes the lags
+// [128f + 256 - L, 128f] within [0, n-L]; the segments meeting a proposed range
+// are listed in ascending order.  info = {proposed frames, segments}.
+__global__ __launch_bounds__(1024) void k_propose(const float* __restrict__ c, int64_t F, float kappa, int64_t n,
+                                                  int64_t L, int64_t V, int32_t max_segments,
+                                                  int32_t* __restrict__ segs, int32_t* __restrict__ info) {
     __shared__ unsigned char mask[kMaxSegList];
-    __shared__ int ncand;
+    __shared__ int nprop;
     const int t = int(threadIdx.x);
-    if (t == 0) ncand = 0;
+    if (t == 0) nprop = 0;
     for (int j = t; j < kMaxSegList; j += 1024) mask[j] = 0;
     __syncthreads();
-    for (int64_t f = t; f < F; f += 1024) {
-        const float v = c[f];
-        if (!(v >= kappa)) continue;
-        bool is_max = true;
-        const int64_t a = f - kNms < 0 ? 0 : f - kNms, b = f + kNms >= F ? F - 1 : f + kNms;
-        for (int64_t g = a; g <= b && is_max; ++g) {
-            if (g < f) is_max = c[g] < v;
-            else if (g > f) is_max = c[g] <= v;
-        }
-        if (is_max) {
-            const int idx = atomicAdd(&ncand, 1);
-            if (idx < kMaxCand) {
-                cf[idx] = int(f);
-                cv[idx] = v;
-            }
-        }
-    }
-    __syncthreads();
-    const int nc = ncand < kMaxCand ? ncand : kMaxCand;
     const int64_t lags = n - L + 1;
-    for (int q = t; q < nc; q += 1024) {
-        int rank = 0;
-        for (int p = 0; p < nc; ++p) rank += (cv[p] > cv[q]) || (cv[p] == cv[q] && cf[p] < cf[q]);
-        if (rank >= kmax) continue;
-        frames[rank] = cf[q];
-        const int64_t lo = int64_t(kHop) * cf[q] + kWin - L < 0 ? 0 : int64_t(kHop) * cf[q] + kWin - L;
-        const int64_t hi = int64_t(kHop) * cf[q] < lags - 1 ? int64_t(kHop) * cf[q] : lags - 1;
+    int mine = 0;
+    for (int64_t f = t; f < F; f += 1024) {
+        if (!(c[f] >= kappa)) continue;
+        ++mine;
+        const int64_t lo = int64_t(kHop) * f + kWin - L < 0 ? 0 : int64_t(kHop) * f + kWin - L;
+        const int64_t hi = int64_t(kHop) * f < lags - 1 ? int64_t(kHop) * f : lags - 1;
         for (int64_t j = lo / V; lo <= hi && j <= hi / V && j < max_segments; ++j) mask[j] = 1;
     }
+    if (mine) atomicAdd(&nprop, mine);
     __syncthreads();
     if (t == 0) {
         int ns = 0;
         const int64_t S = (lags + V - 1) / V;
         for (int64_t j = 0; j < S && j < max_segments; ++j)
             if (mask[j]) segs[ns++] = int32_t(j);
-        info[0] = nc < kmax ? nc : kmax;
+        info[0] = nprop;
         info[1] = ns;
-        info[2] = ncand;
     }
 }
 
@@ -785,11 +761,10 @@ hipError_t launch_window(const float* y, int64_t F, float* c, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_propose(const float* c, int64_t F, float kappa, int kmax, int64_t n, int64_t L, int64_t V,
-                          int32_t max_segments, int32_t* frames, int32_t* segs, int32_t* out_info, hipStream_t st) {
-    if (max_segments > kMaxSegList || kmax < 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_propose, dim3(1), dim3(1024), 0, st, c, F, kappa, kmax, n, L, V, max_segments, frames, segs,
-                       out_info);
+hipError_t launch_propose(const float* c, int64_t F, float kappa, int64_t n, int64_t L, int64_t V,
+                          int32_t max_segments, int32_t* segs, int32_t* out_info, hipStream_t st) {
+    if (max_segments > kMaxSegList) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_propose, dim3(1), dim3(1024), 0, st, c, F, kappa, n, L, V, max_segments, segs, out_info);
     return hipGetLastError();
 }
 

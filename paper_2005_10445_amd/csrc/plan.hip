@@ -490,8 +490,7 @@ int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n
     if (rc != ACQ_OK) return rc;
     if (!cnn || !lp || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
     if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
-    if (lp->max_proposals < 0 || !(lp->max_fraction >= 0.0f))
-        return acq::fail(ACQ_ERR_INVALID_ARG, "bad proposal parameters");
+    if (!(lp->max_fraction >= 0.0f)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad proposal parameters");
     *n_found = 0;
     acq_learned_report rep{};
     double floor = 0.0;
@@ -507,8 +506,8 @@ int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n
     bt.one = single_desc(p, block, n);
     rep.total_segments = bt.one.nseg;
     acq::ProposalResult pr{};
-    rc = acq::cnn_propose(cnn, block, n, p->g.L, p->g.V, int32_t(p->g.max_segments), lp->kappa, lp->max_proposals,
-                          p->d_seglist, p->stream, &pr);
+    rc = acq::cnn_propose(cnn, block, n, p->g.L, p->g.V, int32_t(p->g.max_segments), lp->kappa, p->d_seglist,
+                          p->stream, &pr);
     if (rc != ACQ_OK) return rc;
     rep.proposals = pr.proposals;
     rep.median = pr.median;

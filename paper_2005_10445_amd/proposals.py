@@ -37,7 +37,6 @@ class SynthTransmission:
 @dataclass
 class LearnedParams:
     kappa: float
-    max_proposals: int = 64
     max_fraction: float = 0.5
     floor_db: float = 1.0
 
@@ -170,8 +169,7 @@ class Network:
         out = (_capi.AcqDetection * plan.num_tags)()
         nf = ctypes.c_int32(0)
         rep = _capi.AcqLearnedReport()
-        lp = _capi.AcqLearnedParams(float(params.kappa), int(params.max_proposals), float(params.max_fraction),
-                                    float(params.floor_db))
+        lp = _capi.AcqLearnedParams(float(params.kappa), float(params.max_fraction), float(params.floor_db))
         check(self._lib.acq_detect_learned(plan._h, self._h, ctypes.c_void_p(_dev(block, "block")), n,
                                            ctypes.byref(lp), out, plan.num_tags, ctypes.byref(nf),
                                            ctypes.byref(rep)), "acq_detect_learned")

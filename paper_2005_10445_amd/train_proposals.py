@@ -74,7 +74,7 @@ def draw_transmissions(g: np.random.Generator, nblocks: int, n: int = BLOCK_LEN,
 
 
 def train(blocks: int, batch: int, seed: int, lr: float, lr_final: float, pos_weight: float,
-          init: np.ndarray | None = None, log_every: int = 200):
+          init: np.ndarray | None = None, log_every: int = 1000):
     rows = batch * ((BLOCK_LEN - 256) // 128 + 1)
     net = Network("bf16", 256, max_rows=rows, max_block_len=BLOCK_LEN)
     net.set_params(he_init(seed) if init is None else init)
@@ -87,46 +87,54 @@ def train(blocks: int, batch: int, seed: int, lr: float, lr_final: float, pos_we
         a = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * s / max(steps - 1, 1)))
         txs = draw_transmissions(g, batch)
         losses.append(net.train_synthetic(seed, s * batch, BLOCK_LEN, CHIPS, SPC, txs, pos_weight, a))
-        if (s + 1) % log_every == 0 or s == steps - 1:
+        if (s + 1) % log_every == 0 or s == steps - 1 or s < 3:
             log(f"[train] step {s + 1}/{steps} blocks {(s + 1) * batch} loss {np.mean(losses[-log_every:]):.4f} "
                 f"lr {a:.2e} {time.time() - t0:.0f} s")
     return net, losses, time.time() - t0
 
 
-def recall_at(plan, net: Network, blocks, kappa: float, kmax: int, exhaustive=None):
-    """Share of exhaustive detections that the proposal search returns with the same values,
-    and the mean share of segments it searched."""
-    hit = total = 0
+def _true_key(d, txs, tol: int = 2):
+    """True when detection d is the detection of an injected transmission."""
+    return any(d.tag == t.tag and d.bin == t.bin and abs(d.lag - t.delay) <= tol for t in txs)
+
+
+def recall_at(plan, net: Network, blocks, kappa: float, exhaustive, truth=None):
+    """(recall over all exhaustive detections, recall over the exhaustive detections of injected
+    transmissions, mean share of segments searched, fallbacks) of the proposal search at kappa,
+    the exhaustive search being the judge (same values required)."""
+    hit = total = thit = ttotal = 0
     frac = []
     fallbacks = 0
     for i, x in enumerate(blocks):
-        full = exhaustive[i] if exhaustive is not None else plan.detect(x)
-        dets, rep = net.detect(plan, x, LearnedParams(kappa=kappa, max_proposals=kmax, max_fraction=1.0,
-                                                      floor_db=0.0))
-        got = {(d.tag, d.bin, d.lag, d.toa) for d in dets}
-        total += len(full)
-        hit += sum((d.tag, d.bin, d.lag, d.toa) in got for d in full)
+        full = exhaustive[i]
+        dets, rep = net.detect(plan, x, LearnedParams(kappa=kappa, max_fraction=1.0, floor_db=0.0))
+        got = {(d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in dets}
+        for d in full:
+            ok = (d.tag, d.bin, d.lag, d.toa, d.peak_power) in got
+            total += 1
+            hit += ok
+            if truth is not None and _true_key(d, truth[i]):
+                ttotal += 1
+                thit += ok
         frac.append(rep.segments / max(rep.total_segments, 1))
         fallbacks += rep.fallback != 0
-    return (hit / total if total else 1.0), float(np.mean(frac)), fallbacks
+    return (hit / total if total else 1.0, thit / ttotal if ttotal else 1.0, float(np.mean(frac)), fallbacks)
 
 
-def calibrate(plan, net: Network, blocks, target: float, kmax: int, lo: float = -5000.0, hi: float = 5000.0,
-              iters: int = 24):
-    """Largest kappa (bisection; recall does not increase with kappa) whose recall >= target."""
+def calibrate(plan, net: Network, blocks, truth, target: float, lo: float = -5000.0, hi: float = 5000.0,
+              iters: int = 30):
+    """Largest kappa (bisection: a larger kappa proposes a subset) whose recall over the
+    exhaustive detections of injected transmissions reaches target."""
     exhaustive = [plan.detect(x) for x in blocks]
-    r_lo, _, _ = recall_at(plan, net, blocks, lo, kmax, exhaustive)
-    if r_lo < target:
-        return lo, r_lo
+    if recall_at(plan, net, blocks, lo, exhaustive, truth)[1] < target:
+        return lo
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        r, _, _ = recall_at(plan, net, blocks, mid, kmax, exhaustive)
-        if r >= target:
+        if recall_at(plan, net, blocks, mid, exhaustive, truth)[1] >= target:
             lo = mid
         else:
             hi = mid
-    r, f, _ = recall_at(plan, net, blocks, lo, kmax, exhaustive)
-    return lo, r
+    return lo
 
 
 def load_model(path: str = WEIGHTS, meta: str = META):
@@ -145,18 +153,20 @@ def cmd_calibrate(args):
     chips = siggen.make_codes(w["seeds"][0], w["num_tags"], w["num_chips"])
     plan = Plan(chips, w["spc"], w["fs_hz"], num_bins=w["num_bins"], bin_step_hz=w["bin_step_hz"],
                 max_block_len=w["block_len"], fft_len=w["fft_len"])
-    blocks = []
+    blocks, truth = [], []
     for i in range(args.blocks):
-        x, _ = siggen.make_block(args.seed + i, w["block_len"], chips, w["spc"], w["fs_hz"], plan.freqs_hz,
-                                 w["n_tx"], snr_db=w["snr_db"])
+        x, txs = siggen.make_block(args.seed + i, w["block_len"], chips, w["spc"], w["fs_hz"], plan.freqs_hz,
+                                   w["n_tx"], snr_db=w["snr_db"])
         blocks.append(torch.from_numpy(x).cuda())
+        truth.append(txs)
         if (i + 1) % 10 == 0:
             log(f"[calibrate] generated {i + 1}/{args.blocks}")
     net = Network("bf16", 256, max_rows=1 << 14, max_block_len=1 << 21)
     net.set_params(np.load(args.weights))
-    kappa, recall = calibrate(plan, net, blocks, args.target, args.kmax)
-    r, frac, fb = recall_at(plan, net, blocks, kappa, args.kmax)
-    meta = {"kappa": kappa, "max_proposals": args.kmax, "target_recall": args.target, "recall": r,
+    kappa = calibrate(plan, net, blocks, truth, args.target)
+    exhaustive = [plan.detect(x) for x in blocks]
+    r, rt, frac, fb = recall_at(plan, net, blocks, kappa, exhaustive, truth)
+    meta = {"kappa": kappa, "target_recall_injected": args.target, "recall_injected": rt, "recall_all": r,
             "segment_fraction": frac, "blocks": args.blocks, "seed": args.seed, "workload": "tagbank_fp32"}
     with open(args.meta, "w") as f:
         json.dump(meta, f, indent=1)
@@ -184,16 +194,15 @@ def cmd_evaluate(args):
                 max_batch_samples=sum(x.numel() for x in xs))
     net = Network("bf16", 256, max_rows=1 << 15, max_block_len=1 << 21)
     net.set_params(np.load(args.weights))
-    lp = LearnedParams(kappa=meta["kappa"], max_proposals=meta["max_proposals"], max_fraction=args.max_fraction,
-                       floor_db=args.floor_db)
+    lp = LearnedParams(kappa=meta["kappa"], max_fraction=args.max_fraction, floor_db=args.floor_db)
     for x in xs[:2]:                      # warm up both paths
         plan.detect(x)
         net.detect(plan, x, lp)
     torch.cuda.synchronize()
     t_full = t_learned = 0.0
-    hit = total = extra = 0
+    hit = total = extra = thit = ttotal = 0
     segs = segs_total = fallbacks = 0
-    for x in xs:
+    for x, (_, txs) in zip(xs, data):
         t0 = time.perf_counter()
         full = plan.detect(x)
         t1 = time.perf_counter()
@@ -206,6 +215,10 @@ def cmd_evaluate(args):
         total += len(fk)
         hit += len(fk & lk)
         extra += len(lk - fk)
+        for d in full:
+            if _true_key(d, txs):
+                ttotal += 1
+                thit += (d.tag, d.bin, d.lag, d.toa, d.peak_power) in lk
         segs += rep.segments
         segs_total += rep.total_segments
         fallbacks += rep.fallback != 0
@@ -214,7 +227,8 @@ def cmd_evaluate(args):
     plan.detect_batch(xs)
     t_batch = time.perf_counter() - t0
     out = {"blocks": len(xs), "samples": int(sum(x.numel() for x in xs)), "kappa": meta["kappa"],
-           "recall": hit / max(total, 1), "exhaustive_detections": total, "extra_detections": extra,
+           "recall_all": hit / max(total, 1), "recall_injected": thit / max(ttotal, 1),
+           "exhaustive_detections": total, "exhaustive_injected_detections": ttotal, "extra_detections": extra,
            "segments_searched": segs / max(segs_total, 1), "fallbacks": fallbacks,
            "ms_exhaustive_per_block_calls": 1e3 * t_full, "ms_exhaustive_batch": 1e3 * t_batch,
            "ms_learned": 1e3 * t_learned, "speedup_vs_per_block": t_full / t_learned,
@@ -232,7 +246,6 @@ def main(argv=None):
     c.add_argument("--blocks", type=int, default=50)
     c.add_argument("--seed", type=int, default=2_000_000)
     c.add_argument("--target", type=float, default=0.995)
-    c.add_argument("--kmax", type=int, default=64)
     c.add_argument("--weights", default=WEIGHTS)
     c.add_argument("--meta", default=META)
     e = sub.add_parser("evaluate")

@@ -283,7 +283,10 @@ def test_proposal_search_is_a_bit_exact_subset(dev):
         full = {d.tag: d for d in plan.detect(xt)}
         m, _ = net.power_map(xt)
         y = net.forward(m).cpu().numpy().astype(np.float64)
-        lp = LearnedParams(kappa=-1e30, max_proposals=4, max_fraction=1.0, floor_db=0.0)
+        # a threshold that proposes some frames but not all: the 97th percentile score
+        c64 = ol.window_scores(y)
+        kappa = float(np.float32(np.quantile(c64, 0.97)))
+        lp = LearnedParams(kappa=kappa, max_fraction=1.0, floor_db=0.0)
         dets, rep = net.detect(plan, xt, lp)
     # window scores summed in FP32 in the device's order, so that candidate
     # decisions (which compare nearly equal sums) are taken on the same values
@@ -295,7 +298,7 @@ def test_proposal_search_is_a_bit_exact_subset(dev):
         for i in range(max(0, f - 63), min(F, f + 65)):
             acc = np.float32(acc + y32[i])
         c[f] = float(acc)
-    frames = ol.propose(c, -1e30, 4)
+    frames = ol.propose(c, kappa)
     segs = set(ol.segments_for_ranges([ol.frame_lag_range(int(f), n, L) for f in frames], V, n, L).tolist())
     assert rep.fallback == 0 and rep.proposals == len(frames)
     assert rep.segments == len(segs) and 0 < rep.segments < rep.total_segments
@@ -317,12 +320,11 @@ def test_proposal_search_fallbacks_equal_exhaustive(dev):
         net.set_params(_flat(_rand_net(41, 256)))
         key = lambda ds: [(d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in ds]   # noqa: E731
         full = key(plan.detect(xt))
-        dets, rep = net.detect(plan, xt, LearnedParams(kappa=-1e30, max_proposals=8, max_fraction=0.0, floor_db=0))
+        dets, rep = net.detect(plan, xt, LearnedParams(kappa=-1e30, max_fraction=0.0, floor_db=0))
         assert rep.fallback == 1 and rep.segments == rep.total_segments and key(dets) == full
         # the noise floor: set by the first call; a 6 dB louder block falls back
-        dets, rep = net.detect(plan, xt, LearnedParams(kappa=1e30, max_proposals=8, max_fraction=1.0, floor_db=1.0))
+        dets, rep = net.detect(plan, xt, LearnedParams(kappa=1e30, max_fraction=1.0, floor_db=1.0))
         assert rep.fallback == 0 and rep.segments == 0 and dets == []
-        dets, rep = net.detect(plan, 2 * xt, LearnedParams(kappa=1e30, max_proposals=8, max_fraction=1.0,
-                                                             floor_db=1.0))
+        dets, rep = net.detect(plan, 2 * xt, LearnedParams(kappa=1e30, max_fraction=1.0, floor_db=1.0))
         assert rep.fallback == 2 and abs(rep.median / rep.floor - 4.0) < 0.5
         assert key(dets) == key(plan.detect(2 * xt))

@@ -203,24 +203,23 @@ def test_window_scores_are_a_library_convolution():
     assert np.allclose(c, ref, atol=1e-10)
 
 
-def test_candidates_brute_force_and_spacing():
-    g = np.random.default_rng(11)
-    c = np.round(g.normal(size=700), 1)          # rounded: plenty of ties
-    cand = ol.candidates(c)
-    for f in range(700):
-        a, b = max(0, f - 64), min(700, f + 65)
-        is_max = all(c[f] > c[i] or (c[f] == c[i] and f <= i) for i in range(a, b))
-        assert (f in set(cand.tolist())) == is_max, f
-    assert np.all(np.diff(cand) > 64)
+def test_propose_threshold():
+    c = np.array([0.0, 5.0, 9.0, 1.0, 9.0, -3.0])
+    assert ol.propose(c, 2.0).tolist() == [1, 2, 4]
+    assert ol.propose(c, 9.0).tolist() == [2, 4]
+    assert ol.propose(c, 100.0).tolist() == []
 
 
-def test_propose_threshold_and_cap():
-    c = np.zeros(1000)
-    for f, v in [(100, 5.0), (300, 9.0), (500, 1.0), (800, 9.0)]:
-        c[f] = v
-    assert ol.propose(c, 2.0, 10).tolist() == [300, 800, 100]
-    assert ol.propose(c, 2.0, 2).tolist() == [300, 800]
-    assert ol.propose(c, 100.0, 10).tolist() == []
+def test_a_transmission_is_proposed_by_any_frame_it_covers():
+    """The proposed ranges of every frame lying wholly inside a replica at lag tau
+    contain tau, and no other frame's range does."""
+    n, L = 1 << 16, 16384
+    for tau in (0, 1, 127, 128, 30000, n - L):
+        inside = [f for f in range(ol.num_frames(n)) if 128 * f >= tau and 128 * f + 256 <= tau + L]
+        for f in range(ol.num_frames(n)):
+            r = ol.frame_lag_range(f, n, L)
+            hit = r is not None and r[0] <= tau <= r[1]
+            assert hit == (f in inside), (tau, f)
 
 
 def test_frame_lag_range_brute_force():
@@ -242,15 +241,6 @@ def test_segments_for_ranges_brute_force():
     want = sorted({t // V for r in ranges if r for t in range(r[0], r[1] + 1)})
     assert segs.tolist() == want
 
-
-def test_transmission_covers_its_middle_frame():
-    """A replica at lag tau covers frame f when 128 f in [tau, tau + L - 256]; the
-    proposed range of such a frame contains tau."""
-    n, L = 1 << 16, 16384
-    for tau in (0, 1, 127, 128, 30000, n - L):
-        f = (tau + L // 2) // 128 - 1
-        r = ol.frame_lag_range(f, n, L)
-        assert r is not None and r[0] <= tau <= r[1], tau
 
 
 def test_power_map_of_an_empty_block_is_zero():
