@@ -86,7 +86,9 @@ def main():
     ap.add_argument("--workload", default="tagbank_fp32")
     ap.add_argument("--fft-len", type=int, default=0, help="override the workload's segment length")
     ap.add_argument("--tag-tile", type=int, default=0)
-    ap.add_argument("--tune", action="store_true", help="time every launch configuration first, keep the fastest")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the plan-time autotuner (by default every launch configuration is timed once "
+                         "before the timed steps and the fastest kept)")
     ap.add_argument("--graph", action="store_true", help="batched workloads: replay one captured hipGraph per step")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0: skip)")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",

@@ -213,8 +213,9 @@ int acq_set_tuning(acq_plan_t plan, const acq_tuning* tuning);
  * Autotune: time every candidate tuning (engines x tag tiles 4..64 that divide
  * the work sensibly) on the device block `block` of n samples, `reps` runs
  * each (HIP events around the correlation kernel), then both batch launch
- * forms with the fastest engine and tile on the same block as a one-block
- * batch (the last two entries; skipped when n exceeds max_batch_samples).
+ * forms with the fastest engine and tile on a batch of copies of the same
+ * block (as many as the batch capacity holds, at most 16; the last two
+ * entries; skipped when n exceeds max_batch_samples).
  * Keeps the fastest in the plan and writes the candidates to host
  * out[0..capacity) (*n_out = count).
  */

@@ -7,14 +7,14 @@
 //   A : 16-point DFT over m in registers -> A[t][k1]
 //   X1: workgroup exchange through LDS: wave w' receives A[l + 64 m'][k1 = w'];
 //       the outer twiddle exp(s j 2 pi t k1 / N) is split into a wave-uniform
-//       part exp(s j 2 pi w' m' / 256) (LDS table, broadcast reads) and a per-lane part
+//       part exp(s j 2 pi w' m' / 256) (scalar registers) and a per-lane part
 //       exp(s j 2 pi w' l / N) that is common to all m' and is folded into the
 //       next twiddle layer;
 //   B1: 16-point DFT over m' -> k2a, twiddle exp(s j 2 pi l (w' + 16 k2a) / N)
 //       from a table laid out [w'][k2a][l] (prefetched while the workgroup
 //       waits at X1);
 //   X2: wave-private exchange: lane (k2a, q) receives the 16 values l = q + 4 m'';
-//   B2: 16-point DFT over m'' -> kb1, twiddle exp(s j 2 pi q kb1 / 64) (same LDS table);
+//   B2: 16-point DFT over m'' -> kb1, twiddle exp(s j 2 pi q kb1 / 64) (LDS table);
 //   X3: wave-private 4 x 4 exchange inside each lane quad;
 //   B3: 4-point DFTs over q.
 //
@@ -72,12 +72,15 @@ struct Fft14 {
     static constexpr int B1_TABLE = 16 * 16 * 64;
 
     int w, l;
+    float2 wu[16];                                  // exp(+j 2 pi w m / 256), wave-uniform
 
     // roots: exp(+j 2 pi x / N), x < N.  extra: LDS table of EXTRA entries,
     // visible to the workgroup after the first transform's X1 barrier.
     __device__ __forceinline__ void init(const float2* __restrict__ roots, float2* extra) {
         w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
         l = int(threadIdx.x) & 63;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) wu[m] = roots[(w * m * 64) & (N - 1)];
         if (threadIdx.x < EXTRA) extra[threadIdx.x] = roots[threadIdx.x * (N / EXTRA)];
     }
 
@@ -123,7 +126,7 @@ struct Fft14 {
 #pragma unroll
         for (int k2a = PRE; k2a < 16; ++k2a) tb[k2a] = bload(b1tab, tboff, k2a * 512);
 #pragma unroll
-        for (int m = 1; m < 16; ++m) v[m] = cmul(v[m], tw_sign<S>(extra[(w * m) & 255]));
+        for (int m = 1; m < 16; ++m) v[m] = cmul(v[m], tw_sign<S>(wu[m]));
         // B1
         dft16<S>(v);
 #pragma unroll

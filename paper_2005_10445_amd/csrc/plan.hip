@@ -10,6 +10,7 @@
 // detections back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -598,16 +599,24 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
     const acq_tuning before{p->engine, p->tile, p->batch_launch};
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
-    // the same block as a one-block batch (device descriptor table)
+    // the same block repeated as a batch (device descriptor table): as many
+    // copies as the plan's batch capacity holds, at most 16
     BlockTable bbt{};
     bbt.descs = p->d_descs;
     bbt.counts = p->d_counts;
-    const bool batch_ok = n <= p->g.max_batch_samples;
+    const int64_t copies = std::min<int64_t>({int64_t(p->g.max_blocks), p->g.max_batch_samples / n, 16});
+    const bool batch_ok = copies >= 1;
+    int32_t batch_seg = 0;
     if (batch_ok) {
-        p->h_descs[0] = bt.one;
-        p->h_counts[0] = 1;
-        p->h_counts[1] = bt.one.nseg;
-        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(BlockDesc), hipMemcpyHostToDevice, p->stream));
+        for (int64_t b = 0; b < copies; ++b) {
+            p->h_descs[b] = bt.one;
+            p->h_descs[b].seg0 = batch_seg;
+            batch_seg += bt.one.nseg;
+        }
+        p->h_counts[0] = int32_t(copies);
+        p->h_counts[1] = batch_seg;
+        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(BlockDesc) * size_t(copies), hipMemcpyHostToDevice,
+                               p->stream));
         ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
     }
     auto time_one = [&](const acq_tuning& t, bool batch, double* mean_ms) -> int {
@@ -615,7 +624,8 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
         double total = 0.0;
         for (int r = 0; r <= reps; ++r) {           // one warm-up run
             reset_timers(p);
-            const int rc2 = enqueue_search(p, batch ? bbt : bt, batch, bt.one.nseg, nullptr, false, p->stream);
+            const int rc2 = enqueue_search(p, batch ? bbt : bt, batch, batch ? batch_seg : bt.one.nseg, nullptr, false,
+                                           p->stream);
             if (rc2 != ACQ_OK) return rc2;
             ACQ_HIP(hipStreamSynchronize(p->stream));
             float ms = 0.f;
