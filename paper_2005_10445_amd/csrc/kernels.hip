@@ -61,13 +61,30 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// One step of a wave maximum: each lane takes the larger of its value and the
+// value DPP control CTRL routes to it (lanes with no source, or in rows outside
+// ROW_MASK, see 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, ROW_MASK, 0xf, true);
+    const unsigned long long t = (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo);
+    return t > v ? t : v;
+}
+
+// Maximum over the wave (uniform result, no LDS): row_shr 1, 2, 4, 8 leave each
+// 16-lane row's maximum in its lane 15; row_bcast 15 (into rows 1 and 3) and
+// row_bcast 31 (into rows 2 and 3) carry the total to lane 63.
 __device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
+    v = dpp_max_step<0x111, 0xf>(v);
+    v = dpp_max_step<0x112, 0xf>(v);
+    v = dpp_max_step<0x114, 0xf>(v);
+    v = dpp_max_step<0x118, 0xf>(v);
+    v = dpp_max_step<0x142, 0xa>(v);
+    v = dpp_max_step<0x143, 0xc>(v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(v)), 63));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(v >> 32)), 63));
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
 // ------------------------------------------------------------------ block power
@@ -322,30 +339,36 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
 #pragma unroll
         for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], St::bload(bank, voff, (tt * N + m * E::NT) * St::BYTES));
         eng.template transform<+1>(v, lds, b1, extra, hi);
-        unsigned long long best = 0ull;
         // per-register indices and masks are the same for every tag: keep the
         // optimiser from holding all of them across the loop (recomputing is cheap)
         int ob = ob0;
         unsigned idx0 = idx00;
         asm volatile("" : "+v"(ob), "+v"(idx0));
+        // this lane's largest valid power; registers are visited in increasing
+        // output index, so the strict comparison keeps the smallest lag of a tie
+        float bp = -1.0f;
+        int boff = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int rr = 0; rr < 16; ++rr) {
+            const int r = ((rr & 3) << 2) | (rr >> 2);
             const int off = E::out_off(r);
             if (omin + off < ulim) {               // wave-uniform: some lane of this register is valid
-                const float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
-                const unsigned idx = idx0 + unsigned(off) * kstep;
-                unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(p)) << 32) |
-                                         static_cast<unsigned long long>(~idx);
-                if (omax + off >= ulim && ob + off >= ulim) key = 0ull;
-                best = key > best ? key : best;
+                float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
                 if constexpr (DUMP) {
                     if (ob + off < ulim) {
                         const int64_t tau = seg0 + int64_t(a.spc) * (ob + off) + rho;
                         a.dump[(size_t(tag0 + tt) * a.K + k) * size_t(d.lags) + size_t(tau)] = p;
                     }
                 }
+                if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
+                boff = p > bp ? off : boff;
+                bp = p > bp ? p : bp;
             }
         }
+        unsigned long long best = bp >= 0.0f
+            ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) |
+                  static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
+            : 0ull;
         best = wave_max(best);
         if (lane == 0) red[tt * NW + wave] = best;
     }
