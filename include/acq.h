@@ -382,6 +382,15 @@ int acq_detect_learned(acq_plan_t plan, acq_cnn_t cnn, const void* block, int64_
                        const acq_learned_params* params, acq_detection* out, int32_t capacity,
                        int32_t* n_found, acq_learned_report* report);
 
+/* The proposal search over a batch of device blocks (as acq_detect_batch):
+ * proposals block by block (in order, each updating the noise floor), then one
+ * batched search over the proposed (or, on a fallback, all) segments of every
+ * block.  reports: host [nblocks] or NULL.  Detections carry their block index.
+ * Synchronous; not captured into a graph. */
+int acq_detect_batch_learned(acq_plan_t plan, acq_cnn_t cnn, const void* const* blocks, const int64_t* lens,
+                             int32_t nblocks, const acq_learned_params* params, acq_detection* out,
+                             int32_t capacity, int32_t* n_found, acq_learned_report* reports);
+
 /* Static description of a status code. */
 const char* acq_strerror(int status);
 

@@ -31,7 +31,7 @@ EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect"
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
             "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
-            "acq_detect_learned", "acq_strerror", "acq_last_error")
+            "acq_detect_learned", "acq_detect_batch_learned", "acq_strerror", "acq_last_error")
 ACQ_SYNTH_MAX_TX = 32
 ACQ_FALLBACK_NONE, ACQ_FALLBACK_FRACTION, ACQ_FALLBACK_FLOOR = 0, 1, 2
 KERNELS = ("block_power", "forward", "correlate", "refine", "compact")
@@ -196,12 +196,14 @@ def lib(path: str = LIB_PATH):
     L.acq_cnn_train_synthetic.argtypes = [vp, P(AcqSynthBatch), f32, f32, P(ctypes.c_float)]
     L.acq_detect_learned.argtypes = [vp, vp, vp, i64, P(AcqLearnedParams), P(AcqDetection), i32, P(i32),
                                      P(AcqLearnedReport)]
+    L.acq_detect_batch_learned.argtypes = [vp, vp, P(vp), P(i64), i32, P(AcqLearnedParams), P(AcqDetection), i32,
+                                           P(i32), P(AcqLearnedReport)]
     for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
                  "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
                  "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create", "acq_cnn_release",
                  "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
                  "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
-                 "acq_detect_learned"):
+                 "acq_detect_learned", "acq_detect_batch_learned"):
         getattr(L, name).restype = ctypes.c_int
     L.acq_strerror.argtypes = [ctypes.c_int]
     L.acq_strerror.restype = ctypes.c_char_p

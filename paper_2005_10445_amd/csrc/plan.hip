@@ -62,7 +62,9 @@ struct acq_plan_s {
     int32_t* h_count = nullptr;         // pinned [1]
     BlockDesc* h_descs = nullptr;       // pinned [blocks]
     int32_t* h_counts = nullptr;        // pinned [2]
-    int32_t* d_seglist = nullptr;       // [max_segments] segments proposed for a learned search
+    int32_t* d_seglist = nullptr;       // [max(max_segments, max_total_segments)] segments searched by a
+                                        // learned search (per block, concatenated for batches)
+    int32_t* h_iota = nullptr;          // pinned [max_segments] 0, 1, 2, ... (full-search lists)
 
     bool profiling = false;
     bool capturing = false;
@@ -110,7 +112,7 @@ void free_plan(acq_plan_s* p) {
                    p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
     for (void* d : dev)
         if (d) (void)hipFree(d);
-    void* host[] = {p->h_out, p->h_count, p->h_descs, p->h_counts};
+    void* host[] = {p->h_out, p->h_count, p->h_descs, p->h_counts, p->h_iota};
     for (void* h : host)
         if (h) (void)hipHostFree(h);
     for (auto& pair : p->ev)
@@ -151,7 +153,10 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_counters, size_t(acq::kXcds)));
     ACQ_HIP(dalloc(&p->d_descs, B));
     ACQ_HIP(dalloc(&p->d_counts, 2));
-    ACQ_HIP(dalloc(&p->d_seglist, size_t(g.max_segments > 0 ? g.max_segments : 1)));
+    const size_t seglist = size_t(std::max<int64_t>({g.max_segments, g.max_total_segments, 1}));
+    ACQ_HIP(dalloc(&p->d_seglist, seglist));
+    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_iota), sizeof(int32_t) * size_t(std::max<int64_t>(g.max_segments, 1))));
+    for (int64_t j = 0; j < g.max_segments; ++j) p->h_iota[j] = int32_t(j);
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_detection) * B * T));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t)));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_descs), sizeof(BlockDesc) * B));
@@ -485,6 +490,38 @@ int acq_detect_batch(acq_plan_t p, const void* const* blocks, const int64_t* len
     return deliver(p, out, capacity, n_found);
 }
 
+// Proposals of one block (n >= L) written to d_segs; on a fallback the full
+// list 0 .. nseg-1 instead.  Fills the report and the searched segment count.
+int propose_block(acq_plan_s* p, acq_cnn_t cnn, const void* block, int64_t n, const acq_learned_params* lp,
+                  int32_t* d_segs, acq_learned_report* rep, int32_t* nseg_out) {
+    double floor = 0.0;
+    const bool have_floor = acq::cnn_floor(cnn, &floor);
+    rep->floor = float(floor);
+    const BlockDesc d = single_desc(p, block, n);
+    rep->total_segments = d.nseg;
+    acq::ProposalResult pr{};
+    const int rc = acq::cnn_propose(cnn, block, n, p->g.L, p->g.V, int32_t(p->g.max_segments), lp->kappa, d_segs,
+                                    p->stream, &pr);
+    if (rc != ACQ_OK) return rc;
+    rep->proposals = pr.proposals;
+    rep->median = pr.median;
+    rep->fallback = ACQ_FALLBACK_NONE;
+    if (double(pr.segments) > double(lp->max_fraction) * double(d.nseg))
+        rep->fallback = ACQ_FALLBACK_FRACTION;
+    else if (lp->floor_db > 0.0f && have_floor && floor > 0.0 && pr.median > 0.0f &&
+             std::fabs(10.0 * std::log10(double(pr.median) / floor)) > double(lp->floor_db))
+        rep->fallback = ACQ_FALLBACK_FLOOR;
+    acq::cnn_update_floor(cnn, double(pr.median));
+    if (rep->fallback == ACQ_FALLBACK_NONE) {
+        rep->segments = pr.segments;
+    } else {
+        rep->segments = d.nseg;
+        ACQ_HIP(hipMemcpyAsync(d_segs, p->h_iota, sizeof(int32_t) * size_t(d.nseg), hipMemcpyHostToDevice, p->stream));
+    }
+    *nseg_out = rep->segments;
+    return ACQ_OK;
+}
+
 int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n, const acq_learned_params* lp,
                        acq_detection* out, int32_t capacity, int32_t* n_found, acq_learned_report* report) {
     int rc = check_block(p, block, n);
@@ -494,10 +531,10 @@ int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n
     if (!(lp->max_fraction >= 0.0f)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad proposal parameters");
     *n_found = 0;
     acq_learned_report rep{};
-    double floor = 0.0;
-    const bool have_floor = acq::cnn_floor(cnn, &floor);
-    rep.floor = float(floor);
     if (n < p->g.L) {
+        double floor = 0.0;
+        (void)acq::cnn_floor(cnn, &floor);
+        rep.floor = float(floor);
         if (report) *report = rep;
         acq::clear_error();
         return ACQ_OK;
@@ -505,32 +542,74 @@ int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n
     reset_timers(p);
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
-    rep.total_segments = bt.one.nseg;
-    acq::ProposalResult pr{};
-    rc = acq::cnn_propose(cnn, block, n, p->g.L, p->g.V, int32_t(p->g.max_segments), lp->kappa, p->d_seglist,
-                          p->stream, &pr);
+    int32_t nseg = 0;
+    rc = propose_block(p, cnn, block, n, lp, p->d_seglist, &rep, &nseg);
     if (rc != ACQ_OK) return rc;
-    rep.proposals = pr.proposals;
-    rep.median = pr.median;
-    if (double(pr.segments) > double(lp->max_fraction) * double(bt.one.nseg))
-        rep.fallback = ACQ_FALLBACK_FRACTION;
-    else if (lp->floor_db > 0.0f && have_floor && floor > 0.0 && pr.median > 0.0f &&
-             std::fabs(10.0 * std::log10(double(pr.median) / floor)) > double(lp->floor_db))
-        rep.fallback = ACQ_FALLBACK_FLOOR;
-    acq::cnn_update_floor(cnn, double(pr.median));
-    if (rep.fallback == ACQ_FALLBACK_NONE) {
-        rep.segments = pr.segments;
-        bt.one.nseg = pr.segments;
-        bt.seg_of = p->d_seglist;
-    } else {
-        rep.segments = bt.one.nseg;
-    }
     if (report) *report = rep;
-    if (bt.one.nseg == 0) {
+    if (nseg == 0) {
         acq::clear_error();
         return ACQ_OK;
     }
-    rc = enqueue_search(p, bt, false, bt.one.nseg, nullptr, true, p->stream);
+    bt.one.nseg = nseg;
+    bt.seg_of = p->d_seglist;
+    rc = enqueue_search(p, bt, false, nseg, nullptr, true, p->stream);
+    if (rc != ACQ_OK) return rc;
+    ACQ_HIP(hipStreamSynchronize(p->stream));
+    return deliver(p, out, capacity, n_found);
+}
+
+int acq_detect_batch_learned(acq_plan_t p, acq_cnn_t cnn, const void* const* blocks, const int64_t* lens,
+                             int32_t nblocks, const acq_learned_params* lp, acq_detection* out, int32_t capacity,
+                             int32_t* n_found, acq_learned_report* reports) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (!cnn || !lp || !blocks || !lens || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (!(lp->max_fraction >= 0.0f)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad proposal parameters");
+    if (nblocks < 1 || nblocks > p->g.max_blocks)
+        return acq::fail(ACQ_ERR_INVALID_ARG, "nblocks outside [1, max_batch_blocks]");
+    int64_t total = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        const int rc = check_block(p, blocks[b], lens[b]);
+        if (rc != ACQ_OK) return rc;
+        total += lens[b];
+    }
+    if (total > p->g.max_batch_samples)
+        return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "batch longer than max_batch_samples");
+    *n_found = 0;
+    reset_timers(p);
+    int32_t seg = 0;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        BlockDesc d = single_desc(p, blocks[b], lens[b]);
+        acq_learned_report rep{};
+        int32_t nseg = 0;
+        if (lens[b] >= p->g.L) {
+            const int rc = propose_block(p, cnn, blocks[b], lens[b], lp, p->d_seglist + seg, &rep, &nseg);
+            if (rc != ACQ_OK) return rc;
+        } else {
+            double floor = 0.0;
+            (void)acq::cnn_floor(cnn, &floor);
+            rep.floor = float(floor);
+        }
+        if (reports) reports[b] = rep;
+        d.seg0 = seg;
+        d.nseg = nseg;
+        seg += nseg;
+        p->h_descs[b] = d;
+    }
+    if (seg == 0) {
+        acq::clear_error();
+        return ACQ_OK;
+    }
+    p->h_counts[0] = nblocks;
+    p->h_counts[1] = seg;
+    BlockTable bt{};
+    bt.descs = p->d_descs;
+    bt.counts = p->d_counts;
+    bt.seg_of = p->d_seglist;
+    ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(BlockDesc) * size_t(nblocks), hipMemcpyHostToDevice,
+                           p->stream));
+    ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+    const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream);
     if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
     return deliver(p, out, capacity, n_found);

@@ -178,6 +178,26 @@ class Network:
         return dets, LearnedReport(rep.proposals, rep.segments, rep.total_segments, rep.fallback, rep.median,
                                    rep.floor)
 
+    def detect_batch(self, plan, blocks, params: LearnedParams):
+        """acq_detect_batch_learned over a list of device blocks: (detections, [LearnedReport])."""
+        from . import Detection
+        n = len(blocks)
+        ptrs = (ctypes.c_void_p * n)()
+        lens = (ctypes.c_int64 * n)()
+        for i, b in enumerate(blocks):
+            ptrs[i], lens[i] = _dev(b, "block"), b.numel()
+        cap = n * plan.num_tags
+        out = (_capi.AcqDetection * cap)()
+        reps = (_capi.AcqLearnedReport * n)()
+        nf = ctypes.c_int32(0)
+        lp = _capi.AcqLearnedParams(float(params.kappa), float(params.max_fraction), float(params.floor_db))
+        check(self._lib.acq_detect_batch_learned(plan._h, self._h, ptrs, lens, n, ctypes.byref(lp), out, cap,
+                                                 ctypes.byref(nf), reps), "acq_detect_batch_learned")
+        dets = [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
+                          d.block_power, d.block, d.flags) for d in out[:nf.value]]
+        return dets, [LearnedReport(r.proposals, r.segments, r.total_segments, r.fallback, r.median, r.floor)
+                      for r in reps]
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.acq_cnn_release(self._h)

@@ -202,9 +202,11 @@ def cmd_evaluate(args):
     t_full = t_learned = 0.0
     hit = total = extra = thit = ttotal = 0
     segs = segs_total = fallbacks = 0
-    for x, (_, txs) in zip(xs, data):
+    full_keys = set()
+    for b, (x, (_, txs)) in enumerate(zip(xs, data)):
         t0 = time.perf_counter()
         full = plan.detect(x)
+        full_keys |= {(b, d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in full}
         t1 = time.perf_counter()
         dets, rep = net.detect(plan, x, lp)
         t2 = time.perf_counter()
@@ -226,13 +228,25 @@ def cmd_evaluate(args):
     t0 = time.perf_counter()
     plan.detect_batch(xs)
     t_batch = time.perf_counter() - t0
+    # the batched proposal search (fresh noise floor, as for the per-block pass)
+    net2 = Network("bf16", 256, max_rows=1 << 15, max_block_len=1 << 21)
+    net2.set_params(np.load(args.weights))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bdets, breps = net2.detect_batch(plan, xs, lp)
+    t_batch_learned = time.perf_counter() - t0
+    bk = {(d.block, d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in bdets}
+
     out = {"blocks": len(xs), "samples": int(sum(x.numel() for x in xs)), "kappa": meta["kappa"],
            "recall_all": hit / max(total, 1), "recall_injected": thit / max(ttotal, 1),
            "exhaustive_detections": total, "exhaustive_injected_detections": ttotal, "extra_detections": extra,
            "segments_searched": segs / max(segs_total, 1), "fallbacks": fallbacks,
            "ms_exhaustive_per_block_calls": 1e3 * t_full, "ms_exhaustive_batch": 1e3 * t_batch,
            "ms_learned": 1e3 * t_learned, "speedup_vs_per_block": t_full / t_learned,
-           "speedup_vs_batch": t_batch / t_learned}
+           "speedup_vs_batch": t_batch / t_learned,
+           "ms_learned_batch": 1e3 * t_batch_learned, "speedup_batch_learned_vs_batch": t_batch / t_batch_learned,
+           "recall_all_batch_learned": len(full_keys & bk) / max(len(full_keys), 1),
+           "extra_detections_batch_learned": len(bk - full_keys)}
     log(json.dumps(out))
     if args.report:
         with open(args.report, "w") as f:

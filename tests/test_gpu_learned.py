@@ -328,3 +328,44 @@ def test_proposal_search_fallbacks_equal_exhaustive(dev):
         dets, rep = net.detect(plan, 2 * xt, LearnedParams(kappa=1e30, max_fraction=1.0, floor_db=1.0))
         assert rep.fallback == 2 and abs(rep.median / rep.floor - 4.0) < 0.5
         assert key(dets) == key(plan.detect(2 * xt))
+
+
+def test_batched_proposal_search_equals_per_block(dev):
+    """One batched search over the proposed segments of several blocks returns
+    what per-block proposal searches return (floor updates in the same order),
+    including a fallback block and a block shorter than a template."""
+    from paper_2005_10445_amd import Plan
+    from paper_2005_10445_amd.proposals import LearnedParams
+    T, C, spc, K, step = 8, 2048, 2, 3, 5e3
+    L = C * spc
+    chips = siggen.make_codes(50, T, C)
+    lens = [1 << 18, 150000, L - 5, 200001]
+    net_params = _flat(_rand_net(51, 256))
+    with Plan(chips, spc, FS, num_bins=K, bin_step_hz=step, max_block_len=1 << 18, fft_len=8192,
+              max_batch_blocks=4) as plan:
+        xs = []
+        for b, n in enumerate(lens):
+            ntx = 3 if n > L else 0
+            x, _ = siggen.make_block(52 + b, n, chips, spc, FS, plan.freqs_hz, ntx, snr_db=(-5.0, 5.0))
+            xs.append(torch.from_numpy(x).to(dev))
+        xs[3] = 1.5 * xs[3]                        # 3.5 dB louder: the floor rule fires
+        with _net("bf16", max_block_len=1 << 18) as net:
+            net.set_params(net_params)
+            m, _ = net.power_map(xs[0])
+            c = ol.window_scores(net.forward(m).cpu().numpy().astype(np.float64))
+            lp = LearnedParams(kappa=float(np.quantile(c, 0.9)), max_fraction=0.6, floor_db=1.0)
+            per, per_rep = [], []
+            for b, x in enumerate(xs):
+                dets, rep = net.detect(plan, x, lp)
+                for d in dets:
+                    d.block = b
+                per += dets
+                per_rep.append(rep)
+        with _net("bf16", max_block_len=1 << 18) as net:
+            net.set_params(net_params)
+            batch, reps = net.detect_batch(plan, xs, lp)
+    key = lambda ds: [(d.block, d.tag, d.bin, d.lag, d.toa, d.peak_power, d.z) for d in ds]   # noqa: E731
+    assert key(batch) == key(per)
+    assert [(r.proposals, r.segments, r.total_segments, r.fallback) for r in reps] == \
+        [(r.proposals, r.segments, r.total_segments, r.fallback) for r in per_rep]
+    assert reps[2].total_segments == 0 and reps[3].fallback == 2
