@@ -54,7 +54,7 @@ struct CorrArgs {
     BlockTable blocks;
     const void* X;              // [segments][M] spectra (storage format)
     const void* bank;           // [T][Msub] 2^bank_exp conj(DFT_Msub(chips)) / M (storage format)
-    const double* parts;        // [block][kPowerParts] partial sums of |x|^2
+    const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
     const float2* rect;         // [M] sum_{r<spc} exp(+j 2 pi i r / M)
     const float2* rootsM;       // [M] exp(+j 2 pi m / M)
     const float2* rootsSub;     // [Msub] exp(+j 2 pi m / Msub)
@@ -70,9 +70,9 @@ struct CorrArgs {
 
 struct FwdArgs {
     BlockTable blocks;
-    float2* X;                  // [segments][M] FP32 spectra (accumulator)
+    float2* X;                  // [segments][M] FP32 spectra (sub-transforms, then the result)
     void* Xh;                   // [segments][M] 16-bit copy (FP16/BF16 plans only)
-    const double* parts;        // [block][kPowerParts]
+    const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
     const float2* rootsM;
     const float2* rootsSub;
     const float2* b1tab;
@@ -95,9 +95,14 @@ struct RefineArgs {
 };
 
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);
+// exps[b] = round(log2(sqrt(M * Pxhat_b))): the 16-bit storage prescale of block b
+hipError_t launch_block_exponent(const BlockTable& bt, int max_blocks, const double* parts, int M, int* exps,
+                                 hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, hipStream_t st);
-hipError_t launch_forward(const FwdArgs& a, int grid, int log2_sub, int prec, hipStream_t st);
+// grid: workgroups of the sub-transforms (items = segments * spc); combine_slots:
+// segment slots the combine step covers (>= the segments in use)
+hipError_t launch_forward(const FwdArgs& a, int grid, int combine_slots, int log2_sub, int prec, hipStream_t st);
 hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const float2* rootsSub,
                        const float2* b1tab, int Msub, int M, int bank_exp, int log2_sub, int prec,
                        hipStream_t st);

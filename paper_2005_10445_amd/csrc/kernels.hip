@@ -1,9 +1,9 @@
 // HIP kernels of the acquisition path (gfx950).
 //
 //   k_block_power  : FP64 partial sums of |x|^2 (mean block power Pxhat)
-//   k_forward      : overlap-save segment j, X_j = DFT_M(x[jV .. jV+M)) with a zero
-//                    tail, as spc decimated Msub-point transforms combined by one
-//                    radix-spc decimation-in-time step
+//   k_forward_*    : overlap-save segment j, X_j = DFT_M(x[jV .. jV+M)) with a zero
+//                    tail, as spc decimated Msub-point transforms (one workgroup
+//                    each) combined by one radix-spc decimation-in-time step
 //   k_bank         : replica spectra conj(DFT_Msub(chip code)) / M, plan time
 //   k_correlate    : the hot loop, see below
 //   k_refine       : FP64 re-correlation around each tag's peak, re-maximisation,
@@ -167,72 +167,79 @@ using dev::make_rsrc;
 
 // ------------------------------------------------------------------ forward spectra
 // Power-of-two prescale of the stored segment spectra for 16-bit storage:
-// 2^-e with e = round(log2(sqrt(M * Pxhat))), so typical |X| is near 1.
-__device__ __forceinline__ int spectrum_exponent(const double* __restrict__ parts, int64_t n, int M) {
-    __shared__ int s_e;
-    if (threadIdx.x == 0) {
-        const double px = block_mean_power(parts, n);
-        s_e = px > 0.0 ? int(rint(0.5 * log2(double(M) * px))) : 0;
-    }
-    __syncthreads();
-    const int e = s_e;
-    __syncthreads();
-    return e;
+// 2^-e with e = round(log2(sqrt(M * Pxhat))), so typical |X| is near 1.  One
+// value per block, computed once after the block power (grid = max_blocks).
+__global__ void k_block_exponent(BlockTable bt, const double* __restrict__ parts, int M, int* __restrict__ exps) {
+    const int b = int(blockIdx.x);
+    if (threadIdx.x != 0 || b >= bt.nblocks()) return;
+    const BlockDesc d = bt.get(b);
+    const double px = block_mean_power(parts + size_t(b) * kPowerParts, d.n);
+    exps[b] = px > 0.0 ? int(rint(0.5 * log2(double(M) * px))) : 0;
 }
 
 // One workgroup per global segment g (looping when the grid is smaller):
 // X_g = DFT_M of the segment held in slot g (segment g - seg0 of its block, or
-// the listed segment when only some segments are searched).
-template <class E, int PREC>
-__global__ __launch_bounds__(E::NT) void k_forward(FwdArgs a) {
-    using St = dev::Storage<PREC>;
+// the listed segment when only some segments are searched), in two kernels:
+//
+// k_forward_sub: work item (g, r), r < spc: the Msub-point DFT of the decimated
+//   samples x[base + spc*i + r] (zero beyond the block), F_r, written to
+//   X_g[r*Msub + i].  One workgroup per item (a loop over items for batches).
+// k_forward_combine: the radix-spc decimation-in-time step, in place per i:
+//   X_g[i + q*Msub] = F_0[i] + sum_{r>=1} exp(-j 2 pi (i + q*Msub) r / M) F_r[i],
+//   accumulated in FP32 in increasing r; 16-bit plans store the result scaled
+//   and packed in the 16-bit copy instead.
+template <class E>
+__global__ __launch_bounds__(E::NT) void k_forward_sub(FwdArgs a) {
     __shared__ float2 lds[E::LDS];
     __shared__ float2 extra[E::EXTRA];
     E eng;
     eng.init(a.rootsSub, extra);
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const int mmask = a.M - 1;
-    const int total = a.blocks.total_seg();
-    for (int g = int(blockIdx.x); g < total; g += int(gridDim.x)) {
+    const int items = a.blocks.total_seg() * a.spc;
+    for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
+        const int g = it / a.spc, r = it - g * a.spc;
         const int bi = a.blocks.block_of_segment(g);
         const BlockDesc d = a.blocks.get(bi);
         const int64_t base = int64_t(a.blocks.segment(g, d)) * a.V;
-        float2* Xg = a.X + size_t(g) * size_t(a.M);
-        float xs = 1.0f;
-        if constexpr (PREC != ACQ_FP32)
-            xs = ldexpf(1.0f, -spectrum_exponent(a.parts + size_t(bi) * kPowerParts, d.n, a.M));
-        for (int r = 0; r < a.spc; ++r) {
-            float2 v[16];
+        float2 v[16];
 #pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const int64_t idx = base + int64_t(a.spc) * eng.in_index(m) + r;
-                v[m] = idx < d.n ? d.x[idx] : make_float2(0.f, 0.f);
-            }
-            eng.template transform<-1>(v, lds, b1, extra);
-            // X[i] += exp(-j 2 pi i r / M) F_r[i mod Msub], accumulated in FP32
-            const int ob = eng.out_base();
-            const bool last = r == a.spc - 1;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const int ip = ob + E::out_off(m);
-                for (int q = 0; q < a.spc; ++q) {
-                    const int i = ip + q * a.Msub;
-                    float2 c = v[m];
-                    if (r) c = cmulc(c, a.rootsM[(int)((int64_t(i) * r) & mmask)]);
-                    if (r) c = cadd(Xg[i], c);
-                    if constexpr (PREC == ACQ_FP32) {
-                        Xg[i] = c;
-                    } else {
-                        if (last)
-                            reinterpret_cast<typename St::T*>(a.Xh)[size_t(g) * size_t(a.M) + i] =
-                                St::pack(make_float2(c.x * xs, c.y * xs));
-                        else
-                            Xg[i] = c;
-                    }
-                }
-            }
-            __syncthreads();
+        for (int m = 0; m < 16; ++m) {
+            const int64_t idx = base + int64_t(a.spc) * eng.in_index(m) + r;
+            v[m] = idx < d.n ? d.x[idx] : make_float2(0.f, 0.f);
         }
+        eng.template transform<-1>(v, lds, b1, extra);
+        float2* F = a.X + size_t(g) * size_t(a.M) + size_t(r) * size_t(a.Msub);
+        const int ob = eng.out_base();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) F[ob + E::out_off(m)] = v[m];
+        __syncthreads();                 // LDS is reused by the next item
+    }
+}
+
+// 256 threads per workgroup, one i per thread; a workgroup's 256 i lie in one
+// slot (Msub is a multiple of 256).  Workgroups past the slots in use exit.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
+    using St = dev::Storage<PREC>;
+    const int per_slot = a.Msub / 256;
+    const int g = int(blockIdx.x) / per_slot;
+    if (g >= a.blocks.total_seg()) return;
+    const int i = (int(blockIdx.x) - g * per_slot) * 256 + int(threadIdx.x);
+    float2* X = a.X + size_t(g) * size_t(a.M);
+    float xs = 1.0f;
+    if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -a.exps[a.blocks.block_of_segment(g)]);
+    const int mmask = a.M - 1;
+    float2 F[8];
+    for (int r = 0; r < a.spc; ++r) F[r] = X[r * a.Msub + i];
+    for (int q = 0; q < a.spc; ++q) {
+        const int io = i + q * a.Msub;
+        float2 c = F[0];
+        for (int r = 1; r < a.spc; ++r) c = cadd(c, cmulc(F[r], a.rootsM[(int)((int64_t(io) * r) & mmask)]));
+        if constexpr (PREC == ACQ_FP32)
+            X[io] = c;
+        else
+            reinterpret_cast<typename St::T*>(a.Xh)[size_t(g) * size_t(a.M) + io] =
+                St::pack(make_float2(c.x * xs, c.y * xs));
     }
 }
 
@@ -286,7 +293,6 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     const int bi = a.blocks.block_of_segment(g);
     const BlockDesc d = a.blocks.get(bi);
     const int j = a.blocks.segment(g, d);
-    const double* parts = a.parts + size_t(bi) * kPowerParts;
     unsigned long long* keys = a.keys + size_t(bi) * a.T;
 
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
@@ -294,7 +300,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
         make_rsrc(static_cast<const char*>(a.bank) + size_t(tag0) * N * St::BYTES, uint32_t(ntag) * N * St::BYTES);
     // stored spectra carry 2^-x_exp (segments) and 2^bank_exp (bank): undo both in G
     float gscale = 1.0f;
-    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, spectrum_exponent(parts, d.n, a.M) - a.bank_exp);
+    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, a.exps[bi] - a.bank_exp);
 
     // tag-independent first step of the inverse transform
     float2 G[16];
@@ -580,6 +586,12 @@ hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* part
     return hipGetLastError();
 }
 
+hipError_t launch_block_exponent(const BlockTable& bt, int max_blocks, const double* parts, int M, int* exps,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_block_exponent, dim3(unsigned(max_blocks)), dim3(64), 0, st, bt, parts, M, exps);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int64_t blocks = (count + 255) / 256;
@@ -595,27 +607,32 @@ hipError_t launch_fill_i32(int* p, int64_t count, hipStream_t st) {
 }
 
 template <class E>
-static hipError_t fwd_e(const FwdArgs& a, int grid, int prec, hipStream_t st) {
-    switch (prec) {
-        case ACQ_FP32: hipLaunchKernelGGL((k_forward<E, ACQ_FP32>), dim3(grid), dim3(E::NT), 0, st, a); break;
-        case ACQ_FP16: hipLaunchKernelGGL((k_forward<E, ACQ_FP16>), dim3(grid), dim3(E::NT), 0, st, a); break;
-        case ACQ_BF16: hipLaunchKernelGGL((k_forward<E, ACQ_BF16>), dim3(grid), dim3(E::NT), 0, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
+static hipError_t fwd_e(const FwdArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((k_forward_sub<E>), dim3(grid), dim3(E::NT), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs& a, int grid, int log2_sub, int prec, hipStream_t st) {
-    if (grid <= 0) return hipSuccess;
-    if ((1 << log2_sub) != a.Msub) return hipErrorInvalidValue;
+hipError_t launch_forward(const FwdArgs& a, int grid, int combine_slots, int log2_sub, int prec, hipStream_t st) {
+    if (grid <= 0 || combine_slots <= 0) return hipSuccess;
+    if ((1 << log2_sub) != a.Msub || a.Msub % 256 || a.spc < 1 || a.spc > 8) return hipErrorInvalidValue;
+    hipError_t e;
     switch (log2_sub) {
-        case 10: return fwd_e<StockhamEngine<10>>(a, grid, prec, st);
-        case 11: return fwd_e<StockhamEngine<11>>(a, grid, prec, st);
-        case 12: return fwd_e<StockhamEngine<12>>(a, grid, prec, st);
-        case 13: return fwd_e<StockhamEngine<13>>(a, grid, prec, st);
-        case 14: return fwd_e<Fft14>(a, grid, prec, st);
+        case 10: e = fwd_e<StockhamEngine<10>>(a, grid, st); break;
+        case 11: e = fwd_e<StockhamEngine<11>>(a, grid, st); break;
+        case 12: e = fwd_e<StockhamEngine<12>>(a, grid, st); break;
+        case 13: e = fwd_e<StockhamEngine<13>>(a, grid, st); break;
+        case 14: e = fwd_e<Fft14>(a, grid, st); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    const dim3 cgrid(unsigned(combine_slots) * unsigned(a.Msub / 256));
+    switch (prec) {
+        case ACQ_FP32: hipLaunchKernelGGL((k_forward_combine<ACQ_FP32>), cgrid, dim3(256), 0, st, a); break;
+        case ACQ_FP16: hipLaunchKernelGGL((k_forward_combine<ACQ_FP16>), cgrid, dim3(256), 0, st, a); break;
+        case ACQ_BF16: hipLaunchKernelGGL((k_forward_combine<ACQ_BF16>), cgrid, dim3(256), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <class E>

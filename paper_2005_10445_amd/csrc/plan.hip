@@ -51,6 +51,7 @@ struct acq_plan_s {
     double* d_freqs = nullptr;          // [K]
     unsigned long long* d_keys = nullptr;   // [blocks][T]
     double* d_parts = nullptr;          // [blocks][kPowerParts]
+    int* d_exps = nullptr;              // [blocks] 16-bit storage prescale exponents
     acq_detection* d_dets = nullptr;    // [blocks][T]
     acq_detection* d_out = nullptr;     // [blocks][T]
     int32_t* d_found = nullptr;         // [blocks][T]
@@ -108,7 +109,7 @@ void free_plan(acq_plan_s* p) {
     drop_graph(p);
     void* dev[] = {p->d_X, p->d_Xh, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
                    p->d_chips,
-                   p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_dets,
+                   p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_exps, p->d_dets,
                    p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
     for (void* d : dev)
         if (d) (void)hipFree(d);
@@ -146,6 +147,7 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_freqs, K));
     ACQ_HIP(dalloc(&p->d_keys, B * T));
     ACQ_HIP(dalloc(&p->d_parts, B * size_t(acq::kPowerParts)));
+    ACQ_HIP(dalloc(&p->d_exps, B));
     ACQ_HIP(dalloc(&p->d_dets, B * T));
     ACQ_HIP(dalloc(&p->d_out, B * T));
     ACQ_HIP(dalloc(&p->d_found, B * T));
@@ -220,13 +222,14 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
         KernelTimer kt(p, ACQ_KERNEL_BLOCK_POWER);
         ACQ_HIP(acq::launch_block_power(bt, nb_grid, p->d_parts, st));
     }
+    if (c.precision != ACQ_FP32) ACQ_HIP(acq::launch_block_exponent(bt, nb_grid, p->d_parts, int(g.M), p->d_exps, st));
     ACQ_HIP(acq::launch_fill_u64(p->d_keys, int64_t(nb_grid) * c.num_tags, st));
 
     acq::FwdArgs fa{};
     fa.blocks = bt;
     fa.X = p->d_X;
     fa.Xh = p->d_Xh;
-    fa.parts = p->d_parts;
+    fa.exps = p->d_exps;
     fa.rootsM = p->d_rootsM;
     fa.rootsSub = p->d_rootsSub;
     fa.b1tab = p->d_b1tab;
@@ -236,15 +239,18 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     fa.Msub = int(g.Msub);
     {
         KernelTimer kt(p, ACQ_KERNEL_FORWARD);
-        const int grid = batch ? p->cus : total_seg_host;
-        ACQ_HIP(acq::launch_forward(fa, grid, g.log2_sub, c.precision, st));
+        // batches: a loop over items on a fixed grid and a combine step sized for
+        // the capacity when captured; single blocks: one workgroup per item
+        const int grid = batch ? p->cus : total_seg_host * c.samples_per_chip;
+        const int slots = batch && p->capturing ? int(g.max_total_segments) : total_seg_host;
+        ACQ_HIP(acq::launch_forward(fa, grid, slots, g.log2_sub, c.precision, st));
     }
 
     acq::CorrArgs ca{};
     ca.blocks = bt;
     ca.X = c.precision == ACQ_FP32 ? static_cast<const void*>(p->d_X) : p->d_Xh;
     ca.bank = p->d_bank;
-    ca.parts = p->d_parts;
+    ca.exps = p->d_exps;
     ca.rect = p->d_rect;
     ca.rootsM = p->d_rootsM;
     ca.rootsSub = p->d_rootsSub;
