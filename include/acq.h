@@ -24,7 +24,10 @@
  * neighbourhood is re-correlated in FP64, re-maximised within +/- refine_radius
  * lags, and the time of arrival is the vertex of the parabola through the
  * powers at the peak lag and its two neighbours (the interpolation of
- * Section 3, step 8).
+ * Section 3, step 8).  The power and SNR sums of the same step become, for a
+ * unit-modulus replica, the relative power A^2 = P / L^2 and the SNR
+ * A^2 / sigma^2 with sigma^2 = (E - P/L) / L, E the block energy under the
+ * replica at the peak.
  *
  * Carrier-offset bins are snapped to multiples of q = Fs / M_min with
  * M_min = 2^ceil(log2(L+1)): f_k = centre + (k - (K-1)/2) * step, where centre
@@ -126,8 +129,10 @@ typedef struct acq_detection {
     double   freq_hz;       /* snapped frequency of bin k*                           */
     double   peak_power;    /* P at (k*, tau*)                                       */
     double   z;             /* P / (L * Pxhat)                                       */
-    double   energy;        /* sum_{n<L} |x[tau*+n]|^2                               */
+    double   energy;        /* E = sum_{n<L} |x[tau*+n]|^2                           */
     double   block_power;   /* Pxhat                                                 */
+    double   power;         /* relative power A^2 = P / L^2 (replica of unit modulus) */
+    double   snr;           /* A^2 / sigma^2, sigma^2 = (E - P/L) / L; +inf if <= 0   */
     int32_t  block;         /* index of the block in a batch call, else 0            */
     uint32_t flags;         /* ACQ_DET_*                                             */
 } acq_detection;

@@ -41,7 +41,7 @@ import numpy as np
 __all__ = [
     "build_library", "library_path", "rotation_grid", "snap_bins", "templates",
     "block_power", "corr_power", "corr_power_at", "corr_power_fft",
-    "default_threshold", "argmax_detect", "parabola", "energy_at",
+    "default_threshold", "argmax_detect", "parabola", "energy_at", "power_snr_estimates",
     "acquire", "NEAR_TIE_REL", "NEAR_THRESHOLD_REL", "num_threads",
 ]
 
@@ -253,6 +253,17 @@ def energy_at(x, tau: int, template_len: int) -> float:
     return float(np.sum(seg.real * seg.real + seg.imag * seg.imag))
 
 
+def power_snr_estimates(P0: float, E: float, L: int):
+    """Relative power and SNR at a peak (the paper's power and SNR sums of
+    Section 3 step 8, read for a unit-modulus replica): x = A s e^{j phi} + w
+    gives c = A L e^{j phi} + noise, so A^2 is estimated by P / L^2; the
+    energy under the replica is E = L (A^2 + sigma^2), so
+    sigma^2 = (E - P / L) / L and SNR = A^2 / sigma^2 (+inf when sigma^2 <= 0)."""
+    a2 = P0 / (float(L) * float(L))
+    s2 = (E - P0 / float(L)) / float(L)
+    return a2, (a2 / s2 if s2 > 0.0 else float("inf"))
+
+
 def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, method: str = "direct",
             refine_window: int = 1, tags: Optional[Sequence[int]] = None):
     """Per-tag acquisition result (list of dicts) by the definitions above.
@@ -296,9 +307,11 @@ def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, metho
         edge = tau == 0 or tau == lags - 1
         d = parabola(pv.get(tau - 1, 0.0), P0, pv.get(tau + 1, 0.0), at_edge=edge)
         z = P0 / (L * Px) if Px > 0 else 0.0
+        E = energy_at(x64, tau, L)
+        a2, snr = power_snr_estimates(P0, E, L)
         out.append(dict(
             tag=int(t), detected=bool(z >= theta), bin=int(k), lag=int(tau), delta=float(d),
-            toa=float(tau + d), peak_power=float(P0), z=float(z), energy=energy_at(x64, tau, L),
+            toa=float(tau + d), peak_power=float(P0), z=float(z), energy=E, power=a2, snr=snr,
             block_power=Px, freq_hz=float(f[k]), near_edge=bool(edge),
             near_tie=bool(far >= P0 * (1 - NEAR_TIE_REL) or near >= P0 * (1 - 1e-12)),
             near_threshold=bool(abs(z - theta) <= NEAR_THRESHOLD_REL * theta), theta=float(theta),

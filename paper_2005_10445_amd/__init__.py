@@ -35,6 +35,8 @@ class Detection:
     block_power: float
     block: int
     flags: int
+    power: float = 0.0          # relative power A^2 = P / L^2
+    snr: float = 0.0            # A^2 / sigma^2, sigma^2 = (E - P/L) / L
 
 
 def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
@@ -132,7 +134,7 @@ class Plan:
         check(self._lib.acq_detect(self._h, ctypes.c_void_p(ptr), n, self._out, self.num_tags,
                                    ctypes.byref(nf)), "acq_detect")
         return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags) for d in self._out[:nf.value]]
+                          d.block_power, d.block, d.flags, d.power, d.snr) for d in self._out[:nf.value]]
 
     def detect_batch(self, blocks) -> List[Detection]:
         """acq_detect_batch over a list of 1-D complex64 device tensors of any lengths."""
@@ -147,7 +149,7 @@ class Plan:
         nf = ctypes.c_int32(0)
         check(self._lib.acq_detect_batch(self._h, ptrs, lens, n, out, cap, ctypes.byref(nf)), "acq_detect_batch")
         return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags) for d in out[:nf.value]]
+                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
 
     @property
     def tuning(self) -> dict:

@@ -85,6 +85,8 @@ class AcqDetection(ctypes.Structure):
         ("z", ctypes.c_double),
         ("energy", ctypes.c_double),
         ("block_power", ctypes.c_double),
+        ("power", ctypes.c_double),
+        ("snr", ctypes.c_double),
         ("block", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
     ]

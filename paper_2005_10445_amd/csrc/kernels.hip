@@ -554,6 +554,11 @@ __global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
                 r.z = z;
                 r.energy = E[wb];
                 r.block_power = px;
+                // relative power and SNR (Section 3 step 8's power and SNR sums)
+                const double Ld = double(a.L);
+                r.power = p0 / (Ld * Ld);
+                const double s2 = (E[wb] - p0 / Ld) / Ld;
+                r.snr = s2 > 0.0 ? r.power / s2 : __builtin_huge_val();
                 r.block = bi;
                 r.flags = flags;
                 a.dets[slot] = r;

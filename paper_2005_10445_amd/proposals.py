@@ -174,7 +174,7 @@ class Network:
                                            ctypes.byref(lp), out, plan.num_tags, ctypes.byref(nf),
                                            ctypes.byref(rep)), "acq_detect_learned")
         dets = [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags) for d in out[:nf.value]]
+                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
         return dets, LearnedReport(rep.proposals, rep.segments, rep.total_segments, rep.fallback, rep.median,
                                    rep.floor)
 
@@ -194,7 +194,7 @@ class Network:
         check(self._lib.acq_detect_batch_learned(plan._h, self._h, ptrs, lens, n, ctypes.byref(lp), out, cap,
                                                  ctypes.byref(nf), reps), "acq_detect_batch_learned")
         dets = [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags) for d in out[:nf.value]]
+                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
         return dets, [LearnedReport(r.proposals, r.segments, r.total_segments, r.fallback, r.median, r.floor)
                       for r in reps]
 

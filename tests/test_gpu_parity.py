@@ -70,6 +70,11 @@ def _compare_detections(dets, ref, L):
         assert abs(d.energy - r["energy"]) <= 1e-9 * max(r["energy"], 1.0)
         assert abs(d.z - r["z"]) <= 1e-9 * max(r["z"], 1.0)
         assert abs(d.block_power - r["block_power"]) <= 1e-12 * r["block_power"]
+        assert abs(d.power - r["power"]) <= 1e-9 * floor / (L * L)
+        if np.isfinite(r["snr"]):
+            # sigma^2 = (E - P/L)/L cancels; the bound scales the P and E errors by 1/sigma^2
+            s2 = (r["energy"] - r["peak_power"] / L) / L
+            assert abs(d.snr - r["snr"]) <= 1e-8 * (floor / (L * L) + r["energy"] / L) / s2 * (1 + r["snr"])
         assert d.freq_hz == r["freq_hz"]
         assert bool(d.flags & 1) == r["near_edge"]
     return got, want

@@ -323,3 +323,28 @@ def test_generator_noise_power_and_determinism():
     p = np.mean(np.abs(x1.astype(np.complex128)) ** 2)
     assert abs(p - 1.0) < 0.02
     assert abs(np.mean(x1.real ** 2) - 0.5) < 0.02
+
+
+def test_power_and_snr_estimates_noise_free_and_statistical():
+    """Noise-free replica at amplitude A: power estimate A^2 exactly, SNR +inf.
+    Replica plus CN(0, s2) noise: the estimates average to A^2 and A^2/s2."""
+    import math
+    L = 4096
+    g = np.random.default_rng(7)
+    s = np.where(g.random(L) < 0.5, -1.0, 1.0)
+    A = 0.7
+    x = (A * np.exp(0.3j) * s).astype(np.complex64)
+    c = np.sum(x.astype(np.complex128) * s)
+    a2, snr = oracle.power_snr_estimates(abs(c) ** 2, oracle.energy_at(x, 0, L), L)
+    assert abs(a2 - float(np.abs(np.complex64(A * np.exp(0.3j))) ** 2)) < 1e-6 and (snr == math.inf or snr > 1e6)
+    s2 = 0.5
+    ests = []
+    for seed in range(200):
+        gg = np.random.default_rng(100 + seed)
+        w = np.sqrt(s2 / 2) * (gg.normal(size=L) + 1j * gg.normal(size=L))
+        xx = A * s + w
+        c = np.sum(xx * s)
+        ests.append(oracle.power_snr_estimates(abs(c) ** 2, float(np.sum(np.abs(xx) ** 2)), L))
+    a2m = np.mean([e[0] for e in ests])
+    snrm = np.median([e[1] for e in ests])
+    assert abs(a2m - A * A) < 0.01 and abs(snrm / (A * A / s2) - 1) < 0.05
