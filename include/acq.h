@@ -76,6 +76,12 @@ typedef enum acq_precision {
 
 /* acq_config.flags */
 #define ACQ_FLAG_GRAPH       0x1u  /* acq_detect_batch replays one captured hipGraph  */
+#define ACQ_FLAG_EXACT_BINS  0x2u  /* bins at the requested frequencies, not snapped:
+                                      f_k = centre + (k - (K-1)/2) * step exactly.  Each
+                                      bin is the nearest integer rotation m_k of the
+                                      M-point spectrum plus a residual offset applied
+                                      to the samples before the forward transform; one
+                                      set of segment spectra per distinct residual. */
 
 /* acq_detection.flags */
 #define ACQ_DET_NEAR_EDGE    0x1u  /* peak at lag 0 or N-L: no parabola, delta = 0    */

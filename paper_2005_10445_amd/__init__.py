@@ -43,7 +43,7 @@ def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
                 bin_center_hz: float = 0.0, bin_step_hz: float = 0.0, max_block_len: int = 1 << 20,
                 fft_len: int = 0, threshold: float = 0.0, precision: str = "fp32",
                 refine_radius: int = 1, tag_tile: int = 0, max_batch_blocks: int = 0,
-                max_batch_samples: int = 0, graph: bool = False):
+                max_batch_samples: int = 0, graph: bool = False, exact_bins: bool = False):
     """Build an AcqConfig; returns (config, chips array that must outlive the call)."""
     ch = np.ascontiguousarray(np.asarray(chips, dtype=np.int8))
     if ch.ndim != 2:
@@ -62,7 +62,7 @@ def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
     cfg.precision = _PRECISION[precision]
     cfg.refine_radius = int(refine_radius)
     cfg.tag_tile = int(tag_tile)
-    cfg.flags = _capi.ACQ_FLAG_GRAPH if graph else 0
+    cfg.flags = (_capi.ACQ_FLAG_GRAPH if graph else 0) | (_capi.ACQ_FLAG_EXACT_BINS if exact_bins else 0)
     cfg.max_batch_blocks = int(max_batch_blocks)
     cfg.max_batch_samples = int(max_batch_samples)
     return cfg, ch
@@ -101,12 +101,12 @@ class Plan:
                  bin_step_hz: float = 0.0, max_block_len: int = 1 << 20, fft_len: int = 0,
                  threshold: float = 0.0, precision: str = "fp32", refine_radius: int = 1,
                  tag_tile: int = 0, max_batch_blocks: int = 0, max_batch_samples: int = 0,
-                 graph: bool = False, stream=None):
+                 graph: bool = False, exact_bins: bool = False, stream=None):
         import torch
         self._lib = _capi.lib()
         cfg, ch = make_config(chips, spc, fs_hz, num_bins, bin_center_hz, bin_step_hz, max_block_len,
                               fft_len, threshold, precision, refine_radius, tag_tile, max_batch_blocks,
-                              max_batch_samples, graph)
+                              max_batch_samples, graph, exact_bins)
         self.max_batch_blocks = max(int(max_batch_blocks), 1)
         self.num_tags, self.num_chips = ch.shape
         self.precision = precision

@@ -24,6 +24,7 @@ ACQ_FP32, ACQ_FP16, ACQ_BF16 = 0, 1, 2
 ACQ_DET_NEAR_EDGE = 0x1
 ACQ_DET_WINDOW_EDGE = 0x2
 ACQ_FLAG_GRAPH = 0x1
+ACQ_FLAG_EXACT_BINS = 0x2
 
 # every symbol include/acq.h declares
 EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",

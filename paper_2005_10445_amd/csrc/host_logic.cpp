@@ -67,7 +67,7 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     if (cfg->refine_radius < 0 || cfg->refine_radius > kMaxRefineRadius)
         return fail(ACQ_ERR_INVALID_ARG, "refine_radius must be in [0, 8]");
     if (cfg->tag_tile < 0) return fail(ACQ_ERR_INVALID_ARG, "tag_tile must be >= 0");
-    if ((cfg->flags & ~ACQ_FLAG_GRAPH) != 0) return fail(ACQ_ERR_INVALID_ARG, "unknown flags");
+    if ((cfg->flags & ~(ACQ_FLAG_GRAPH | ACQ_FLAG_EXACT_BINS)) != 0) return fail(ACQ_ERR_INVALID_ARG, "unknown flags");
     if (cfg->max_batch_blocks < 0 || cfg->max_batch_samples < 0)
         return fail(ACQ_ERR_INVALID_ARG, "negative batch capacity");
 
@@ -125,15 +125,40 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     G.freqs_hz.resize(size_t(K));
     G.rot.resize(size_t(K));
     G.rot_signed.resize(size_t(K));
+    G.exact = (cfg->flags & ACQ_FLAG_EXACT_BINS) != 0;
+    G.cls.assign(size_t(K), 0);
+    G.cyc.resize(size_t(K));
+    G.cls_cyc.clear();
+    if (!G.exact) G.cls_cyc.push_back(0.0);
+    const double qM = cfg->sample_rate_hz / double(G.M);       // rotation quantum at M
     for (int64_t k = 0; k < K; ++k) {
-        const int64_t fq = G.centre_q + (k - half) * G.step_q;   // frequency in quanta
-        G.freqs_hz[size_t(k)] = double(fq) * G.q;
-        const int64_t m = fq * ratio;                            // rotation at M
+        int64_t m;
+        if (G.exact) {
+            const double f = cfg->bin_center_hz + double(k - half) * cfg->bin_step_hz;
+            G.freqs_hz[size_t(k)] = f;
+            m = int64_t(std::llround(f / qM));                  // nearest rotation at M
+            const double resid = (f - double(m) * qM) / cfg->sample_rate_hz;   // cycles per sample
+            // residual classes: bins whose residuals agree to 1e-12 cycles per sample share spectra
+            int c = -1;
+            for (size_t j = 0; j < G.cls_cyc.size() && c < 0; ++j)
+                if (std::fabs(G.cls_cyc[j] - resid) <= 1e-12) c = int(j);
+            if (c < 0) {
+                G.cls_cyc.push_back(resid);
+                c = int(G.cls_cyc.size()) - 1;
+            }
+            G.cls[size_t(k)] = c;
+        } else {
+            const int64_t fq = G.centre_q + (k - half) * G.step_q;   // frequency in quanta
+            G.freqs_hz[size_t(k)] = double(fq) * G.q;
+            m = fq * ratio;                                          // rotation at M
+        }
+        G.cyc[size_t(k)] = G.freqs_hz[size_t(k)] / cfg->sample_rate_hz;
         G.rot_signed[size_t(k)] = m;
         int64_t r = m % G.M;
         if (r < 0) r += G.M;
         G.rot[size_t(k)] = int32_t(r);
     }
+    G.ncls = int(G.cls_cyc.size());
 
     // batch capacity: segments of a batch are bounded by sum(n_b)/V + blocks
     G.max_blocks = cfg->max_batch_blocks > 0 ? cfg->max_batch_blocks : 1;
@@ -152,8 +177,8 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     // device memory: spectra of segments, replica bank, tables, small buffers
     int64_t bytes = 0;
     const int64_t sbytes = cfg->precision == ACQ_FP32 ? 8 : 4;
-    bytes += G.max_total_segments * G.M * 8;  // forward spectra X[S][M] (FP32)
-    if (sbytes == 4) bytes += G.max_total_segments * G.M * 4;   // their 16-bit copy
+    bytes += G.max_total_segments * G.ncls * G.M * 8;  // forward spectra X[S][classes][M] (FP32)
+    if (sbytes == 4) bytes += G.max_total_segments * G.ncls * G.M * 4;   // their 16-bit copy
     bytes += T * G.Msub * sbytes;             // replica bank [T][M/spc]
     bytes += G.M * 8 * 2 + G.Msub * 8;        // rect spectrum, roots at M and M/spc
     bytes += T * C;                           // chips

@@ -32,9 +32,14 @@ struct Geometry {
     int     max_blocks = 1;         // blocks per batch call
     int64_t max_batch_samples = 0;  // samples per batch call
     int64_t max_total_segments = 0; // segment spectra allocated
-    std::vector<double>  freqs_hz;   // K snapped frequencies
+    std::vector<double>  freqs_hz;   // K bin frequencies (snapped unless exact)
     std::vector<int32_t> rot;        // per-bin rotation of the M-point spectrum, in [0, M)
     std::vector<int64_t> rot_signed; // per-bin signed rotation at M
+    bool exact = false;              // ACQ_FLAG_EXACT_BINS
+    int ncls = 1;                    // distinct residual offsets (sets of segment spectra)
+    std::vector<int32_t> cls;        // per-bin residual class
+    std::vector<double>  cls_cyc;    // per-class residual offset, cycles per sample
+    std::vector<double>  cyc;        // per-bin f_k / Fs
     int64_t device_bytes = 0;
 };
 

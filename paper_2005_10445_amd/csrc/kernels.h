@@ -52,7 +52,7 @@ struct BlockTable {
 
 struct CorrArgs {
     BlockTable blocks;
-    const void* X;              // [segments][M] spectra (storage format)
+    const void* X;              // [segments][ncls][M] spectra (storage format)
     const void* bank;           // [T][Msub] 2^bank_exp conj(DFT_Msub(chips)) / M (storage format)
     const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
     const float2* rect;         // [M] sum_{r<spc} exp(+j 2 pi i r / M)
@@ -60,24 +60,26 @@ struct CorrArgs {
     const float2* rootsSub;     // [Msub] exp(+j 2 pi m / Msub)
     const float2* b1tab;        // 2^14-point engine twiddle table (else unused)
     const int32_t* rot;         // [K] rotation of bin k, in [0, M)
+    const int32_t* cls;         // [K] residual class of bin k (spectra slot g * ncls + cls[k])
     unsigned long long* keys;   // [block][T] packed (power bits, ~(lag*K + k)), max-reduced
     float* dump;                // optional [T][K][lags] power (single-block calls)
     int* counters;              // [kXcds] work-item counters (persistent launches)
     int64_t V;                  // valid lags per segment
-    int32_t K, spc, M, Msub, T, tile, ntiles, bank_exp;
+    int32_t K, spc, M, Msub, T, tile, ntiles, bank_exp, ncls;
     int32_t persistent;         // 1: loop over work items from the counters
 };
 
 struct FwdArgs {
     BlockTable blocks;
-    float2* X;                  // [segments][M] FP32 spectra (sub-transforms, then the result)
+    float2* X;                  // [segments][ncls][M] FP32 spectra (sub-transforms, then the result)
     void* Xh;                   // [segments][M] 16-bit copy (FP16/BF16 plans only)
     const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
     const float2* rootsM;
     const float2* rootsSub;
     const float2* b1tab;
+    const double* cls_cyc;      // [ncls] residual offset of each class, cycles per sample
     int64_t V;
-    int32_t spc, M, Msub;
+    int32_t spc, M, Msub, ncls;
 };
 
 struct RefineArgs {
@@ -86,12 +88,13 @@ struct RefineArgs {
     const int64_t* rot_signed;  // [K] signed rotation at M
     const double* freqs;        // [K]
     const double2* roots64;     // [M] (cos, sin)(2 pi m / M), FP64
+    const double* cyc;          // [K] f_k / Fs (exact bins)
     const unsigned long long* keys;   // [block][T]
     const double* parts;        // [block][kPowerParts]
     acq_detection* dets;        // [block][T]
     int32_t* found;             // [block][T] 1 if detected
     int64_t L;
-    int32_t T, C, K, spc, log2_spc, M, radius;
+    int32_t T, C, K, spc, log2_spc, M, radius, exact;
 };
 
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);

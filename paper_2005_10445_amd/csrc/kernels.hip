@@ -195,20 +195,29 @@ __global__ __launch_bounds__(E::NT) void k_forward_sub(FwdArgs a) {
     E eng;
     eng.init(a.rootsSub, extra);
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const int items = a.blocks.total_seg() * a.spc;
+    const int per_seg = a.ncls * a.spc;
+    const int items = a.blocks.total_seg() * per_seg;
     for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
-        const int g = it / a.spc, r = it - g * a.spc;
+        const int g = it / per_seg, rem = it - g * per_seg, c = rem / a.spc, r = rem - c * a.spc;
         const int bi = a.blocks.block_of_segment(g);
         const BlockDesc d = a.blocks.get(bi);
         const int64_t base = int64_t(a.blocks.segment(g, d)) * a.V;
+        const double cyc = a.cls_cyc[c];          // residual offset of the class (exact bins)
         float2 v[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int64_t idx = base + int64_t(a.spc) * eng.in_index(m) + r;
             v[m] = idx < d.n ? d.x[idx] : make_float2(0.f, 0.f);
+            if (cyc != 0.0) {                      // x * exp(-j 2 pi cyc idx), phase reduced in FP64
+                double ph = cyc * double(idx);
+                ph -= floor(ph);
+                float sn, cs;
+                sincospif(2.0f * float(ph), &sn, &cs);
+                v[m] = make_float2(fmaf(v[m].x, cs, v[m].y * sn), fmaf(v[m].y, cs, -v[m].x * sn));
+            }
         }
         eng.template transform<-1>(v, lds, b1, extra);
-        float2* F = a.X + size_t(g) * size_t(a.M) + size_t(r) * size_t(a.Msub);
+        float2* F = a.X + (size_t(g) * size_t(a.ncls) + size_t(c)) * size_t(a.M) + size_t(r) * size_t(a.Msub);
         const int ob = eng.out_base();
 #pragma unroll
         for (int m = 0; m < 16; ++m) F[ob + E::out_off(m)] = v[m];
@@ -222,12 +231,12 @@ template <int PREC>
 __global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
     using St = dev::Storage<PREC>;
     const int per_slot = a.Msub / 256;
-    const int g = int(blockIdx.x) / per_slot;
-    if (g >= a.blocks.total_seg()) return;
+    const int g = int(blockIdx.x) / per_slot;           // spectra slot: segment * ncls + class
+    if (g >= a.blocks.total_seg() * a.ncls) return;
     const int i = (int(blockIdx.x) - g * per_slot) * 256 + int(threadIdx.x);
     float2* X = a.X + size_t(g) * size_t(a.M);
     float xs = 1.0f;
-    if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -a.exps[a.blocks.block_of_segment(g)]);
+    if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -a.exps[a.blocks.block_of_segment(g / a.ncls)]);
     const int mmask = a.M - 1;
     float2 F[8];
     for (int r = 0; r < a.spc; ++r) F[r] = X[r * a.Msub + i];
@@ -305,7 +314,8 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     // tag-independent first step of the inverse transform
     float2 G[16];
     {
-        const typename St::T* Xj = static_cast<const typename St::T*>(a.X) + size_t(g) * size_t(a.M);
+        const typename St::T* Xj =
+            static_cast<const typename St::T*>(a.X) + (size_t(g) * size_t(a.ncls) + size_t(a.cls[k])) * size_t(a.M);
         const int rot = a.rot[k];
         const int mmask = a.M - 1;
 #pragma unroll
@@ -468,6 +478,7 @@ __global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
     if (W > WMAX) return;            // the launcher picks WMAX >= W
     const int64_t mrot = a.rot_signed[k];
     const int64_t mmask = int64_t(a.M) - 1;
+    const double fk = a.cyc[k];
     const int8_t* ch = a.chips + size_t(tag) * size_t(a.C);
 
     for (int pass = 0; pass < 2; ++pass) {
@@ -480,7 +491,14 @@ __global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
             if (i < 0 || i >= d.n) continue;
             const float2 xv = d.x[i];
             const double xr = xv.x, xi = xv.y;
-            const double2 cs = a.roots64[(mrot * i) & mmask];
+            double2 cs;
+            if (a.exact) {                          // exp(-j 2 pi (f_k / Fs) i), phase reduced in FP64
+                double ph = fk * double(i);
+                ph -= floor(ph);
+                sincospi(2.0 * ph, &cs.y, &cs.x);
+            } else {
+                cs = a.roots64[(mrot * i) & mmask];
+            }
             const double mr = xr * cs.x + xi * cs.y;      // x * exp(-j 2 pi m i / M)
             const double mi = xi * cs.x - xr * cs.y;
             const double pw = xr * xr + xi * xi;

@@ -36,8 +36,11 @@ struct acq_plan_s {
     int tile = 16;                      // acq_tuning.tag_tile
     int batch_launch = ACQ_BATCH_GRID;  // acq_tuning.batch_launch
 
-    float2* d_X = nullptr;              // [segments][M] FP32 segment spectra
-    void* d_Xh = nullptr;               // [segments][M] 16-bit segment spectra (FP16/BF16 plans)
+    float2* d_X = nullptr;              // [segments][classes][M] FP32 segment spectra
+    void* d_Xh = nullptr;               // [segments][classes][M] 16-bit segment spectra (FP16/BF16 plans)
+    int32_t* d_cls = nullptr;           // [K] residual class of each bin
+    double* d_cls_cyc = nullptr;        // [classes] residual offsets, cycles per sample
+    double* d_cyc = nullptr;            // [K] f_k / Fs
     void* d_bank = nullptr;             // [T][Msub] in the plan's storage format
     int bank_exp = 0;                   // power-of-two prescale of the stored bank
     float2* d_rect = nullptr;           // [M]
@@ -107,7 +110,7 @@ void drop_graph(acq_plan_s* p) {
 void free_plan(acq_plan_s* p) {
     if (!p) return;
     drop_graph(p);
-    void* dev[] = {p->d_X, p->d_Xh, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
+    void* dev[] = {p->d_X, p->d_Xh, p->d_cls, p->d_cls_cyc, p->d_cyc, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
                    p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_exps, p->d_dets,
                    p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
@@ -130,8 +133,12 @@ int build_plan(acq_plan_s* p) {
     const size_t B = size_t(g.max_blocks);
     const size_t S = size_t(g.max_total_segments > 0 ? g.max_total_segments : 1);
     const bool half = c.precision != ACQ_FP32;
-    ACQ_HIP(dalloc(&p->d_X, S * size_t(g.M)));
-    if (half) ACQ_HIP(hipMalloc(&p->d_Xh, S * size_t(g.M) * 4));
+    const size_t ncls = size_t(g.ncls);
+    ACQ_HIP(dalloc(&p->d_X, S * ncls * size_t(g.M)));
+    if (half) ACQ_HIP(hipMalloc(&p->d_Xh, S * ncls * size_t(g.M) * 4));
+    ACQ_HIP(dalloc(&p->d_cls, K));
+    ACQ_HIP(dalloc(&p->d_cls_cyc, ncls));
+    ACQ_HIP(dalloc(&p->d_cyc, K));
     ACQ_HIP(hipMalloc(&p->d_bank, T * size_t(g.Msub) * (half ? 4 : 8)));
     // 16-bit banks are stored with rms magnitude near 1: 2^round(log2(M / sqrt(C)))
     p->bank_exp = half ? int(std::lrint(std::log2(double(g.M) / std::sqrt(double(C))))) : 0;
@@ -178,6 +185,9 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(hipMemcpyAsync(p->d_rot, g.rot.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rot_signed, g.rot_signed.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_freqs, g.freqs_hz.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
+    ACQ_HIP(hipMemcpyAsync(p->d_cls, g.cls.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    ACQ_HIP(hipMemcpyAsync(p->d_cls_cyc, g.cls_cyc.data(), ncls * sizeof(double), hipMemcpyHostToDevice, st));
+    ACQ_HIP(hipMemcpyAsync(p->d_cyc, g.cyc.data(), K * sizeof(double), hipMemcpyHostToDevice, st));
     ACQ_HIP(acq::launch_bank(p->d_chips, int(T), int(C), p->d_bank, p->d_rootsSub, p->d_b1tab, int(g.Msub),
                              int(g.M), p->bank_exp, g.log2_sub, c.precision, st));
     ACQ_HIP(hipStreamSynchronize(st));
@@ -230,6 +240,8 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     fa.X = p->d_X;
     fa.Xh = p->d_Xh;
     fa.exps = p->d_exps;
+    fa.cls_cyc = p->d_cls_cyc;
+    fa.ncls = g.ncls;
     fa.rootsM = p->d_rootsM;
     fa.rootsSub = p->d_rootsSub;
     fa.b1tab = p->d_b1tab;
@@ -241,8 +253,8 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
         KernelTimer kt(p, ACQ_KERNEL_FORWARD);
         // batches: a loop over items on a fixed grid and a combine step sized for
         // the capacity when captured; single blocks: one workgroup per item
-        const int grid = batch ? p->cus : total_seg_host * c.samples_per_chip;
-        const int slots = batch && p->capturing ? int(g.max_total_segments) : total_seg_host;
+        const int grid = batch ? p->cus : total_seg_host * g.ncls * c.samples_per_chip;
+        const int slots = (batch && p->capturing ? int(g.max_total_segments) : total_seg_host) * g.ncls;
         ACQ_HIP(acq::launch_forward(fa, grid, slots, g.log2_sub, c.precision, st));
     }
 
@@ -256,6 +268,8 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ca.rootsSub = p->d_rootsSub;
     ca.b1tab = p->d_b1tab;
     ca.rot = p->d_rot;
+    ca.cls = p->d_cls;
+    ca.ncls = g.ncls;
     ca.keys = p->d_keys;
     ca.dump = dump;
     ca.counters = p->d_counters;
@@ -303,6 +317,8 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ra.spc = c.samples_per_chip;
     ra.log2_spc = c.samples_per_chip == 1 ? 0 : c.samples_per_chip == 2 ? 1 : c.samples_per_chip == 4 ? 2 : 3;
     ra.roots64 = p->d_roots64;
+    ra.cyc = p->d_cyc;
+    ra.exact = g.exact ? 1 : 0;
     ra.M = int(g.M);
     ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
     {

@@ -158,3 +158,18 @@ def test_network_config_validation_without_gpu(capi):
     for cfg in bad:
         assert L.acq_cnn_create(ctypes.byref(cfg), None, ctypes.byref(h)) in (-1, -7)
         assert not h.value
+
+
+def test_exact_bins_report_the_requested_frequencies(capi):
+    import numpy as np
+    from paper_2005_10445_amd import bin_frequencies, geometry
+    chips = np.ones((2, 1000), np.int8)
+    kw = dict(chips=chips, spc=2, fs_hz=8e6, num_bins=5, bin_center_hz=123.4, bin_step_hz=1000.3,
+              max_block_len=50000)
+    f = bin_frequencies(exact_bins=True, **kw)
+    assert np.array_equal(f, 123.4 + (np.arange(5) - 2) * 1000.3)
+    snapped = bin_frequencies(**kw)
+    q = 8e6 / 2048
+    assert np.allclose(snapped / q, np.round(snapped / q)) and not np.array_equal(f, snapped)
+    g = geometry(exact_bins=True, **kw)
+    assert g["device_bytes"] > geometry(**kw)["device_bytes"]      # one set of spectra per residual
