@@ -4,7 +4,9 @@ One step = one acq_detect call on one resident block: block power, segment
 spectra, correlation of every tag x bin x lag, peak keys, FP64 refinement and
 the copy of the detections to the host (--workload batched_stream: one
 acq_detect_batch call over 64 resident blocks of uneven length, 256 tags x 21
-bins, optionally replayed from a captured hipGraph).  Default workload: 64 tags with
+bins, optionally replayed from a captured hipGraph; --workload tracking: one
+acq_track_batch call over 256 tracking tasks, each one tag x 21 bins over a
+block 1.5 templates long).  Default workload: 64 tags with
 8192-chip codes at 2 samples/chip, 11 carrier-offset bins over +/-5 kHz,
 2^20-sample blocks at 8 Msps, overlap-save segments of 2^15 samples, ten
 transmissions per block at -15..-5 dB (synthetic, seeded).
@@ -78,6 +80,27 @@ def cpu_baseline(x, chips, spc, freqs, fs, budget_s: float):
             "sample": f"{done} (tag, bin) pairs x {N} samples, direct FP64 correlation, {dt:.1f} s"}
 
 
+def cpu_baseline_tasks(tasks, chips, spc, freqs, fs, budget_s: float):
+    """Direct FP64 oracle over (task, bin) pairs of tracking tasks until the time budget is used."""
+    import oracle
+    oracle.build_library(force=False)
+    done, samples = 0, 0
+    t0 = time.perf_counter()
+    for x, tag in tasks:
+        for f in freqs:
+            oracle.corr_power(x, chips[tag:tag + 1], spc, [f], fs)
+            done += 1
+            samples += x.size
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": samples / dt / 1e6, "unit": "tag*freq*Msample/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{done} (task, bin) pairs, {samples} samples in all, direct FP64 correlation, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +139,7 @@ def main():
 
     w = siggen.workload(args.workload)
     batched = "num_blocks" in w
+    tracking = "num_tasks" in w
     T, C, spc, K = w["num_tags"], w["num_chips"], w["spc"], w["num_bins"]
     fs = w["fs_hz"]
     seed = w["seeds"][0]
@@ -137,6 +161,22 @@ def main():
                     max_batch_samples=sum(lens), graph=args.graph, **bins)
         x = blocks[0][0]
         run = lambda: len(plan.detect_batch(xds))      # noqa: E731
+    elif tracking:
+        fft_len = args.fft_len or w["fft_len"]
+        L0 = C * spc
+        n_task = int(math.floor(w["block_factor"] * L0))
+        freqs = bin_frequencies(chips=chips, spc=spc, fs_hz=fs, max_block_len=n_task, fft_len=fft_len, **bins)
+        log(f"[bench] generating {w['num_tasks']} tracking tasks")
+        batch = siggen.make_tracking_batch(seed, chips, spc, fs, freqs, w["num_tasks"], w["block_factor"],
+                                           w["p_present"], w["n_other"], w["snr_db"])
+        lens = [xb.size for xb, _, _ in batch]
+        tasks = [(torch.from_numpy(xb).to(dev), tag) for xb, tag, _ in batch]
+        plan = Plan(chips, spc, fs, max_block_len=max(lens), fft_len=fft_len, precision=prec,
+                    refine_radius=w.get("refine_radius", 1), max_batch_blocks=len(lens),
+                    max_batch_samples=sum(lens), graph=args.graph, **bins)
+        x = batch[0][0]
+        task_arr = plan.task_array(tasks)
+        run = lambda: plan.track_raw(task_arr)         # noqa: E731
     else:
         N = w["block_len"]
         fft_len = args.fft_len or w["fft_len"]
@@ -151,6 +191,11 @@ def main():
     M, V = g["fft_len"], g["valid_per_segment"]
     S = sum(-(-(n - L + 1) // V) for n in lens if n >= L)
     samples = sum(lens)
+    if tracking:
+        args.tune = False                              # tag tiles do not apply: one tag per task
+        T_eff = 1
+    else:
+        T_eff = T
     if args.tune:
         table = plan.tune(xds[int(np.argmax(lens))] if batched else xd, reps=3)
         log(f"[bench] tuning table {table} -> {plan.tuning}")
@@ -159,7 +204,7 @@ def main():
 
     for _ in range(args.warmup):
         run()
-    profiled = not (batched and args.graph)
+    profiled = not ((batched or tracking) and args.graph)
     plan.set_profiling(profiled)
     corr_ms, fwd_ms, total_kernel_ms = [], [], []
     torch.cuda.synchronize()
@@ -176,13 +221,15 @@ def main():
     t1 = time.perf_counter()
     plan.set_profiling(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = T * K * samples / (ms_per_step * 1e-3) / 1e6
-    flops = correlate_flops(T, K, S, M, V)
+    value = T_eff * K * samples / (ms_per_step * 1e-3) / 1e6
+    flops = correlate_flops(T_eff, K, S, M, V)
     if profiled:
         corr_avg = float(np.mean(corr_ms))
         achieved = flops / (corr_avg * 1e-3) / 1e12
         log(f"[bench] {ms_per_step:.3f} ms/step, correlate {corr_avg:.3f} ms (min {min(corr_ms):.3f}), "
             f"forward {np.mean(fwd_ms):.3f} ms, kernels {np.mean(total_kernel_ms):.3f} ms, detections {ndet}")
+        if tracking:
+            log(f"[bench] {len(lens) / (ms_per_step * 1e-3):.0f} tracking tasks/s")
     else:
         corr_avg, achieved = None, None
         log(f"[bench] {ms_per_step:.3f} ms/step (graph replays, no per-kernel events), detections {ndet}")
@@ -201,8 +248,9 @@ def main():
         "dtype": "f32" if prec == "fp32" else f"f32 ({prec} storage)",
         "data": "synthetic (seeded BPSK tags in AWGN)",
         "config": {"workload": args.workload, "tags": T, "bins": K, "blocks": len(lens), "samples": samples,
+                   "tags_per_block": T_eff,
                    "template_len": L, "fft_len": M, "segments": S, "precision": prec, "tuning": plan.tuning,
-                   "graph": bool(batched and args.graph), "parallelism": "single GPU"},
+                   "graph": bool((batched or tracking) and args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS if achieved else None,
                      "traffic": traffic_per_launch() if args.workload == "tagbank_fp32" else None,
@@ -210,7 +258,11 @@ def main():
     }
     if args.cpu_budget > 0:
         log("[bench] cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(x, chips, spc, freqs, fs, args.cpu_budget)
+        if tracking:
+            out["cpu_baseline"] = cpu_baseline_tasks([(xb, tag) for xb, tag, _ in batch], chips, spc, freqs, fs,
+                                                     args.cpu_budget)
+        else:
+            out["cpu_baseline"] = cpu_baseline(x, chips, spc, freqs, fs, args.cpu_budget)
     plan.close()
     print(json.dumps(out), flush=True)
 

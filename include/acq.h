@@ -182,7 +182,7 @@ int acq_detect(acq_plan_t plan, const void* block, int64_t n,
  * arrays on the host, 1 <= nblocks <= max_batch_blocks, every lens[b] <=
  * max_block_len and their sum <= max_batch_samples.  Each block is searched
  * independently, exactly as acq_detect would (same kernels, same results);
- * the work items of all blocks share one persistent correlation launch.
+ * the work items of all blocks share one correlation launch.
  * Detections are sorted by (block, tag) and carry their block index.  With
  * ACQ_FLAG_GRAPH the launch sequence is captured once as a hipGraph (on a
  * private stream) and replayed on the plan's stream for every later call;
@@ -191,6 +191,34 @@ int acq_detect(acq_plan_t plan, const void* block, int64_t n,
  */
 int acq_detect_batch(acq_plan_t plan, const void* const* blocks, const int64_t* lens, int32_t nblocks,
                      acq_detection* out, int32_t capacity, int32_t* n_found);
+
+/*
+ * Tracking-mode tasks (Section 2: a task looks for one packet of one
+ * particular tag in a block of samples a little longer than the packet,
+ * placed around its predicted arrival).  Each task names a device block and
+ * the tag to look for; its search is the plan's search restricted to that one
+ * code: every bin, every valid lag, the same kernels and FP64 refinement, at
+ * most one detection.  With threshold <= 0 the per-task threshold counts the
+ * hypotheses of one code, ln(K*(n-L+1) / 1e-3).
+ */
+typedef struct acq_track_task {
+    const void* block;      /* device pointer, n complex64 samples (8-byte aligned) */
+    int64_t     n;          /* samples; n <= max_block_len; n < L gives no detection */
+    int32_t     tag;        /* index into the plan's codes, [0, num_tags)            */
+    int32_t     reserved;   /* 0                                                     */
+} acq_track_task;
+
+/*
+ * Run ntasks tracking tasks (1 <= ntasks <= max_batch_blocks, total samples
+ * <= max_batch_samples; tasks may share a block or a tag) in one launch
+ * sequence.  Detections are in task order, detection.block = task index.
+ * ACQ_FLAG_GRAPH captures and replays a graph of its own for tracking
+ * batches.  Errors: ACQ_ERR_INVALID_ARG for a tag outside [0, num_tags),
+ * otherwise as acq_detect_batch.  Synchronous; capacity and truncation as in
+ * acq_detect.
+ */
+int acq_track_batch(acq_plan_t plan, const acq_track_task* tasks, int32_t ntasks,
+                    acq_detection* out, int32_t capacity, int32_t* n_found);
 
 /*
  * Launch configuration of the correlation kernel.  engine: 0 = the default
@@ -202,6 +230,8 @@ typedef struct acq_tuning {
     int32_t engine;
     int32_t tag_tile;
     int32_t batch_launch;       /* ACQ_BATCH_GRID or ACQ_BATCH_PERSISTENT */
+    int32_t track_bins;         /* bins per work item of tracking batches, 1..64;
+                                   0 = chosen per launch from the work size      */
 } acq_tuning;
 
 /* Launch forms of the correlation kernel in batched searches.  GRID: one

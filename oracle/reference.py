@@ -42,14 +42,14 @@ __all__ = [
     "build_library", "library_path", "rotation_grid", "snap_bins", "templates",
     "block_power", "corr_power", "corr_power_at", "corr_power_fft",
     "default_threshold", "argmax_detect", "parabola", "energy_at", "power_snr_estimates",
-    "acquire", "NEAR_TIE_REL", "NEAR_THRESHOLD_REL", "num_threads",
+    "acquire", "track", "NEAR_TIE_REL", "NEAR_THRESHOLD_REL", "num_threads",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "direct.c")
 _LIB = os.path.join(_HERE, "_direct.so")
 
-# Q10-style flags: decisions this close to a tie are reported, not pinned.
+# Decisions this close to a tie (or to the threshold) are flagged, not pinned.
 NEAR_TIE_REL = 1e-5
 NEAR_THRESHOLD_REL = 1e-5
 
@@ -317,3 +317,18 @@ def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, metho
             near_threshold=bool(abs(z - theta) <= NEAR_THRESHOLD_REL * theta), theta=float(theta),
         ))
     return out
+
+
+def track(x, chips, spc, freqs_hz, fs_hz, tag: int, theta: Optional[float] = None, method: str = "direct"):
+    """One tracking-mode task (Section 2): look for one packet of one given tag
+    in a block.  The acquisition of `acquire` restricted to that single code;
+    the default threshold counts the hypotheses of one code, K (N-L+1).
+    Returns the tag's result dict (tag = the given index)."""
+    chips = np.asarray(chips)
+    one = chips[int(tag):int(tag) + 1]
+    res = acquire(x, one, spc, freqs_hz, fs_hz, theta=theta, method=method)
+    if not res:
+        return None
+    r = dict(res[0])
+    r["tag"] = int(tag)
+    return r

@@ -151,17 +151,53 @@ class Plan:
         return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
                           d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
 
+    def track(self, tasks) -> List[Detection]:
+        """acq_track_batch over (1-D complex64 device tensor, tag) pairs: at most one
+        detection per task, detection.block = task index."""
+        arr = self.task_array(tasks)
+        n = len(arr)
+        out = (AcqDetection * n)()
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_track_batch(self._h, arr, n, out, n, ctypes.byref(nf)), "acq_track_batch")
+        return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
+                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
+
+    @staticmethod
+    def task_array(tasks):
+        """acq_track_task array of (device tensor, tag) pairs (the tensors must stay alive)."""
+        arr = (_capi.AcqTrackTask * len(tasks))()
+        for i, (b, tag) in enumerate(tasks):
+            ptr, m = _device_ptr(b)
+            arr[i] = _capi.AcqTrackTask(ptr, m, int(tag), 0)
+        return arr
+
+    def track_raw(self, arr) -> int:
+        """acq_track_batch on a prebuilt task_array, without building Python records (for
+        timing); returns the count."""
+        n = len(arr)
+        if getattr(self, "_track_out", None) is None or len(self._track_out) < n:
+            self._track_out = (AcqDetection * n)()
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_track_batch(self._h, arr, n, self._track_out, n, ctypes.byref(nf)), "acq_track_batch")
+        return nf.value
+
     @property
     def tuning(self) -> dict:
         t = _capi.AcqTuning()
         check(self._lib.acq_get_tuning(self._h, ctypes.byref(t)), "acq_get_tuning")
-        return {"engine": t.engine, "tag_tile": t.tag_tile, "batch_launch": t.batch_launch}
+        return {"engine": t.engine, "tag_tile": t.tag_tile, "batch_launch": t.batch_launch,
+                "track_bins": t.track_bins}
 
-    def set_tuning(self, engine: int, tag_tile: int, batch_launch: Optional[int] = None):
-        """batch_launch: 0 grid over work items (default), 1 persistent workgroups; None keeps it."""
+    def set_tuning(self, engine: int, tag_tile: int, batch_launch: Optional[int] = None,
+                   track_bins: Optional[int] = None):
+        """batch_launch: 0 grid over work items (default), 1 persistent workgroups; track_bins:
+        bins per tracking work item (0: chosen per launch); None keeps the current value."""
+        cur = self.tuning
         if batch_launch is None:
-            batch_launch = self.tuning["batch_launch"]
-        t = _capi.AcqTuning(int(engine), int(tag_tile), int(batch_launch))
+            batch_launch = cur["batch_launch"]
+        if track_bins is None:
+            track_bins = cur["track_bins"]
+        t = _capi.AcqTuning(int(engine), int(tag_tile), int(batch_launch), int(track_bins))
         check(self._lib.acq_set_tuning(self._h, ctypes.byref(t)), "acq_set_tuning")
 
     def tune(self, block, reps: int = 3) -> list:

@@ -28,7 +28,7 @@ ACQ_FLAG_EXACT_BINS = 0x2
 
 # every symbol include/acq.h declares
 EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
-            "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
+            "acq_track_batch", "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
             "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
@@ -94,7 +94,8 @@ class AcqDetection(ctypes.Structure):
 
 
 class AcqTuning(ctypes.Structure):
-    _fields_ = [("engine", ctypes.c_int32), ("tag_tile", ctypes.c_int32), ("batch_launch", ctypes.c_int32)]
+    _fields_ = [("engine", ctypes.c_int32), ("tag_tile", ctypes.c_int32), ("batch_launch", ctypes.c_int32),
+                ("track_bins", ctypes.c_int32)]
 
 
 ACQ_BATCH_GRID, ACQ_BATCH_PERSISTENT = 0, 1
@@ -111,6 +112,11 @@ class AcqCnnConfig(ctypes.Structure):
         ("max_rows", ctypes.c_int64),
         ("max_block_len", ctypes.c_int64),
     ]
+
+
+class AcqTrackTask(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_void_p), ("n", ctypes.c_int64), ("tag", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class AcqSynthTx(ctypes.Structure):
@@ -176,6 +182,8 @@ def lib(path: str = LIB_PATH):
     L.acq_correlate_power.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     L.acq_detect_batch.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_int64), ctypes.c_int32,
                                    P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32)]
+    L.acq_track_batch.argtypes = [ctypes.c_void_p, P(AcqTrackTask), ctypes.c_int32, P(AcqDetection),
+                                  ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_get_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
     L.acq_set_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
     L.acq_tune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, P(AcqTuneEntry),
@@ -202,7 +210,7 @@ def lib(path: str = LIB_PATH):
     L.acq_detect_batch_learned.argtypes = [vp, vp, P(vp), P(i64), i32, P(AcqLearnedParams), P(AcqDetection), i32,
                                            P(i32), P(AcqLearnedReport)]
     for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
-                 "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
+                 "acq_track_batch", "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
                  "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create", "acq_cnn_release",
                  "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
                  "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",

@@ -180,7 +180,7 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     bytes += G.max_total_segments * G.ncls * G.M * 8;  // forward spectra X[S][classes][M] (FP32)
     if (sbytes == 4) bytes += G.max_total_segments * G.ncls * G.M * 4;   // their 16-bit copy
     bytes += T * G.Msub * sbytes;             // replica bank [T][M/spc]
-    bytes += G.M * 8 * 2 + G.Msub * 8;        // rect spectrum, roots at M and M/spc
+    bytes += G.M * 8 * (spc + 1) + G.Msub * 8;  // phase weights [spc][M], roots at M and M/spc
     bytes += T * C;                           // chips
     bytes += K * (4 + 8);                     // rotations, frequencies
     bytes += int64_t(G.max_blocks) * (T * (8 + 4 + 2 * int64_t(sizeof(acq_detection))) + 2048 + 64) + 4096;
@@ -239,20 +239,22 @@ std::vector<float> fft14_b1_table() {
     return out;
 }
 
-std::vector<float> rect_spectrum_conj(int64_t M, int spc) {
-    std::vector<float> out(size_t(2 * M));
+std::vector<float> phase_weights(int64_t M, int spc) {
+    std::vector<float> out(size_t(2 * M * spc));
     const double two_pi = 6.283185307179586476925286766559;
-    for (int64_t i = 0; i < M; ++i) {
-        double re = 0.0, im = 0.0;
-        for (int r = 0; r < spc; ++r) {
-            const int64_t e = (i * r) % M;
-            const double a = two_pi * double(e) / double(M);
-            re += std::cos(a);
-            im += std::sin(a);
+    for (int rho = 0; rho < spc; ++rho)
+        for (int64_t i = 0; i < M; ++i) {
+            double re = 0.0, im = 0.0;
+            for (int r = 0; r < spc; ++r) {
+                const int64_t e = (i * (r + rho)) % M;      // exact reduction of the angle
+                const double a = two_pi * double(e) / double(M);
+                re += std::cos(a);
+                im += std::sin(a);
+            }
+            const size_t o = size_t(2 * (int64_t(rho) * M + i));
+            out[o] = float(re);
+            out[o + 1] = float(im);
         }
-        out[size_t(2 * i)] = float(re);
-        out[size_t(2 * i + 1)] = float(im);
-    }
     return out;
 }
 

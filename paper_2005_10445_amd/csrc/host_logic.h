@@ -65,8 +65,10 @@ std::vector<double> unit_roots64(int64_t n);
 // entry exp(+j 2 pi l (w + 16 k2a) / 2^14), w, k2a < 16, l < 64.
 std::vector<float> fft14_b1_table();
 
-// conj of the spectrum of a length-spc run of ones at M points:
-// sum_{r<spc} exp(+j 2 pi i r / M), i in [0, M); interleaved FP32 from FP64.
-std::vector<float> rect_spectrum_conj(int64_t M, int spc);
+// Weights of the tag-independent first step of the split inverse transform:
+// W_rho[i] = conj(Rect[i]) exp(+j 2 pi i rho / M) = sum_{r<spc} exp(+j 2 pi i (r + rho) / M)
+// for rho in [0, spc), i in [0, M), with Rect the M-point spectrum of a run of
+// spc ones.  Layout [rho][i], interleaved FP32 rounded once from FP64.
+std::vector<float> phase_weights(int64_t M, int spc);
 
 }  // namespace acq

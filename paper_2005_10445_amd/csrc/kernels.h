@@ -21,6 +21,8 @@ struct BlockDesc {
     int32_t seg0;               // first global segment index
     int32_t nseg;               // overlap-save segments of this block
     double theta;               // detection threshold for this block
+    int32_t tag;                // -1: search every tag; >= 0: a tracking task for this one tag
+    int32_t reserved;
 };
 
 // The blocks of one launch: a single inline descriptor (single-block calls), or
@@ -55,7 +57,7 @@ struct CorrArgs {
     const void* X;              // [segments][ncls][M] spectra (storage format)
     const void* bank;           // [T][Msub] 2^bank_exp conj(DFT_Msub(chips)) / M (storage format)
     const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
-    const float2* rect;         // [M] sum_{r<spc} exp(+j 2 pi i r / M)
+    const float2* wts;          // [spc][M] W_rho[i] = sum_{r<spc} exp(+j 2 pi i (r + rho) / M)
     const float2* rootsM;       // [M] exp(+j 2 pi m / M)
     const float2* rootsSub;     // [Msub] exp(+j 2 pi m / Msub)
     const float2* b1tab;        // 2^14-point engine twiddle table (else unused)
@@ -67,6 +69,7 @@ struct CorrArgs {
     int64_t V;                  // valid lags per segment
     int32_t K, spc, M, Msub, T, tile, ntiles, bank_exp, ncls;
     int32_t persistent;         // 1: loop over work items from the counters
+    int32_t track;              // 1: tracking tasks; `tile` then counts bins per work item
 };
 
 struct FwdArgs {
@@ -95,6 +98,7 @@ struct RefineArgs {
     int32_t* found;             // [block][T] 1 if detected
     int64_t L;
     int32_t T, C, K, spc, log2_spc, M, radius, exact;
+    int32_t track;              // 1: one workgroup per block, for the block's own tag
 };
 
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);
@@ -112,7 +116,8 @@ hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const floa
 // engine: 0 = the library's choice for the size, 1 = Stockham passes (any size)
 hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec, int engine, hipStream_t st);
 hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st);
-hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T,
+// track: one candidate per block (its tag), else T per block
+hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T, int track,
                           acq_detection* out, int32_t* count, hipStream_t st);
 
 }  // namespace acq

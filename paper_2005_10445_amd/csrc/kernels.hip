@@ -281,6 +281,35 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
 }
 
 // ------------------------------------------------------------------ correlation
+// First step of the split inverse transform for (global segment slot g, bin k,
+// phase rho): G[m] = sum_q X_g[(i + m_k) mod M] W_rho[i], i = in_index(m) +
+// q Msub, for the 16 inputs this thread holds.  The q loop is outside the
+// unrolled m loop so each pass issues its 32 loads back to back.
+template <class E, int PREC>
+__device__ __forceinline__ void first_step(const CorrArgs& a, const E& eng, int g, int k, int rho, float gscale,
+                                           float2 (&G)[16]) {
+    using St = dev::Storage<PREC>;
+    const typename St::T* Xj =
+        static_cast<const typename St::T*>(a.X) + (size_t(g) * size_t(a.ncls) + size_t(a.cls[k])) * size_t(a.M);
+    const float2* W = a.wts + size_t(rho) * size_t(a.M);
+    const int rot = a.rot[k];
+    const int mmask = a.M - 1;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) G[m] = make_float2(0.f, 0.f);
+    for (int q = 0; q < a.spc; ++q) {
+        const int base = q * a.Msub;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int i = eng.in_index(m) + base;
+            G[m] = cadd(G[m], cmul(St::unpack(Xj[(i + rot) & mmask]), W[i]));
+        }
+    }
+    if constexpr (PREC != ACQ_FP32) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) G[m] = make_float2(G[m].x * gscale, G[m].y * gscale);
+    }
+}
+
 // One work item: (tile of tags, global segment g, bin k, phase rho), item index
 // wi = ((tile * segments + g) * K + k) * spc + rho.
 template <class E, int PREC, bool DUMP>
@@ -296,11 +325,12 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     rem /= a.K;
     const int g = rem % total_seg;
     const int tile = rem / total_seg;
-    const int tag0 = tile * a.tile;
-    const int ntag = min(a.tile, a.T - tag0);
     const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
     const int bi = a.blocks.block_of_segment(g);
     const BlockDesc d = a.blocks.get(bi);
+    // a tracking task searches its own tag only (launched with one tile)
+    const int tag0 = d.tag >= 0 ? d.tag : tile * a.tile;
+    const int ntag = d.tag >= 0 ? 1 : min(a.tile, a.T - tag0);
     const int j = a.blocks.segment(g, d);
     unsigned long long* keys = a.keys + size_t(bi) * a.T;
 
@@ -313,27 +343,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
 
     // tag-independent first step of the inverse transform
     float2 G[16];
-    {
-        const typename St::T* Xj =
-            static_cast<const typename St::T*>(a.X) + (size_t(g) * size_t(a.ncls) + size_t(a.cls[k])) * size_t(a.M);
-        const int rot = a.rot[k];
-        const int mmask = a.M - 1;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int ip = eng.in_index(m);
-            float2 acc = make_float2(0.f, 0.f);
-            for (int q = 0; q < a.spc; ++q) {
-                const int i = ip + q * a.Msub;
-                float2 xv = cmul(St::unpack(Xj[(i + rot) & mmask]), a.rect[i]);
-                const int e = (a.Msub * q * rho) & mmask;
-                if (e) xv = cmul(xv, a.rootsM[e]);
-                acc = cadd(acc, xv);
-            }
-            if (rho) acc = cmul(acc, a.rootsM[ip * rho]);
-            if constexpr (PREC != ACQ_FP32) acc = make_float2(acc.x * gscale, acc.y * gscale);
-            G[m] = acc;
-        }
-    }
+    first_step<E, PREC>(a, eng, g, k, rho, gscale, G);
 
     // valid outputs: segment lag spc*u + rho < min(V, lags - jV)  <=>  u < ulim
     const int64_t seg0 = int64_t(j) * a.V;
@@ -397,9 +407,88 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     __syncthreads();                             // red[] is rewritten by the next item
 }
 
+// One tracking work item: (global segment g, tile of bins, phase rho) for the
+// block's own tag, item index wi = (g * bin_tiles + tile) * spc + rho, with
+// a.tile bins per tile.  Every bin forms its G_rho and runs one inverse
+// transform; each lane keeps its largest key over all the item's bins, so one
+// wave reduction and one atomic per item remain.
+template <class E, int PREC>
+__device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int wi, float2* lds,
+                                           const float2* extra, unsigned long long* red) {
+    using St = dev::Storage<PREC>;
+    constexpr int NW = E::NT / 64;
+    const int ntl = (a.K + a.tile - 1) / a.tile;
+    int rem = wi;
+    const int rho = rem % a.spc;
+    rem /= a.spc;
+    const int btile = rem % ntl;
+    const int g = rem / ntl;
+    const int k0 = btile * a.tile, k1 = min(a.K, k0 + a.tile);
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const int bi = a.blocks.block_of_segment(g);
+    const BlockDesc d = a.blocks.get(bi);
+    const int j = a.blocks.segment(g, d);
+    const int tag = d.tag;
+
+    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
+    const __amdgpu_buffer_rsrc_t bank =
+        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag) * E::N * St::BYTES, uint32_t(E::N) * St::BYTES);
+    float gscale = 1.0f;
+    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, a.exps[bi] - a.bank_exp);
+
+    const int64_t seg0 = int64_t(j) * a.V;
+    const int64_t vlim64 = d.lags - seg0 < a.V ? d.lags - seg0 : a.V;
+    const int vlim = int(vlim64);
+    const int ulim = vlim > rho ? (vlim - rho + a.spc - 1) / a.spc : 0;
+    const unsigned kstep = unsigned(a.spc * a.K);
+    const int ob0 = eng.out_base();
+    const int omin = eng.out_min(), omax = eng.out_max();
+    const bool hi = omin + E::HI_OFF < ulim;
+    const int voff = eng.in_index(0) * St::BYTES;
+
+    unsigned long long best = 0ull;
+    for (int k = k0; k < k1; ++k) {
+        float2 v[16];
+        first_step<E, PREC>(a, eng, g, k, rho, gscale, v);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = cmul(v[m], St::bload(bank, voff, (m * E::NT) * St::BYTES));
+        eng.template transform<+1>(v, lds, b1, extra, hi);
+        int ob = ob0;
+        unsigned idx0 = unsigned((seg0 + rho) * a.K + k) + unsigned(ob0) * kstep;
+        asm volatile("" : "+v"(ob), "+v"(idx0));
+        float bp = -1.0f;
+        int boff = 0;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            const int r = ((rr & 3) << 2) | (rr >> 2);
+            const int off = E::out_off(r);
+            if (omin + off < ulim) {
+                float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
+                if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
+                boff = p > bp ? off : boff;
+                bp = p > bp ? p : bp;
+            }
+        }
+        const unsigned long long key = bp >= 0.0f
+            ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) |
+                  static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
+            : 0ull;
+        best = key > best ? key : best;
+    }
+    best = wave_max(best);
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0ull;
+        for (int q = 0; q < NW; ++q) m = red[q] > m ? red[q] : m;
+        if (m) atomicMax(&a.keys[size_t(bi) * a.T + tag], m);
+    }
+    __syncthreads();
+}
+
 // Launch forms of the correlation kernel.  Each is its own instantiation so the
 // persistent loop's live state does not weigh on the one-item-per-workgroup forms.
-enum CorrMode { kCorrGrid = 0, kCorrGridDump = 1, kCorrPersistent = 2 };
+enum CorrMode { kCorrGrid = 0, kCorrGridDump = 1, kCorrPersistent = 2, kCorrTrack = 3 };
 
 template <class E, int PREC, int MODE>
 __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
@@ -410,7 +499,8 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
     __shared__ unsigned long long red[kMaxTagTile * NW];
     __shared__ int s_item;
     const int total_seg = a.blocks.total_seg();
-    const int total = a.ntiles * total_seg * a.K * a.spc;
+    const int total = MODE == kCorrTrack ? total_seg * ((a.K + a.tile - 1) / a.tile) * a.spc
+                                         : a.ntiles * total_seg * a.K * a.spc;
     // Workgroups are dealt round-robin to the XCDs; each XCD takes a contiguous
     // range of work items, so items sharing a segment and a tag tile share its L2.
     const int xcd = int(blockIdx.x) % kXcds;
@@ -439,7 +529,10 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
         const int wi = xcd * per + q;
         if (q >= per || wi >= total) return;
         eng.init(a.rootsSub, extra);
-        correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red);
+        if constexpr (MODE == kCorrTrack)
+            track_item<E, PREC>(a, eng, wi, lds, extra, red);
+        else
+            correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red);
     }
 }
 
@@ -454,9 +547,12 @@ constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
 template <int WMAX, int NT>
 __global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
     constexpr int NW = NT / 64;
-    const int bi = int(blockIdx.x) / a.T, tag = int(blockIdx.x) % a.T;
+    const int per = a.track ? 1 : a.T;
+    const int bi = int(blockIdx.x) / per;
     if (bi >= a.blocks.nblocks()) return;
     const BlockDesc d = a.blocks.get(bi);
+    const int tag = a.track ? d.tag : int(blockIdx.x) % per;
+    if (tag < 0 || tag >= a.T) return;
     const size_t slot = size_t(bi) * a.T + tag;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     __shared__ double s_px;
@@ -589,16 +685,46 @@ __global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
     }
 }
 
-// detections in (block, tag) order
-__global__ void k_compact(BlockTable bt, const acq_detection* __restrict__ dets, const int32_t* __restrict__ found,
-                          int T, acq_detection* __restrict__ out, int32_t* __restrict__ count) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Detections in (block, tag) order.  One workgroup: each thread takes a
+// contiguous run of candidates, counts its detections, an exclusive scan over
+// the threads gives its first output slot, and it copies its run in order.
+// Candidates are every (block, tag), or (block, its tag) for tracking tasks.
+constexpr int kCompactThreads = 1024;
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(BlockTable bt, const acq_detection* __restrict__ dets,
+                                                             const int32_t* __restrict__ found, int T, int track,
+                                                             acq_detection* __restrict__ out,
+                                                             int32_t* __restrict__ count) {
+    __shared__ int scan[kCompactThreads];
+    const int t = int(threadIdx.x);
     const int nb = bt.nblocks();
+    const int64_t n = track ? int64_t(nb) : int64_t(nb) * T;
+    const int64_t per = (n + kCompactThreads - 1) / kCompactThreads;
+    const int64_t e0 = min(n, int64_t(t) * per), e1 = min(n, e0 + per);
+    auto slot = [&](int64_t e) -> int64_t {
+        if (!track) return e;
+        const int tag = bt.get(int(e)).tag;
+        return tag >= 0 && tag < T ? e * T + tag : -1;
+    };
     int c = 0;
-    for (int b = 0; b < nb; ++b)
-        for (int i = 0; i < T; ++i)
-            if (found[size_t(b) * T + i]) out[c++] = dets[size_t(b) * T + i];
-    *count = c;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t s = slot(e);
+        c += s >= 0 && found[s] ? 1 : 0;
+    }
+    scan[t] = c;
+    __syncthreads();
+    for (int off = 1; off < kCompactThreads; off <<= 1) {     // inclusive Hillis-Steele scan
+        const int v = t >= off ? scan[t - off] : 0;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    int o = scan[t] - c;
+    for (int64_t e = e0; e < e1; ++e) {
+        const int64_t s = slot(e);
+        if (s >= 0 && found[s]) out[o++] = dets[s];
+    }
+    if (t == kCompactThreads - 1) *count = scan[t];
 }
 
 }  // namespace
@@ -695,7 +821,9 @@ hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const floa
 
 template <class E, int PREC>
 static void corr_ep(const CorrArgs& a, int grid, hipStream_t st) {
-    if (a.persistent)
+    if (a.track)
+        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrTrack>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (a.persistent)
         hipLaunchKernelGGL((k_correlate<E, PREC, kCorrPersistent>), dim3(grid), dim3(E::NT), 0, st, a);
     else if (a.dump)
         hipLaunchKernelGGL((k_correlate<E, PREC, kCorrGridDump>), dim3(grid), dim3(E::NT), 0, st, a);
@@ -717,6 +845,7 @@ static hipError_t corr_e(const CorrArgs& a, int grid, int prec, hipStream_t st) 
 hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec, int engine, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile || grid % kXcds) return hipErrorInvalidValue;
+    if (a.track && (a.persistent || a.dump)) return hipErrorInvalidValue;
     switch (log2_sub) {
         case 10: return corr_e<StockhamEngine<10>>(a, grid, prec, st);
         case 11: return corr_e<StockhamEngine<11>>(a, grid, prec, st);
@@ -731,16 +860,17 @@ hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec,
 hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
     if (a.radius < 0 || a.radius > kMaxRefineRadius || (a.M & (a.M - 1)) || (1 << a.log2_spc) != a.spc)
         return hipErrorInvalidValue;
+    const unsigned grid = unsigned(max_blocks) * unsigned(a.track ? 1 : a.T);
     if (a.radius <= 1)
-        hipLaunchKernelGGL((k_refine<5, 1024>), dim3(unsigned(max_blocks) * a.T), dim3(1024), 0, st, a);
+        hipLaunchKernelGGL((k_refine<5, 1024>), dim3(grid), dim3(1024), 0, st, a);
     else
-        hipLaunchKernelGGL((k_refine<kMaxWin, 256>), dim3(unsigned(max_blocks) * a.T), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_refine<kMaxWin, 256>), dim3(grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T,
+hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T, int track,
                           acq_detection* out, int32_t* count, hipStream_t st) {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, bt, dets, found, T, out, count);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, bt, dets, found, T, track, out, count);
     return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct acq_plan_s {
     int engine = 0;                     // acq_tuning.engine
     int tile = 16;                      // acq_tuning.tag_tile
     int batch_launch = ACQ_BATCH_GRID;  // acq_tuning.batch_launch
+    int track_bins = 0;                 // acq_tuning.track_bins (0: chosen per launch)
 
     float2* d_X = nullptr;              // [segments][classes][M] FP32 segment spectra
     void* d_Xh = nullptr;               // [segments][classes][M] 16-bit segment spectra (FP16/BF16 plans)
@@ -43,7 +44,7 @@ struct acq_plan_s {
     double* d_cyc = nullptr;            // [K] f_k / Fs
     void* d_bank = nullptr;             // [T][Msub] in the plan's storage format
     int bank_exp = 0;                   // power-of-two prescale of the stored bank
-    float2* d_rect = nullptr;           // [M]
+    float2* d_wts = nullptr;            // [spc][M] first-step weights of the split inverse transform
     float2* d_rootsM = nullptr;         // [M]
     float2* d_rootsSub = nullptr;       // [Msub]
     double2* d_roots64 = nullptr;       // [M] FP64 unit roots (refinement mix)
@@ -75,9 +76,11 @@ struct acq_plan_s {
     hipEvent_t ev[ACQ_NUM_KERNELS][2] = {};
     bool ev_used[ACQ_NUM_KERNELS] = {};
 
-    hipStream_t cap_stream = nullptr;   // private stream the batch graph is captured on
-    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream the batch graphs are captured on
+    hipGraph_t graph = nullptr;         // searching batch
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t tgraph = nullptr;        // tracking batch
+    hipGraphExec_t tgexec = nullptr;
 };
 
 namespace {
@@ -103,14 +106,18 @@ hipError_t dalloc(T** p, size_t count) {
 void drop_graph(acq_plan_s* p) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->tgexec) (void)hipGraphExecDestroy(p->tgexec);
+    if (p->tgraph) (void)hipGraphDestroy(p->tgraph);
     p->gexec = nullptr;
     p->graph = nullptr;
+    p->tgexec = nullptr;
+    p->tgraph = nullptr;
 }
 
 void free_plan(acq_plan_s* p) {
     if (!p) return;
     drop_graph(p);
-    void* dev[] = {p->d_X, p->d_Xh, p->d_cls, p->d_cls_cyc, p->d_cyc, p->d_bank, p->d_rect, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
+    void* dev[] = {p->d_X, p->d_Xh, p->d_cls, p->d_cls_cyc, p->d_cyc, p->d_bank, p->d_wts, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
                    p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_exps, p->d_dets,
                    p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
@@ -142,7 +149,7 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(hipMalloc(&p->d_bank, T * size_t(g.Msub) * (half ? 4 : 8)));
     // 16-bit banks are stored with rms magnitude near 1: 2^round(log2(M / sqrt(C)))
     p->bank_exp = half ? int(std::lrint(std::log2(double(g.M) / std::sqrt(double(C))))) : 0;
-    ACQ_HIP(dalloc(&p->d_rect, size_t(g.M)));
+    ACQ_HIP(dalloc(&p->d_wts, size_t(g.M) * size_t(c.samples_per_chip)));
     ACQ_HIP(dalloc(&p->d_rootsM, size_t(g.M)));
     ACQ_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
     ACQ_HIP(dalloc(&p->d_roots64, size_t(g.M)));
@@ -174,12 +181,12 @@ int build_plan(acq_plan_s* p) {
     const std::vector<float> rootsM = acq::unit_roots(g.M);
     const std::vector<float> rootsSub = acq::unit_roots(g.Msub);
     const std::vector<double> roots64 = acq::unit_roots64(g.M);
-    const std::vector<float> rect = acq::rect_spectrum_conj(g.M, c.samples_per_chip);
+    const std::vector<float> wts = acq::phase_weights(g.M, c.samples_per_chip);
     hipStream_t st = p->stream;
     ACQ_HIP(hipMemcpyAsync(p->d_rootsM, rootsM.data(), rootsM.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rootsSub, rootsSub.data(), rootsSub.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_roots64, roots64.data(), roots64.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    ACQ_HIP(hipMemcpyAsync(p->d_rect, rect.data(), rect.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    ACQ_HIP(hipMemcpyAsync(p->d_wts, wts.data(), wts.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_b1tab, b1.data(), b1.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_chips, c.chips, T * C, hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rot, g.rot.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, st));
@@ -222,9 +229,10 @@ double threshold_for(const acq_plan_s* p, int64_t n) {
 // Launch sequence of a search on stream st.  `bt` holds one inline block
 // (single-block calls: plain grids sized on the host) or the plan's device
 // block table (batches: persistent grids that do not depend on the batch, so
-// the sequence can be captured once and replayed).
+// the sequence can be captured once and replayed).  track: every block is a
+// tracking task searched for its own tag only.
 int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_seg_host, float* dump,
-                   bool refine, hipStream_t st) {
+                   bool refine, hipStream_t st, bool track = false) {
     const Geometry& g = p->g;
     const acq_config& c = p->cfg;
     const int nb_grid = batch ? g.max_blocks : 1;
@@ -263,7 +271,7 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ca.X = c.precision == ACQ_FP32 ? static_cast<const void*>(p->d_X) : p->d_Xh;
     ca.bank = p->d_bank;
     ca.exps = p->d_exps;
-    ca.rect = p->d_rect;
+    ca.wts = p->d_wts;
     ca.rootsM = p->d_rootsM;
     ca.rootsSub = p->d_rootsSub;
     ca.b1tab = p->d_b1tab;
@@ -282,9 +290,28 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ca.tile = p->tile;
     ca.ntiles = (c.num_tags + p->tile - 1) / p->tile;
     ca.bank_exp = p->bank_exp;
-    ca.persistent = batch && p->batch_launch == ACQ_BATCH_PERSISTENT ? 1 : 0;
+    ca.persistent = batch && !track && p->batch_launch == ACQ_BATCH_PERSISTENT ? 1 : 0;
+    ca.track = track ? 1 : 0;
     int grid;
-    if (ca.persistent) {
+    if (track) {
+        // bins per work item: enough items to give every compute unit about
+        // eight, each amortising its launch over as many bins as that allows
+        const int64_t segs = p->capturing ? int64_t(g.max_total_segments) : int64_t(total_seg_host);
+        int bins = p->track_bins;
+        if (bins <= 0) {
+            const int64_t per_bin = segs * c.samples_per_chip;
+            const int64_t want = int64_t(8) * p->cus;
+            bins = int(std::max<int64_t>(1, std::min<int64_t>(c.num_bins, per_bin * c.num_bins / want)));
+            const int ntl = (c.num_bins + bins - 1) / bins;      // even tiles
+            bins = (c.num_bins + ntl - 1) / ntl;
+        }
+        bins = std::min(bins, c.num_bins);
+        ca.tile = bins;
+        ca.ntiles = 1;
+        const int64_t nwork = segs * ((c.num_bins + bins - 1) / bins) * c.samples_per_chip;
+        if (nwork >= (int64_t(1) << 31) - 8) return acq::fail(ACQ_ERR_UNSUPPORTED, "too many work items");
+        grid = int((nwork + acq::kXcds - 1) / acq::kXcds) * acq::kXcds;
+    } else if (ca.persistent) {
         ACQ_HIP(acq::launch_fill_i32(p->d_counters, acq::kXcds, st));
         grid = p->cus;
     } else {
@@ -321,17 +348,19 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ra.exact = g.exact ? 1 : 0;
     ra.M = int(g.M);
     ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
+    ra.track = track ? 1 : 0;
     {
         KernelTimer kt(p, ACQ_KERNEL_REFINE);
         ACQ_HIP(acq::launch_refine(ra, nb_grid, st));
     }
     {
         KernelTimer kt(p, ACQ_KERNEL_COMPACT);
-        ACQ_HIP(acq::launch_compact(bt, p->d_dets, p->d_found, c.num_tags, p->d_out, p->d_count, st));
+        ACQ_HIP(acq::launch_compact(bt, p->d_dets, p->d_found, c.num_tags, track ? 1 : 0, p->d_out, p->d_count, st));
     }
     ACQ_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    ACQ_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_detection) * size_t(nb_grid) * size_t(c.num_tags),
-                           hipMemcpyDeviceToHost, st));
+    // at most one detection per (block, tag), per task when tracking
+    const size_t most = size_t(nb_grid) * size_t(track ? 1 : c.num_tags);
+    ACQ_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_detection) * most, hipMemcpyDeviceToHost, st));
     return ACQ_OK;
 }
 
@@ -353,7 +382,50 @@ BlockDesc single_desc(const acq_plan_s* p, const void* block, int64_t n) {
     d.seg0 = 0;
     d.nseg = d.lags > 0 ? int((d.lags + p->g.V - 1) / p->g.V) : 0;
     d.theta = threshold_for(p, n);
+    d.tag = -1;
     return d;
+}
+
+// Copies the staged descriptors and runs a batch search: eagerly, or by
+// replaying the plan's captured graph for this kind of batch (captured on
+// first use with grids sized for the plan's capacity).
+int launch_batch(acq_plan_s* p, int32_t seg, bool track) {
+    BlockTable bt{};
+    bt.descs = p->d_descs;
+    bt.counts = p->d_counts;
+    const size_t desc_bytes = sizeof(BlockDesc) * size_t(p->g.max_blocks);
+    if (p->cfg.flags & ACQ_FLAG_GRAPH) {
+        hipGraph_t& graph_ref = track ? p->tgraph : p->graph;
+        hipGraphExec_t& exec_ref = track ? p->tgexec : p->gexec;
+        if (!exec_ref) {
+            if (!p->cap_stream) ACQ_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            ACQ_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            p->capturing = true;
+            int rc = ACQ_OK;
+            hipError_t e = hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->cap_stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   p->cap_stream);
+            if (e == hipSuccess) rc = enqueue_search(p, bt, true, 0, nullptr, true, p->cap_stream, track);
+            p->capturing = false;
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+            if (e != hipSuccess || rc != ACQ_OK || e2 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                if (rc != ACQ_OK) return rc;
+                return acq::fail(ACQ_ERR_DEVICE, hip_msg("graph capture", e != hipSuccess ? e : e2));
+            }
+            graph_ref = graph;
+            ACQ_HIP(hipGraphInstantiate(&exec_ref, graph_ref, nullptr, nullptr, 0));
+        }
+        ACQ_HIP(hipGraphLaunch(exec_ref, p->stream));
+    } else {
+        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->stream));
+        ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+        const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream, track);
+        if (rc != ACQ_OK) return rc;
+    }
+    return ACQ_OK;
 }
 
 int deliver(acq_plan_s* p, acq_detection* out, int32_t capacity, int32_t* n_found) {
@@ -475,39 +547,46 @@ int acq_detect_batch(acq_plan_t p, const void* const* blocks, const int64_t* len
     p->h_counts[1] = seg;
     reset_timers(p);
 
-    BlockTable bt{};
-    bt.descs = p->d_descs;
-    bt.counts = p->d_counts;
-    const size_t desc_bytes = sizeof(BlockDesc) * size_t(p->g.max_blocks);
-    if (p->cfg.flags & ACQ_FLAG_GRAPH) {
-        if (!p->gexec) {
-            if (!p->cap_stream) ACQ_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-            ACQ_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-            p->capturing = true;
-            int rc = ACQ_OK;
-            hipError_t e = hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->cap_stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice,
-                                   p->cap_stream);
-            if (e == hipSuccess) rc = enqueue_search(p, bt, true, 0, nullptr, true, p->cap_stream);
-            p->capturing = false;
-            hipGraph_t graph = nullptr;
-            const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
-            if (e != hipSuccess || rc != ACQ_OK || e2 != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
-                if (rc != ACQ_OK) return rc;
-                return acq::fail(ACQ_ERR_DEVICE, hip_msg("graph capture", e != hipSuccess ? e : e2));
-            }
-            p->graph = graph;
-            ACQ_HIP(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
-        }
-        ACQ_HIP(hipGraphLaunch(p->gexec, p->stream));
-    } else {
-        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->stream));
-        ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
-        const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream);
+    const int rc = launch_batch(p, seg, false);
+    if (rc != ACQ_OK) return rc;
+    ACQ_HIP(hipStreamSynchronize(p->stream));
+    return deliver(p, out, capacity, n_found);
+}
+
+int acq_track_batch(acq_plan_t p, const acq_track_task* tasks, int32_t ntasks, acq_detection* out,
+                    int32_t capacity, int32_t* n_found) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (!tasks || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (ntasks < 1 || ntasks > p->g.max_blocks)
+        return acq::fail(ACQ_ERR_INVALID_ARG, "ntasks outside [1, max_batch_blocks]");
+    int64_t total = 0;
+    for (int32_t b = 0; b < ntasks; ++b) {
+        const int rc = check_block(p, tasks[b].block, tasks[b].n);
         if (rc != ACQ_OK) return rc;
+        if (tasks[b].tag < 0 || tasks[b].tag >= p->cfg.num_tags)
+            return acq::fail(ACQ_ERR_INVALID_ARG, "task tag outside [0, num_tags)");
+        total += tasks[b].n;
     }
+    if (total > p->g.max_batch_samples)
+        return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "batch longer than max_batch_samples");
+    *n_found = 0;
+    const acq_config& c = p->cfg;
+    int32_t seg = 0;
+    for (int32_t b = 0; b < ntasks; ++b) {
+        BlockDesc d = single_desc(p, tasks[b].block, tasks[b].n);
+        d.seg0 = seg;
+        d.tag = tasks[b].tag;
+        // one code is tested: K * (n - L + 1) hypotheses
+        d.theta = c.threshold > 0.0 ? c.threshold : acq::default_threshold(1, c.num_bins, tasks[b].n, p->g.L);
+        seg += d.nseg;
+        p->h_descs[b] = d;
+    }
+    p->h_counts[0] = ntasks;
+    p->h_counts[1] = seg;
+    reset_timers(p);
+    const int rc = launch_batch(p, seg, true);
+    if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
     return deliver(p, out, capacity, n_found);
 }
@@ -660,20 +739,25 @@ int acq_get_tuning(acq_plan_t p, acq_tuning* out) {
     out->engine = p->engine;
     out->tag_tile = p->tile;
     out->batch_launch = p->batch_launch;
+    out->track_bins = p->track_bins;
     return ACQ_OK;
 }
 
 int acq_set_tuning(acq_plan_t p, const acq_tuning* t) {
     if (!p || !t) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
     if (t->engine < 0 || t->engine > 1 || t->tag_tile < 1 || t->tag_tile > acq::kMaxTagTile ||
-        (t->batch_launch != ACQ_BATCH_GRID && t->batch_launch != ACQ_BATCH_PERSISTENT))
-        return acq::fail(ACQ_ERR_INVALID_ARG, "engine must be 0 or 1, tag_tile in [1, 64], batch_launch 0 or 1");
+        (t->batch_launch != ACQ_BATCH_GRID && t->batch_launch != ACQ_BATCH_PERSISTENT) || t->track_bins < 0 ||
+        t->track_bins > acq::kMaxTagTile)
+        return acq::fail(ACQ_ERR_INVALID_ARG,
+                         "engine must be 0 or 1, tag_tile in [1, 64], batch_launch 0 or 1, track_bins in [0, 64]");
     const int tile = t->tag_tile < p->cfg.num_tags ? t->tag_tile : p->cfg.num_tags;
-    if (t->engine != p->engine || tile != p->tile || t->batch_launch != p->batch_launch)
+    if (t->engine != p->engine || tile != p->tile || t->batch_launch != p->batch_launch ||
+        t->track_bins != p->track_bins)
         drop_graph(p);   // the captured kernels change
     p->engine = t->engine;
     p->tile = tile;
     p->batch_launch = t->batch_launch;
+    p->track_bins = t->track_bins;
     return ACQ_OK;
 }
 
@@ -697,7 +781,7 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
             c.tuning.tag_tile = tile;
             cand.push_back(c);
         }
-    const acq_tuning before{p->engine, p->tile, p->batch_launch};
+    const acq_tuning before{p->engine, p->tile, p->batch_launch, p->track_bins};
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
     // the same block repeated as a batch (device descriptor table): as many
@@ -739,6 +823,7 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
     size_t best = 0;
     for (size_t i = 0; i < cand.size() && rc == ACQ_OK; ++i) {
         cand[i].tuning.batch_launch = before.batch_launch;
+        cand[i].tuning.track_bins = before.track_bins;
         rc = time_one(cand[i].tuning, false, &cand[i].ms);
         if (cand[i].ms < cand[best].ms) best = i;
     }

@@ -35,6 +35,7 @@ import numpy as np
 __all__ = [
     "rng", "make_codes", "chip_waveform", "delayed_waveform", "Transmission",
     "make_block", "add_noise", "WORKLOADS", "workload", "batch_lengths", "make_stream_batch",
+    "make_tracking_batch",
 ]
 
 # stream identifiers (second SeedSequence word)
@@ -192,6 +193,12 @@ WORKLOADS = {
                            bin_center_hz=0.0, bin_step_hz=1000.0, fft_len=0, num_blocks=64,
                            block_len_log2=(18.0, 21.0), receivers=8, n_tx=(0, 20),
                            snr_db=(-15.0, -5.0), precision="fp32", seeds=(4000, 4005)),
+    # tracking tasks: one code per task, blocks 1.5 templates long (the 12 ms
+    # window around an 8 ms packet), 256 tasks per batch over the same bank
+    "tracking": dict(num_tags=256, num_chips=8192, spc=2, fs_hz=8e6, num_bins=21,
+                     bin_center_hz=0.0, bin_step_hz=1000.0, fft_len=0, num_tasks=256,
+                     block_factor=1.5, p_present=0.9, n_other=(0, 1), snr_db=(-15.0, -5.0),
+                     precision="fp32", seeds=(5000, 5005)),
 }
 
 
@@ -223,4 +230,29 @@ def make_stream_batch(seed: int, chips: np.ndarray, spc: int, fs_hz: float, freq
         k = int(g.integers(n_tx[0], n_tx[1] + 1)) if n >= L + 1 else 0
         sub = (b % receivers) * 100000 + b
         out.append(make_block(seed, n, chips, spc, fs_hz, freqs_hz, k, snr_db=snr_db, sub=sub))
+    return out
+
+
+def make_tracking_batch(seed: int, chips: np.ndarray, spc: int, fs_hz: float, freqs_hz: Sequence[float],
+                        num_tasks: int, block_factor: float = 1.5, p_present: float = 0.9, n_other=(0, 1),
+                        snr_db=(-15.0, -5.0)):
+    """Tracking tasks: task i looks for one tag in a block of floor(block_factor * L)
+    samples.  The tag is drawn uniformly; its packet is in the block with
+    probability p_present, joined by a uniform number in [n_other[0], n_other[1]]
+    of other tags' packets.  Returns a list of (x complex64, tag, list[Transmission])."""
+    chips = np.asarray(chips)
+    T = chips.shape[0]
+    L = chips.shape[1] * spc
+    n = int(np.floor(block_factor * L))
+    g = rng(seed, _STREAM_LENGTHS, 2)
+    out = []
+    for i in range(num_tasks):
+        tag = int(g.integers(0, T))
+        present = bool(g.random() < p_present)
+        k_other = int(g.integers(n_other[0], n_other[1] + 1))
+        others = [int(t) for t in g.choice([t for t in range(T) if t != tag], size=k_other, replace=False)]
+        tags = ([tag] if present else []) + others
+        x, txs = make_block(seed, n, chips, spc, fs_hz, freqs_hz, len(tags), snr_db=snr_db, tags=tags,
+                            sub=300000 + i)
+        out.append((x, tag, txs))
     return out

@@ -173,3 +173,13 @@ def test_exact_bins_report_the_requested_frequencies(capi):
     assert np.allclose(snapped / q, np.round(snapped / q)) and not np.array_equal(f, snapped)
     g = geometry(exact_bins=True, **kw)
     assert g["device_bytes"] > geometry(**kw)["device_bytes"]      # one set of spectra per residual
+
+
+def test_track_batch_validates_without_a_gpu(capi):
+    import ctypes
+    from paper_2005_10445_amd import _capi
+    L = _capi.lib()
+    assert ctypes.sizeof(_capi.AcqTrackTask) == 24
+    nf = ctypes.c_int32(7)
+    task = _capi.AcqTrackTask(None, 0, 0, 0)
+    assert L.acq_track_batch(None, ctypes.byref(task), 1, None, 0, ctypes.byref(nf)) == _capi.ACQ_ERR_INVALID_ARG

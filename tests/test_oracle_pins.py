@@ -348,3 +348,44 @@ def test_power_and_snr_estimates_noise_free_and_statistical():
     a2m = np.mean([e[0] for e in ests])
     snrm = np.median([e[1] for e in ests])
     assert abs(a2m - A * A) < 0.01 and abs(snrm / (A * A / s2) - 1) < 0.05
+
+
+def test_tracking_task_is_the_one_code_search(oracle_lib):
+    """A tracking task for tag t: (bin, lag) is the brute-force argmax of that one
+    template's |c|^2 (ties to the smaller lag, then bin) even with other tags'
+    transmissions in the block, and the default threshold counts K (N-L+1)
+    hypotheses, not T K (N-L+1)."""
+    fs = 8e6
+    chips = siggen.make_codes(31, 3, 4)
+    freqs = [-250e3, 0.0, 375e3]
+    x, _ = siggen.make_block(32, 64, chips, 2, fs, freqs, 3, snr_db=(3.0, 3.0), tags=[0, 1, 2],
+                             delays=[3, 20, 41], fracs=[0.0, 0.0, 0.0], bins=[2, 0, 1])
+    s = [[float(chips[t][n // 2]) for n in range(8)] for t in range(3)]
+    B = _brute_power(x, s, freqs, fs)
+    for tag in range(3):
+        r = oracle.track(x, chips, 2, freqs, fs, tag)
+        Bt = B[tag]
+        best = max(((Bt[k, tau], -tau, -k) for k in range(3) for tau in range(Bt.shape[1])))
+        assert (r["bin"], r["lag"]) == (-best[2], -best[1]) and r["tag"] == tag
+        assert abs(r["peak_power"] - best[0]) <= 1e-9 * best[0]
+        assert r["theta"] == math.log(3 * 57 / 1e-3)
+    assert oracle.track(x[:7], chips, 2, freqs, fs, 0) is None
+
+
+def test_tracking_task_exact_recovery(oracle_lib):
+    """Noise-free packet of tag 2 in a block 1.5 L long among other tags' packets:
+    lag exact, P = L^2 exactly, vertex exactly on the lag."""
+    C, spc, fs = 256, 2, 8e6
+    L = C * spc
+    N = 3 * L // 2
+    chips = siggen.make_codes(33, 4, C)
+    x, _ = siggen.make_block(34, N, chips, spc, fs, [0.0], 2, snr_db=(0.0, 0.0), noise=False,
+                             tags=[2, 0], delays=[100, 200], fracs=[0.0, 0.0], bins=[0, 0], phases=[0.0, 0.0])
+    r = oracle.track(x, chips, spc, [0.0], fs, 2)
+    assert r["lag"] == 100 and r["delta"] == 0.0
+    # the other packet adds its cross-correlation with tag 2's code: the peak is
+    # (L + cross)^2 where cross is the chip-level overlap sum, an integer
+    s2 = oracle.templates(chips, spc)[2]
+    s0 = oracle.templates(chips, spc)[0]
+    cross = float(np.dot(s2[100:], s0[:L - 100]))
+    assert r["peak_power"] == (L + cross) ** 2
