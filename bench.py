@@ -33,7 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "correlate_tagbank_traffic.json")
+# rocprofv3 HBM byte counts of the correlation kernel, per workload
+TRAFFIC_FILES = {"tagbank_fp32": os.path.join(ROOT, "profiles", "correlate_tagbank_traffic.json"),
+                 "tracking": os.path.join(ROOT, "profiles", "correlate_tracking_traffic.json")}
 
 
 def log(*a):
@@ -44,11 +46,13 @@ def correlate_flops(T, K, S, M, V) -> float:
     return float(T) * K * S * (5.0 * M * math.log2(M) + 6.0 * M + 4.0 * V)
 
 
-def traffic_per_launch():
-    """HBM bytes per correlation launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
+def traffic_per_launch(workload: str):
+    """HBM bytes per correlation launch from the committed counter summary of the
+    workload, if it was taken on the current kernel source; else None."""
+    if workload not in TRAFFIC_FILES:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -119,7 +123,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(the path is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+              f"(the path runs on a single GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -253,7 +257,7 @@ def main():
                    "graph": bool((batched or tracking) and args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS if achieved else None,
-                     "traffic": traffic_per_launch() if args.workload == "tagbank_fp32" else None,
+                     "traffic": traffic_per_launch(args.workload),
                      "kernel": "k_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},
     }
     if args.cpu_budget > 0:

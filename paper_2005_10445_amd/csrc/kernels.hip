@@ -5,107 +5,62 @@
 //                    tail, as spc decimated Msub-point transforms (one workgroup
 //                    each) combined by one radix-spc decimation-in-time step
 //   k_bank         : replica spectra conj(DFT_Msub(chip code)) / M, plan time
-//   k_correlate    : the hot loop, see below
+//   k_correlate    : the hot loop, in correlate.hip
 //   k_refine       : FP64 re-correlation around each tag's peak, re-maximisation,
 //                    parabolic vertex, z and energy
 //   k_compact      : detections in tag order
 //
-// Correlation by overlap-save (the FFT identity of Section 4.1 with the
-// conjugate on the replica; segmented processing as in Section 4.1's
-// overlap-add remark, here overlap-save so each segment yields V = M-L+1 lags):
-//
-//   c_j[tau] = (1/M) sum_i X_j[(i + m_k) mod M] conj(S_t[i]) exp(+j 2 pi i tau / M)
-//
-// equals c[t,k,jV+tau] up to a unit-modulus factor for tau < V (the bin's
-// frequency shift is the rotation by m_k = f_k M / Fs).  The replica is a
-// +/-1 code held spc samples per chip, so its spectrum factors as
-// S_t[i] = Chat_t[i mod Msub] * Rect[i], Msub = M / spc, with Chat_t the
-// Msub-point spectrum of the chip code and Rect the spectrum of a run of spc
-// ones.  Splitting i = i' + Msub*a and the output lag tau = spc*u + rho turns
-// the M-point inverse transform into a radix-spc first step that does not
-// depend on the tag,
-//
-//   G_rho[i'] = exp(+j 2 pi i' rho / M) sum_a X_j[(i'+Msub a + m_k) mod M]
-//               conj(Rect[i'+Msub a]) exp(+j 2 pi a rho / spc),
-//
-// followed per tag by an Msub-point inverse transform of conj(Chat_t) G_rho,
-// whose output u is the lag spc*u + rho.  One work item is (segment j, bin k,
-// phase rho, tile of tags): it forms G_rho once in registers, then for each tag
-// multiplies by the stored conj(Chat_t)/M, runs the LDS-resident inverse
-// transform, squares, masks invalid lags and max-reduces a 64-bit key per tag:
-// key = float_bits(P) << 32 | ~(tau*K + k), so the largest key is the largest
-// power with ties going to the smaller lag and then the smaller bin (the
-// argmax of Section 3, step 8).  P >= 0, so its bit pattern orders like its
-// value.
 #include <hip/hip_runtime.h>
 
-#include "device_fft.h"
-#include "fft14.h"
-#include "storage.h"
+#include <algorithm>
+
+#include "device_common.h"
 #include "host_logic.h"
 #include "kernels.h"
 
 namespace acq {
 
-using dev::cadd;
-using dev::cmul;
-using dev::cmulc;
-using dev::Fft;
-using dev::dft16;
+using namespace kdev;
 
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// One step of a wave maximum: each lane takes the larger of its value and the
-// value DPP control CTRL routes to it (lanes with no source, or in rows outside
-// ROW_MASK, see 0).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, ROW_MASK, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, ROW_MASK, 0xf, true);
-    const unsigned long long t = (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo);
-    return t > v ? t : v;
-}
-
-// Maximum over the wave (uniform result, no LDS): row_shr 1, 2, 4, 8 leave each
-// 16-lane row's maximum in its lane 15; row_bcast 15 (into rows 1 and 3) and
-// row_bcast 31 (into rows 2 and 3) carry the total to lane 63.
-__device__ __forceinline__ unsigned long long wave_max(unsigned long long v) {
-    v = dpp_max_step<0x111, 0xf>(v);
-    v = dpp_max_step<0x112, 0xf>(v);
-    v = dpp_max_step<0x114, 0xf>(v);
-    v = dpp_max_step<0x118, 0xf>(v);
-    v = dpp_max_step<0x142, 0xa>(v);
-    v = dpp_max_step<0x143, 0xc>(v);
-    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(v)), 63));
-    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(v >> 32)), 63));
-    return (static_cast<unsigned long long>(hi) << 32) | lo;
-}
-
 // ------------------------------------------------------------------ block power
-// grid = max_blocks * kPowerParts; partial sums of block b in parts[b][*]
+// Partial sums of block b in parts[b][*]: item part * blocks + b sums
+// the part-th chunk of the block (chunks of at least kPowerMinChunk samples,
+// so short blocks use few parts and the rest hold zeros); workgroups stride
+// over the items of the batch, and every item is summed in the same order
+// whichever workgroup takes it, so the sums are deterministic.
+constexpr int kPowerMaxGrid = 4096;
+constexpr int64_t kPowerMinChunk = 4096;
+
 __global__ __launch_bounds__(256) void k_block_power(BlockTable bt, double* __restrict__ parts) {
-    const int b = int(blockIdx.x) / kPowerParts, part = int(blockIdx.x) % kPowerParts;
-    if (b >= bt.nblocks()) return;
-    const BlockDesc d = bt.get(b);
-    const int64_t chunk = (d.n + kPowerParts - 1) / kPowerParts;
-    const int64_t beg = int64_t(part) * chunk;
-    const int64_t end = beg + chunk < d.n ? beg + chunk : d.n;
-    double acc = 0.0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
-        const float2 v = d.x[i];
-        acc += double(v.x) * double(v.x) + double(v.y) * double(v.y);
-    }
-    acc = wave_sum(acc);
     __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) parts[size_t(b) * kPowerParts + part] = (red[0] + red[1]) + (red[2] + red[3]);
+    const int nb = bt.nblocks();
+    const int items = nb * kPowerParts;
+    // part-major order: the non-empty low parts of every block come first and
+    // spread over distinct workgroups
+    for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
+        const int b = it % nb, part = it / nb;
+        const BlockDesc d = bt.get(b);
+        int64_t chunk = (d.n + kPowerParts - 1) / kPowerParts;
+        chunk = chunk > kPowerMinChunk ? chunk : kPowerMinChunk;
+        const int64_t beg = int64_t(part) * chunk;
+        if (beg >= d.n) {                            // uniform: an empty part
+            if (threadIdx.x == 0) parts[size_t(b) * kPowerParts + part] = 0.0;
+            continue;
+        }
+        const int64_t end = beg + chunk < d.n ? beg + chunk : d.n;
+        double acc = 0.0;
+        for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
+            const float2 v = d.x[i];
+            acc += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+        }
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) parts[size_t(b) * kPowerParts + part] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t count) {
@@ -124,46 +79,6 @@ __device__ __forceinline__ double block_mean_power(const double* __restrict__ pa
     for (int i = 0; i < kPowerParts; ++i) s += parts[i];
     return n > 0 ? s / double(n) : 0.0;
 }
-
-// ------------------------------------------------------------------ transform engines
-// Both engines take v[m] = a[in_index(m)] and leave output index
-// out_base() + out_off(r) in v[r].
-
-// Stockham passes (2^10 .. 2^13 points), see device_fft.h.
-template <int LOGN_>
-struct StockhamEngine {
-    using F = Fft<LOGN_>;
-    static constexpr int LOGN = LOGN_;
-    static constexpr int N = F::N;
-    static constexpr int NT = F::NT;
-    static constexpr int LDS = F::LDS;
-    static constexpr int EXTRA = 1;
-    static constexpr int B1_TABLE = 1;
-    int t;
-    const float2* roots;
-    __device__ __forceinline__ void init(const float2* __restrict__ r, float2*) {
-        t = int(threadIdx.x);
-        roots = r;
-    }
-    __device__ __forceinline__ int in_index(int m) const { return t + m * NT; }
-    __device__ __forceinline__ int out_base() const { return t; }
-    // smallest / largest out_base() over the wave (wave-uniform)
-    __device__ __forceinline__ int out_min() const { return __builtin_amdgcn_readfirstlane(t & ~63); }
-    __device__ __forceinline__ int out_max() const { return out_min() + 63; }
-    static constexpr int out_off(int r) { return r * NT; }
-    static constexpr int HI_OFF = 1 << 30;      // no output is ever pruned
-    template <int S>
-    __device__ __forceinline__ void transform(float2 (&v)[16], float2* lds, __amdgpu_buffer_rsrc_t,
-                                              const float2*, bool = true) const {
-        int tq = t;
-        asm volatile("" : "+v"(tq));            // recompute addressing per call, no hoisting
-        F::template transform<S>(v, lds, roots, tq);
-    }
-};
-
-using dev::bload;
-using dev::Fft14;
-using dev::make_rsrc;
 
 // ------------------------------------------------------------------ forward spectra
 // Power-of-two prescale of the stored segment spectra for 16-bit storage:
@@ -278,262 +193,6 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
     typename St::T* out = reinterpret_cast<typename St::T*>(bank) + size_t(tag) * E::N;
 #pragma unroll
     for (int m = 0; m < 16; ++m) out[ob + E::out_off(m)] = St::pack(make_float2(v[m].x * s, -v[m].y * s));
-}
-
-// ------------------------------------------------------------------ correlation
-// First step of the split inverse transform for (global segment slot g, bin k,
-// phase rho): G[m] = sum_q X_g[(i + m_k) mod M] W_rho[i], i = in_index(m) +
-// q Msub, for the 16 inputs this thread holds.  The q loop is outside the
-// unrolled m loop so each pass issues its 32 loads back to back.
-template <class E, int PREC>
-__device__ __forceinline__ void first_step(const CorrArgs& a, const E& eng, int g, int k, int rho, float gscale,
-                                           float2 (&G)[16]) {
-    using St = dev::Storage<PREC>;
-    const typename St::T* Xj =
-        static_cast<const typename St::T*>(a.X) + (size_t(g) * size_t(a.ncls) + size_t(a.cls[k])) * size_t(a.M);
-    const float2* W = a.wts + size_t(rho) * size_t(a.M);
-    const int rot = a.rot[k];
-    const int mmask = a.M - 1;
-#pragma unroll
-    for (int m = 0; m < 16; ++m) G[m] = make_float2(0.f, 0.f);
-    for (int q = 0; q < a.spc; ++q) {
-        const int base = q * a.Msub;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int i = eng.in_index(m) + base;
-            G[m] = cadd(G[m], cmul(St::unpack(Xj[(i + rot) & mmask]), W[i]));
-        }
-    }
-    if constexpr (PREC != ACQ_FP32) {
-#pragma unroll
-        for (int m = 0; m < 16; ++m) G[m] = make_float2(G[m].x * gscale, G[m].y * gscale);
-    }
-}
-
-// One work item: (tile of tags, global segment g, bin k, phase rho), item index
-// wi = ((tile * segments + g) * K + k) * spc + rho.
-template <class E, int PREC, bool DUMP>
-__device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, int wi, int total_seg,
-                                               float2* lds, const float2* extra, unsigned long long* red) {
-    using St = dev::Storage<PREC>;
-    constexpr int N = E::N;
-    constexpr int NW = E::NT / 64;
-    int rem = wi;
-    const int rho = rem % a.spc;
-    rem /= a.spc;
-    const int k = rem % a.K;
-    rem /= a.K;
-    const int g = rem % total_seg;
-    const int tile = rem / total_seg;
-    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
-    const int bi = a.blocks.block_of_segment(g);
-    const BlockDesc d = a.blocks.get(bi);
-    // a tracking task searches its own tag only (launched with one tile)
-    const int tag0 = d.tag >= 0 ? d.tag : tile * a.tile;
-    const int ntag = d.tag >= 0 ? 1 : min(a.tile, a.T - tag0);
-    const int j = a.blocks.segment(g, d);
-    unsigned long long* keys = a.keys + size_t(bi) * a.T;
-
-    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const __amdgpu_buffer_rsrc_t bank =
-        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag0) * N * St::BYTES, uint32_t(ntag) * N * St::BYTES);
-    // stored spectra carry 2^-x_exp (segments) and 2^bank_exp (bank): undo both in G
-    float gscale = 1.0f;
-    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, a.exps[bi] - a.bank_exp);
-
-    // tag-independent first step of the inverse transform
-    float2 G[16];
-    first_step<E, PREC>(a, eng, g, k, rho, gscale, G);
-
-    // valid outputs: segment lag spc*u + rho < min(V, lags - jV)  <=>  u < ulim
-    const int64_t seg0 = int64_t(j) * a.V;
-    const int64_t vlim64 = d.lags - seg0 < a.V ? d.lags - seg0 : a.V;
-    const int vlim = int(vlim64);
-    const int ulim = vlim > rho ? (vlim - rho + a.spc - 1) / a.spc : 0;
-    // key index tau*K + k = kbase + u*kstep (fits in 32 bits for valid lags)
-    const unsigned kbase = unsigned((seg0 + rho) * a.K + k);
-    const unsigned kstep = unsigned(a.spc * a.K);
-    const int ob0 = eng.out_base();
-    const unsigned idx00 = kbase + unsigned(ob0) * kstep;
-    const int omin = eng.out_min(), omax = eng.out_max();   // wave-uniform
-    const bool hi = omin + E::HI_OFF < ulim;               // any output of the upper half needed
-
-    const int voff = eng.in_index(0) * St::BYTES;   // bank element of register m: in_index(0) + m*NT
-
-    for (int tt = 0; tt < ntag; ++tt) {
-        float2 v[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], St::bload(bank, voff, (tt * N + m * E::NT) * St::BYTES));
-        eng.template transform<+1>(v, lds, b1, extra, hi);
-        // per-register indices and masks are the same for every tag: keep the
-        // optimiser from holding all of them across the loop (recomputing is cheap)
-        int ob = ob0;
-        unsigned idx0 = idx00;
-        asm volatile("" : "+v"(ob), "+v"(idx0));
-        // this lane's largest valid power; registers are visited in increasing
-        // output index, so the strict comparison keeps the smallest lag of a tie
-        float bp = -1.0f;
-        int boff = 0;
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            const int r = ((rr & 3) << 2) | (rr >> 2);
-            const int off = E::out_off(r);
-            if (omin + off < ulim) {               // wave-uniform: some lane of this register is valid
-                float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
-                if constexpr (DUMP) {
-                    if (ob + off < ulim) {
-                        const int64_t tau = seg0 + int64_t(a.spc) * (ob + off) + rho;
-                        a.dump[(size_t(tag0 + tt) * a.K + k) * size_t(d.lags) + size_t(tau)] = p;
-                    }
-                }
-                if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
-                boff = p > bp ? off : boff;
-                bp = p > bp ? p : bp;
-            }
-        }
-        unsigned long long best = bp >= 0.0f
-            ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) |
-                  static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
-            : 0ull;
-        best = wave_max(best);
-        if (lane == 0) red[tt * NW + wave] = best;
-    }
-    __syncthreads();
-    for (int i = int(threadIdx.x); i < ntag; i += E::NT) {
-        unsigned long long m = 0ull;
-        for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
-        if (m) atomicMax(&keys[tag0 + i], m);
-    }
-    __syncthreads();                             // red[] is rewritten by the next item
-}
-
-// One tracking work item: (global segment g, tile of bins, phase rho) for the
-// block's own tag, item index wi = (g * bin_tiles + tile) * spc + rho, with
-// a.tile bins per tile.  Every bin forms its G_rho and runs one inverse
-// transform; each lane keeps its largest key over all the item's bins, so one
-// wave reduction and one atomic per item remain.
-template <class E, int PREC>
-__device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int wi, float2* lds,
-                                           const float2* extra, unsigned long long* red) {
-    using St = dev::Storage<PREC>;
-    constexpr int NW = E::NT / 64;
-    const int ntl = (a.K + a.tile - 1) / a.tile;
-    int rem = wi;
-    const int rho = rem % a.spc;
-    rem /= a.spc;
-    const int btile = rem % ntl;
-    const int g = rem / ntl;
-    const int k0 = btile * a.tile, k1 = min(a.K, k0 + a.tile);
-    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
-    const int bi = a.blocks.block_of_segment(g);
-    const BlockDesc d = a.blocks.get(bi);
-    const int j = a.blocks.segment(g, d);
-    const int tag = d.tag;
-
-    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const __amdgpu_buffer_rsrc_t bank =
-        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag) * E::N * St::BYTES, uint32_t(E::N) * St::BYTES);
-    float gscale = 1.0f;
-    if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, a.exps[bi] - a.bank_exp);
-
-    const int64_t seg0 = int64_t(j) * a.V;
-    const int64_t vlim64 = d.lags - seg0 < a.V ? d.lags - seg0 : a.V;
-    const int vlim = int(vlim64);
-    const int ulim = vlim > rho ? (vlim - rho + a.spc - 1) / a.spc : 0;
-    const unsigned kstep = unsigned(a.spc * a.K);
-    const int ob0 = eng.out_base();
-    const int omin = eng.out_min(), omax = eng.out_max();
-    const bool hi = omin + E::HI_OFF < ulim;
-    const int voff = eng.in_index(0) * St::BYTES;
-
-    unsigned long long best = 0ull;
-    for (int k = k0; k < k1; ++k) {
-        float2 v[16];
-        first_step<E, PREC>(a, eng, g, k, rho, gscale, v);
-#pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = cmul(v[m], St::bload(bank, voff, (m * E::NT) * St::BYTES));
-        eng.template transform<+1>(v, lds, b1, extra, hi);
-        int ob = ob0;
-        unsigned idx0 = unsigned((seg0 + rho) * a.K + k) + unsigned(ob0) * kstep;
-        asm volatile("" : "+v"(ob), "+v"(idx0));
-        float bp = -1.0f;
-        int boff = 0;
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            const int r = ((rr & 3) << 2) | (rr >> 2);
-            const int off = E::out_off(r);
-            if (omin + off < ulim) {
-                float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
-                if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
-                boff = p > bp ? off : boff;
-                bp = p > bp ? p : bp;
-            }
-        }
-        const unsigned long long key = bp >= 0.0f
-            ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) |
-                  static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
-            : 0ull;
-        best = key > best ? key : best;
-    }
-    best = wave_max(best);
-    if (lane == 0) red[wave] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long m = 0ull;
-        for (int q = 0; q < NW; ++q) m = red[q] > m ? red[q] : m;
-        if (m) atomicMax(&a.keys[size_t(bi) * a.T + tag], m);
-    }
-    __syncthreads();
-}
-
-// Launch forms of the correlation kernel.  Each is its own instantiation so the
-// persistent loop's live state does not weigh on the one-item-per-workgroup forms.
-enum CorrMode { kCorrGrid = 0, kCorrGridDump = 1, kCorrPersistent = 2, kCorrTrack = 3 };
-
-template <class E, int PREC, int MODE>
-__global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
-    constexpr int NW = E::NT / 64;
-    constexpr bool DUMP = MODE == kCorrGridDump;
-    __shared__ float2 lds[E::LDS];
-    __shared__ float2 extra[E::EXTRA];
-    __shared__ unsigned long long red[kMaxTagTile * NW];
-    __shared__ int s_item;
-    const int total_seg = a.blocks.total_seg();
-    const int total = MODE == kCorrTrack ? total_seg * ((a.K + a.tile - 1) / a.tile) * a.spc
-                                         : a.ntiles * total_seg * a.K * a.spc;
-    // Workgroups are dealt round-robin to the XCDs; each XCD takes a contiguous
-    // range of work items, so items sharing a segment and a tag tile share its L2.
-    const int xcd = int(blockIdx.x) % kXcds;
-    E eng;
-    if constexpr (MODE == kCorrPersistent) {
-        eng.init(a.rootsSub, extra);
-        const int chunk = (total + kXcds - 1) / kXcds;
-        const int begin = xcd * chunk;
-        const int end = min(total, begin + chunk);
-        for (;;) {
-            if (threadIdx.x == 0) s_item = atomicAdd(&a.counters[xcd], 1);
-            __syncthreads();
-            // uniform by construction; saying so keeps every address derived from
-            // the item (bank rows, segment) scalar, with no per-lane resource loops
-            const int it = begin + __builtin_amdgcn_readfirstlane(s_item);
-            __syncthreads();
-            if (it >= end) break;
-            correlate_item<E, PREC, false>(a, eng, it, total_seg, lds, extra, red);
-        }
-    } else {
-        // one item per workgroup; the grid may exceed the work (a batch captured
-        // for its capacity): the first ceil(total/8) workgroups of each XCD take
-        // its contiguous range, the rest exit
-        const int per = (total + kXcds - 1) / kXcds;
-        const int q = int(blockIdx.x) / kXcds;
-        const int wi = xcd * per + q;
-        if (q >= per || wi >= total) return;
-        eng.init(a.rootsSub, extra);
-        if constexpr (MODE == kCorrTrack)
-            track_item<E, PREC>(a, eng, wi, lds, extra, red);
-        else
-            correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red);
-    }
 }
 
 // ------------------------------------------------------------------ refine
@@ -731,7 +390,8 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(BlockTable bt, cons
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st) {
-    hipLaunchKernelGGL(k_block_power, dim3(unsigned(max_blocks) * kPowerParts), dim3(256), 0, st, bt, parts);
+    const unsigned grid = unsigned(std::min<int64_t>(int64_t(max_blocks) * kPowerParts, kPowerMaxGrid));
+    hipLaunchKernelGGL(k_block_power, dim3(grid), dim3(256), 0, st, bt, parts);
     return hipGetLastError();
 }
 
@@ -815,44 +475,6 @@ hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const floa
         case 12: return bank_e<StockhamEngine<12>>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
         case 13: return bank_e<StockhamEngine<13>>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
         case 14: return bank_e<Fft14>(chips, T, C, bank, rootsSub, b1tab, M, bank_exp, prec, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <class E, int PREC>
-static void corr_ep(const CorrArgs& a, int grid, hipStream_t st) {
-    if (a.track)
-        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrTrack>), dim3(grid), dim3(E::NT), 0, st, a);
-    else if (a.persistent)
-        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrPersistent>), dim3(grid), dim3(E::NT), 0, st, a);
-    else if (a.dump)
-        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrGridDump>), dim3(grid), dim3(E::NT), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_correlate<E, PREC, kCorrGrid>), dim3(grid), dim3(E::NT), 0, st, a);
-}
-
-template <class E>
-static hipError_t corr_e(const CorrArgs& a, int grid, int prec, hipStream_t st) {
-    switch (prec) {
-        case ACQ_FP32: corr_ep<E, ACQ_FP32>(a, grid, st); break;
-        case ACQ_FP16: corr_ep<E, ACQ_FP16>(a, grid, st); break;
-        case ACQ_BF16: corr_ep<E, ACQ_BF16>(a, grid, st); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec, int engine, hipStream_t st) {
-    if (grid <= 0) return hipSuccess;
-    if ((1 << log2_sub) != a.Msub || a.tile < 1 || a.tile > kMaxTagTile || grid % kXcds) return hipErrorInvalidValue;
-    if (a.track && (a.persistent || a.dump)) return hipErrorInvalidValue;
-    switch (log2_sub) {
-        case 10: return corr_e<StockhamEngine<10>>(a, grid, prec, st);
-        case 11: return corr_e<StockhamEngine<11>>(a, grid, prec, st);
-        case 12: return corr_e<StockhamEngine<12>>(a, grid, prec, st);
-        case 13: return corr_e<StockhamEngine<13>>(a, grid, prec, st);
-        case 14:
-            return engine == 1 ? corr_e<StockhamEngine<14>>(a, grid, prec, st) : corr_e<Fft14>(a, grid, prec, st);
         default: return hipErrorInvalidValue;
     }
 }

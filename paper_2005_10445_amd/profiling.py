@@ -19,8 +19,9 @@ import os
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# the correlation kernel and everything it includes from the library
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_10445_amd", "csrc", f)
-                  for f in ("kernels.hip", "device_fft.h", "fft14.h")]
+                  for f in ("correlate.hip", "device_common.h", "device_fft.h", "fft14.h", "storage.h", "kernels.h")]
 
 
 def kernel_source_hash() -> str:

@@ -7,7 +7,7 @@ transmissions of 8192 chips at 2 samples per chip, per-sample SNR uniform in
 -- with CN(0,1) noise.  Only the transmission parameters are drawn on the
 host.  Calibration picks the proposal threshold kappa on held-out blocks so
 that the proposal search keeps a target share of the exhaustive search's
-detections; the exhaustive search is the judge.
+detections; the exhaustive search is the reference.
 
     python -m paper_2005_10445_amd.train_proposals train --blocks 200000 --batch 8
     python -m paper_2005_10445_amd.train_proposals calibrate
@@ -101,7 +101,7 @@ def _true_key(d, txs, tol: int = 2):
 def recall_at(plan, net: Network, blocks, kappa: float, exhaustive, truth=None):
     """(recall over all exhaustive detections, recall over the exhaustive detections of injected
     transmissions, mean share of segments searched, fallbacks) of the proposal search at kappa,
-    the exhaustive search being the judge (same values required)."""
+    the exhaustive search being the reference (same values required)."""
     hit = total = thit = ttotal = 0
     frac = []
     fallbacks = 0

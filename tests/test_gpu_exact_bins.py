@@ -94,7 +94,7 @@ def test_scalloping_loss_curve_matches_the_closed_form(dev):
     bin at f0: the peak power follows the Dirichlet kernel
     A^2 sin^2(pi df L / Fs) / sin^2(pi df / Fs) (integer delay) over the main
     lobe; with exact bins df takes any value.  The measured curve is written to
-    gpurun_out/."""
+    $ACQ_RESULTS_DIR when that names a directory."""
     T, C, spc, N = 1, 2048, 2, 1 << 16
     L = C * spc
     chips = siggen.make_codes(620, T, C)
@@ -112,7 +112,7 @@ def test_scalloping_loss_curve_matches_the_closed_form(dev):
         assert abs(got - want) <= 1e-6 * L * L, (df, got, want)
         rows.append({"offset_hz": float(df), "offset_bins_of_Fs_over_L": float(df * L / FS),
                      "peak_power_over_L2": got / (L * L), "closed_form": want / (L * L)})
-    out = os.path.join(os.path.dirname(os.path.dirname(__file__)), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("ACQ_RESULTS_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "scalloping_exact_bins.json"), "w") as f:
             json.dump({"L": L, "fs_hz": FS, "rows": rows}, f, indent=1)

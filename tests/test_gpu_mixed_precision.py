@@ -123,7 +123,7 @@ def test_tag_bank_mixed_precision_report(dev, tagbank_case):
                         "oracle_detections": len(want)}
         assert perr.max() <= TOL.get(prec, 1e-4)
     print(json.dumps(report, indent=1), flush=True)
-    out = os.path.join(os.path.dirname(os.path.dirname(__file__)), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("ACQ_RESULTS_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "mixed_precision_report.json"), "w") as f:
             json.dump(report, f, indent=1)
