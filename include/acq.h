@@ -432,6 +432,87 @@ int acq_detect_batch_learned(acq_plan_t plan, acq_cnn_t cnn, const void* const* 
                              int32_t nblocks, const acq_learned_params* params, acq_detection* out,
                              int32_t capacity, int32_t* n_found, acq_learned_report* reports);
 
+/* ------------------------------------------------------------------------
+ * FSK searching pipeline (Section 3, steps 1-8, with the FFT methods of
+ * Section 4.1): int16 IQ samples -> complex, local-oscillator mix, band-pass
+ * filter composed with two one-bit matched filters (one per FSK tone) and
+ * applied by overlap-save FFTs, demodulation d = (|f1|-|f0|)/(|f1|+|f0|) and
+ * u = |f1|-|f0|, real cross-correlation of d with each tag's demodulated
+ * replica d^(c) (computed on the GPU at plan time by the same filters and
+ * demodulator from a noise-free continuous-phase FSK packet of the tag's
+ * bits), argmax of |xcorr|, parabolic interpolation and the sums w_c, q, p_c
+ * of step 8 in FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct acq_fsk_plan_s* acq_fsk_plan_t;
+
+typedef struct acq_fsk_config {
+    double         sample_rate_hz;  /* Fs > 0                                              */
+    double         lo_hz;           /* mix: x[n] * exp(-j 2 pi lo n / Fs), n from the block start */
+    double         f1_hz, f0_hz;    /* tones of a 1 and a 0 bit after the mix, |f| < Fs/2  */
+    double         threshold;       /* report tags with z = w_c^2 / (q E_c) >= threshold;
+                                       <= 0 reports every tag's peak                      */
+    const float*   bp_taps;         /* host [bp_len][2] band-pass taps (re, im), copied   */
+    const uint8_t* bits;            /* host [num_tags][num_bits] of 0/1, copied           */
+    int64_t        max_block_len;   /* largest n accepted by acq_fsk_detect               */
+    int32_t        bp_len;          /* 1 .. 1024                                          */
+    int32_t        mf_len;          /* matched-filter length = samples per bit, 1 .. 64   */
+    int32_t        num_tags;        /* >= 1                                               */
+    int32_t        num_bits;        /* >= 1                                               */
+    int32_t        fft_len;         /* correlation segment M: power of two in
+                                       [2^10, 2^17], > template length; 0 = choice      */
+    int32_t        reserved;        /* 0                                                  */
+} acq_fsk_config;
+
+/* One tag's result.  The template length is n_t = num_bits * mf_len +
+ * bp_len + mf_len - 2 (the nonzero span of d^(c)); lags are 0 .. n - n_t. */
+typedef struct acq_fsk_detection {
+    int32_t  tag;
+    uint32_t flags;          /* ACQ_DET_NEAR_EDGE, ACQ_DET_WINDOW_EDGE                 */
+    int64_t  lag;            /* j*: argmax of |xcorr| (FP64 re-maximised over +/-1)    */
+    double   toa_samples;    /* j* + delta, delta the parabola vertex through |xcorr|  */
+    double   xcorr;          /* w_c = sum_{i<n_t} d^(c)[i] d[i+j*]                     */
+    double   q;              /* sum_{i<n_t} d[i+j*]^2                                  */
+    double   p;              /* p_c = sum_{i<n_t} d^(c)[i] u[i+j*]                     */
+    double   z;              /* w_c^2 / (q E_c), E_c = sum d^(c)^2                     */
+} acq_fsk_detection;
+
+/* Geometry of an FSK configuration (no GPU involved): template length, the
+ * correlation segment M and its valid lags, and the front end's FFT length. */
+typedef struct acq_fsk_geometry {
+    int64_t template_len;    /* n_t                                                    */
+    int64_t fft_len;         /* M                                                      */
+    int64_t valid_per_segment; /* M - n_t + 1                                          */
+    int64_t filter_len;      /* composed filter length bp_len + mf_len - 1             */
+    int64_t front_fft_len;   /* overlap-save length of the composed filters (4096)     */
+    int64_t device_bytes;
+} acq_fsk_geometry;
+
+int acq_fsk_plan_geometry(const acq_fsk_config* cfg, acq_fsk_geometry* out);
+
+/* Plan: composed filter spectra, replica templates d^(c) and their spectra,
+ * all buffers for blocks up to max_block_len.  Synchronous on `stream`. */
+int acq_fsk_plan(const acq_fsk_config* cfg, void* stream, acq_fsk_plan_t* out);
+int acq_fsk_release(acq_fsk_plan_t plan);     /* NULL-safe */
+
+/* Steps 1-5 only (test hook): d and u of a device int16 block iq[n][2] into
+ * device float arrays d[n], u[n].  Synchronous. */
+int acq_fsk_demod(acq_fsk_plan_t plan, const int16_t* iq, int64_t n, float* d, float* u);
+
+/* The stored replica template d^(c) of a tag (test hook): device float[n_t]. */
+int acq_fsk_template(acq_fsk_plan_t plan, int32_t tag, float* out);
+
+/* Steps 1-7 (test hook): the FFT path's correlation xcorr(d, d^(c)) of every
+ * tag at every lag into device float out[num_tags][n - n_t + 1] (n >= n_t).
+ * Synchronous. */
+int acq_fsk_xcorr(acq_fsk_plan_t plan, const int16_t* iq, int64_t n, float* out);
+
+/* Steps 1-8 on a device int16 block iq[n][2] (n <= max_block_len): one
+ * result per tag whose z reaches the threshold, in tag order, to the host
+ * array out[capacity].  n < n_t gives none.  Errors and truncation as
+ * acq_detect.  Synchronous. */
+int acq_fsk_detect(acq_fsk_plan_t plan, const int16_t* iq, int64_t n, acq_fsk_detection* out,
+                   int32_t capacity, int32_t* n_found);
+
 /* Static description of a status code. */
 const char* acq_strerror(int status);
 

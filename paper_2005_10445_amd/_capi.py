@@ -32,7 +32,9 @@ EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect"
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
             "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
-            "acq_detect_learned", "acq_detect_batch_learned", "acq_strerror", "acq_last_error")
+            "acq_detect_learned", "acq_detect_batch_learned", "acq_fsk_plan_geometry", "acq_fsk_plan",
+            "acq_fsk_release", "acq_fsk_demod", "acq_fsk_template", "acq_fsk_xcorr", "acq_fsk_detect", "acq_strerror",
+            "acq_last_error")
 ACQ_SYNTH_MAX_TX = 32
 ACQ_FALLBACK_NONE, ACQ_FALLBACK_FRACTION, ACQ_FALLBACK_FLOOR = 0, 1, 2
 KERNELS = ("block_power", "forward", "correlate", "refine", "compact")
@@ -112,6 +114,26 @@ class AcqCnnConfig(ctypes.Structure):
         ("max_rows", ctypes.c_int64),
         ("max_block_len", ctypes.c_int64),
     ]
+
+
+class AcqFskConfig(ctypes.Structure):
+    _fields_ = [("sample_rate_hz", ctypes.c_double), ("lo_hz", ctypes.c_double), ("f1_hz", ctypes.c_double),
+                ("f0_hz", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("bp_taps", ctypes.POINTER(ctypes.c_float)), ("bits", ctypes.POINTER(ctypes.c_uint8)),
+                ("max_block_len", ctypes.c_int64), ("bp_len", ctypes.c_int32), ("mf_len", ctypes.c_int32),
+                ("num_tags", ctypes.c_int32), ("num_bits", ctypes.c_int32), ("fft_len", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class AcqFskDetection(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int32), ("flags", ctypes.c_uint32), ("lag", ctypes.c_int64),
+                ("toa_samples", ctypes.c_double), ("xcorr", ctypes.c_double), ("q", ctypes.c_double),
+                ("p", ctypes.c_double), ("z", ctypes.c_double)]
+
+
+class AcqFskGeometry(ctypes.Structure):
+    _fields_ = [("template_len", ctypes.c_int64), ("fft_len", ctypes.c_int64), ("valid_per_segment", ctypes.c_int64),
+                ("filter_len", ctypes.c_int64), ("front_fft_len", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
 class AcqTrackTask(ctypes.Structure):
@@ -209,6 +231,16 @@ def lib(path: str = LIB_PATH):
                                      P(AcqLearnedReport)]
     L.acq_detect_batch_learned.argtypes = [vp, vp, P(vp), P(i64), i32, P(AcqLearnedParams), P(AcqDetection), i32,
                                            P(i32), P(AcqLearnedReport)]
+    L.acq_fsk_plan_geometry.argtypes = [P(AcqFskConfig), P(AcqFskGeometry)]
+    L.acq_fsk_plan.argtypes = [P(AcqFskConfig), vp, P(vp)]
+    L.acq_fsk_release.argtypes = [vp]
+    L.acq_fsk_demod.argtypes = [vp, vp, i64, vp, vp]
+    L.acq_fsk_template.argtypes = [vp, i32, vp]
+    L.acq_fsk_detect.argtypes = [vp, vp, i64, P(AcqFskDetection), i32, P(i32)]
+    L.acq_fsk_xcorr.argtypes = [vp, vp, i64, vp]
+    for name in ("acq_fsk_plan_geometry", "acq_fsk_plan", "acq_fsk_release", "acq_fsk_demod", "acq_fsk_template",
+                 "acq_fsk_xcorr", "acq_fsk_detect"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
                  "acq_track_batch", "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
                  "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create", "acq_cnn_release",

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libacq.so")
 
-HIP_SOURCES = ["kernels.hip", "correlate.hip", "plan.hip", "learned_kernels.hip", "cnn.hip"]
+HIP_SOURCES = ["kernels.hip", "correlate.hip", "plan.hip", "learned_kernels.hip", "cnn.hip", "fsk.hip"]
 CXX_SOURCES = ["host_logic.cpp"]
 ARCH = os.environ.get("ACQ_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

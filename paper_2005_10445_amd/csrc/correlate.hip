@@ -136,7 +136,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
         int boff = 0;
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
-            const int r = ((rr & 3) << 2) | (rr >> 2);
+            const int r = E::visit(rr);
             const int off = E::out_off(r);
             if (omin + off < ulim) {               // wave-uniform: some lane of this register is valid
                 float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
@@ -220,7 +220,7 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
         int boff = 0;
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
-            const int r = ((rr & 3) << 2) | (rr >> 2);
+            const int r = E::visit(rr);
             const int off = E::out_off(r);
             if (omin + off < ulim) {
                 float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);

@@ -76,6 +76,8 @@ struct StockhamEngine {
     __device__ __forceinline__ int out_max() const { return out_min() + 63; }
     static constexpr int out_off(int r) { return r * NT; }
     static constexpr int HI_OFF = 1 << 30;      // no output is ever pruned
+    // register holding the rr-th smallest output offset
+    static constexpr int visit(int rr) { return rr; }
     template <int S>
     __device__ __forceinline__ void transform(float2 (&v)[16], float2* lds, __amdgpu_buffer_rsrc_t,
                                               const float2*, bool = true) const {

@@ -93,6 +93,8 @@ struct Fft14 {
     __device__ __forceinline__ int out_max() const { return w + 16 * 15 + 1024 * 3; }
     static constexpr int out_off(int r) { return 256 * (r >> 2) + 4096 * (r & 3); }
     static constexpr int HI_OFF = 8192;         // outputs with kb2 >= 2 start here
+    // register holding the rr-th smallest output offset (out_off increases with rr)
+    static constexpr int visit(int rr) { return ((rr & 3) << 2) | (rr >> 2); }
 
     template <int S>
     __device__ __forceinline__ void transform(float2 (&v)[16], float2* lds, __amdgpu_buffer_rsrc_t b1tab,

@@ -1,0 +1,913 @@
+// FSK searching pipeline of Section 3 (steps 1-8) on gfx950, with the FFT
+// methods of Section 4.1.
+//
+//   k_fsk_front     : one workgroup per overlap-save segment of the composed
+//                     filters: int16 -> complex and local-oscillator mix (or,
+//                     at plan time, the noise-free continuous-phase replica of
+//                     a tag's bits), forward 4096-point transform, products
+//                     with the spectra of h_BP * h_1 and h_BP * h_0, two inverse
+//                     transforms, demodulation d = (|f1|-|f0|)/(|f1|+|f0|),
+//                     u = |f1|-|f0|.  Output d and u (block) or d (replica).
+//   k_fsk_pack      : overlap-save segments 2g and 2g+1 of d as the real and
+//                     imaginary parts of one complex M-point input (slot g)
+//   (forward spectra of the slots and of the templates: launch_forward, the
+//    decimation-in-time transform of the acquisition path)
+//   k_fsk_correlate : the real cross-correlation of d with each template by
+//                     overlap-save.  The template d^(c) is real, so the inverse
+//                     transform of Z_g conj(D^(c)) / M holds the correlation of
+//                     segment 2g in its real part and of segment 2g+1 in its
+//                     imaginary part: one complex transform per two segments.
+//                     The peak search uses |c|.  An M-point inverse
+//                     transform (M up to 2^17) runs as P = M / Msub phases of
+//                     an Msub-point transform: for output lag tau = P u + rho,
+//                       G_rho[i'] = exp(+j 2 pi i' rho / M)
+//                                   sum_a Y[i' + Msub a] exp(+j 2 pi a rho / P),
+//                     Y the spectrum product, then an Msub-point inverse
+//                     transform of G_rho.  Keys: bits(|Re c|) << 32 | ~tau.
+//   k_fsk_refine    : FP64 sums over +/-2 lags of the peak from the stored d,
+//                     u and template, re-maximisation, parabola, w_c, q, p_c, z.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "acq.h"
+#include "device_common.h"
+#include "host_logic.h"
+#include "kernels.h"
+
+namespace acq {
+
+using namespace kdev;
+
+namespace {
+
+constexpr int kFrontLog = 12;                 // composed filters applied on 4096-point segments
+constexpr int kFrontN = 1 << kFrontLog;
+constexpr int kFskTile = 16;                  // templates per correlation work item
+
+struct FrontArgs {
+    const int16_t* iq;          // block: [n_in][2]
+    const uint8_t* bits;        // replica: [T][nbits]
+    const double* bit_cyc;      // replica: [T][nbits] carrier phase (cycles, in [0,1)) at each bit start
+    const float2* G1;           // [kFrontN] DFT(h_BP * h_1) / kFrontN
+    const float2* G0;
+    const float2* roots;        // [kFrontN] exp(+j 2 pi m / kFrontN)
+    float2* out;                // replica: [T][out_stride] (d, 0)
+    float* out_d;               // block: d[n_out]
+    float* out_u;               // block: u[n_out]
+    int64_t n_in, n_out, out_stride;
+    double lo_cyc;              // f_LO / Fs
+    double f1_cyc, f0_cyc;      // tones, cycles per sample
+    int32_t nbits, sps, lg, vf, nseg, replica;
+};
+
+// One workgroup per (template, segment): outputs s*vf .. s*vf + vf - 1 of the
+// causal convolution with the composed filters, from inputs s*vf - (lg-1) ..
+__global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
+    using E = StockhamEngine<kFrontLog>;
+    __shared__ float2 lds[E::LDS];
+    E eng;
+    eng.init(a.roots, nullptr);
+    const int s = int(blockIdx.x) % a.nseg;
+    const int tag = int(blockIdx.x) / a.nseg;
+    const int64_t base = int64_t(s) * a.vf - (a.lg - 1);
+    float2 x[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int64_t p = base + eng.in_index(m);
+        float2 v = make_float2(0.f, 0.f);
+        if (p >= 0 && p < a.n_in) {
+            double cyc;
+            if (a.replica) {
+                const int64_t b = p / a.sps;
+                const size_t bi = size_t(tag) * size_t(a.nbits) + size_t(b);
+                cyc = a.bit_cyc[bi] + (a.bits[bi] ? a.f1_cyc : a.f0_cyc) * double(p - b * a.sps);
+                v = make_float2(1.f, 0.f);
+            } else {
+                v = make_float2(float(a.iq[2 * p]), float(a.iq[2 * p + 1]));
+                cyc = -a.lo_cyc * double(p);
+            }
+            cyc -= floor(cyc);                              // exact phase reduction in FP64
+            float sn, cs;
+            sincospif(2.0f * float(cyc), &sn, &cs);
+            v = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+        }
+        x[m] = v;
+    }
+    const __amdgpu_buffer_rsrc_t dummy = make_rsrc(a.roots, 8);   // unused by the Stockham engine
+    eng.template transform<-1>(x, lds, dummy, nullptr);
+    float a1[16];
+    float2 w[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) w[m] = cmul(x[m], a.G1[eng.in_index(m)]);
+    eng.template transform<+1>(w, lds, dummy, nullptr);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a1[m] = sqrtf(fmaf(w[m].x, w[m].x, w[m].y * w[m].y));
+#pragma unroll
+    for (int m = 0; m < 16; ++m) w[m] = cmul(x[m], a.G0[eng.in_index(m)]);
+    eng.template transform<+1>(w, lds, dummy, nullptr);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int idx = eng.in_index(m);                     // natural order in and out
+        const int64_t o = int64_t(s) * a.vf + idx - (a.lg - 1);
+        if (idx >= a.lg - 1 && o < a.n_out) {
+            const float a0 = sqrtf(fmaf(w[m].x, w[m].x, w[m].y * w[m].y));
+            const float sum = a1[m] + a0, dif = a1[m] - a0;
+            const float d = sum > 0.f ? dif / sum : 0.f;
+            if (a.replica) {
+                a.out[size_t(tag) * size_t(a.out_stride) + size_t(o)] = make_float2(d, 0.f);
+            } else {
+                a.out_d[o] = d;
+                a.out_u[o] = dif;
+            }
+        }
+    }
+}
+
+// zp[g][i] = (d[2g V + i], d[(2g+1) V + i]), zero past the block or past the
+// last segment; grid covers slots * M.
+__global__ void k_fsk_pack(const float* __restrict__ d, int64_t n, int64_t V, int64_t M, int nseg, int nslots,
+                           float2* __restrict__ zp) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= int64_t(nslots) * M) return;
+    const int64_t g = k / M, i = k - g * M;
+    const int64_t p0 = 2 * g * V + i, p1 = (2 * g + 1) * V + i;
+    const float re = p0 < n ? d[p0] : 0.f;
+    const float im = (2 * g + 1 < nseg && p1 < n) ? d[p1] : 0.f;
+    zp[k] = make_float2(re, im);
+}
+
+// bank[t][i] = conj(X_t[i]) / M in place
+__global__ void k_fsk_conj_scale(float2* bank, int64_t count, float scale) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) {
+        const float2 v = bank[i];
+        bank[i] = make_float2(v.x * scale, -v.y * scale);
+    }
+}
+
+__global__ void k_fsk_fill(float2* p, int64_t count) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = make_float2(0.f, 0.f);
+}
+
+struct FskCorrArgs {
+    const float2* X;            // [slots][M] spectra of the packed segment pairs
+    const float2* bank;         // [T][M] conj(DFT_M(d^(c))) / M
+    const float2* rootsM;       // [M]
+    const float2* rootsSub;     // [Msub]
+    const float2* b1tab;
+    unsigned long long* keys;   // [T]
+    float* dump;                // optional [T][lags]: c at every lag (test hook)
+    int64_t V, lags;
+    int32_t M, Msub, P, T, tile, ntiles, nseg, nslots;
+};
+
+// Work item wi = ((tile * nslots) + g) * P + rho: segments 2g (real part) and
+// 2g+1 (imaginary part).
+template <class E, bool DUMP>
+__global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
+    constexpr int NW = E::NT / 64;
+    __shared__ float2 lds[E::LDS];
+    __shared__ float2 extra[E::EXTRA];
+    __shared__ unsigned long long red[kFskTile * NW];
+    const int total = a.ntiles * a.nslots * a.P;
+    const int xcd = int(blockIdx.x) % kXcds;
+    const int per = (total + kXcds - 1) / kXcds;
+    const int wi = xcd * per + int(blockIdx.x) / kXcds;
+    if (int(blockIdx.x) / kXcds >= per || wi >= total) return;
+    E eng;
+    eng.init(a.rootsSub, extra);
+    int rem = wi;
+    const int rho = rem % a.P;
+    rem /= a.P;
+    const int j = rem % a.nslots;
+    const int tile = rem / a.nslots;
+    const int tag0 = tile * a.tile;
+    const int ntag = min(a.tile, a.T - tag0);
+    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+    const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
+    const float2* Xj = a.X + size_t(j) * size_t(a.M);
+    const int mmask = a.M - 1;
+
+    // valid outputs of the two segments: lag P u + rho < min(V, lags - segment start)
+    int ulim[2];
+    int64_t sbeg[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        sbeg[h] = int64_t(2 * j + h) * a.V;
+        const int64_t v64 = (2 * j + h < a.nseg) ? (a.lags - sbeg[h] < a.V ? a.lags - sbeg[h] : a.V) : 0;
+        const int vlim = int(v64);
+        ulim[h] = vlim > rho ? (vlim - rho + a.P - 1) / a.P : 0;
+    }
+    const int ob0 = eng.out_base();
+    const int omin = eng.out_min(), omax = eng.out_max();
+    const bool hi = omin + E::HI_OFF < max(ulim[0], ulim[1]);
+
+    for (int tt = 0; tt < ntag; ++tt) {
+        const float2* B = a.bank + size_t(tag0 + tt) * size_t(a.M);
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = make_float2(0.f, 0.f);
+        for (int q = 0; q < a.P; ++q) {
+            const float2 wq = a.rootsM[(q * rho * a.Msub) & mmask];   // exp(+j 2 pi q rho / P), uniform
+            const int off = q * a.Msub;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int i = eng.in_index(m) + off;
+                v[m] = cadd(v[m], cmul(cmul(Xj[i], B[i]), wq));
+            }
+        }
+        if (rho) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) v[m] = cmul(v[m], a.rootsM[(eng.in_index(m) * rho) & mmask]);
+        }
+        eng.template transform<+1>(v, lds, b1, extra, hi);
+        int ob = ob0;
+        asm volatile("" : "+v"(ob));
+        // this lane's largest |c|: the first segment's lags (all smaller) before
+        // the second's, each in increasing lag, so the strict comparison keeps
+        // the smallest lag of a tie
+        float bp = -1.0f;
+        int boff = 0, bh = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) {
+                const int r = E::visit(rr);
+                const int off = E::out_off(r);
+                if (omin + off < ulim[h]) {
+                    const float cv = h ? v[r].y : v[r].x;
+                    float pv = fabsf(cv);
+                    if constexpr (DUMP) {
+                        if (ob + off < ulim[h]) {
+                            const int64_t tau = sbeg[h] + int64_t(a.P) * (ob + off) + rho;
+                            a.dump[size_t(tag0 + tt) * size_t(a.lags) + size_t(tau)] = cv;
+                        }
+                    }
+                    if (omax + off >= ulim[h] && ob + off >= ulim[h]) pv = -1.0f;
+                    const bool take = pv > bp;
+                    boff = take ? off : boff;
+                    bh = take ? h : bh;
+                    bp = take ? pv : bp;
+                }
+            }
+        }
+        const unsigned lag = unsigned(sbeg[bh] + rho) + unsigned(ob + boff) * unsigned(a.P);
+        unsigned long long best = bp >= 0.0f
+            ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) | static_cast<unsigned long long>(~lag)
+            : 0ull;
+        best = wave_max(best);
+        if (lane == 0) red[tt * NW + wave] = best;
+    }
+    __syncthreads();
+    for (int i = int(threadIdx.x); i < ntag; i += E::NT) {
+        unsigned long long m = 0ull;
+        for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
+        if (m) atomicMax(&a.keys[tag0 + i], m);
+    }
+}
+
+struct FskRefineArgs {
+    const float* d;             // [n]
+    const float* u;             // [n]
+    const float2* tmpl;         // [T][tstride] (d^(c), 0)
+    const unsigned long long* keys;
+    acq_fsk_detection* dets;    // [T]
+    int32_t* found;             // [T]
+    int64_t n, nt, tstride, lags;
+    double theta;
+};
+
+constexpr int kFskWin = 5;      // lags tau*-2 .. tau*+2
+
+// One workgroup of 256 threads per tag.
+__global__ __launch_bounds__(256) void k_fsk_refine(FskRefineArgs a) {
+    constexpr int NT = 256, NW = NT / 64;
+    const int tag = int(blockIdx.x);
+    const int t = int(threadIdx.x), lane = t & 63, wave = t >> 6;
+    __shared__ double red[NW][kFskWin * 3 + 1];
+    __shared__ long long s_center;
+    __shared__ int s_again;
+    const unsigned long long key = a.lags > 0 ? a.keys[tag] : 0ull;
+    if (key == 0ull) {
+        if (t == 0) a.found[tag] = 0;
+        return;
+    }
+    const float2* dc = a.tmpl + size_t(tag) * size_t(a.tstride);
+    int64_t center = int64_t(~unsigned(key & 0xffffffffull));
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t lam0 = center - (kFskWin / 2);
+        double wv[kFskWin], pv[kFskWin], qv[kFskWin], ec = 0.0;
+#pragma unroll
+        for (int w = 0; w < kFskWin; ++w) wv[w] = pv[w] = qv[w] = 0.0;
+        // e walks the block from lam0; lag lam0 + w pairs z[lam0 + e] with dc[e - w]
+        for (int64_t e = t; e < a.nt + kFskWin - 1; e += NT) {
+            const int64_t i = lam0 + e;
+            double zd = 0.0, zu = 0.0;
+            if (i >= 0 && i < a.n) {
+                zd = a.d[i];
+                zu = a.u[i];
+            }
+            if (e < a.nt) {
+                const double c0 = dc[e].x;
+                ec += c0 * c0;
+            }
+#pragma unroll
+            for (int w = 0; w < kFskWin; ++w) {
+                const int64_t nn = e - w;
+                if (nn >= 0 && nn < a.nt) {
+                    const double c = dc[nn].x;
+                    wv[w] += c * zd;
+                    pv[w] += c * zu;
+                    qv[w] += zd * zd;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < kFskWin; ++w) {
+            const double r0 = wave_sum(wv[w]), r1 = wave_sum(pv[w]), r2 = wave_sum(qv[w]);
+            if (lane == 0) {
+                red[wave][3 * w] = r0;
+                red[wave][3 * w + 1] = r1;
+                red[wave][3 * w + 2] = r2;
+            }
+        }
+        const double ecs = wave_sum(ec);
+        if (lane == 0) red[wave][3 * kFskWin] = ecs;
+        __syncthreads();
+        if (t == 0) {
+            double W[kFskWin], Pc[kFskWin], Q[kFskWin], A[kFskWin];
+            double Ec = 0.0;
+            for (int q = 0; q < NW; ++q) Ec += red[q][3 * kFskWin];
+            for (int w = 0; w < kFskWin; ++w) {
+                W[w] = Pc[w] = Q[w] = 0.0;
+                for (int q = 0; q < NW; ++q) {
+                    W[w] += red[q][3 * w];
+                    Pc[w] += red[q][3 * w + 1];
+                    Q[w] += red[q][3 * w + 2];
+                }
+                const int64_t lam = lam0 + w;
+                A[w] = (lam >= 0 && lam < a.lags) ? fabs(W[w]) : -1.0;
+            }
+            int wb = kFskWin / 2;
+            for (int w = 1; w <= kFskWin - 2; ++w)
+                if (A[w] > A[wb] || (A[w] == A[wb] && w < wb)) wb = w;
+            const int64_t lam = lam0 + wb;
+            const bool hit = (wb == 1 && lam > 0) || (wb == kFskWin - 2 && lam < a.lags - 1);
+            if (hit && pass == 0) {
+                s_center = lam;
+                s_again = 1;
+            } else {
+                s_again = 0;
+                unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
+                const double p0 = A[wb];
+                const double pm = A[wb - 1] < 0.0 ? 0.0 : A[wb - 1];
+                const double pp = A[wb + 1] < 0.0 ? 0.0 : A[wb + 1];
+                double delta = 0.0;
+                if (lam == 0 || lam == a.lags - 1) {
+                    flags |= ACQ_DET_NEAR_EDGE;
+                } else {
+                    const double den = pm - 2.0 * p0 + pp;
+                    if (den < 0.0) {
+                        delta = 0.5 * (pm - pp) / den;
+                        delta = delta > 0.5 ? 0.5 : (delta < -0.5 ? -0.5 : delta);
+                    }
+                }
+                acq_fsk_detection r;
+                r.tag = tag;
+                r.flags = flags;
+                r.lag = lam;
+                r.toa_samples = double(lam) + delta;
+                r.xcorr = W[wb];
+                r.q = Q[wb];
+                r.p = Pc[wb];
+                r.z = (Q[wb] > 0.0 && Ec > 0.0) ? W[wb] * W[wb] / (Q[wb] * Ec) : 0.0;
+                a.dets[tag] = r;
+                a.found[tag] = (a.theta <= 0.0 || r.z >= a.theta) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (!s_again) break;
+        center = s_center;
+    }
+}
+
+__global__ void k_fsk_compact(const acq_fsk_detection* __restrict__ dets, const int32_t* __restrict__ found,
+                              int T, acq_fsk_detection* __restrict__ out, int32_t* __restrict__ count) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int c = 0;
+    for (int i = 0; i < T; ++i)
+        if (found[i]) out[c++] = dets[i];
+    *count = c;
+}
+
+template <class E>
+hipError_t launch_fsk_corr_e(const FskCorrArgs& a, int grid, hipStream_t st) {
+    if (a.tile < 1 || a.tile > kFskTile) return hipErrorInvalidValue;
+    if (a.dump)
+        hipLaunchKernelGGL((k_fsk_correlate<E, true>), dim3(grid), dim3(E::NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_fsk_correlate<E, false>), dim3(grid), dim3(E::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fsk_correlate(const FskCorrArgs& a, int grid, int log2_sub, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    switch (log2_sub) {
+        case 10: return launch_fsk_corr_e<StockhamEngine<10>>(a, grid, st);
+        case 11: return launch_fsk_corr_e<StockhamEngine<11>>(a, grid, st);
+        case 12: return launch_fsk_corr_e<StockhamEngine<12>>(a, grid, st);
+        case 13: return launch_fsk_corr_e<StockhamEngine<13>>(a, grid, st);
+        case 14: return launch_fsk_corr_e<Fft14>(a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+struct FskGeometry {
+    int64_t lg = 0, nt = 0, M = 0, Msub = 0, V = 0, vf = 0, max_seg = 0, max_front_seg = 0, bytes = 0;
+    int P = 1, log2_sub = 0;
+};
+
+int fsk_geometry(const acq_fsk_config* c, FskGeometry* g) {
+    if (!c) return fail(ACQ_ERR_INVALID_ARG, "null configuration");
+    if (!(c->sample_rate_hz > 0.0) || !std::isfinite(c->lo_hz) || !std::isfinite(c->f1_hz) ||
+        !std::isfinite(c->f0_hz) || !std::isfinite(c->threshold))
+        return fail(ACQ_ERR_INVALID_ARG, "sample rate must be positive and frequencies finite");
+    if (!c->bp_taps || !c->bits) return fail(ACQ_ERR_INVALID_ARG, "null taps or bits");
+    if (c->bp_len < 1 || c->bp_len > 1024) return fail(ACQ_ERR_INVALID_ARG, "bp_len outside [1, 1024]");
+    if (c->mf_len < 1 || c->mf_len > 64) return fail(ACQ_ERR_INVALID_ARG, "mf_len outside [1, 64]");
+    if (c->num_tags < 1 || c->num_bits < 1) return fail(ACQ_ERR_INVALID_ARG, "num_tags and num_bits must be >= 1");
+    if (c->max_block_len < 1) return fail(ACQ_ERR_INVALID_ARG, "max_block_len must be >= 1");
+    g->lg = int64_t(c->bp_len) + c->mf_len - 1;
+    g->nt = int64_t(c->num_bits) * c->mf_len + g->lg - 1;
+    g->vf = kFrontN - g->lg + 1;
+    int64_t M = c->fft_len;
+    if (M == 0) {
+        M = 1024;
+        while (M <= g->nt) M <<= 1;                   // smallest power of two > n_t ...
+        if (M < (int64_t(1) << 17) && M - g->nt + 1 < g->nt / 2) M <<= 1;   // ... doubled when few lags remain
+    }
+    if (M < 1024 || M > (int64_t(1) << 17) || (M & (M - 1)))
+        return fail(ACQ_ERR_UNSUPPORTED, "fft_len must be a power of two in [2^10, 2^17]");
+    if (M <= g->nt) return fail(ACQ_ERR_UNSUPPORTED, "template longer than the correlation segment (at most 2^17 - 1)");
+    g->M = M;
+    g->Msub = std::min<int64_t>(M, int64_t(1) << 14);
+    g->P = int(M / g->Msub);
+    g->log2_sub = 0;
+    while ((int64_t(1) << g->log2_sub) < g->Msub) ++g->log2_sub;
+    g->V = M - g->nt + 1;
+    const int64_t lags = c->max_block_len - g->nt + 1;
+    g->max_seg = lags > 0 ? (lags + g->V - 1) / g->V : 0;
+    g->max_front_seg = (c->max_block_len + g->vf - 1) / g->vf;
+    const int64_t T = c->num_tags;
+    g->bytes = c->max_block_len * 8 + std::max<int64_t>(g->max_seg, 1) * M * 8 + 2 * T * M * 8 + T * c->num_bits * 9 +
+               kFrontN * 8 * 3 + M * 8 + g->Msub * 8 + T * (8 + 4 + 2 * int64_t(sizeof(acq_fsk_detection)));
+    return ACQ_OK;
+}
+
+// composed filter h_BP * h_b, FP64
+std::vector<double> composed(const acq_fsk_config* c, double f_hz) {
+    const int lb = c->bp_len, lm = c->mf_len;
+    std::vector<double> g(size_t(2 * (lb + lm - 1)), 0.0);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 0; k < lm; ++k) {
+        // h_b[k] = exp(-j 2 pi f (lm-1-k) / Fs), phase reduced in cycles
+        double cyc = -f_hz * double(lm - 1 - k) / c->sample_rate_hz;
+        cyc -= std::floor(cyc);
+        const double hr = std::cos(two_pi * cyc), hi = std::sin(two_pi * cyc);
+        for (int i = 0; i < lb; ++i) {
+            const double br = c->bp_taps[2 * i], bi = c->bp_taps[2 * i + 1];
+            g[size_t(2 * (i + k))] += br * hr - bi * hi;
+            g[size_t(2 * (i + k) + 1)] += br * hi + bi * hr;
+        }
+    }
+    return g;
+}
+
+// DFT_kFrontN(g) / kFrontN in FP64 (direct sum, exact index reduction), as FP32 pairs
+std::vector<float> filter_spectrum(const std::vector<double>& g) {
+    const int64_t lg = int64_t(g.size() / 2);
+    const std::vector<double> roots = unit_roots64(kFrontN);        // (cos, sin)(2 pi m / N)
+    std::vector<float> out(size_t(2 * kFrontN));
+    for (int64_t k = 0; k < kFrontN; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int64_t i = 0; i < lg; ++i) {
+            const int64_t e = (i * k) % kFrontN;
+            const double cr = roots[size_t(2 * e)], ci = -roots[size_t(2 * e + 1)];   // exp(-j 2 pi i k / N)
+            re += g[size_t(2 * i)] * cr - g[size_t(2 * i + 1)] * ci;
+            im += g[size_t(2 * i)] * ci + g[size_t(2 * i + 1)] * cr;
+        }
+        out[size_t(2 * k)] = float(re / kFrontN);
+        out[size_t(2 * k + 1)] = float(im / kFrontN);
+    }
+    return out;
+}
+
+}  // namespace
+}  // namespace acq
+
+using acq::BlockDesc;
+using acq::BlockTable;
+
+struct acq_fsk_plan_s {
+    acq_fsk_config cfg{};
+    acq::FskGeometry g;
+    hipStream_t stream = nullptr;
+    float2* d_G1 = nullptr;             // [kFrontN]
+    float2* d_G0 = nullptr;
+    float2* d_rootsF = nullptr;         // [kFrontN]
+    uint8_t* d_bits = nullptr;          // [T][nbits]
+    double* d_bitcyc = nullptr;         // [T][nbits]
+    float2* d_tmpl = nullptr;           // [T][M] (d^(c), 0), zero beyond n_t
+    float2* d_bank = nullptr;           // [T][M] conj(DFT_M(d^(c))) / M
+    float* d_d = nullptr;               // [max_block_len] demodulated d
+    float* d_u = nullptr;               // [max_block_len] u
+    float2* d_zp = nullptr;             // [slots][M] packed segment pairs of d
+    float2* d_X = nullptr;              // [slots][M] their spectra
+    float2* d_rootsM = nullptr;
+    float2* d_rootsSub = nullptr;
+    float2* d_b1tab = nullptr;
+    double* d_zero = nullptr;           // [1] residual offset 0 for the forward transform
+    BlockDesc* d_tdescs = nullptr;      // [T] templates as blocks of the forward transform
+    int32_t* d_tcounts = nullptr;       // [2]
+    unsigned long long* d_keys = nullptr;
+    acq_fsk_detection* d_dets = nullptr;
+    acq_fsk_detection* d_out = nullptr;
+    int32_t* d_found = nullptr;
+    int32_t* d_count = nullptr;
+    acq_fsk_detection* h_out = nullptr;     // pinned [T]
+    int32_t* h_count = nullptr;             // pinned [1]
+};
+
+namespace {
+
+#define FSK_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return acq::fail(e_ == hipErrorOutOfMemory ? ACQ_ERR_OOM : ACQ_ERR_DEVICE,         \
+                             std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+    return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count ? count : 1));
+}
+
+void free_fsk(acq_fsk_plan_s* p) {
+    if (!p) return;
+    void* dev[] = {p->d_G1, p->d_G0, p->d_rootsF, p->d_bits, p->d_bitcyc, p->d_tmpl, p->d_bank, p->d_d, p->d_u, p->d_zp, p->d_X,
+                   p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_zero, p->d_tdescs, p->d_tcounts, p->d_keys,
+                   p->d_dets, p->d_out, p->d_found, p->d_count};
+    for (void* d : dev)
+        if (d) (void)hipFree(d);
+    if (p->h_out) (void)hipHostFree(p->h_out);
+    if (p->h_count) (void)hipHostFree(p->h_count);
+    delete p;
+}
+
+hipError_t launch_front(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, bool replica, float2* out) {
+    // block mode writes the plan's d and u arrays; replica mode writes `out`
+    const acq_fsk_config& c = p->cfg;
+    acq::FrontArgs a{};
+    a.iq = iq;
+    a.bits = p->d_bits;
+    a.bit_cyc = p->d_bitcyc;
+    a.G1 = p->d_G1;
+    a.G0 = p->d_G0;
+    a.roots = p->d_rootsF;
+    a.out = out;
+    a.out_d = p->d_d;
+    a.out_u = p->d_u;
+    a.n_in = replica ? int64_t(c.num_bits) * c.mf_len : n;
+    a.n_out = replica ? p->g.nt : n;
+    a.out_stride = replica ? p->g.M : 0;
+    a.lo_cyc = c.lo_hz / c.sample_rate_hz;
+    a.f1_cyc = c.f1_hz / c.sample_rate_hz;
+    a.f0_cyc = c.f0_hz / c.sample_rate_hz;
+    a.nbits = c.num_bits;
+    a.sps = c.mf_len;
+    a.lg = int(p->g.lg);
+    a.vf = int(p->g.vf);
+    a.nseg = int((a.n_out + p->g.vf - 1) / p->g.vf);
+    a.replica = replica ? 1 : 0;
+    if (a.nseg <= 0) return hipSuccess;
+    const unsigned grid = unsigned(a.nseg) * unsigned(replica ? c.num_tags : 1);
+    hipLaunchKernelGGL(acq::k_fsk_front, dim3(grid), dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+acq::FwdArgs fwd_args(acq_fsk_plan_s* p, const BlockTable& bt, float2* X, int64_t V) {
+    acq::FwdArgs fa{};
+    fa.blocks = bt;
+    fa.X = X;
+    fa.Xh = nullptr;
+    fa.exps = nullptr;
+    fa.cls_cyc = p->d_zero;
+    fa.ncls = 1;
+    fa.rootsM = p->d_rootsM;
+    fa.rootsSub = p->d_rootsSub;
+    fa.b1tab = p->d_b1tab;
+    fa.V = V;
+    fa.spc = p->g.P;
+    fa.M = int(p->g.M);
+    fa.Msub = int(p->g.Msub);
+    return fa;
+}
+
+int build_fsk(acq_fsk_plan_s* p, const acq_fsk_config* cfg) {
+    const acq::FskGeometry& g = p->g;
+    const acq_fsk_config& c = *cfg;
+    const size_t T = size_t(c.num_tags), NB = size_t(c.num_bits), M = size_t(g.M);
+    hipStream_t st = p->stream;
+    FSK_HIP(dalloc(&p->d_G1, size_t(acq::kFrontN)));
+    FSK_HIP(dalloc(&p->d_G0, size_t(acq::kFrontN)));
+    FSK_HIP(dalloc(&p->d_rootsF, size_t(acq::kFrontN)));
+    FSK_HIP(dalloc(&p->d_bits, T * NB));
+    FSK_HIP(dalloc(&p->d_bitcyc, T * NB));
+    FSK_HIP(dalloc(&p->d_tmpl, T * M));
+    FSK_HIP(dalloc(&p->d_bank, T * M));
+    const size_t slots = size_t(std::max<int64_t>((g.max_seg + 1) / 2, 1));
+    FSK_HIP(dalloc(&p->d_d, size_t(c.max_block_len)));
+    FSK_HIP(dalloc(&p->d_u, size_t(c.max_block_len)));
+    FSK_HIP(dalloc(&p->d_zp, slots * M));
+    FSK_HIP(dalloc(&p->d_X, slots * M));
+    FSK_HIP(dalloc(&p->d_rootsM, M));
+    FSK_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
+    const std::vector<float> b1 = g.log2_sub == 14 ? acq::fft14_b1_table() : std::vector<float>(2, 0.f);
+    FSK_HIP(dalloc(&p->d_b1tab, b1.size() / 2));
+    FSK_HIP(dalloc(&p->d_zero, 1));
+    FSK_HIP(dalloc(&p->d_tdescs, T));
+    FSK_HIP(dalloc(&p->d_tcounts, 2));
+    FSK_HIP(dalloc(&p->d_keys, T));
+    FSK_HIP(dalloc(&p->d_dets, T));
+    FSK_HIP(dalloc(&p->d_out, T));
+    FSK_HIP(dalloc(&p->d_found, T));
+    FSK_HIP(dalloc(&p->d_count, 1));
+    FSK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_fsk_detection) * T));
+    FSK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t)));
+
+    // tables: composed filter spectra, unit roots, replica bit phases (FP64 on the host)
+    const std::vector<float> G1 = acq::filter_spectrum(acq::composed(&c, c.f1_hz));
+    const std::vector<float> G0 = acq::filter_spectrum(acq::composed(&c, c.f0_hz));
+    const std::vector<float> rootsF = acq::unit_roots(acq::kFrontN);
+    const std::vector<float> rootsM = acq::unit_roots(g.M);
+    const std::vector<float> rootsSub = acq::unit_roots(g.Msub);
+    std::vector<double> bitcyc(T * NB);
+    std::vector<uint8_t> bits(T * NB);
+    for (size_t t = 0; t < T; ++t) {
+        long double acc = 0.0L;                   // cycles at the bit start, reduced as it grows
+        for (size_t b = 0; b < NB; ++b) {
+            const uint8_t bit = c.bits[t * NB + b] ? 1 : 0;
+            bits[t * NB + b] = bit;
+            bitcyc[t * NB + b] = double(acc);
+            acc += (long double)(bit ? c.f1_hz : c.f0_hz) * (long double)c.mf_len / (long double)c.sample_rate_hz;
+            acc -= std::floor(acc);
+        }
+    }
+    const double zero = 0.0;
+    FSK_HIP(hipMemcpyAsync(p->d_G1, G1.data(), G1.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_G0, G0.data(), G0.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_rootsF, rootsF.data(), rootsF.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_rootsM, rootsM.data(), rootsM.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_rootsSub, rootsSub.data(), rootsSub.size() * sizeof(float), hipMemcpyHostToDevice,
+                           st));
+    FSK_HIP(hipMemcpyAsync(p->d_b1tab, b1.data(), b1.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_bits, bits.data(), bits.size(), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_bitcyc, bitcyc.data(), bitcyc.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_zero, &zero, sizeof(double), hipMemcpyHostToDevice, st));
+
+    // replica templates d^(c) (zero beyond n_t), then their spectra
+    const int64_t tcount = int64_t(T * M);
+    hipLaunchKernelGGL(acq::k_fsk_fill, dim3(unsigned((tcount + 255) / 256)), dim3(256), 0, st, p->d_tmpl, tcount);
+    FSK_HIP(hipGetLastError());
+    FSK_HIP(launch_front(p, nullptr, 0, true, p->d_tmpl));
+    std::vector<BlockDesc> descs(T);
+    for (size_t t = 0; t < T; ++t) {
+        BlockDesc d{};
+        d.x = p->d_tmpl + t * M;
+        d.n = g.nt;
+        d.lags = 1;
+        d.seg0 = int32_t(t);
+        d.nseg = 1;
+        d.tag = -1;
+        descs[t] = d;
+    }
+    const int32_t counts[2] = {int32_t(T), int32_t(T)};
+    FSK_HIP(hipMemcpyAsync(p->d_tdescs, descs.data(), T * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
+    FSK_HIP(hipMemcpyAsync(p->d_tcounts, counts, sizeof(counts), hipMemcpyHostToDevice, st));
+    BlockTable bt{};
+    bt.descs = p->d_tdescs;
+    bt.counts = p->d_tcounts;
+    const acq::FwdArgs fa = fwd_args(p, bt, p->d_bank, g.M);
+    FSK_HIP(acq::launch_forward(fa, int(T) * g.P, int(T), g.log2_sub, ACQ_FP32, st));
+    hipLaunchKernelGGL(acq::k_fsk_conj_scale, dim3(unsigned((tcount + 255) / 256)), dim3(256), 0, st, p->d_bank, tcount,
+                       float(1.0 / double(g.M)));
+    FSK_HIP(hipGetLastError());
+    FSK_HIP(hipStreamSynchronize(st));
+    return ACQ_OK;
+}
+
+int check_iq(acq_fsk_plan_s* p, const int16_t* iq, int64_t n) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (n < 0) return acq::fail(ACQ_ERR_INVALID_ARG, "negative block length");
+    if (n > p->cfg.max_block_len) return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "block longer than max_block_len");
+    if (n > 0 && !iq) return acq::fail(ACQ_ERR_INVALID_ARG, "null block");
+    if (reinterpret_cast<uintptr_t>(iq) % 4 != 0) return acq::fail(ACQ_ERR_INVALID_ARG, "block must be 4-byte aligned");
+    return ACQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acq_fsk_plan_geometry(const acq_fsk_config* cfg, acq_fsk_geometry* out) {
+    if (!out) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
+    acq::FskGeometry g;
+    const int rc = acq::fsk_geometry(cfg, &g);
+    if (rc != ACQ_OK) return rc;
+    out->template_len = g.nt;
+    out->fft_len = g.M;
+    out->valid_per_segment = g.V;
+    out->filter_len = g.lg;
+    out->front_fft_len = acq::kFrontN;
+    out->device_bytes = g.bytes;
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+int acq_fsk_plan(const acq_fsk_config* cfg, void* stream, acq_fsk_plan_t* out) {
+    if (!out) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    acq::FskGeometry g;
+    int rc = acq::fsk_geometry(cfg, &g);
+    if (rc != ACQ_OK) return rc;
+    acq_fsk_plan_s* p = new (std::nothrow) acq_fsk_plan_s();
+    if (!p) return acq::fail(ACQ_ERR_OOM, "host allocation failed");
+    p->cfg = *cfg;
+    p->g = g;
+    p->stream = static_cast<hipStream_t>(stream);
+    rc = build_fsk(p, cfg);
+    p->cfg.bits = nullptr;           // copied to the device; the caller keeps its buffers
+    p->cfg.bp_taps = nullptr;
+    if (rc != ACQ_OK) {
+        free_fsk(p);
+        return rc;
+    }
+    *out = p;
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+int acq_fsk_release(acq_fsk_plan_t p) {
+    if (p) {
+        (void)hipStreamSynchronize(p->stream);
+        free_fsk(p);
+    }
+    return ACQ_OK;
+}
+
+int acq_fsk_demod(acq_fsk_plan_t p, const int16_t* iq, int64_t n, float* d, float* u) {
+    int rc = check_iq(p, iq, n);
+    if (rc != ACQ_OK) return rc;
+    if (n > 0 && (!d || !u)) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
+    if (n == 0) return ACQ_OK;
+    FSK_HIP(launch_front(p, iq, n, false, nullptr));
+    FSK_HIP(hipMemcpyAsync(d, p->d_d, sizeof(float) * size_t(n), hipMemcpyDeviceToDevice, p->stream));
+    FSK_HIP(hipMemcpyAsync(u, p->d_u, sizeof(float) * size_t(n), hipMemcpyDeviceToDevice, p->stream));
+    FSK_HIP(hipStreamSynchronize(p->stream));
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+int acq_fsk_template(acq_fsk_plan_t p, int32_t tag, float* out) {
+    if (!p || !out) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (tag < 0 || tag >= p->cfg.num_tags) return acq::fail(ACQ_ERR_INVALID_ARG, "tag outside [0, num_tags)");
+    FSK_HIP(hipMemcpy2DAsync(out, sizeof(float), p->d_tmpl + size_t(tag) * size_t(p->g.M), sizeof(float2),
+                             sizeof(float), size_t(p->g.nt), hipMemcpyDeviceToDevice, p->stream));
+    FSK_HIP(hipStreamSynchronize(p->stream));
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Steps 1-7 and the peak keys on the plan's stream; dump (device [T][lags]) gets
+// Re c for every lag when not null.
+int enqueue_fsk_search(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, float* dump) {
+    const acq::FskGeometry& g = p->g;
+    const int T = p->cfg.num_tags;
+    hipStream_t st = p->stream;
+    FSK_HIP(launch_front(p, iq, n, false, nullptr));
+    const int64_t lags = n - g.nt + 1;
+    const int nseg = int((lags + g.V - 1) / g.V);
+    const int nslots = (nseg + 1) / 2;
+    const int64_t packed = int64_t(nslots) * g.M;
+    hipLaunchKernelGGL(acq::k_fsk_pack, dim3(unsigned((packed + 255) / 256)), dim3(256), 0, st, p->d_d, n, g.V, g.M,
+                       nseg, nslots, p->d_zp);
+    FSK_HIP(hipGetLastError());
+    BlockTable bt{};
+    bt.one.x = p->d_zp;
+    bt.one.n = packed;
+    bt.one.lags = packed;
+    bt.one.seg0 = 0;
+    bt.one.nseg = nslots;
+    bt.one.tag = -1;
+    const acq::FwdArgs fa = fwd_args(p, bt, p->d_X, g.M);
+    FSK_HIP(acq::launch_forward(fa, nslots * g.P, nslots, g.log2_sub, ACQ_FP32, st));
+    FSK_HIP(acq::launch_fill_u64(p->d_keys, T, st));
+    acq::FskCorrArgs ca{};
+    ca.X = p->d_X;
+    ca.bank = p->d_bank;
+    ca.rootsM = p->d_rootsM;
+    ca.rootsSub = p->d_rootsSub;
+    ca.b1tab = p->d_b1tab;
+    ca.keys = p->d_keys;
+    ca.dump = dump;
+    ca.V = g.V;
+    ca.lags = lags;
+    ca.M = int(g.M);
+    ca.Msub = int(g.Msub);
+    ca.P = g.P;
+    ca.T = T;
+    ca.tile = std::min(T, acq::kFskTile);
+    ca.ntiles = (T + ca.tile - 1) / ca.tile;
+    ca.nseg = nseg;
+    ca.nslots = nslots;
+    const int64_t total = int64_t(ca.ntiles) * nslots * g.P;
+    const int grid = int((total + acq::kXcds - 1) / acq::kXcds) * acq::kXcds;
+    FSK_HIP(acq::launch_fsk_correlate(ca, grid, g.log2_sub, st));
+    return ACQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acq_fsk_xcorr(acq_fsk_plan_t p, const int16_t* iq, int64_t n, float* out) {
+    int rc = check_iq(p, iq, n);
+    if (rc != ACQ_OK) return rc;
+    if (n < p->g.nt) return acq::fail(ACQ_ERR_INVALID_ARG, "block shorter than a template");
+    if (!out) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
+    rc = enqueue_fsk_search(p, iq, n, out);
+    if (rc != ACQ_OK) return rc;
+    FSK_HIP(hipStreamSynchronize(p->stream));
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+int acq_fsk_detect(acq_fsk_plan_t p, const int16_t* iq, int64_t n, acq_fsk_detection* out, int32_t capacity,
+                   int32_t* n_found) {
+    int rc = check_iq(p, iq, n);
+    if (rc != ACQ_OK) return rc;
+    if (!n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null n_found");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    *n_found = 0;
+    const acq::FskGeometry& g = p->g;
+    if (n < g.nt) {
+        acq::clear_error();
+        return ACQ_OK;
+    }
+    const int T = p->cfg.num_tags;
+    hipStream_t st = p->stream;
+    const int64_t lags = n - g.nt + 1;
+    rc = enqueue_fsk_search(p, iq, n, nullptr);
+    if (rc != ACQ_OK) return rc;
+    acq::FskRefineArgs ra{};
+    ra.d = p->d_d;
+    ra.u = p->d_u;
+    ra.tmpl = p->d_tmpl;
+    ra.keys = p->d_keys;
+    ra.dets = p->d_dets;
+    ra.found = p->d_found;
+    ra.n = n;
+    ra.nt = g.nt;
+    ra.tstride = g.M;
+    ra.lags = lags;
+    ra.theta = p->cfg.threshold;
+    hipLaunchKernelGGL(acq::k_fsk_refine, dim3(unsigned(T)), dim3(256), 0, st, ra);
+    FSK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(acq::k_fsk_compact, dim3(1), dim3(64), 0, st, p->d_dets, p->d_found, T, p->d_out, p->d_count);
+    FSK_HIP(hipGetLastError());
+    FSK_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FSK_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_fsk_detection) * size_t(T), hipMemcpyDeviceToHost, st));
+    FSK_HIP(hipStreamSynchronize(st));
+    const int32_t found = *p->h_count;
+    *n_found = found;
+    const int32_t ncopy = found < capacity ? found : capacity;
+    if (ncopy > 0) std::memcpy(out, p->h_out, sizeof(acq_fsk_detection) * size_t(ncopy));
+    if (found > capacity) return acq::fail(ACQ_ERR_TRUNCATED, "more detections than capacity");
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+}  // extern "C"

@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "rng", "make_codes", "chip_waveform", "delayed_waveform", "Transmission",
     "make_block", "add_noise", "WORKLOADS", "workload", "batch_lengths", "make_stream_batch",
-    "make_tracking_batch",
+    "make_tracking_batch", "fsk_bandpass", "make_fsk_bits", "make_fsk_block",
 ]
 
 # stream identifiers (second SeedSequence word)
@@ -199,6 +199,12 @@ WORKLOADS = {
                      bin_center_hz=0.0, bin_step_hz=1000.0, fft_len=0, num_tasks=256,
                      block_factor=1.5, p_present=0.9, n_other=(0, 1), snr_db=(-15.0, -5.0),
                      precision="fp32", seeds=(5000, 5005)),
+    # FSK searching task of the paper's shape: a 100 ms window at 8 Msps, 8192-bit
+    # packets at 1 Mb/s (8 samples per bit, tones +/-250 kHz), 200-tap band-pass,
+    # 128 codes; six packets per window at -10..0 dB, int16 samples
+    "fsk_search": dict(num_tags=128, num_bits=8192, sps=8, fs_hz=8e6, block_len=800000, lo_hz=1.0e6,
+                       f1_hz=250e3, f0_hz=-250e3, bp_taps=200, bp_cutoff_hz=600e3, n_tx=6,
+                       snr_db=(-10.0, 0.0), noise_rms=1000.0, seeds=(6000, 6005)),
 }
 
 
@@ -256,3 +262,53 @@ def make_tracking_batch(seed: int, chips: np.ndarray, spc: int, fs_hz: float, fr
                             sub=300000 + i)
         out.append((x, tag, txs))
     return out
+
+
+def fsk_bandpass(num_taps: int, cutoff_hz: float, fs_hz: float) -> np.ndarray:
+    """Band-pass taps of the FSK workload, centred at 0 Hz after the mix: a
+    Hann-windowed sinc low-pass of the given cutoff, unit gain at 0 Hz, complex128."""
+    k = np.arange(num_taps) - (num_taps - 1) / 2.0
+    h = np.sinc(2.0 * cutoff_hz / fs_hz * k) * np.hanning(num_taps + 2)[1:-1]
+    return (h / h.sum()).astype(np.complex128)
+
+
+def make_fsk_bits(seed: int, num_tags: int, num_bits: int) -> np.ndarray:
+    """Random 0/1 codes, uint8 [num_tags][num_bits]; tag t uses stream (CODES, t, 1)."""
+    out = np.empty((num_tags, num_bits), dtype=np.uint8)
+    for t in range(num_tags):
+        out[t] = rng(seed, _STREAM_CODES, t, 1).integers(0, 2, size=num_bits, dtype=np.uint8)
+    return out
+
+
+def make_fsk_block(seed: int, n: int, bits: np.ndarray, sps: int, fs_hz: float, f1_hz: float, f0_hz: float,
+                   lo_hz: float, n_tx: int, snr_db=(-10.0, 0.0), noise_rms: float = 1000.0,
+                   tags=None, delays=None, noise: bool = True):
+    """Receiver block of int16 (I, Q) pairs [n][2]: continuous-phase FSK packets
+    (bit b held sps samples at f1 or f0, random start phase) on a carrier at
+    lo_hz, at integer delays, per-sample SNR drawn in dB against complex noise
+    of rms noise_rms, rounded and clipped to int16.  Returns (iq, list of
+    (tag, delay, snr_db))."""
+    bits = np.asarray(bits)
+    T, nb = bits.shape
+    plen = nb * sps
+    g = rng(seed, _STREAM_BLOCK, 7)
+    x = np.zeros(n, dtype=np.complex128)
+    txs = []
+    tag_list = list(tags) if tags is not None else list(g.choice(T, size=n_tx, replace=False))
+    for i in range(n_tx):
+        D = int(delays[i]) if delays is not None else int(g.integers(0, max(n - plen, 1)))
+        if D + plen > n:
+            raise ValueError("packet does not fit in the block")
+        snr = float(snr_db[0] + (snr_db[1] - snr_db[0]) * g.random())
+        th0 = float(2 * np.pi * g.random())
+        f = np.where(np.repeat(bits[tag_list[i]], sps) == 1, f1_hz, f0_hz) / fs_hz
+        cyc = np.mod(np.concatenate(([0.0], np.cumsum(f)[:-1])), 1.0)
+        A = noise_rms * 10.0 ** (snr / 20.0)
+        x[D:D + plen] += A * np.exp(1j * (2 * np.pi * cyc + th0))
+        txs.append((int(tag_list[i]), D, snr))
+    x *= np.exp(2j * np.pi * np.mod(lo_hz / fs_hz * np.arange(n), 1.0))
+    if noise:
+        w = rng(seed, _STREAM_NOISE, 7).standard_normal((n, 2)) * (noise_rms / np.sqrt(2.0))
+        x += w[:, 0] + 1j * w[:, 1]
+    iq = np.stack([np.round(x.real), np.round(x.imag)], axis=1)
+    return np.clip(iq, -32768, 32767).astype(np.int16), txs
