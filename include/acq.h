@@ -501,6 +501,19 @@ int acq_fsk_demod(acq_fsk_plan_t plan, const int16_t* iq, int64_t n, float* d, f
 /* The stored replica template d^(c) of a tag (test hook): device float[n_t]. */
 int acq_fsk_template(acq_fsk_plan_t plan, int32_t tag, float* out);
 
+/* Kernel timing of the FSK search (HIP events on the plan's stream around
+ * each launch of the last acq_fsk_detect while profiling is on), in ms:
+ * ms[ACQ_FSK_KERNEL_*], n >= ACQ_FSK_NUM_KERNELS. */
+enum {
+    ACQ_FSK_KERNEL_FRONT = 0,       /* conversion, mixing, composed filters, demodulation */
+    ACQ_FSK_KERNEL_FORWARD = 1,     /* segment spectra of d                               */
+    ACQ_FSK_KERNEL_CORRELATE = 2,   /* correlation with every template, peak keys         */
+    ACQ_FSK_KERNEL_REFINE = 3,      /* FP64 peak sums                                     */
+    ACQ_FSK_NUM_KERNELS = 4
+};
+int acq_fsk_set_profiling(acq_fsk_plan_t plan, int on);
+int acq_fsk_last_kernel_times(acq_fsk_plan_t plan, double* ms, int32_t n);
+
 /* Steps 1-7 (test hook): the FFT path's correlation xcorr(d, d^(c)) of every
  * tag at every lag into device float out[num_tags][n - n_t + 1] (n >= n_t).
  * Synchronous. */

@@ -24,8 +24,9 @@
 //                                   sum_a Y[i' + Msub a] exp(+j 2 pi a rho / P),
 //                     Y the spectrum product, then an Msub-point inverse
 //                     transform of G_rho.  Keys: bits(|Re c|) << 32 | ~tau.
-//   k_fsk_refine    : FP64 sums over +/-2 lags of the peak from the stored d,
-//                     u and template, re-maximisation, parabola, w_c, q, p_c, z.
+//   k_fsk_refine_*  : FP64 sums over +/-3 lags of the peak from the stored d,
+//                     u and template (in parts, added in order), re-maximisation,
+//                     parabola, w_c, q, p_c, z.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,7 +49,7 @@ namespace {
 
 constexpr int kFrontLog = 12;                 // composed filters applied on 4096-point segments
 constexpr int kFrontN = 1 << kFrontLog;
-constexpr int kFskTile = 16;                  // templates per correlation work item
+constexpr int kFskMaxGrid = 512;              // workgroups (and scratch slots) of the correlation
 
 struct FrontArgs {
     const int16_t* iq;          // block: [n_in][2]
@@ -162,114 +163,139 @@ struct FskCorrArgs {
     const float2* rootsM;       // [M]
     const float2* rootsSub;     // [Msub]
     const float2* b1tab;
+    float2* scratch;            // [gridDim.x][M]: the P first-step outputs of the workgroup's item
     unsigned long long* keys;   // [T]
     float* dump;                // optional [T][lags]: c at every lag (test hook)
     int64_t V, lags;
-    int32_t M, Msub, P, T, tile, ntiles, nseg, nslots;
+    int32_t M, Msub, P, T, nseg, nslots;
 };
 
-// Work item wi = ((tile * nslots) + g) * P + rho: segments 2g (real part) and
-// 2g+1 (imaginary part).
-template <class E, bool DUMP>
+// Work item (tag t, slot g), items t * nslots + g taken with a stride of the
+// grid: segments 2g (real part) and 2g+1 (imaginary part) against template t.
+//   first step, once per item: for each i' < Msub, the spectrum products
+//     Y_a = Z_g[i' + Msub a] conj(D_t[i' + Msub a]) / M, a < P, and
+//     G_rho[i'] = exp(+j 2 pi i' rho / M) sum_a Y_a exp(+j 2 pi a rho / P),
+//     written to the workgroup's scratch (each input read once);
+//   then, per phase rho, the Msub-point inverse transform of G_rho (lag
+//   P u + rho) and the lane maximum of |c| over both segments and all phases.
+// exp(+j 2 pi k / 8), k < 8 (the values FP64 rounds to in FP32)
+__device__ __forceinline__ float2 root8(int k) {
+    constexpr float h = 0.70710678118654752f;
+    switch (k) {
+        case 0: return make_float2(1.f, 0.f);
+        case 1: return make_float2(h, h);
+        case 2: return make_float2(0.f, 1.f);
+        case 3: return make_float2(-h, h);
+        case 4: return make_float2(-1.f, 0.f);
+        case 5: return make_float2(-h, -h);
+        case 6: return make_float2(0.f, -1.f);
+        default: return make_float2(h, -h);
+    }
+}
+
+template <class E, int PP, bool DUMP>
 __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
     constexpr int NW = E::NT / 64;
     __shared__ float2 lds[E::LDS];
     __shared__ float2 extra[E::EXTRA];
-    __shared__ unsigned long long red[kFskTile * NW];
-    const int total = a.ntiles * a.nslots * a.P;
-    const int xcd = int(blockIdx.x) % kXcds;
-    const int per = (total + kXcds - 1) / kXcds;
-    const int wi = xcd * per + int(blockIdx.x) / kXcds;
-    if (int(blockIdx.x) / kXcds >= per || wi >= total) return;
+    __shared__ unsigned long long red[NW];
     E eng;
     eng.init(a.rootsSub, extra);
-    int rem = wi;
-    const int rho = rem % a.P;
-    rem /= a.P;
-    const int j = rem % a.nslots;
-    const int tile = rem / a.nslots;
-    const int tag0 = tile * a.tile;
-    const int ntag = min(a.tile, a.T - tag0);
     const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
-    const float2* Xj = a.X + size_t(j) * size_t(a.M);
     const int mmask = a.M - 1;
-
-    // valid outputs of the two segments: lag P u + rho < min(V, lags - segment start)
-    int ulim[2];
-    int64_t sbeg[2];
+    float2* G = a.scratch + size_t(blockIdx.x) * size_t(a.M);
+    const int items = a.T * a.nslots;
+    for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
+        const int tag = it / a.nslots, j = it - tag * a.nslots;
+        const float2* Xj = a.X + size_t(j) * size_t(a.M);
+        const float2* B = a.bank + size_t(tag) * size_t(a.M);
+        // first step: P outputs per i' from P products; the P-point DFT uses
+        // constant eighth roots of unity, so each i' issues its 2P product
+        // loads and P-1 twiddle loads together (one i' at a time keeps them in
+        // registers without holding all 16)
+#pragma unroll 1
+        for (int m = 0; m < 16; ++m) {
+            const int ip = eng.in_index(m);
+            float2 y[PP], tw[PP];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        sbeg[h] = int64_t(2 * j + h) * a.V;
-        const int64_t v64 = (2 * j + h < a.nseg) ? (a.lags - sbeg[h] < a.V ? a.lags - sbeg[h] : a.V) : 0;
-        const int vlim = int(v64);
-        ulim[h] = vlim > rho ? (vlim - rho + a.P - 1) / a.P : 0;
-    }
-    const int ob0 = eng.out_base();
-    const int omin = eng.out_min(), omax = eng.out_max();
-    const bool hi = omin + E::HI_OFF < max(ulim[0], ulim[1]);
-
-    for (int tt = 0; tt < ntag; ++tt) {
-        const float2* B = a.bank + size_t(tag0 + tt) * size_t(a.M);
-        float2 v[16];
+            for (int q = 0; q < PP; ++q) y[q] = cmul(Xj[ip + q * a.Msub], B[ip + q * a.Msub]);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = make_float2(0.f, 0.f);
-        for (int q = 0; q < a.P; ++q) {
-            const float2 wq = a.rootsM[(q * rho * a.Msub) & mmask];   // exp(+j 2 pi q rho / P), uniform
-            const int off = q * a.Msub;
+            for (int r = 1; r < PP; ++r) tw[r] = a.rootsM[(ip * r) & mmask];
 #pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                const int i = eng.in_index(m) + off;
-                v[m] = cadd(v[m], cmul(cmul(Xj[i], B[i]), wq));
+            for (int rho = 0; rho < PP; ++rho) {
+                float2 acc = y[0];
+#pragma unroll
+                for (int q = 1; q < PP; ++q) acc = cadd(acc, cmul(y[q], root8((q * rho * (8 / PP)) & 7)));
+                if (rho) acc = cmul(acc, tw[rho]);
+                G[rho * a.Msub + ip] = acc;
             }
         }
-        if (rho) {
+        __threadfence_block();
+        __syncthreads();
+        int ulim[2];
+        int64_t sbeg[2];
+        unsigned long long best = 0ull;
+        for (int rho = 0; rho < PP; ++rho) {
 #pragma unroll
-            for (int m = 0; m < 16; ++m) v[m] = cmul(v[m], a.rootsM[(eng.in_index(m) * rho) & mmask]);
-        }
-        eng.template transform<+1>(v, lds, b1, extra, hi);
-        int ob = ob0;
-        asm volatile("" : "+v"(ob));
-        // this lane's largest |c|: the first segment's lags (all smaller) before
-        // the second's, each in increasing lag, so the strict comparison keeps
-        // the smallest lag of a tie
-        float bp = -1.0f;
-        int boff = 0, bh = 0;
+            for (int h = 0; h < 2; ++h) {
+                sbeg[h] = int64_t(2 * j + h) * a.V;
+                const int64_t v64 = (2 * j + h < a.nseg) ? (a.lags - sbeg[h] < a.V ? a.lags - sbeg[h] : a.V) : 0;
+                const int vlim = int(v64);
+                ulim[h] = vlim > rho ? (vlim - rho + PP - 1) / PP : 0;
+            }
+            const int ob0 = eng.out_base();
+            const int omin = eng.out_min(), omax = eng.out_max();
+            const bool hi = omin + E::HI_OFF < max(ulim[0], ulim[1]);
+            float2 v[16];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+            for (int m = 0; m < 16; ++m) v[m] = G[rho * a.Msub + eng.in_index(m)];
+            eng.template transform<+1>(v, lds, b1, extra, hi);
+            int ob = ob0;
+            asm volatile("" : "+v"(ob));
+            // this lane's largest |c| of the phase: the first segment's lags
+            // before the second's, each in increasing lag (strict comparison:
+            // the smallest lag of a tie within the phase)
+            float bp = -1.0f;
+            int boff = 0, bh = 0;
 #pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                const int r = E::visit(rr);
-                const int off = E::out_off(r);
-                if (omin + off < ulim[h]) {
-                    const float cv = h ? v[r].y : v[r].x;
-                    float pv = fabsf(cv);
-                    if constexpr (DUMP) {
-                        if (ob + off < ulim[h]) {
-                            const int64_t tau = sbeg[h] + int64_t(a.P) * (ob + off) + rho;
-                            a.dump[size_t(tag0 + tt) * size_t(a.lags) + size_t(tau)] = cv;
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr) {
+                    const int r = E::visit(rr);
+                    const int off = E::out_off(r);
+                    if (omin + off < ulim[h]) {
+                        const float cv = h ? v[r].y : v[r].x;
+                        float pv = fabsf(cv);
+                        if constexpr (DUMP) {
+                            if (ob + off < ulim[h]) {
+                                const int64_t tau = sbeg[h] + int64_t(PP) * (ob + off) + rho;
+                                a.dump[size_t(tag) * size_t(a.lags) + size_t(tau)] = cv;
+                            }
                         }
+                        if (omax + off >= ulim[h] && ob + off >= ulim[h]) pv = -1.0f;
+                        const bool take = pv > bp;
+                        boff = take ? off : boff;
+                        bh = take ? h : bh;
+                        bp = take ? pv : bp;
                     }
-                    if (omax + off >= ulim[h] && ob + off >= ulim[h]) pv = -1.0f;
-                    const bool take = pv > bp;
-                    boff = take ? off : boff;
-                    bh = take ? h : bh;
-                    bp = take ? pv : bp;
                 }
             }
+            const unsigned lag = unsigned(sbeg[bh] + rho) + unsigned(ob + boff) * unsigned(PP);
+            const unsigned long long key = bp >= 0.0f
+                ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) | static_cast<unsigned long long>(~lag)
+                : 0ull;
+            best = key > best ? key : best;          // across phases the key order decides ties
         }
-        const unsigned lag = unsigned(sbeg[bh] + rho) + unsigned(ob + boff) * unsigned(a.P);
-        unsigned long long best = bp >= 0.0f
-            ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) | static_cast<unsigned long long>(~lag)
-            : 0ull;
         best = wave_max(best);
-        if (lane == 0) red[tt * NW + wave] = best;
-    }
-    __syncthreads();
-    for (int i = int(threadIdx.x); i < ntag; i += E::NT) {
-        unsigned long long m = 0ull;
-        for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
-        if (m) atomicMax(&a.keys[tag0 + i], m);
+        if (lane == 0) red[wave] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long m = 0ull;
+            for (int q = 0; q < NW; ++q) m = red[q] > m ? red[q] : m;
+            if (m) atomicMax(&a.keys[tag], m);
+        }
+        __syncthreads();                     // red[], scratch and LDS are reused by the next item
     }
 }
 
@@ -278,155 +304,188 @@ struct FskRefineArgs {
     const float* u;             // [n]
     const float2* tmpl;         // [T][tstride] (d^(c), 0)
     const unsigned long long* keys;
+    double* partial;            // [T][kFskParts][kFskSums]
     acq_fsk_detection* dets;    // [T]
     int32_t* found;             // [T]
     int64_t n, nt, tstride, lags;
     double theta;
 };
 
-constexpr int kFskWin = 5;      // lags tau*-2 .. tau*+2
+// FP64 sums over lags tau*-3 .. tau*+3 around the peak key: w_c, p_c and q at
+// each lag and E_c, enough for the re-maximisation over +/-1 and one
+// re-centring.  Each (tag, part) workgroup sums a fixed chunk of the template
+// in a fixed order and the parts are added in order: deterministic.
+constexpr int kFskWin = 7;
+constexpr int kFskParts = 16;
+constexpr int kFskSums = 3 * kFskWin + 1;
 
-// One workgroup of 256 threads per tag.
-__global__ __launch_bounds__(256) void k_fsk_refine(FskRefineArgs a) {
+__global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
     constexpr int NT = 256, NW = NT / 64;
-    const int tag = int(blockIdx.x);
+    const int tag = int(blockIdx.x) / kFskParts, part = int(blockIdx.x) % kFskParts;
     const int t = int(threadIdx.x), lane = t & 63, wave = t >> 6;
-    __shared__ double red[NW][kFskWin * 3 + 1];
-    __shared__ long long s_center;
-    __shared__ int s_again;
+    __shared__ double red[NW][kFskSums];
+    double* out = a.partial + (size_t(tag) * kFskParts + part) * kFskSums;
     const unsigned long long key = a.lags > 0 ? a.keys[tag] : 0ull;
     if (key == 0ull) {
-        if (t == 0) a.found[tag] = 0;
+        if (t < kFskSums) out[t] = 0.0;
         return;
     }
+    const int64_t lam0 = int64_t(~unsigned(key & 0xffffffffull)) - kFskWin / 2;
     const float2* dc = a.tmpl + size_t(tag) * size_t(a.tstride);
-    int64_t center = int64_t(~unsigned(key & 0xffffffffull));
-    for (int pass = 0; pass < 2; ++pass) {
-        const int64_t lam0 = center - (kFskWin / 2);
-        double wv[kFskWin], pv[kFskWin], qv[kFskWin], ec = 0.0;
+    const int64_t ch = (a.nt + kFskParts - 1) / kFskParts;
+    const int64_t i0 = int64_t(part) * ch, i1 = min(a.nt, i0 + ch);
+    double wv[kFskWin], pv[kFskWin], qv[kFskWin], ec = 0.0;
 #pragma unroll
-        for (int w = 0; w < kFskWin; ++w) wv[w] = pv[w] = qv[w] = 0.0;
-        // e walks the block from lam0; lag lam0 + w pairs z[lam0 + e] with dc[e - w]
-        for (int64_t e = t; e < a.nt + kFskWin - 1; e += NT) {
-            const int64_t i = lam0 + e;
-            double zd = 0.0, zu = 0.0;
-            if (i >= 0 && i < a.n) {
-                zd = a.d[i];
-                zu = a.u[i];
-            }
-            if (e < a.nt) {
-                const double c0 = dc[e].x;
-                ec += c0 * c0;
-            }
-#pragma unroll
-            for (int w = 0; w < kFskWin; ++w) {
-                const int64_t nn = e - w;
-                if (nn >= 0 && nn < a.nt) {
-                    const double c = dc[nn].x;
-                    wv[w] += c * zd;
-                    pv[w] += c * zu;
-                    qv[w] += zd * zd;
-                }
-            }
-        }
+    for (int w = 0; w < kFskWin; ++w) wv[w] = pv[w] = qv[w] = 0.0;
+    for (int64_t i = i0 + t; i < i1; i += NT) {
+        const double c = dc[i].x;
+        ec += c * c;
 #pragma unroll
         for (int w = 0; w < kFskWin; ++w) {
-            const double r0 = wave_sum(wv[w]), r1 = wave_sum(pv[w]), r2 = wave_sum(qv[w]);
-            if (lane == 0) {
-                red[wave][3 * w] = r0;
-                red[wave][3 * w + 1] = r1;
-                red[wave][3 * w + 2] = r2;
+            const int64_t k = lam0 + w + i;
+            if (k >= 0 && k < a.n) {
+                const double zd = a.d[k], zu = a.u[k];
+                wv[w] += c * zd;
+                pv[w] += c * zu;
+                qv[w] += zd * zd;
             }
         }
-        const double ecs = wave_sum(ec);
-        if (lane == 0) red[wave][3 * kFskWin] = ecs;
-        __syncthreads();
-        if (t == 0) {
-            double W[kFskWin], Pc[kFskWin], Q[kFskWin], A[kFskWin];
-            double Ec = 0.0;
-            for (int q = 0; q < NW; ++q) Ec += red[q][3 * kFskWin];
-            for (int w = 0; w < kFskWin; ++w) {
-                W[w] = Pc[w] = Q[w] = 0.0;
-                for (int q = 0; q < NW; ++q) {
-                    W[w] += red[q][3 * w];
-                    Pc[w] += red[q][3 * w + 1];
-                    Q[w] += red[q][3 * w + 2];
-                }
-                const int64_t lam = lam0 + w;
-                A[w] = (lam >= 0 && lam < a.lags) ? fabs(W[w]) : -1.0;
-            }
-            int wb = kFskWin / 2;
-            for (int w = 1; w <= kFskWin - 2; ++w)
-                if (A[w] > A[wb] || (A[w] == A[wb] && w < wb)) wb = w;
-            const int64_t lam = lam0 + wb;
-            const bool hit = (wb == 1 && lam > 0) || (wb == kFskWin - 2 && lam < a.lags - 1);
-            if (hit && pass == 0) {
-                s_center = lam;
-                s_again = 1;
-            } else {
-                s_again = 0;
-                unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
-                const double p0 = A[wb];
-                const double pm = A[wb - 1] < 0.0 ? 0.0 : A[wb - 1];
-                const double pp = A[wb + 1] < 0.0 ? 0.0 : A[wb + 1];
-                double delta = 0.0;
-                if (lam == 0 || lam == a.lags - 1) {
-                    flags |= ACQ_DET_NEAR_EDGE;
-                } else {
-                    const double den = pm - 2.0 * p0 + pp;
-                    if (den < 0.0) {
-                        delta = 0.5 * (pm - pp) / den;
-                        delta = delta > 0.5 ? 0.5 : (delta < -0.5 ? -0.5 : delta);
-                    }
-                }
-                acq_fsk_detection r;
-                r.tag = tag;
-                r.flags = flags;
-                r.lag = lam;
-                r.toa_samples = double(lam) + delta;
-                r.xcorr = W[wb];
-                r.q = Q[wb];
-                r.p = Pc[wb];
-                r.z = (Q[wb] > 0.0 && Ec > 0.0) ? W[wb] * W[wb] / (Q[wb] * Ec) : 0.0;
-                a.dets[tag] = r;
-                a.found[tag] = (a.theta <= 0.0 || r.z >= a.theta) ? 1 : 0;
-            }
+    }
+#pragma unroll
+    for (int w = 0; w < kFskWin; ++w) {
+        const double r0 = wave_sum(wv[w]), r1 = wave_sum(pv[w]), r2 = wave_sum(qv[w]);
+        if (lane == 0) {
+            red[wave][3 * w] = r0;
+            red[wave][3 * w + 1] = r1;
+            red[wave][3 * w + 2] = r2;
         }
-        __syncthreads();
-        if (!s_again) break;
-        center = s_center;
+    }
+    const double es = wave_sum(ec);
+    if (lane == 0) red[wave][3 * kFskWin] = es;
+    __syncthreads();
+    if (t < kFskSums) {
+        double v = 0.0;
+        for (int q = 0; q < NW; ++q) v += red[q][t];
+        out[t] = v;
     }
 }
 
-__global__ void k_fsk_compact(const acq_fsk_detection* __restrict__ dets, const int32_t* __restrict__ found,
-                              int T, acq_fsk_detection* __restrict__ out, int32_t* __restrict__ count) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One thread per tag: parts summed in order, re-maximisation of |w_c| over
+// +/-1 lag (one re-centring when it lands on the edge), parabola, results.
+__global__ void k_fsk_refine_final(FskRefineArgs a, int T) {
+    const int tag = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (tag >= T) return;
+    const unsigned long long key = a.lags > 0 ? a.keys[tag] : 0ull;
+    if (key == 0ull) {
+        a.found[tag] = 0;
+        return;
+    }
+    double S[kFskSums];
+    for (int k = 0; k < kFskSums; ++k) S[k] = 0.0;
+    for (int p = 0; p < kFskParts; ++p)
+        for (int k = 0; k < kFskSums; ++k) S[k] += a.partial[(size_t(tag) * kFskParts + p) * kFskSums + k];
+    const int64_t lam0 = int64_t(~unsigned(key & 0xffffffffull)) - kFskWin / 2;
+    double A[kFskWin];
+    for (int w = 0; w < kFskWin; ++w) {
+        const int64_t lam = lam0 + w;
+        A[w] = (lam >= 0 && lam < a.lags) ? fabs(S[3 * w]) : -1.0;
+    }
+    const double Ec = S[3 * kFskWin];
+    int c = kFskWin / 2;
+    bool hit = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        int wb = c;
+        for (int w = c - 1; w <= c + 1; ++w)
+            if (A[w] > A[wb] || (A[w] == A[wb] && w < wb)) wb = w;
+        const int64_t lam = lam0 + wb;
+        hit = (wb == c - 1 && lam > 0) || (wb == c + 1 && lam < a.lags - 1);
+        c = wb;
+        if (!hit) break;
+    }
+    const int64_t lam = lam0 + c;
+    unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
+    const double p0 = A[c];
+    const double pm = A[c - 1] < 0.0 ? 0.0 : A[c - 1];
+    const double pp = A[c + 1] < 0.0 ? 0.0 : A[c + 1];
+    double delta = 0.0;
+    if (lam == 0 || lam == a.lags - 1) {
+        flags |= ACQ_DET_NEAR_EDGE;
+    } else {
+        const double den = pm - 2.0 * p0 + pp;
+        if (den < 0.0) {
+            delta = 0.5 * (pm - pp) / den;
+            delta = delta > 0.5 ? 0.5 : (delta < -0.5 ? -0.5 : delta);
+        }
+    }
+    acq_fsk_detection r;
+    r.tag = tag;
+    r.flags = flags;
+    r.lag = lam;
+    r.toa_samples = double(lam) + delta;
+    r.xcorr = S[3 * c];
+    r.p = S[3 * c + 1];
+    r.q = S[3 * c + 2];
+    r.z = (r.q > 0.0 && Ec > 0.0) ? r.xcorr * r.xcorr / (r.q * Ec) : 0.0;
+    a.dets[tag] = r;
+    a.found[tag] = (a.theta <= 0.0 || r.z >= a.theta) ? 1 : 0;
+}
+
+// Results in tag order: one workgroup of 1024 threads, runs of tags per
+// thread, a scan of the counts gives each run's output offset.
+__global__ __launch_bounds__(1024) void k_fsk_compact(const acq_fsk_detection* __restrict__ dets,
+                                                      const int32_t* __restrict__ found, int T,
+                                                      acq_fsk_detection* __restrict__ out,
+                                                      int32_t* __restrict__ count) {
+    __shared__ int scan[1024];
+    const int t = int(threadIdx.x);
+    const int per = (T + 1023) / 1024;
+    const int b0 = min(T, t * per), b1 = min(T, b0 + per);
     int c = 0;
-    for (int i = 0; i < T; ++i)
-        if (found[i]) out[c++] = dets[i];
-    *count = c;
+    for (int i = b0; i < b1; ++i) c += found[i] ? 1 : 0;
+    scan[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? scan[t - off] : 0;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    int o = scan[t] - c;
+    for (int i = b0; i < b1; ++i)
+        if (found[i]) out[o++] = dets[i];
+    if (t == 1023) *count = scan[t];
 }
 
-template <class E>
-hipError_t launch_fsk_corr_e(const FskCorrArgs& a, int grid, hipStream_t st) {
-    if (a.tile < 1 || a.tile > kFskTile) return hipErrorInvalidValue;
+template <class E, int PP>
+void launch_fsk_corr_ep(const FskCorrArgs& a, int grid, hipStream_t st) {
     if (a.dump)
-        hipLaunchKernelGGL((k_fsk_correlate<E, true>), dim3(grid), dim3(E::NT), 0, st, a);
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, true>), dim3(grid), dim3(E::NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_fsk_correlate<E, false>), dim3(grid), dim3(E::NT), 0, st, a);
-    return hipGetLastError();
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false>), dim3(grid), dim3(E::NT), 0, st, a);
 }
 
+// M <= 2^14 runs as one phase (P = 1) on the Stockham engine of that size;
+// larger M as P = M / 2^14 phases on the 2^14-point engine.
 hipError_t launch_fsk_correlate(const FskCorrArgs& a, int grid, int log2_sub, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
+    if ((log2_sub < 14 && a.P != 1) || (1 << log2_sub) != a.Msub) return hipErrorInvalidValue;
     switch (log2_sub) {
-        case 10: return launch_fsk_corr_e<StockhamEngine<10>>(a, grid, st);
-        case 11: return launch_fsk_corr_e<StockhamEngine<11>>(a, grid, st);
-        case 12: return launch_fsk_corr_e<StockhamEngine<12>>(a, grid, st);
-        case 13: return launch_fsk_corr_e<StockhamEngine<13>>(a, grid, st);
-        case 14: return launch_fsk_corr_e<Fft14>(a, grid, st);
+        case 10: launch_fsk_corr_ep<StockhamEngine<10>, 1>(a, grid, st); break;
+        case 11: launch_fsk_corr_ep<StockhamEngine<11>, 1>(a, grid, st); break;
+        case 12: launch_fsk_corr_ep<StockhamEngine<12>, 1>(a, grid, st); break;
+        case 13: launch_fsk_corr_ep<StockhamEngine<13>, 1>(a, grid, st); break;
+        case 14:
+            switch (a.P) {
+                case 1: launch_fsk_corr_ep<Fft14, 1>(a, grid, st); break;
+                case 2: launch_fsk_corr_ep<Fft14, 2>(a, grid, st); break;
+                case 4: launch_fsk_corr_ep<Fft14, 4>(a, grid, st); break;
+                case 8: launch_fsk_corr_ep<Fft14, 8>(a, grid, st); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ host side
@@ -467,7 +526,9 @@ int fsk_geometry(const acq_fsk_config* c, FskGeometry* g) {
     g->max_seg = lags > 0 ? (lags + g->V - 1) / g->V : 0;
     g->max_front_seg = (c->max_block_len + g->vf - 1) / g->vf;
     const int64_t T = c->num_tags;
-    g->bytes = c->max_block_len * 8 + std::max<int64_t>(g->max_seg, 1) * M * 8 + 2 * T * M * 8 + T * c->num_bits * 9 +
+    const int64_t slots = std::max<int64_t>((g->max_seg + 1) / 2, 1);
+    g->bytes = c->max_block_len * 8 + 2 * slots * M * 8 + std::min<int64_t>(T * slots, kFskMaxGrid) * M * 8 +
+               2 * T * M * 8 + T * c->num_bits * 9 +
                kFrontN * 8 * 3 + M * 8 + g->Msub * 8 + T * (8 + 4 + 2 * int64_t(sizeof(acq_fsk_detection)));
     return ACQ_OK;
 }
@@ -531,6 +592,9 @@ struct acq_fsk_plan_s {
     float* d_u = nullptr;               // [max_block_len] u
     float2* d_zp = nullptr;             // [slots][M] packed segment pairs of d
     float2* d_X = nullptr;              // [slots][M] their spectra
+    float2* d_scratch = nullptr;        // [correlation workgroups][M]
+    double* d_partial = nullptr;        // [T][parts][sums] refinement partial sums
+    int corr_grid = 0;
     float2* d_rootsM = nullptr;
     float2* d_rootsSub = nullptr;
     float2* d_b1tab = nullptr;
@@ -544,6 +608,8 @@ struct acq_fsk_plan_s {
     int32_t* d_count = nullptr;
     acq_fsk_detection* h_out = nullptr;     // pinned [T]
     int32_t* h_count = nullptr;             // pinned [1]
+    bool profiling = false;
+    hipEvent_t ev[ACQ_FSK_NUM_KERNELS][2] = {};
 };
 
 namespace {
@@ -561,9 +627,24 @@ hipError_t dalloc(T** p, size_t count) {
     return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count ? count : 1));
 }
 
+// Event pair around one launch when profiling is on.
+struct FskTimer {
+    acq_fsk_plan_s* p;
+    int id;
+    FskTimer(acq_fsk_plan_s* plan, int kernel) : p(plan), id(kernel) {
+        if (p->profiling) (void)hipEventRecord(p->ev[id][0], p->stream);
+    }
+    ~FskTimer() {
+        if (p->profiling) (void)hipEventRecord(p->ev[id][1], p->stream);
+    }
+};
+
 void free_fsk(acq_fsk_plan_s* p) {
     if (!p) return;
-    void* dev[] = {p->d_G1, p->d_G0, p->d_rootsF, p->d_bits, p->d_bitcyc, p->d_tmpl, p->d_bank, p->d_d, p->d_u, p->d_zp, p->d_X,
+    for (auto& pair : p->ev)
+        for (hipEvent_t e : pair)
+            if (e) (void)hipEventDestroy(e);
+    void* dev[] = {p->d_G1, p->d_G0, p->d_rootsF, p->d_bits, p->d_bitcyc, p->d_tmpl, p->d_bank, p->d_d, p->d_u, p->d_zp, p->d_X, p->d_scratch, p->d_partial,
                    p->d_rootsM, p->d_rootsSub, p->d_b1tab, p->d_zero, p->d_tdescs, p->d_tcounts, p->d_keys,
                    p->d_dets, p->d_out, p->d_found, p->d_count};
     for (void* d : dev)
@@ -639,6 +720,8 @@ int build_fsk(acq_fsk_plan_s* p, const acq_fsk_config* cfg) {
     FSK_HIP(dalloc(&p->d_u, size_t(c.max_block_len)));
     FSK_HIP(dalloc(&p->d_zp, slots * M));
     FSK_HIP(dalloc(&p->d_X, slots * M));
+    p->corr_grid = int(std::min<size_t>(T * slots, size_t(acq::kFskMaxGrid)));
+    FSK_HIP(dalloc(&p->d_scratch, size_t(p->corr_grid) * M));
     FSK_HIP(dalloc(&p->d_rootsM, M));
     FSK_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
     const std::vector<float> b1 = g.log2_sub == 14 ? acq::fft14_b1_table() : std::vector<float>(2, 0.f);
@@ -647,6 +730,7 @@ int build_fsk(acq_fsk_plan_s* p, const acq_fsk_config* cfg) {
     FSK_HIP(dalloc(&p->d_tdescs, T));
     FSK_HIP(dalloc(&p->d_tcounts, 2));
     FSK_HIP(dalloc(&p->d_keys, T));
+    FSK_HIP(dalloc(&p->d_partial, T * size_t(acq::kFskParts) * size_t(acq::kFskSums)));
     FSK_HIP(dalloc(&p->d_dets, T));
     FSK_HIP(dalloc(&p->d_out, T));
     FSK_HIP(dalloc(&p->d_found, T));
@@ -807,7 +891,10 @@ int enqueue_fsk_search(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, float* d
     const acq::FskGeometry& g = p->g;
     const int T = p->cfg.num_tags;
     hipStream_t st = p->stream;
-    FSK_HIP(launch_front(p, iq, n, false, nullptr));
+    {
+        FskTimer kt(p, ACQ_FSK_KERNEL_FRONT);
+        FSK_HIP(launch_front(p, iq, n, false, nullptr));
+    }
     const int64_t lags = n - g.nt + 1;
     const int nseg = int((lags + g.V - 1) / g.V);
     const int nslots = (nseg + 1) / 2;
@@ -823,7 +910,10 @@ int enqueue_fsk_search(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, float* d
     bt.one.nseg = nslots;
     bt.one.tag = -1;
     const acq::FwdArgs fa = fwd_args(p, bt, p->d_X, g.M);
-    FSK_HIP(acq::launch_forward(fa, nslots * g.P, nslots, g.log2_sub, ACQ_FP32, st));
+    {
+        FskTimer kt(p, ACQ_FSK_KERNEL_FORWARD);
+        FSK_HIP(acq::launch_forward(fa, nslots * g.P, nslots, g.log2_sub, ACQ_FP32, st));
+    }
     FSK_HIP(acq::launch_fill_u64(p->d_keys, T, st));
     acq::FskCorrArgs ca{};
     ca.X = p->d_X;
@@ -839,19 +929,40 @@ int enqueue_fsk_search(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, float* d
     ca.Msub = int(g.Msub);
     ca.P = g.P;
     ca.T = T;
-    ca.tile = std::min(T, acq::kFskTile);
-    ca.ntiles = (T + ca.tile - 1) / ca.tile;
+    ca.scratch = p->d_scratch;
     ca.nseg = nseg;
     ca.nslots = nslots;
-    const int64_t total = int64_t(ca.ntiles) * nslots * g.P;
-    const int grid = int((total + acq::kXcds - 1) / acq::kXcds) * acq::kXcds;
-    FSK_HIP(acq::launch_fsk_correlate(ca, grid, g.log2_sub, st));
+    const int grid = int(std::min<int64_t>(int64_t(T) * nslots, p->corr_grid));
+    {
+        FskTimer kt(p, ACQ_FSK_KERNEL_CORRELATE);
+        FSK_HIP(acq::launch_fsk_correlate(ca, grid, g.log2_sub, st));
+    }
     return ACQ_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+int acq_fsk_set_profiling(acq_fsk_plan_t p, int on) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (on && !p->ev[0][0])
+        for (auto& pair : p->ev)
+            for (hipEvent_t& e : pair) FSK_HIP(hipEventCreate(&e));
+    p->profiling = on != 0;
+    return ACQ_OK;
+}
+
+int acq_fsk_last_kernel_times(acq_fsk_plan_t p, double* ms, int32_t n) {
+    if (!p || !ms || n < ACQ_FSK_NUM_KERNELS) return acq::fail(ACQ_ERR_INVALID_ARG, "bad arguments");
+    if (!p->profiling) return acq::fail(ACQ_ERR_INVALID_ARG, "profiling is off");
+    for (int k = 0; k < ACQ_FSK_NUM_KERNELS; ++k) {
+        float t = 0.f;
+        FSK_HIP(hipEventElapsedTime(&t, p->ev[k][0], p->ev[k][1]));
+        ms[k] = t;
+    }
+    return ACQ_OK;
+}
 
 int acq_fsk_xcorr(acq_fsk_plan_t p, const int16_t* iq, int64_t n, float* out) {
     int rc = check_iq(p, iq, n);
@@ -894,9 +1005,15 @@ int acq_fsk_detect(acq_fsk_plan_t p, const int16_t* iq, int64_t n, acq_fsk_detec
     ra.tstride = g.M;
     ra.lags = lags;
     ra.theta = p->cfg.threshold;
-    hipLaunchKernelGGL(acq::k_fsk_refine, dim3(unsigned(T)), dim3(256), 0, st, ra);
-    FSK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(acq::k_fsk_compact, dim3(1), dim3(64), 0, st, p->d_dets, p->d_found, T, p->d_out, p->d_count);
+    ra.partial = p->d_partial;
+    {
+        FskTimer kt(p, ACQ_FSK_KERNEL_REFINE);
+        hipLaunchKernelGGL(acq::k_fsk_refine_sums, dim3(unsigned(T) * acq::kFskParts), dim3(256), 0, st, ra);
+        FSK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(acq::k_fsk_refine_final, dim3(unsigned((T + 63) / 64)), dim3(64), 0, st, ra, T);
+        FSK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(acq::k_fsk_compact, dim3(1), dim3(1024), 0, st, p->d_dets, p->d_found, T, p->d_out, p->d_count);
     FSK_HIP(hipGetLastError());
     FSK_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FSK_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_fsk_detection) * size_t(T), hipMemcpyDeviceToHost, st));

@@ -128,6 +128,14 @@ class FskPlan:
                                        ctypes.byref(nf)), "acq_fsk_detect")
         return nf.value
 
+    def set_profiling(self, on: bool):
+        check(self._lib.acq_fsk_set_profiling(self._h, 1 if on else 0), "acq_fsk_set_profiling")
+
+    def last_kernel_times(self) -> dict:
+        ms = (ctypes.c_double * 4)()
+        check(self._lib.acq_fsk_last_kernel_times(self._h, ms, 4), "acq_fsk_last_kernel_times")
+        return dict(zip(("front", "forward", "correlate", "refine"), list(ms)))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.acq_fsk_release(self._h)

@@ -19,15 +19,17 @@ import os
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2005_10445_amd", "csrc")
 # the correlation kernel and everything it includes from the library
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_10445_amd", "csrc", f)
-                  for f in ("correlate.hip", "device_common.h", "device_fft.h", "fft14.h", "storage.h", "kernels.h")]
+KERNEL_SOURCES = ("correlate.hip", "device_common.h", "device_fft.h", "fft14.h", "storage.h", "kernels.h")
+# the FSK pipeline's kernels
+FSK_SOURCES = ("fsk.hip", "device_common.h", "device_fft.h", "fft14.h", "storage.h", "kernels.h")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
+    for name in sources:
+        with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -61,7 +63,7 @@ def mean_counter(d: str, kernel_substr: str, counter: str) -> float:
     return sum(vals) / len(vals)
 
 
-def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_bytes, cmd):
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_bytes, cmd, sources=KERNEL_SOURCES):
     copy_name = "copyBuffer"
     f_copy = mean_counter(copy_fetch_dir, copy_name, "FETCH_SIZE")
     w_copy = mean_counter(copy_write_dir, copy_name, "WRITE_SIZE")
@@ -76,17 +78,18 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_b
         "fetch_scale_bytes_per_kib": f_scale, "write_scale_bytes_per_kib": w_scale,
         "bytes_read_per_launch": f_k * f_scale, "bytes_written_per_launch": w_k * w_scale,
         "bytes_per_launch": f_k * f_scale + w_k * w_scale,
-        "kernel_source_hash": kernel_source_hash(),
+        "kernel_source_hash": kernel_source_hash(sources),
+        "kernel_sources": list(sources),
         "command": cmd,
     }
 
 
-def trace_summary(trace_dir: str, cmd: str, top: int = 12) -> str:
+def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCES) -> str:
     path = _find(trace_dir, "kernel_stats.csv")
     with open(path) as f:
         rows = list(csv.DictReader(f))
     lines = [f"# rocprofv3 kernel trace summary", f"# command: {cmd}",
-             f"# kernel source hash: {kernel_source_hash()}", "",
+             f"# kernel source hash: {kernel_source_hash(sources)} ({', '.join(sources)})", "",
              f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
     rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
     for r in rows[:top]:
@@ -104,6 +107,7 @@ def main(argv=None):
     t.add_argument("trace_dir")
     t.add_argument("out")
     t.add_argument("--cmd", required=True)
+    t.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
@@ -113,13 +117,14 @@ def main(argv=None):
     c.add_argument("--kernel", default="k_correlate")
     c.add_argument("--copy-bytes", type=int, default=256 << 20)
     c.add_argument("--cmd", required=True)
+    c.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
     a = ap.parse_args(argv)
     if a.what == "trace":
         with open(a.out, "w") as f:
-            f.write(trace_summary(a.trace_dir, a.cmd))
+            f.write(trace_summary(a.trace_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES))
     else:
         res = traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir, a.kernel,
-                      a.copy_bytes, a.cmd)
+                      a.copy_bytes, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES)
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)
             f.write("\n")
