@@ -184,6 +184,8 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     bytes += T * C;                           // chips
     bytes += K * (4 + 8);                     // rotations, frequencies
     bytes += int64_t(G.max_blocks) * (T * (8 + 4 + 2 * int64_t(sizeof(acq_detection))) + 2048 + 64) + 4096;
+    const int64_t wmax = cfg->refine_radius <= 1 ? 5 : 2 * kMaxRefineRadius + 3;
+    bytes += int64_t(G.max_blocks) * T * (16 * 3 * wmax * 8 + 8);   // refinement partial sums, centres
     G.device_bytes = bytes;
     *g = std::move(G);
     clear_error();

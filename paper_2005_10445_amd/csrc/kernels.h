@@ -98,8 +98,15 @@ struct RefineArgs {
     int32_t* found;             // [block][T] 1 if detected
     int64_t L;
     int32_t T, C, K, spc, log2_spc, M, radius, exact;
-    int32_t track;              // 1: one workgroup per block, for the block's own tag
+    int32_t track;              // 1: one candidate per block, the block's own tag
+    double* partial;            // [items][kRefineParts][3 * window] FP64 partial sums
+    int64_t* center;            // [items] window centre of the second round (-1: none)
 };
+
+// Refinement work: items = blocks * (tracking ? 1 : T); each item's sums run in
+// kRefineParts workgroups, each writing 3 * WMAX doubles (WMAX = 5 for radius
+// <= 1, else 2 * kMaxRefineRadius + 3).
+constexpr int kRefineParts = 16;
 
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);
 // exps[b] = round(log2(sqrt(M * Pxhat_b))): the 16-bit storage prescale of block b

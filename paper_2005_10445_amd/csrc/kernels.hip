@@ -198,150 +198,203 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
 // ------------------------------------------------------------------ refine
 constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
 
-// grid = max_blocks * T: one workgroup of NT threads per (block, tag).  WMAX
-// bounds the window W = 2R + 3 (5 for the FP32 plans' R = 1, with 1024
-// threads; kMaxWin with 256 threads, whose register budget holds the 3*WMAX
-// FP64 accumulators).  The mix exp(-j 2 pi m_k i / M) is an FP64 table entry at
-// (m_k i) mod M (M a power of two, so the reduction is exact).
-template <int WMAX, int NT>
-__global__ __launch_bounds__(NT) void k_refine(RefineArgs a) {
-    constexpr int NW = NT / 64;
-    const int per = a.track ? 1 : a.T;
-    const int bi = int(blockIdx.x) / per;
-    if (bi >= a.blocks.nblocks()) return;
-    const BlockDesc d = a.blocks.get(bi);
-    const int tag = a.track ? d.tag : int(blockIdx.x) % per;
-    if (tag < 0 || tag >= a.T) return;
-    const size_t slot = size_t(bi) * a.T + tag;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    __shared__ double s_px;
-    __shared__ double red[NW][WMAX][3];
-    __shared__ long long s_center;
-    __shared__ int s_again;
+// FP64 refinement of each (block, tag) peak key, in two rounds of two
+// kernels.  Round 0 takes the window of W = 2R + 3 lags centred on the key's
+// lag; k_refine_sums adds, in kRefineParts workgroups per item, the re- and
+// im-sums of the mixed samples against the tag's replica and the sample
+// energy under it for every lag of the window; k_refine_decide (one thread
+// per item) adds the parts in order, re-maximises over the inner 2R+1 lags and
+// either writes the detection or, when the maximum sits on the inner edge,
+// records a re-centred window for round 1, which repeats both steps once.
+// The mix exp(-j 2 pi m_k i / M) is an FP64 table entry at (m_k i) mod M (M a
+// power of two, so the reduction is exact), or the exact bin's FP64 phase.
+struct RefineItem {
+    int bi, tag;
+    size_t slot;
+    BlockDesc d;
+};
 
-    const unsigned long long key = d.lags > 0 ? a.keys[slot] : 0ull;
-    if (key == 0ull) {               // no valid lag was searched for this tag
-        if (t == 0) a.found[slot] = 0;
-        return;
-    }
-    if (t == 0) s_px = block_mean_power(a.parts + size_t(bi) * kPowerParts, d.n);
+__device__ __forceinline__ bool refine_item(const RefineArgs& a, int item, RefineItem* r) {
+    const int per = a.track ? 1 : a.T;
+    r->bi = item / per;
+    if (r->bi >= a.blocks.nblocks()) return false;
+    r->d = a.blocks.get(r->bi);
+    r->tag = a.track ? r->d.tag : item % per;
+    if (r->tag < 0 || r->tag >= a.T) return false;
+    r->slot = size_t(r->bi) * a.T + r->tag;
+    return true;
+}
+
+constexpr int kRefineChipsLds = 4096;     // chips of one part staged in LDS (else read from global)
+
+template <int WMAX>
+__global__ __launch_bounds__(256) void k_refine_sums(RefineArgs a, int round) {
+    constexpr int NT = 256, NW = NT / 64;
+    const int item = int(blockIdx.x) / kRefineParts, part = int(blockIdx.x) % kRefineParts;
+    RefineItem it;
+    if (!refine_item(a, item, &it)) return;
+    const BlockDesc& d = it.d;
+    const unsigned long long key = d.lags > 0 ? a.keys[it.slot] : 0ull;
+    if (key == 0ull) return;
     const unsigned idx = ~unsigned(key & 0xffffffffull);
     const int k = int(idx % unsigned(a.K));
-    int64_t center = int64_t(idx / unsigned(a.K));
+    const int64_t center = round == 0 ? int64_t(idx / unsigned(a.K)) : a.center[item];
+    if (center < 0) return;
     const int R = a.radius;
     const int W = 2 * R + 3;
-    if (W > WMAX) return;            // the launcher picks WMAX >= W
+    if (W > WMAX) return;                    // the launcher picks WMAX >= W
+    const int t = int(threadIdx.x), lane = t & 63, wave = t >> 6;
+    const int64_t lam0 = center - R - 1;
+    // samples of the window inside the block, split into parts
+    const int64_t e_lo = lam0 < 0 ? -lam0 : 0;
+    const int64_t e_hi = min(int64_t(a.L) + W - 1, d.n - lam0);
+    const int64_t ch = (e_hi - e_lo + kRefineParts - 1) / kRefineParts;
+    const int64_t p0 = e_lo + int64_t(part) * ch, p1 = min(e_hi, p0 + ch);
+    // the part's chips (replica samples e - w, w < W) in LDS when they fit
+    __shared__ int8_t s_chips[kRefineChipsLds];
+    const int8_t* chips = a.chips + size_t(it.tag) * size_t(a.C);
+    const int64_t c0 = max(int64_t(0), (p0 - W + 1) >> a.log2_spc);
+    const int64_t c1 = min(int64_t(a.C), ((p1 - 1) >> a.log2_spc) + 1);
+    const bool lds = c1 - c0 <= kRefineChipsLds;
+    if (lds) {
+        for (int64_t q = c0 + t; q < c1; q += NT) s_chips[q - c0] = chips[q];
+    }
+    __syncthreads();
     const int64_t mrot = a.rot_signed[k];
     const int64_t mmask = int64_t(a.M) - 1;
     const double fk = a.cyc[k];
-    const int8_t* ch = a.chips + size_t(tag) * size_t(a.C);
-
-    for (int pass = 0; pass < 2; ++pass) {
-        const int64_t lam0 = center - R - 1;
-        double cr[WMAX], ci[WMAX], en[WMAX];
+    double cr[WMAX], ci[WMAX], en[WMAX];
 #pragma unroll
-        for (int w = 0; w < WMAX; ++w) cr[w] = ci[w] = en[w] = 0.0;
-        for (int64_t e = t; e < a.L + W - 1; e += NT) {
-            const int64_t i = lam0 + e;
-            if (i < 0 || i >= d.n) continue;
-            const float2 xv = d.x[i];
-            const double xr = xv.x, xi = xv.y;
-            double2 cs;
-            if (a.exact) {                          // exp(-j 2 pi (f_k / Fs) i), phase reduced in FP64
-                double ph = fk * double(i);
-                ph -= floor(ph);
-                sincospi(2.0 * ph, &cs.y, &cs.x);
-            } else {
-                cs = a.roots64[(mrot * i) & mmask];
-            }
-            const double mr = xr * cs.x + xi * cs.y;      // x * exp(-j 2 pi m i / M)
-            const double mi = xi * cs.x - xr * cs.y;
-            const double pw = xr * xr + xi * xi;
-#pragma unroll
-            for (int w = 0; w < WMAX; ++w) {
-                const int64_t nn = e - w;
-                if (w < W && nn >= 0 && nn < a.L) {
-                    const double sg = double(ch[nn >> a.log2_spc]);
-                    cr[w] += mr * sg;
-                    ci[w] += mi * sg;
-                    en[w] += pw;
-                }
-            }
+    for (int w = 0; w < WMAX; ++w) cr[w] = ci[w] = en[w] = 0.0;
+    for (int64_t e = p0 + t; e < p1; e += NT) {
+        const int64_t i = lam0 + e;
+        const float2 xv = d.x[i];
+        const double xr = xv.x, xi = xv.y;
+        double2 cs;
+        if (a.exact) {                          // exp(-j 2 pi (f_k / Fs) i), phase reduced in FP64
+            double ph = fk * double(i);
+            ph -= floor(ph);
+            sincospi(2.0 * ph, &cs.y, &cs.x);
+        } else {
+            cs = a.roots64[(mrot * i) & mmask];
         }
+        const double mr = xr * cs.x + xi * cs.y;      // x * exp(-j 2 pi m i / M)
+        const double mi = xi * cs.x - xr * cs.y;
+        const double pw = xr * xr + xi * xi;
 #pragma unroll
         for (int w = 0; w < WMAX; ++w) {
-            const double r0 = wave_sum(cr[w]), r1 = wave_sum(ci[w]), r2 = wave_sum(en[w]);
-            if (lane == 0) {
-                red[wave][w][0] = r0;
-                red[wave][w][1] = r1;
-                red[wave][w][2] = r2;
+            const int64_t nn = e - w;
+            if (w < W && nn >= 0 && nn < a.L) {
+                const int64_t c = nn >> a.log2_spc;
+                const double sg = double(lds ? s_chips[c - c0] : chips[c]);
+                cr[w] += mr * sg;
+                ci[w] += mi * sg;
+                en[w] += pw;
             }
         }
-        __syncthreads();
-        if (t == 0) {
-            double P[WMAX], E[WMAX];
-            for (int w = 0; w < W; ++w) {
-                double re = 0.0, im = 0.0, en2 = 0.0;
-                for (int q = 0; q < NW; ++q) {
-                    re += red[q][w][0];
-                    im += red[q][w][1];
-                    en2 += red[q][w][2];
-                }
-                E[w] = en2;
-                const int64_t lam = lam0 + w;
-                P[w] = (lam >= 0 && lam < d.lags) ? re * re + im * im : -1.0;
-            }
-            int wb = R + 1;
-            for (int w = 1; w <= W - 2; ++w)
-                if (P[w] > P[wb] || (P[w] == P[wb] && w < wb)) wb = w;
-            const int64_t lam = lam0 + wb;
-            const bool hit = (wb == 1 && lam > 0) || (wb == W - 2 && lam < d.lags - 1);
-            if (hit && pass == 0) {
-                s_center = lam;
-                s_again = 1;
-            } else {
-                s_again = 0;
-                unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
-                const double p0 = P[wb];
-                const double pm = P[wb - 1] < 0.0 ? 0.0 : P[wb - 1];
-                const double pp = P[wb + 1] < 0.0 ? 0.0 : P[wb + 1];
-                double delta = 0.0;
-                if (lam == 0 || lam == d.lags - 1) {
-                    flags |= ACQ_DET_NEAR_EDGE;
-                } else {
-                    const double den = pm - 2.0 * p0 + pp;
-                    if (den < 0.0) {
-                        delta = 0.5 * (pm - pp) / den;
-                        delta = delta > 0.5 ? 0.5 : (delta < -0.5 ? -0.5 : delta);
-                    }
-                }
-                const double px = s_px;
-                const double z = px > 0.0 ? p0 / (double(a.L) * px) : 0.0;
-                acq_detection r;
-                r.tag = tag;
-                r.bin = k;
-                r.lag = lam;
-                r.toa_samples = double(lam) + delta;
-                r.freq_hz = a.freqs[k];
-                r.peak_power = p0;
-                r.z = z;
-                r.energy = E[wb];
-                r.block_power = px;
-                // relative power and SNR (Section 3 step 8's power and SNR sums)
-                const double Ld = double(a.L);
-                r.power = p0 / (Ld * Ld);
-                const double s2 = (E[wb] - p0 / Ld) / Ld;
-                r.snr = s2 > 0.0 ? r.power / s2 : __builtin_huge_val();
-                r.block = bi;
-                r.flags = flags;
-                a.dets[slot] = r;
-                a.found[slot] = z >= d.theta ? 1 : 0;
-            }
-        }
-        __syncthreads();
-        if (!s_again) break;
-        center = s_center;
     }
+    __shared__ double red[NW][3 * WMAX];
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) {
+        const double r0 = wave_sum(cr[w]), r1 = wave_sum(ci[w]), r2 = wave_sum(en[w]);
+        if (lane == 0) {
+            red[wave][3 * w] = r0;
+            red[wave][3 * w + 1] = r1;
+            red[wave][3 * w + 2] = r2;
+        }
+    }
+    __syncthreads();
+    if (t < 3 * W) {
+        double v = 0.0;
+        for (int q = 0; q < NW; ++q) v += red[q][t];
+        a.partial[(size_t(item) * kRefineParts + part) * size_t(3 * WMAX) + t] = v;
+    }
+}
+
+// One wave per item: lane s < 3W adds sum s over the parts in order, lane 0
+// decides.
+template <int WMAX>
+__global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int round) {
+    const int item = int(blockIdx.x);
+    RefineItem it;
+    if (!refine_item(a, item, &it)) return;
+    const BlockDesc& d = it.d;
+    const int t = int(threadIdx.x);
+    const unsigned long long key = d.lags > 0 ? a.keys[it.slot] : 0ull;
+    if (key == 0ull) {                       // no valid lag was searched for this tag
+        if (round == 0 && t == 0) {
+            a.found[it.slot] = 0;
+            a.center[item] = -1;
+        }
+        return;
+    }
+    const unsigned idx = ~unsigned(key & 0xffffffffull);
+    const int k = int(idx % unsigned(a.K));
+    const int64_t center = round == 0 ? int64_t(idx / unsigned(a.K)) : a.center[item];
+    if (center < 0) return;
+    const int R = a.radius;
+    const int W = 2 * R + 3;
+    if (W > WMAX) return;
+    __shared__ double sums[3 * WMAX];
+    if (t < 3 * W) {
+        double v = 0.0;
+        for (int q = 0; q < kRefineParts; ++q) v += a.partial[(size_t(item) * kRefineParts + q) * size_t(3 * WMAX) + t];
+        sums[t] = v;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    const int64_t lam0 = center - R - 1;
+    double P[WMAX], E[WMAX];
+    for (int w = 0; w < W; ++w) {
+        const double re = sums[3 * w], im = sums[3 * w + 1];
+        E[w] = sums[3 * w + 2];
+        const int64_t lam = lam0 + w;
+        P[w] = (lam >= 0 && lam < d.lags) ? re * re + im * im : -1.0;
+    }
+    int wb = R + 1;
+    for (int w = 1; w <= W - 2; ++w)
+        if (P[w] > P[wb] || (P[w] == P[wb] && w < wb)) wb = w;
+    const int64_t lam = lam0 + wb;
+    const bool hit = (wb == 1 && lam > 0) || (wb == W - 2 && lam < d.lags - 1);
+    if (round == 0) {
+        a.center[item] = hit ? lam : -1;
+        if (hit) return;                     // round 1 re-centres on lam
+    }
+    unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
+    const double p0 = P[wb];
+    const double pm = P[wb - 1] < 0.0 ? 0.0 : P[wb - 1];
+    const double pp = P[wb + 1] < 0.0 ? 0.0 : P[wb + 1];
+    double delta = 0.0;
+    if (lam == 0 || lam == d.lags - 1) {
+        flags |= ACQ_DET_NEAR_EDGE;
+    } else {
+        const double den = pm - 2.0 * p0 + pp;
+        if (den < 0.0) {
+            delta = 0.5 * (pm - pp) / den;
+            delta = delta > 0.5 ? 0.5 : (delta < -0.5 ? -0.5 : delta);
+        }
+    }
+    const double px = block_mean_power(a.parts + size_t(it.bi) * kPowerParts, d.n);
+    const double z = px > 0.0 ? p0 / (double(a.L) * px) : 0.0;
+    acq_detection r;
+    r.tag = it.tag;
+    r.bin = k;
+    r.lag = lam;
+    r.toa_samples = double(lam) + delta;
+    r.freq_hz = a.freqs[k];
+    r.peak_power = p0;
+    r.z = z;
+    r.energy = E[wb];
+    r.block_power = px;
+    // relative power and SNR (Section 3 step 8's power and SNR sums)
+    const double Ld = double(a.L);
+    r.power = p0 / (Ld * Ld);
+    const double s2 = (E[wb] - p0 / Ld) / Ld;
+    r.snr = s2 > 0.0 ? r.power / s2 : __builtin_huge_val();
+    r.block = it.bi;
+    r.flags = flags;
+    a.dets[it.slot] = r;
+    a.found[it.slot] = z >= d.theta ? 1 : 0;
 }
 
 // Detections in (block, tag) order.  One workgroup: each thread takes a
@@ -480,13 +533,20 @@ hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const floa
 }
 
 hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
-    if (a.radius < 0 || a.radius > kMaxRefineRadius || (a.M & (a.M - 1)) || (1 << a.log2_spc) != a.spc)
+    if (a.radius < 0 || a.radius > kMaxRefineRadius || (a.M & (a.M - 1)) || (1 << a.log2_spc) != a.spc ||
+        !a.partial || !a.center)
         return hipErrorInvalidValue;
-    const unsigned grid = unsigned(max_blocks) * unsigned(a.track ? 1 : a.T);
-    if (a.radius <= 1)
-        hipLaunchKernelGGL((k_refine<5, 1024>), dim3(grid), dim3(1024), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_refine<kMaxWin, 256>), dim3(grid), dim3(256), 0, st, a);
+    const int items = max_blocks * (a.track ? 1 : a.T);
+    const dim3 sgrid(unsigned(items) * kRefineParts), dgrid{unsigned(items)};
+    for (int round = 0; round < 2; ++round) {
+        if (a.radius <= 1) {
+            hipLaunchKernelGGL((k_refine_sums<5>), sgrid, dim3(256), 0, st, a, round);
+            hipLaunchKernelGGL((k_refine_decide<5>), dgrid, dim3(64), 0, st, a, round);
+        } else {
+            hipLaunchKernelGGL((k_refine_sums<kMaxWin>), sgrid, dim3(256), 0, st, a, round);
+            hipLaunchKernelGGL((k_refine_decide<kMaxWin>), dgrid, dim3(64), 0, st, a, round);
+        }
+    }
     return hipGetLastError();
 }
 

@@ -59,6 +59,8 @@ struct acq_plan_s {
     acq_detection* d_dets = nullptr;    // [blocks][T]
     acq_detection* d_out = nullptr;     // [blocks][T]
     int32_t* d_found = nullptr;         // [blocks][T]
+    double* d_refpart = nullptr;        // refinement partial sums [blocks * T][parts][3 * window]
+    int64_t* d_refcenter = nullptr;     // [blocks * T] refinement re-centring
     int32_t* d_count = nullptr;         // [1]
     int* d_counters = nullptr;          // [kXcds]
     BlockDesc* d_descs = nullptr;       // [blocks]
@@ -120,7 +122,7 @@ void free_plan(acq_plan_s* p) {
     void* dev[] = {p->d_X, p->d_Xh, p->d_cls, p->d_cls_cyc, p->d_cyc, p->d_bank, p->d_wts, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
                    p->d_chips,
                    p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_exps, p->d_dets,
-                   p->d_out, p->d_found, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
+                   p->d_out, p->d_found, p->d_refpart, p->d_refcenter, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     void* host[] = {p->h_out, p->h_count, p->h_descs, p->h_counts, p->h_iota};
@@ -165,6 +167,9 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_dets, B * T));
     ACQ_HIP(dalloc(&p->d_out, B * T));
     ACQ_HIP(dalloc(&p->d_found, B * T));
+    const size_t wmax = c.refine_radius <= 1 ? 5 : size_t(2 * acq::kMaxRefineRadius + 3);
+    ACQ_HIP(dalloc(&p->d_refpart, B * T * size_t(acq::kRefineParts) * 3 * wmax));
+    ACQ_HIP(dalloc(&p->d_refcenter, B * T));
     ACQ_HIP(dalloc(&p->d_count, 1));
     ACQ_HIP(dalloc(&p->d_counters, size_t(acq::kXcds)));
     ACQ_HIP(dalloc(&p->d_descs, B));
@@ -349,6 +354,8 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ra.M = int(g.M);
     ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
     ra.track = track ? 1 : 0;
+    ra.partial = p->d_refpart;
+    ra.center = p->d_refcenter;
     {
         KernelTimer kt(p, ACQ_KERNEL_REFINE);
         ACQ_HIP(acq::launch_refine(ra, nb_grid, st));
