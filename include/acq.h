@@ -460,7 +460,7 @@ typedef struct acq_fsk_config {
     int32_t        num_bits;        /* >= 1                                               */
     int32_t        fft_len;         /* correlation segment M: power of two in
                                        [2^10, 2^17], > template length; 0 = choice      */
-    int32_t        reserved;        /* 0                                                  */
+    int32_t        max_track_tasks; /* tasks per acq_fsk_track call; 0 -> 16             */
 } acq_fsk_config;
 
 /* One tag's result.  The template length is n_t = num_bits * mf_len +
@@ -474,6 +474,8 @@ typedef struct acq_fsk_detection {
     double   q;              /* sum_{i<n_t} d[i+j*]^2                                  */
     double   p;              /* p_c = sum_{i<n_t} d^(c)[i] u[i+j*]                     */
     double   z;              /* w_c^2 / (q E_c), E_c = sum d^(c)^2                     */
+    int32_t  block;          /* task index of acq_fsk_track, else 0                    */
+    int32_t  reserved;
 } acq_fsk_detection;
 
 /* Geometry of an FSK configuration (no GPU involved): template length, the
@@ -518,6 +520,25 @@ int acq_fsk_last_kernel_times(acq_fsk_plan_t plan, double* ms, int32_t n);
  * tag at every lag into device float out[num_tags][n - n_t + 1] (n >= n_t).
  * Synchronous. */
 int acq_fsk_xcorr(acq_fsk_plan_t plan, const int16_t* iq, int64_t n, float* out);
+
+/* FSK tracking tasks (Section 2: one packet of one tag in a block a little
+ * longer than the packet, around its predicted arrival): each task names a
+ * device int16 block iq[n][2] and a tag; steps 1-8 run on every block (its
+ * own LO phase from its first sample) against that tag's template only, all
+ * tasks in one launch sequence.  1 <= ntasks <= max_track_tasks; the tasks'
+ * total length is at most max_block_len; n < n_t gives no result.  One result
+ * per task whose z reaches the threshold, in task order, block = task index.
+ * Errors as acq_fsk_detect; ACQ_ERR_INVALID_ARG for a tag outside
+ * [0, num_tags).  Synchronous. */
+typedef struct acq_fsk_task {
+    const int16_t* iq;
+    int64_t        n;
+    int32_t        tag;
+    int32_t        reserved;      /* 0 */
+} acq_fsk_task;
+
+int acq_fsk_track(acq_fsk_plan_t plan, const acq_fsk_task* tasks, int32_t ntasks, acq_fsk_detection* out,
+                  int32_t capacity, int32_t* n_found);
 
 /* Steps 1-8 on a device int16 block iq[n][2] (n <= max_block_len): one
  * result per tag whose z reaches the threshold, in tag order, to the host

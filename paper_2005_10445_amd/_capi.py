@@ -34,7 +34,7 @@ EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect"
             "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
             "acq_detect_learned", "acq_detect_batch_learned", "acq_fsk_plan_geometry", "acq_fsk_plan",
             "acq_fsk_release", "acq_fsk_demod", "acq_fsk_template", "acq_fsk_xcorr", "acq_fsk_detect",
-            "acq_fsk_set_profiling", "acq_fsk_last_kernel_times", "acq_strerror",
+            "acq_fsk_track", "acq_fsk_set_profiling", "acq_fsk_last_kernel_times", "acq_strerror",
             "acq_last_error")
 ACQ_SYNTH_MAX_TX = 32
 ACQ_FALLBACK_NONE, ACQ_FALLBACK_FRACTION, ACQ_FALLBACK_FLOOR = 0, 1, 2
@@ -123,13 +123,19 @@ class AcqFskConfig(ctypes.Structure):
                 ("bp_taps", ctypes.POINTER(ctypes.c_float)), ("bits", ctypes.POINTER(ctypes.c_uint8)),
                 ("max_block_len", ctypes.c_int64), ("bp_len", ctypes.c_int32), ("mf_len", ctypes.c_int32),
                 ("num_tags", ctypes.c_int32), ("num_bits", ctypes.c_int32), ("fft_len", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("max_track_tasks", ctypes.c_int32)]
 
 
 class AcqFskDetection(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_int32), ("flags", ctypes.c_uint32), ("lag", ctypes.c_int64),
                 ("toa_samples", ctypes.c_double), ("xcorr", ctypes.c_double), ("q", ctypes.c_double),
-                ("p", ctypes.c_double), ("z", ctypes.c_double)]
+                ("p", ctypes.c_double), ("z", ctypes.c_double), ("block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class AcqFskTask(ctypes.Structure):
+    _fields_ = [("iq", ctypes.c_void_p), ("n", ctypes.c_int64), ("tag", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class AcqFskGeometry(ctypes.Structure):
@@ -239,10 +245,12 @@ def lib(path: str = LIB_PATH):
     L.acq_fsk_template.argtypes = [vp, i32, vp]
     L.acq_fsk_detect.argtypes = [vp, vp, i64, P(AcqFskDetection), i32, P(i32)]
     L.acq_fsk_xcorr.argtypes = [vp, vp, i64, vp]
+    L.acq_fsk_track.argtypes = [vp, P(AcqFskTask), i32, P(AcqFskDetection), i32, P(i32)]
     L.acq_fsk_set_profiling.argtypes = [vp, ctypes.c_int]
     L.acq_fsk_last_kernel_times.argtypes = [vp, P(ctypes.c_double), i32]
     for name in ("acq_fsk_plan_geometry", "acq_fsk_plan", "acq_fsk_release", "acq_fsk_demod", "acq_fsk_template",
-                 "acq_fsk_xcorr", "acq_fsk_detect", "acq_fsk_set_profiling", "acq_fsk_last_kernel_times"):
+                 "acq_fsk_xcorr", "acq_fsk_detect", "acq_fsk_track", "acq_fsk_set_profiling",
+                 "acq_fsk_last_kernel_times"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
                  "acq_track_batch", "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",

@@ -51,38 +51,82 @@ constexpr int kFrontLog = 12;                 // composed filters applied on 409
 constexpr int kFrontN = 1 << kFrontLog;
 constexpr int kFskMaxGrid = 512;              // workgroups (and scratch slots) of the correlation
 
+// One block of an FSK call: the searching window (tag -1: every template) or
+// one tracking task (its tag only).  Front-end segments and packed segment
+// pairs are numbered globally over the call's blocks.
+struct FskTask {
+    const int16_t* iq;          // device [n][2]
+    int64_t n;                  // samples
+    int64_t lags;               // n - n_t + 1 (<= 0: nothing to search)
+    int64_t zoff;               // offset of the block's d and u in the plan's arrays
+    int32_t tag;                // -1 searching; else the tracked template
+    int32_t fseg0, nfseg;       // front-end segments
+    int32_t slot0, nslots;      // packed segment pairs
+    int32_t nseg;               // overlap-save segments of the correlation
+};
+
+struct FskTasks {
+    const FskTask* t;           // device [count]
+    int32_t count;
+    int32_t track;              // 1: tracking tasks (one template each)
+};
+
+// block holding global index g of the field (fseg0 or slot0), by binary search
+template <int32_t FskTask::*FIRST>
+__device__ __forceinline__ int fsk_task_of(const FskTasks& tt, int g) {
+    int lo = 0, hi = tt.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tt.t[mid].*FIRST <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 struct FrontArgs {
-    const int16_t* iq;          // block: [n_in][2]
+    FskTasks tasks;             // blocks (block mode)
     const uint8_t* bits;        // replica: [T][nbits]
     const double* bit_cyc;      // replica: [T][nbits] carrier phase (cycles, in [0,1)) at each bit start
     const float2* G1;           // [kFrontN] DFT(h_BP * h_1) / kFrontN
     const float2* G0;
     const float2* roots;        // [kFrontN] exp(+j 2 pi m / kFrontN)
     float2* out;                // replica: [T][out_stride] (d, 0)
-    float* out_d;               // block: d[n_out]
-    float* out_u;               // block: u[n_out]
-    int64_t n_in, n_out, out_stride;
+    float* out_d;               // block: d at the block's zoff
+    float* out_u;               // block: u at the block's zoff
+    int64_t n_in, n_out, out_stride;     // replica mode
     double lo_cyc;              // f_LO / Fs
     double f1_cyc, f0_cyc;      // tones, cycles per sample
-    int32_t nbits, sps, lg, vf, nseg, replica;
+    int32_t nbits, sps, lg, vf, nseg, replica;   // nseg: segments per replica
 };
 
-// One workgroup per (template, segment): outputs s*vf .. s*vf + vf - 1 of the
-// causal convolution with the composed filters, from inputs s*vf - (lg-1) ..
+// One workgroup per (template, segment) of the replicas or per global segment
+// of the blocks: outputs s*vf .. s*vf + vf - 1 of the causal convolution with
+// the composed filters, from inputs s*vf - (lg-1) ..
 __global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
     using E = StockhamEngine<kFrontLog>;
     __shared__ float2 lds[E::LDS];
     E eng;
     eng.init(a.roots, nullptr);
-    const int s = int(blockIdx.x) % a.nseg;
-    const int tag = int(blockIdx.x) / a.nseg;
+    int s, tag = 0;
+    const int16_t* iq = nullptr;
+    int64_t n_in = a.n_in, n_out = a.n_out, zoff = 0;
+    if (a.replica) {
+        s = int(blockIdx.x) % a.nseg;
+        tag = int(blockIdx.x) / a.nseg;
+    } else {
+        const int b = fsk_task_of<&FskTask::fseg0>(a.tasks, int(blockIdx.x));
+        const FskTask tk = a.tasks.t[b];
+        s = int(blockIdx.x) - tk.fseg0;
+        iq = tk.iq;
+        n_in = n_out = tk.n;
+        zoff = tk.zoff;
+    }
     const int64_t base = int64_t(s) * a.vf - (a.lg - 1);
     float2 x[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         const int64_t p = base + eng.in_index(m);
         float2 v = make_float2(0.f, 0.f);
-        if (p >= 0 && p < a.n_in) {
+        if (p >= 0 && p < n_in) {
             double cyc;
             if (a.replica) {
                 const int64_t b = p / a.sps;
@@ -90,7 +134,7 @@ __global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
                 cyc = a.bit_cyc[bi] + (a.bits[bi] ? a.f1_cyc : a.f0_cyc) * double(p - b * a.sps);
                 v = make_float2(1.f, 0.f);
             } else {
-                v = make_float2(float(a.iq[2 * p]), float(a.iq[2 * p + 1]));
+                v = make_float2(float(iq[2 * p]), float(iq[2 * p + 1]));
                 cyc = -a.lo_cyc * double(p);
             }
             cyc -= floor(cyc);                              // exact phase reduction in FP64
@@ -116,30 +160,33 @@ __global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
     for (int m = 0; m < 16; ++m) {
         const int idx = eng.in_index(m);                     // natural order in and out
         const int64_t o = int64_t(s) * a.vf + idx - (a.lg - 1);
-        if (idx >= a.lg - 1 && o < a.n_out) {
+        if (idx >= a.lg - 1 && o < n_out) {
             const float a0 = sqrtf(fmaf(w[m].x, w[m].x, w[m].y * w[m].y));
             const float sum = a1[m] + a0, dif = a1[m] - a0;
             const float d = sum > 0.f ? dif / sum : 0.f;
             if (a.replica) {
                 a.out[size_t(tag) * size_t(a.out_stride) + size_t(o)] = make_float2(d, 0.f);
             } else {
-                a.out_d[o] = d;
-                a.out_u[o] = dif;
+                a.out_d[zoff + o] = d;
+                a.out_u[zoff + o] = dif;
             }
         }
     }
 }
 
-// zp[g][i] = (d[2g V + i], d[(2g+1) V + i]), zero past the block or past the
-// last segment; grid covers slots * M.
-__global__ void k_fsk_pack(const float* __restrict__ d, int64_t n, int64_t V, int64_t M, int nseg, int nslots,
+// zp[s][i] = (d[2g V + i], d[(2g+1) V + i]) of slot s = slot0 + g of its
+// block, zero past the block or past its last segment; grid covers slots * M.
+__global__ void k_fsk_pack(FskTasks tt, const float* __restrict__ d, int64_t V, int64_t M, int nslots,
                            float2* __restrict__ zp) {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= int64_t(nslots) * M) return;
-    const int64_t g = k / M, i = k - g * M;
+    const int64_t s = k / M, i = k - s * M;
+    const FskTask tk = tt.t[fsk_task_of<&FskTask::slot0>(tt, int(s))];
+    const int64_t g = s - tk.slot0;
+    const float* db = d + tk.zoff;
     const int64_t p0 = 2 * g * V + i, p1 = (2 * g + 1) * V + i;
-    const float re = p0 < n ? d[p0] : 0.f;
-    const float im = (2 * g + 1 < nseg && p1 < n) ? d[p1] : 0.f;
+    const float re = p0 < tk.n ? db[p0] : 0.f;
+    const float im = (2 * g + 1 < tk.nseg && p1 < tk.n) ? db[p1] : 0.f;
     zp[k] = make_float2(re, im);
 }
 
@@ -164,14 +211,17 @@ struct FskCorrArgs {
     const float2* rootsSub;     // [Msub]
     const float2* b1tab;
     float2* scratch;            // [gridDim.x][M]: the P first-step outputs of the workgroup's item
-    unsigned long long* keys;   // [T]
-    float* dump;                // optional [T][lags]: c at every lag (test hook)
-    int64_t V, lags;
-    int32_t M, Msub, P, T, nseg, nslots;
+    unsigned long long* keys;   // [T] (searching) or [tasks] (tracking)
+    float* dump;                // optional [T][lags]: c at every lag (test hook, searching)
+    FskTasks tasks;
+    int64_t V;
+    int32_t M, Msub, P, T, nslots;      // nslots: slots of the call
 };
 
-// Work item (tag t, slot g), items t * nslots + g taken with a stride of the
-// grid: segments 2g (real part) and 2g+1 (imaginary part) against template t.
+// Work item (template t, slot s), taken with a stride of the grid: searching,
+// items t * nslots + s for every template; tracking, item s for its task's
+// template.  Slot s holds segments 2g (real part) and 2g+1 (imaginary part)
+// of its block, g = s - slot0.
 //   first step, once per item: for each i' < Msub, the spectrum products
 //     Y_a = Z_g[i' + Msub a] conj(D_t[i' + Msub a]) / M, a < P, and
 //     G_rho[i'] = exp(+j 2 pi i' rho / M) sum_a Y_a exp(+j 2 pi a rho / P),
@@ -205,10 +255,15 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     const int mmask = a.M - 1;
     float2* G = a.scratch + size_t(blockIdx.x) * size_t(a.M);
-    const int items = a.T * a.nslots;
+    const int items = a.tasks.track ? a.nslots : a.T * a.nslots;
     for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
-        const int tag = it / a.nslots, j = it - tag * a.nslots;
-        const float2* Xj = a.X + size_t(j) * size_t(a.M);
+        const int slot = a.tasks.track ? it : it % a.nslots;
+        const int bi = fsk_task_of<&FskTask::slot0>(a.tasks, slot);
+        const FskTask tk = a.tasks.t[bi];
+        const int tag = a.tasks.track ? tk.tag : it / a.nslots;
+        const int kidx = a.tasks.track ? bi : tag;          // key of the result
+        const int j = slot - tk.slot0;
+        const float2* Xj = a.X + size_t(slot) * size_t(a.M);
         const float2* B = a.bank + size_t(tag) * size_t(a.M);
         // first step: P outputs per i' from P products; the P-point DFT uses
         // constant eighth roots of unity, so each i' issues its 2P product
@@ -240,7 +295,7 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 sbeg[h] = int64_t(2 * j + h) * a.V;
-                const int64_t v64 = (2 * j + h < a.nseg) ? (a.lags - sbeg[h] < a.V ? a.lags - sbeg[h] : a.V) : 0;
+                const int64_t v64 = (2 * j + h < tk.nseg) ? (tk.lags - sbeg[h] < a.V ? tk.lags - sbeg[h] : a.V) : 0;
                 const int vlim = int(v64);
                 ulim[h] = vlim > rho ? (vlim - rho + PP - 1) / PP : 0;
             }
@@ -270,7 +325,7 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
                         if constexpr (DUMP) {
                             if (ob + off < ulim[h]) {
                                 const int64_t tau = sbeg[h] + int64_t(PP) * (ob + off) + rho;
-                                a.dump[size_t(tag) * size_t(a.lags) + size_t(tau)] = cv;
+                                a.dump[size_t(tag) * size_t(tk.lags) + size_t(tau)] = cv;
                             }
                         }
                         if (omax + off >= ulim[h] && ob + off >= ulim[h]) pv = -1.0f;
@@ -293,23 +348,39 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
         if (threadIdx.x == 0) {
             unsigned long long m = 0ull;
             for (int q = 0; q < NW; ++q) m = red[q] > m ? red[q] : m;
-            if (m) atomicMax(&a.keys[tag], m);
+            if (m) atomicMax(&a.keys[kidx], m);
         }
         __syncthreads();                     // red[], scratch and LDS are reused by the next item
     }
 }
 
+// Results: searching, one item per template of the window; tracking, one item
+// per task (its template).
 struct FskRefineArgs {
-    const float* d;             // [n]
-    const float* u;             // [n]
+    const float* d;             // the blocks' d (each at its zoff)
+    const float* u;
     const float2* tmpl;         // [T][tstride] (d^(c), 0)
-    const unsigned long long* keys;
-    double* partial;            // [T][kFskParts][kFskSums]
-    acq_fsk_detection* dets;    // [T]
-    int32_t* found;             // [T]
-    int64_t n, nt, tstride, lags;
+    const unsigned long long* keys;     // [items]
+    double* partial;            // [items][kFskParts][kFskSums]
+    acq_fsk_detection* dets;    // [items]
+    int32_t* found;             // [items]
+    FskTasks tasks;
+    int64_t nt, tstride;
     double theta;
 };
+
+struct FskItem {
+    int tag, block;
+    FskTask tk;
+};
+
+__device__ __forceinline__ FskItem fsk_item(const FskRefineArgs& a, int item) {
+    FskItem r;
+    r.block = a.tasks.track ? item : 0;
+    r.tk = a.tasks.t[r.block];
+    r.tag = a.tasks.track ? r.tk.tag : item;
+    return r;
+}
 
 // FP64 sums over lags tau*-3 .. tau*+3 around the peak key: w_c, p_c and q at
 // each lag and E_c, enough for the re-maximisation over +/-1 and one
@@ -321,17 +392,20 @@ constexpr int kFskSums = 3 * kFskWin + 1;
 
 __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
     constexpr int NT = 256, NW = NT / 64;
-    const int tag = int(blockIdx.x) / kFskParts, part = int(blockIdx.x) % kFskParts;
+    const int item = int(blockIdx.x) / kFskParts, part = int(blockIdx.x) % kFskParts;
+    const FskItem fi = fsk_item(a, item);
     const int t = int(threadIdx.x), lane = t & 63, wave = t >> 6;
     __shared__ double red[NW][kFskSums];
-    double* out = a.partial + (size_t(tag) * kFskParts + part) * kFskSums;
-    const unsigned long long key = a.lags > 0 ? a.keys[tag] : 0ull;
+    double* out = a.partial + (size_t(item) * kFskParts + part) * kFskSums;
+    const unsigned long long key = fi.tk.lags > 0 ? a.keys[item] : 0ull;
     if (key == 0ull) {
         if (t < kFskSums) out[t] = 0.0;
         return;
     }
     const int64_t lam0 = int64_t(~unsigned(key & 0xffffffffull)) - kFskWin / 2;
-    const float2* dc = a.tmpl + size_t(tag) * size_t(a.tstride);
+    const float2* dc = a.tmpl + size_t(fi.tag) * size_t(a.tstride);
+    const float* db = a.d + fi.tk.zoff;
+    const float* ub = a.u + fi.tk.zoff;
     const int64_t ch = (a.nt + kFskParts - 1) / kFskParts;
     const int64_t i0 = int64_t(part) * ch, i1 = min(a.nt, i0 + ch);
     double wv[kFskWin], pv[kFskWin], qv[kFskWin], ec = 0.0;
@@ -343,8 +417,8 @@ __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
 #pragma unroll
         for (int w = 0; w < kFskWin; ++w) {
             const int64_t k = lam0 + w + i;
-            if (k >= 0 && k < a.n) {
-                const double zd = a.d[k], zu = a.u[k];
+            if (k >= 0 && k < fi.tk.n) {
+                const double zd = db[k], zu = ub[k];
                 wv[w] += c * zd;
                 pv[w] += c * zu;
                 qv[w] += zd * zd;
@@ -372,23 +446,25 @@ __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
 
 // One thread per tag: parts summed in order, re-maximisation of |w_c| over
 // +/-1 lag (one re-centring when it lands on the edge), parabola, results.
-__global__ void k_fsk_refine_final(FskRefineArgs a, int T) {
-    const int tag = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
-    if (tag >= T) return;
-    const unsigned long long key = a.lags > 0 ? a.keys[tag] : 0ull;
+__global__ void k_fsk_refine_final(FskRefineArgs a, int items) {
+    const int item = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
+    if (item >= items) return;
+    const FskItem fi = fsk_item(a, item);
+    const int64_t lags = fi.tk.lags;
+    const unsigned long long key = lags > 0 ? a.keys[item] : 0ull;
     if (key == 0ull) {
-        a.found[tag] = 0;
+        a.found[item] = 0;
         return;
     }
     double S[kFskSums];
     for (int k = 0; k < kFskSums; ++k) S[k] = 0.0;
     for (int p = 0; p < kFskParts; ++p)
-        for (int k = 0; k < kFskSums; ++k) S[k] += a.partial[(size_t(tag) * kFskParts + p) * kFskSums + k];
+        for (int k = 0; k < kFskSums; ++k) S[k] += a.partial[(size_t(item) * kFskParts + p) * kFskSums + k];
     const int64_t lam0 = int64_t(~unsigned(key & 0xffffffffull)) - kFskWin / 2;
     double A[kFskWin];
     for (int w = 0; w < kFskWin; ++w) {
         const int64_t lam = lam0 + w;
-        A[w] = (lam >= 0 && lam < a.lags) ? fabs(S[3 * w]) : -1.0;
+        A[w] = (lam >= 0 && lam < lags) ? fabs(S[3 * w]) : -1.0;
     }
     const double Ec = S[3 * kFskWin];
     int c = kFskWin / 2;
@@ -398,7 +474,7 @@ __global__ void k_fsk_refine_final(FskRefineArgs a, int T) {
         for (int w = c - 1; w <= c + 1; ++w)
             if (A[w] > A[wb] || (A[w] == A[wb] && w < wb)) wb = w;
         const int64_t lam = lam0 + wb;
-        hit = (wb == c - 1 && lam > 0) || (wb == c + 1 && lam < a.lags - 1);
+        hit = (wb == c - 1 && lam > 0) || (wb == c + 1 && lam < lags - 1);
         c = wb;
         if (!hit) break;
     }
@@ -408,7 +484,7 @@ __global__ void k_fsk_refine_final(FskRefineArgs a, int T) {
     const double pm = A[c - 1] < 0.0 ? 0.0 : A[c - 1];
     const double pp = A[c + 1] < 0.0 ? 0.0 : A[c + 1];
     double delta = 0.0;
-    if (lam == 0 || lam == a.lags - 1) {
+    if (lam == 0 || lam == lags - 1) {
         flags |= ACQ_DET_NEAR_EDGE;
     } else {
         const double den = pm - 2.0 * p0 + pp;
@@ -418,7 +494,9 @@ __global__ void k_fsk_refine_final(FskRefineArgs a, int T) {
         }
     }
     acq_fsk_detection r;
-    r.tag = tag;
+    r.tag = fi.tag;
+    r.block = fi.block;
+    r.reserved = 0;
     r.flags = flags;
     r.lag = lam;
     r.toa_samples = double(lam) + delta;
@@ -426,8 +504,8 @@ __global__ void k_fsk_refine_final(FskRefineArgs a, int T) {
     r.p = S[3 * c + 1];
     r.q = S[3 * c + 2];
     r.z = (r.q > 0.0 && Ec > 0.0) ? r.xcorr * r.xcorr / (r.q * Ec) : 0.0;
-    a.dets[tag] = r;
-    a.found[tag] = (a.theta <= 0.0 || r.z >= a.theta) ? 1 : 0;
+    a.dets[item] = r;
+    a.found[item] = (a.theta <= 0.0 || r.z >= a.theta) ? 1 : 0;
 }
 
 // Results in tag order: one workgroup of 1024 threads, runs of tags per
@@ -491,7 +569,10 @@ hipError_t launch_fsk_correlate(const FskCorrArgs& a, int grid, int log2_sub, hi
 // ------------------------------------------------------------------ host side
 struct FskGeometry {
     int64_t lg = 0, nt = 0, M = 0, Msub = 0, V = 0, vf = 0, max_seg = 0, max_front_seg = 0, bytes = 0;
+    int64_t slots = 0;          // packed segment pairs a call may use
     int P = 1, log2_sub = 0;
+    int max_tasks = 16;         // tracking tasks per call
+    int items = 0;              // results per call: max(templates, tasks)
 };
 
 int fsk_geometry(const acq_fsk_config* c, FskGeometry* g) {
@@ -525,10 +606,17 @@ int fsk_geometry(const acq_fsk_config* c, FskGeometry* g) {
     const int64_t lags = c->max_block_len - g->nt + 1;
     g->max_seg = lags > 0 ? (lags + g->V - 1) / g->V : 0;
     g->max_front_seg = (c->max_block_len + g->vf - 1) / g->vf;
+    if (c->max_track_tasks < 0 || c->max_track_tasks > 65536)
+        return fail(ACQ_ERR_INVALID_ARG, "max_track_tasks outside [0, 65536]");
+    g->max_tasks = c->max_track_tasks > 0 ? c->max_track_tasks : 16;
+    // a searching window uses ceil(max_seg / 2) pairs; tracking blocks of total
+    // length <= max_block_len use at most max_block_len / (2V) + one per task
+    g->slots = (g->max_seg + 1) / 2 + g->max_tasks + 1;
+    g->items = std::max<int>(c->num_tags, g->max_tasks);
     const int64_t T = c->num_tags;
-    const int64_t slots = std::max<int64_t>((g->max_seg + 1) / 2, 1);
+    const int64_t slots = g->slots;
     g->bytes = c->max_block_len * 8 + 2 * slots * M * 8 + std::min<int64_t>(T * slots, kFskMaxGrid) * M * 8 +
-               2 * T * M * 8 + T * c->num_bits * 9 +
+               2 * T * M * 8 + T * c->num_bits * 9 + int64_t(g->items) * (kFskParts * kFskSums * 8 + 64) +
                kFrontN * 8 * 3 + M * 8 + g->Msub * 8 + T * (8 + 4 + 2 * int64_t(sizeof(acq_fsk_detection)));
     return ACQ_OK;
 }
@@ -606,7 +694,9 @@ struct acq_fsk_plan_s {
     acq_fsk_detection* d_out = nullptr;
     int32_t* d_found = nullptr;
     int32_t* d_count = nullptr;
-    acq_fsk_detection* h_out = nullptr;     // pinned [T]
+    acq::FskTask* d_tasks = nullptr;        // [max_tasks] blocks of a call
+    acq::FskTask* h_tasks = nullptr;        // pinned [max_tasks]
+    acq_fsk_detection* h_out = nullptr;     // pinned [items]
     int32_t* h_count = nullptr;             // pinned [1]
     bool profiling = false;
     hipEvent_t ev[ACQ_FSK_NUM_KERNELS][2] = {};
@@ -650,15 +740,18 @@ void free_fsk(acq_fsk_plan_s* p) {
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->h_out) (void)hipHostFree(p->h_out);
+    if (p->h_tasks) (void)hipHostFree(p->h_tasks);
+    if (p->d_tasks) (void)hipFree(p->d_tasks);
     if (p->h_count) (void)hipHostFree(p->h_count);
     delete p;
 }
 
-hipError_t launch_front(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, bool replica, float2* out) {
-    // block mode writes the plan's d and u arrays; replica mode writes `out`
+// Replica mode writes `out` ([T][M]); block mode processes the call's blocks
+// (device task table, fsegs front-end segments in all) into the plan's d, u.
+hipError_t launch_front(acq_fsk_plan_s* p, const acq::FskTasks& tasks, int fsegs, bool replica, float2* out) {
     const acq_fsk_config& c = p->cfg;
     acq::FrontArgs a{};
-    a.iq = iq;
+    a.tasks = tasks;
     a.bits = p->d_bits;
     a.bit_cyc = p->d_bitcyc;
     a.G1 = p->d_G1;
@@ -667,9 +760,9 @@ hipError_t launch_front(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, bool re
     a.out = out;
     a.out_d = p->d_d;
     a.out_u = p->d_u;
-    a.n_in = replica ? int64_t(c.num_bits) * c.mf_len : n;
-    a.n_out = replica ? p->g.nt : n;
-    a.out_stride = replica ? p->g.M : 0;
+    a.n_in = int64_t(c.num_bits) * c.mf_len;
+    a.n_out = p->g.nt;
+    a.out_stride = p->g.M;
     a.lo_cyc = c.lo_hz / c.sample_rate_hz;
     a.f1_cyc = c.f1_hz / c.sample_rate_hz;
     a.f0_cyc = c.f0_hz / c.sample_rate_hz;
@@ -679,8 +772,8 @@ hipError_t launch_front(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, bool re
     a.vf = int(p->g.vf);
     a.nseg = int((a.n_out + p->g.vf - 1) / p->g.vf);
     a.replica = replica ? 1 : 0;
-    if (a.nseg <= 0) return hipSuccess;
-    const unsigned grid = unsigned(a.nseg) * unsigned(replica ? c.num_tags : 1);
+    const unsigned grid = replica ? unsigned(a.nseg) * unsigned(c.num_tags) : unsigned(fsegs);
+    if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(acq::k_fsk_front, dim3(grid), dim3(256), 0, p->stream, a);
     return hipGetLastError();
 }
@@ -715,12 +808,15 @@ int build_fsk(acq_fsk_plan_s* p, const acq_fsk_config* cfg) {
     FSK_HIP(dalloc(&p->d_bitcyc, T * NB));
     FSK_HIP(dalloc(&p->d_tmpl, T * M));
     FSK_HIP(dalloc(&p->d_bank, T * M));
-    const size_t slots = size_t(std::max<int64_t>((g.max_seg + 1) / 2, 1));
+    const size_t slots = size_t(g.slots);
+    const size_t items = size_t(g.items);
     FSK_HIP(dalloc(&p->d_d, size_t(c.max_block_len)));
     FSK_HIP(dalloc(&p->d_u, size_t(c.max_block_len)));
     FSK_HIP(dalloc(&p->d_zp, slots * M));
     FSK_HIP(dalloc(&p->d_X, slots * M));
     p->corr_grid = int(std::min<size_t>(T * slots, size_t(acq::kFskMaxGrid)));
+    FSK_HIP(dalloc(&p->d_tasks, size_t(g.max_tasks)));
+    FSK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_tasks), sizeof(acq::FskTask) * size_t(g.max_tasks)));
     FSK_HIP(dalloc(&p->d_scratch, size_t(p->corr_grid) * M));
     FSK_HIP(dalloc(&p->d_rootsM, M));
     FSK_HIP(dalloc(&p->d_rootsSub, size_t(g.Msub)));
@@ -729,13 +825,13 @@ int build_fsk(acq_fsk_plan_s* p, const acq_fsk_config* cfg) {
     FSK_HIP(dalloc(&p->d_zero, 1));
     FSK_HIP(dalloc(&p->d_tdescs, T));
     FSK_HIP(dalloc(&p->d_tcounts, 2));
-    FSK_HIP(dalloc(&p->d_keys, T));
-    FSK_HIP(dalloc(&p->d_partial, T * size_t(acq::kFskParts) * size_t(acq::kFskSums)));
-    FSK_HIP(dalloc(&p->d_dets, T));
-    FSK_HIP(dalloc(&p->d_out, T));
-    FSK_HIP(dalloc(&p->d_found, T));
+    FSK_HIP(dalloc(&p->d_keys, items));
+    FSK_HIP(dalloc(&p->d_partial, items * size_t(acq::kFskParts) * size_t(acq::kFskSums)));
+    FSK_HIP(dalloc(&p->d_dets, items));
+    FSK_HIP(dalloc(&p->d_out, items));
+    FSK_HIP(dalloc(&p->d_found, items));
     FSK_HIP(dalloc(&p->d_count, 1));
-    FSK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_fsk_detection) * T));
+    FSK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_fsk_detection) * items));
     FSK_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t)));
 
     // tables: composed filter spectra, unit roots, replica bit phases (FP64 on the host)
@@ -772,7 +868,7 @@ int build_fsk(acq_fsk_plan_s* p, const acq_fsk_config* cfg) {
     const int64_t tcount = int64_t(T * M);
     hipLaunchKernelGGL(acq::k_fsk_fill, dim3(unsigned((tcount + 255) / 256)), dim3(256), 0, st, p->d_tmpl, tcount);
     FSK_HIP(hipGetLastError());
-    FSK_HIP(launch_front(p, nullptr, 0, true, p->d_tmpl));
+    FSK_HIP(launch_front(p, acq::FskTasks{}, 0, true, p->d_tmpl));
     std::vector<BlockDesc> descs(T);
     for (size_t t = 0; t < T; ++t) {
         BlockDesc d{};
@@ -863,7 +959,14 @@ int acq_fsk_demod(acq_fsk_plan_t p, const int16_t* iq, int64_t n, float* d, floa
     if (rc != ACQ_OK) return rc;
     if (n > 0 && (!d || !u)) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
     if (n == 0) return ACQ_OK;
-    FSK_HIP(launch_front(p, iq, n, false, nullptr));
+    acq::FskTask& tk = p->h_tasks[0];
+    tk = acq::FskTask{};
+    tk.iq = iq;
+    tk.n = n;
+    tk.tag = -1;
+    tk.nfseg = int((n + p->g.vf - 1) / p->g.vf);
+    FSK_HIP(hipMemcpyAsync(p->d_tasks, p->h_tasks, sizeof(acq::FskTask), hipMemcpyHostToDevice, p->stream));
+    FSK_HIP(launch_front(p, acq::FskTasks{p->d_tasks, 1, 0}, tk.nfseg, false, nullptr));
     FSK_HIP(hipMemcpyAsync(d, p->d_d, sizeof(float) * size_t(n), hipMemcpyDeviceToDevice, p->stream));
     FSK_HIP(hipMemcpyAsync(u, p->d_u, sizeof(float) * size_t(n), hipMemcpyDeviceToDevice, p->stream));
     FSK_HIP(hipStreamSynchronize(p->stream));
@@ -885,36 +988,57 @@ int acq_fsk_template(acq_fsk_plan_t p, int32_t tag, float* out) {
 
 namespace {
 
-// Steps 1-7 and the peak keys on the plan's stream; dump (device [T][lags]) gets
-// Re c for every lag when not null.
-int enqueue_fsk_search(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, float* dump) {
+// Steps 1-7 and the peak keys on the plan's stream for the call's blocks,
+// staged in h_tasks[0 .. nblocks) with iq, n and tag set (tag -1: searching,
+// one block).  Fills the rest of each entry, copies the table and launches.
+// dump (device [T][lags], searching only) gets c at every lag.  Returns the
+// result items (templates or tasks) in *items.
+int enqueue_fsk(acq_fsk_plan_s* p, int nblocks, bool track, float* dump, int* items) {
     const acq::FskGeometry& g = p->g;
     const int T = p->cfg.num_tags;
     hipStream_t st = p->stream;
+    int64_t zoff = 0;
+    int fsegs = 0, slots = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        acq::FskTask& tk = p->h_tasks[b];
+        tk.lags = tk.n - g.nt + 1;
+        tk.zoff = zoff;
+        tk.nseg = tk.lags > 0 ? int((tk.lags + g.V - 1) / g.V) : 0;
+        tk.nslots = (tk.nseg + 1) / 2;
+        tk.nfseg = tk.lags > 0 ? int((tk.n + g.vf - 1) / g.vf) : 0;
+        tk.fseg0 = fsegs;
+        tk.slot0 = slots;
+        zoff += tk.n;
+        fsegs += tk.nfseg;
+        slots += tk.nslots;
+    }
+    if (zoff > p->cfg.max_block_len) return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "blocks longer than max_block_len in all");
+    if (slots > g.slots) return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "blocks need more segments than the plan holds");
+    *items = track ? nblocks : T;
+    FSK_HIP(hipMemcpyAsync(p->d_tasks, p->h_tasks, sizeof(acq::FskTask) * size_t(nblocks), hipMemcpyHostToDevice, st));
+    acq::FskTasks tt{p->d_tasks, nblocks, track ? 1 : 0};
+    FSK_HIP(acq::launch_fill_u64(p->d_keys, *items, st));
+    if (slots == 0) return ACQ_OK;
     {
         FskTimer kt(p, ACQ_FSK_KERNEL_FRONT);
-        FSK_HIP(launch_front(p, iq, n, false, nullptr));
+        FSK_HIP(launch_front(p, tt, fsegs, false, nullptr));
     }
-    const int64_t lags = n - g.nt + 1;
-    const int nseg = int((lags + g.V - 1) / g.V);
-    const int nslots = (nseg + 1) / 2;
-    const int64_t packed = int64_t(nslots) * g.M;
-    hipLaunchKernelGGL(acq::k_fsk_pack, dim3(unsigned((packed + 255) / 256)), dim3(256), 0, st, p->d_d, n, g.V, g.M,
-                       nseg, nslots, p->d_zp);
+    const int64_t packed = int64_t(slots) * g.M;
+    hipLaunchKernelGGL(acq::k_fsk_pack, dim3(unsigned((packed + 255) / 256)), dim3(256), 0, st, tt, p->d_d, g.V, g.M,
+                       slots, p->d_zp);
     FSK_HIP(hipGetLastError());
     BlockTable bt{};
     bt.one.x = p->d_zp;
     bt.one.n = packed;
     bt.one.lags = packed;
     bt.one.seg0 = 0;
-    bt.one.nseg = nslots;
+    bt.one.nseg = slots;
     bt.one.tag = -1;
     const acq::FwdArgs fa = fwd_args(p, bt, p->d_X, g.M);
     {
         FskTimer kt(p, ACQ_FSK_KERNEL_FORWARD);
-        FSK_HIP(acq::launch_forward(fa, nslots * g.P, nslots, g.log2_sub, ACQ_FP32, st));
+        FSK_HIP(acq::launch_forward(fa, slots * g.P, slots, g.log2_sub, ACQ_FP32, st));
     }
-    FSK_HIP(acq::launch_fill_u64(p->d_keys, T, st));
     acq::FskCorrArgs ca{};
     ca.X = p->d_X;
     ca.bank = p->d_bank;
@@ -923,20 +1047,59 @@ int enqueue_fsk_search(acq_fsk_plan_s* p, const int16_t* iq, int64_t n, float* d
     ca.b1tab = p->d_b1tab;
     ca.keys = p->d_keys;
     ca.dump = dump;
+    ca.tasks = tt;
     ca.V = g.V;
-    ca.lags = lags;
     ca.M = int(g.M);
     ca.Msub = int(g.Msub);
     ca.P = g.P;
     ca.T = T;
     ca.scratch = p->d_scratch;
-    ca.nseg = nseg;
-    ca.nslots = nslots;
-    const int grid = int(std::min<int64_t>(int64_t(T) * nslots, p->corr_grid));
+    ca.nslots = slots;
+    const int64_t work = track ? int64_t(slots) : int64_t(T) * slots;
+    const int grid = int(std::min<int64_t>(work, p->corr_grid));
     {
         FskTimer kt(p, ACQ_FSK_KERNEL_CORRELATE);
         FSK_HIP(acq::launch_fsk_correlate(ca, grid, g.log2_sub, st));
     }
+    return ACQ_OK;
+}
+
+// Step 8 for the call's result items, compaction and the copy to the host.
+int finish_fsk(acq_fsk_plan_s* p, int nblocks, bool track, int items, acq_fsk_detection* out, int32_t capacity,
+               int32_t* n_found) {
+    const acq::FskGeometry& g = p->g;
+    hipStream_t st = p->stream;
+    acq::FskRefineArgs ra{};
+    ra.d = p->d_d;
+    ra.u = p->d_u;
+    ra.tmpl = p->d_tmpl;
+    ra.keys = p->d_keys;
+    ra.partial = p->d_partial;
+    ra.dets = p->d_dets;
+    ra.found = p->d_found;
+    ra.tasks = acq::FskTasks{p->d_tasks, nblocks, track ? 1 : 0};
+    ra.nt = g.nt;
+    ra.tstride = g.M;
+    ra.theta = p->cfg.threshold;
+    {
+        FskTimer kt(p, ACQ_FSK_KERNEL_REFINE);
+        hipLaunchKernelGGL(acq::k_fsk_refine_sums, dim3(unsigned(items) * acq::kFskParts), dim3(256), 0, st, ra);
+        FSK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(acq::k_fsk_refine_final, dim3(unsigned((items + 63) / 64)), dim3(64), 0, st, ra, items);
+        FSK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(acq::k_fsk_compact, dim3(1), dim3(1024), 0, st, p->d_dets, p->d_found, items, p->d_out,
+                       p->d_count);
+    FSK_HIP(hipGetLastError());
+    FSK_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FSK_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_fsk_detection) * size_t(items), hipMemcpyDeviceToHost, st));
+    FSK_HIP(hipStreamSynchronize(st));
+    const int32_t found = *p->h_count;
+    *n_found = found;
+    const int32_t ncopy = found < capacity ? found : capacity;
+    if (ncopy > 0) std::memcpy(out, p->h_out, sizeof(acq_fsk_detection) * size_t(ncopy));
+    if (found > capacity) return acq::fail(ACQ_ERR_TRUNCATED, "more detections than capacity");
+    acq::clear_error();
     return ACQ_OK;
 }
 
@@ -969,7 +1132,12 @@ int acq_fsk_xcorr(acq_fsk_plan_t p, const int16_t* iq, int64_t n, float* out) {
     if (rc != ACQ_OK) return rc;
     if (n < p->g.nt) return acq::fail(ACQ_ERR_INVALID_ARG, "block shorter than a template");
     if (!out) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
-    rc = enqueue_fsk_search(p, iq, n, out);
+    p->h_tasks[0] = acq::FskTask{};
+    p->h_tasks[0].iq = iq;
+    p->h_tasks[0].n = n;
+    p->h_tasks[0].tag = -1;
+    int items = 0;
+    rc = enqueue_fsk(p, 1, false, out, &items);
     if (rc != ACQ_OK) return rc;
     FSK_HIP(hipStreamSynchronize(p->stream));
     acq::clear_error();
@@ -983,48 +1151,46 @@ int acq_fsk_detect(acq_fsk_plan_t p, const int16_t* iq, int64_t n, acq_fsk_detec
     if (!n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null n_found");
     if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
     *n_found = 0;
-    const acq::FskGeometry& g = p->g;
-    if (n < g.nt) {
+    if (n < p->g.nt) {
         acq::clear_error();
         return ACQ_OK;
     }
-    const int T = p->cfg.num_tags;
-    hipStream_t st = p->stream;
-    const int64_t lags = n - g.nt + 1;
-    rc = enqueue_fsk_search(p, iq, n, nullptr);
+    p->h_tasks[0] = acq::FskTask{};
+    p->h_tasks[0].iq = iq;
+    p->h_tasks[0].n = n;
+    p->h_tasks[0].tag = -1;
+    int items = 0;
+    rc = enqueue_fsk(p, 1, false, nullptr, &items);
     if (rc != ACQ_OK) return rc;
-    acq::FskRefineArgs ra{};
-    ra.d = p->d_d;
-    ra.u = p->d_u;
-    ra.tmpl = p->d_tmpl;
-    ra.keys = p->d_keys;
-    ra.dets = p->d_dets;
-    ra.found = p->d_found;
-    ra.n = n;
-    ra.nt = g.nt;
-    ra.tstride = g.M;
-    ra.lags = lags;
-    ra.theta = p->cfg.threshold;
-    ra.partial = p->d_partial;
-    {
-        FskTimer kt(p, ACQ_FSK_KERNEL_REFINE);
-        hipLaunchKernelGGL(acq::k_fsk_refine_sums, dim3(unsigned(T) * acq::kFskParts), dim3(256), 0, st, ra);
-        FSK_HIP(hipGetLastError());
-        hipLaunchKernelGGL(acq::k_fsk_refine_final, dim3(unsigned((T + 63) / 64)), dim3(64), 0, st, ra, T);
-        FSK_HIP(hipGetLastError());
+    return finish_fsk(p, 1, false, items, out, capacity, n_found);
+}
+
+int acq_fsk_track(acq_fsk_plan_t p, const acq_fsk_task* tasks, int32_t ntasks, acq_fsk_detection* out,
+                  int32_t capacity, int32_t* n_found) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (!tasks || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (ntasks < 1 || ntasks > p->g.max_tasks) return acq::fail(ACQ_ERR_INVALID_ARG, "ntasks outside [1, max_track_tasks]");
+    int64_t total = 0;
+    for (int32_t b = 0; b < ntasks; ++b) {
+        const int rc = check_iq(p, tasks[b].iq, tasks[b].n);
+        if (rc != ACQ_OK) return rc;
+        if (tasks[b].tag < 0 || tasks[b].tag >= p->cfg.num_tags)
+            return acq::fail(ACQ_ERR_INVALID_ARG, "task tag outside [0, num_tags)");
+        total += tasks[b].n;
     }
-    hipLaunchKernelGGL(acq::k_fsk_compact, dim3(1), dim3(1024), 0, st, p->d_dets, p->d_found, T, p->d_out, p->d_count);
-    FSK_HIP(hipGetLastError());
-    FSK_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    FSK_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_fsk_detection) * size_t(T), hipMemcpyDeviceToHost, st));
-    FSK_HIP(hipStreamSynchronize(st));
-    const int32_t found = *p->h_count;
-    *n_found = found;
-    const int32_t ncopy = found < capacity ? found : capacity;
-    if (ncopy > 0) std::memcpy(out, p->h_out, sizeof(acq_fsk_detection) * size_t(ncopy));
-    if (found > capacity) return acq::fail(ACQ_ERR_TRUNCATED, "more detections than capacity");
-    acq::clear_error();
-    return ACQ_OK;
+    if (total > p->cfg.max_block_len) return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "tasks longer than max_block_len in all");
+    *n_found = 0;
+    for (int32_t b = 0; b < ntasks; ++b) {
+        p->h_tasks[b] = acq::FskTask{};
+        p->h_tasks[b].iq = tasks[b].iq;
+        p->h_tasks[b].n = tasks[b].n;
+        p->h_tasks[b].tag = tasks[b].tag;
+    }
+    int items = 0;
+    const int rc = enqueue_fsk(p, ntasks, true, nullptr, &items);
+    if (rc != ACQ_OK) return rc;
+    return finish_fsk(p, ntasks, true, items, out, capacity, n_found);
 }
 
 }  // extern "C"

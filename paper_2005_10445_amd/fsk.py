@@ -25,9 +25,11 @@ class FskDetection:
     p: float
     z: float
     flags: int
+    block: int = 0
 
 
-def _config(bits, fs_hz, lo_hz, f1_hz, f0_hz, bp_taps, mf_len, max_block_len, fft_len=0, threshold=0.0):
+def _config(bits, fs_hz, lo_hz, f1_hz, f0_hz, bp_taps, mf_len, max_block_len, fft_len=0, threshold=0.0,
+            max_track_tasks=0):
     b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
     if b.ndim != 2:
         raise ValueError("bits must be [num_tags][num_bits]")
@@ -46,7 +48,7 @@ def _config(bits, fs_hz, lo_hz, f1_hz, f0_hz, bp_taps, mf_len, max_block_len, ff
     cfg.mf_len = int(mf_len)
     cfg.num_tags, cfg.num_bits = int(b.shape[0]), int(b.shape[1])
     cfg.fft_len = int(fft_len)
-    cfg.reserved = 0
+    cfg.max_track_tasks = int(max_track_tasks)
     return cfg, (b, t)
 
 
@@ -71,10 +73,13 @@ class FskPlan:
     """An FSK searching plan bound to one HIP stream (default: torch's current stream)."""
 
     def __init__(self, bits, fs_hz: float, lo_hz: float, f1_hz: float, f0_hz: float, bp_taps, mf_len: int,
-                 max_block_len: int, fft_len: int = 0, threshold: float = 0.0, stream=None):
+                 max_block_len: int, fft_len: int = 0, threshold: float = 0.0, max_track_tasks: int = 0,
+                 stream=None):
         import torch
         self._lib = _capi.lib()
-        cfg, keep = _config(bits, fs_hz, lo_hz, f1_hz, f0_hz, bp_taps, mf_len, max_block_len, fft_len, threshold)
+        cfg, keep = _config(bits, fs_hz, lo_hz, f1_hz, f0_hz, bp_taps, mf_len, max_block_len, fft_len, threshold,
+                            max_track_tasks)
+        self.max_track_tasks = int(max_track_tasks) if max_track_tasks > 0 else 16
         g = _capi.AcqFskGeometry()
         check(self._lib.acq_fsk_plan_geometry(ctypes.byref(cfg), ctypes.byref(g)), "acq_fsk_plan_geometry")
         self.geometry = {name: getattr(g, name) for name, _ in _capi.AcqFskGeometry._fields_}
@@ -118,8 +123,20 @@ class FskPlan:
         nf = ctypes.c_int32(0)
         check(self._lib.acq_fsk_detect(self._h, ctypes.c_void_p(ptr), n, self._out, self.num_tags,
                                        ctypes.byref(nf)), "acq_fsk_detect")
-        return [FskDetection(d.tag, d.lag, d.toa_samples, d.xcorr, d.q, d.p, d.z, d.flags)
+        return [FskDetection(d.tag, d.lag, d.toa_samples, d.xcorr, d.q, d.p, d.z, d.flags, d.block)
                 for d in self._out[:nf.value]]
+
+    def track(self, tasks) -> List[FskDetection]:
+        """acq_fsk_track over (int16 [n, 2] device tensor, tag) pairs; detection.block = task index."""
+        arr = (_capi.AcqFskTask * len(tasks))()
+        for i, (iq, tag) in enumerate(tasks):
+            ptr, n = _iq_ptr(iq)
+            arr[i] = _capi.AcqFskTask(ptr, n, int(tag), 0)
+        out = (_capi.AcqFskDetection * len(tasks))()
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_fsk_track(self._h, arr, len(tasks), out, len(tasks), ctypes.byref(nf)), "acq_fsk_track")
+        return [FskDetection(d.tag, d.lag, d.toa_samples, d.xcorr, d.q, d.p, d.z, d.flags, d.block)
+                for d in out[:nf.value]]
 
     def detect_raw(self, iq) -> int:
         ptr, n = _iq_ptr(iq)

@@ -26,7 +26,7 @@ def test_geometry():
 @pytest.mark.parametrize("over, status", [
     (dict(bp_taps=np.ones(1025)), -1), (dict(mf_len=0), -1), (dict(fs_hz=0.0), -1),
     (dict(max_block_len=0), -1), (dict(fft_len=3000), -7), (dict(fft_len=512), -7),
-    (dict(bits=np.zeros((1, 20000), np.uint8)), -7),
+    (dict(bits=np.zeros((1, 20000), np.uint8)), -7), (dict(max_track_tasks=-1), -1),
 ])
 def test_invalid_configurations(over, status):
     with pytest.raises(AcqError) as e:
@@ -39,4 +39,5 @@ def test_entry_points_reject_null_plans():
     nf = ctypes.c_int32(0)
     assert L.acq_fsk_detect(None, None, 0, None, 0, ctypes.byref(nf)) == -1
     assert L.acq_fsk_release(None) == 0
-    assert ctypes.sizeof(_capi.AcqFskDetection) == 56
+    assert ctypes.sizeof(_capi.AcqFskDetection) == 64 and ctypes.sizeof(_capi.AcqFskTask) == 24
+    assert L.acq_fsk_track(None, None, 0, None, 0, ctypes.byref(nf)) == -1

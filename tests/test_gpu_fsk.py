@@ -219,3 +219,55 @@ def test_paper_shaped_window(dev):
     for t in check:
         r = ofsk.fsk_acquire(d, u, tm, method="fft", tags=[t])[0]
         _check_peak(dets[t], r, d, u, s, tm[t], _template_front(case, bits[t], bp))
+
+
+def test_tracking_tasks(dev):
+    """FSK tracking tasks (one tag per block, blocks about 1.5 templates long,
+    the tag's packet present or not, another tag's packet as interference, one
+    block shorter than a template) against the oracle per task; a task equals
+    the searching result for that tag on the same block."""
+    case = CASES[1]
+    name, T, nb, sps, ntaps, cut, f1, f0, lo, N, M, ntx = case
+    bits = siggen.make_fsk_bits(840, T, nb)
+    bp = siggen.fsk_bandpass(ntaps, cut, FS)
+    n_t = nb * sps + ntaps + sps - 2
+    n = (3 * n_t) // 2
+    blocks, tasks = [], []
+    for i, (tags, track) in enumerate([([0], 0), ([1, 2], 1), ([3], 0), ([], 2), ([2], 2)]):
+        iq, txs = siggen.make_fsk_block(841 + i, n, bits, sps, FS, f1, f0, lo, len(tags), snr_db=(-3.0, 3.0),
+                                        tags=tags, delays=[(k + 1) * 1000 for k in range(len(tags))])
+        blocks.append(iq)
+        tasks.append((i, track))
+    short = np.zeros((n_t - 1, 2), np.int16)
+    blocks.append(short)
+    tasks.append((len(blocks) - 1, 1))
+    dev_blocks = [torch.from_numpy(b).to(dev) for b in blocks]
+    with _plan(case, bits, bp, max_track_tasks=8) as plan:
+        got = plan.track([(dev_blocks[b], t) for b, t in tasks])
+        searched = [plan.detect(x) for x in dev_blocks[:-1]]
+    assert [d.block for d in got] == list(range(len(tasks) - 1))       # the short block yields nothing
+    for d, (b, t) in zip(got, tasks):
+        s = searched[b][t]
+        assert (d.tag, d.lag, d.toa, d.xcorr, d.q, d.p, d.z) == (s.tag, s.lag, s.toa, s.xcorr, s.q, s.p, s.z)
+        dd, uu, ss = _oracle_front(case, blocks[b], bp)
+        tm = {t: ofsk.replica_template(bits[t], FS, bp, f1, f0, sps)}
+        r = ofsk.fsk_acquire(dd, uu, tm, tags=[t])[0]
+        _check_peak(d, r, dd, uu, ss, tm[t], _template_front(case, bits[t], bp))
+
+
+def test_tracking_errors(dev):
+    from paper_2005_10445_amd import AcqError
+    case = CASES[0]
+    bits, bp, iq, _ = _setup(case, 850)
+    xt = torch.from_numpy(iq).to(dev)
+    name, T, nb, sps, ntaps, cut, f1, f0, lo, N, M, ntx = case
+    with _plan(case, bits, bp, max_track_tasks=2) as plan:
+        with pytest.raises(AcqError) as e:
+            plan.track([(xt, T)])
+        assert e.value.status == -1
+        with pytest.raises(AcqError) as e:
+            plan.track([(xt, 0)] * 3)
+        assert e.value.status == -1
+        with pytest.raises(AcqError) as e:                    # total length above max_block_len
+            plan.track([(xt, 0), (xt, 1)])
+        assert e.value.status == -5
