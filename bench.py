@@ -322,42 +322,72 @@ def bench_fsk(args, w):
     seed = w["seeds"][0]
     bits = siggen.make_fsk_bits(seed, T, w["num_bits"])
     bp = siggen.fsk_bandpass(w["bp_taps"], w["bp_cutoff_hz"], fs)
-    iq, txs = siggen.make_fsk_block(seed + 1, N, bits, w["sps"], fs, w["f1_hz"], w["f0_hz"], w["lo_hz"], w["n_tx"],
-                                    snr_db=w["snr_db"], noise_rms=w["noise_rms"])
-    x = torch.from_numpy(iq).to("cuda:0")
-    plan = FskPlan(bits, fs, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], N)
+    tracking = "num_tasks" in w
+    if tracking:
+        rng = np.random.default_rng(seed)
+        tasks, txs_all = [], []
+        for i in range(w["num_tasks"]):
+            tag = int(rng.integers(0, T))
+            present = bool(rng.random() < w["p_present"])
+            iq_i, txs_i = siggen.make_fsk_block(seed + 1 + i, N, bits, w["sps"], fs, w["f1_hz"], w["f0_hz"],
+                                                w["lo_hz"], 1 if present else 0, snr_db=w["snr_db"],
+                                                noise_rms=w["noise_rms"], tags=[tag] if present else None)
+            tasks.append((torch.from_numpy(iq_i).to("cuda:0"), tag))
+            txs_all.append(txs_i)
+        iq = None
+        plan = FskPlan(bits, fs, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], N * len(tasks),
+                       max_track_tasks=len(tasks))
+        run = lambda: len(plan.track(tasks))          # noqa: E731
+        total_samples = N * len(tasks)
+    else:
+        iq, txs = siggen.make_fsk_block(seed + 1, N, bits, w["sps"], fs, w["f1_hz"], w["f0_hz"], w["lo_hz"],
+                                        w["n_tx"], snr_db=w["snr_db"], noise_rms=w["noise_rms"])
+        x = torch.from_numpy(iq).to("cuda:0")
+        plan = FskPlan(bits, fs, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], N)
+        run = lambda: plan.detect_raw(x)               # noqa: E731
+        total_samples = N
     g = plan.geometry
     M, V, n_t = g["fft_len"], g["valid_per_segment"], g["template_len"]
     S = -(-(N - n_t + 1) // V)
     slots = -(-S // 2)
+    if tracking:
+        slots *= len(tasks)
     log(f"[bench] workload={args.workload} codes={T} N={N} n_t={n_t} M={M} V={V} segments={S} slots={slots}")
     for _ in range(args.warmup):
-        plan.detect_raw(x)
+        run()
     plan.set_profiling(True)
     corr_ms, kern_ms = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan.detect_raw(x)
+        run()
         kt = plan.last_kernel_times()
         corr_ms.append(kt["correlate"])
         kern_ms.append(kt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plan.set_profiling(False)
-    found = plan.detect(x)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = T * N / (ms_per_step * 1e-3) / 1e6
-    # per code pair of segments: one M-point inverse transform + spectrum product + |c| per valid lag
-    flops = float(T) * slots * (5.0 * M * math.log2(M) + 6.0 * M + 4.0 * V)
+    # codes x samples searched per second (tracking: one code per task)
+    value = (total_samples if tracking else T * N) / (ms_per_step * 1e-3) / 1e6
+    # per code and pair of segments: one M-point inverse transform + spectrum product + |c| per valid lag
+    flops = float(1 if tracking else T) * slots * (5.0 * M * math.log2(M) + 6.0 * M + 4.0 * V)
     corr_avg = float(np.mean(corr_ms))
     achieved = flops / (corr_avg * 1e-3) / 1e12
     window_s = N / fs
     codes_rt = 0.5 * window_s / (ms_per_step * 1e-3 / T)      # the paper's throughput: 50% of the time searching
     mean = {k: float(np.mean([m[k] for m in kern_ms])) for k in kern_ms[0]}
-    hits = sum(1 for t, D, _ in txs if abs(found[t].lag - D) <= 1 and found[t].z > 0.02)
-    log(f"[bench] {ms_per_step:.3f} ms per window, kernels {mean}, {hits}/{len(txs)} packets found, "
-        f"{codes_rt:.0f} codes searchable in real time at 50% duty")
+    if tracking:
+        found = {d.block: d for d in plan.track(tasks)}
+        want = [(i, tx[0][1]) for i, tx in enumerate(txs_all) if tx]
+        hits = sum(1 for i, D in want if i in found and abs(found[i].lag - D) <= 1)
+        log(f"[bench] {ms_per_step:.3f} ms per {len(tasks)} tasks ({len(tasks) / (ms_per_step * 1e-3):.0f} tasks/s), "
+            f"kernels {mean}, {hits}/{len(want)} packets found")
+    else:
+        found = plan.detect(x)
+        hits = sum(1 for t, D, _ in txs if abs(found[t].lag - D) <= 1 and found[t].z > 0.02)
+        log(f"[bench] {ms_per_step:.3f} ms per window, kernels {mean}, {hits}/{len(txs)} packets found, "
+            f"{codes_rt:.0f} codes searchable in real time at 50% duty")
     out = {
         "metric": "acquisition tag*freq*Msample/s",
         "value": value,
@@ -373,12 +403,13 @@ def bench_fsk(args, w):
         "data": "synthetic (seeded CPFSK packets in AWGN, int16)",
         "config": {"workload": args.workload, "codes": T, "bits": w["num_bits"], "samples_per_bit": w["sps"],
                    "window_samples": N, "template_len": n_t, "fft_len": M, "segments": S,
-                   "codes_realtime_half_duty": codes_rt, "parallelism": "single GPU"},
+                   "tasks": len(tasks) if tracking else None,
+                   "codes_realtime_half_duty": None if tracking else codes_rt, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_per_launch(args.workload),
                      "kernel": "k_fsk_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},
     }
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and not tracking:
         log("[bench] cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline_fsk(iq, bits, w, args.cpu_budget)
     plan.close()

@@ -205,6 +205,11 @@ WORKLOADS = {
     "fsk_search": dict(num_tags=128, num_bits=8192, sps=8, fs_hz=8e6, block_len=800000, lo_hz=1.0e6,
                        f1_hz=250e3, f0_hz=-250e3, bp_taps=200, bp_cutoff_hz=600e3, n_tx=6,
                        snr_db=(-10.0, 0.0), noise_rms=1000.0, seeds=(6000, 6005)),
+    # FSK tracking tasks: 64 tasks per call, each a 12 ms block (96,000 samples) for
+    # one of the 128 codes, the code's packet present with probability 0.9
+    "fsk_tracking": dict(num_tags=128, num_bits=8192, sps=8, fs_hz=8e6, block_len=96000, lo_hz=1.0e6,
+                         f1_hz=250e3, f0_hz=-250e3, bp_taps=200, bp_cutoff_hz=600e3, num_tasks=64,
+                         p_present=0.9, snr_db=(-10.0, 0.0), noise_rms=1000.0, seeds=(6100, 6105)),
 }
 
 
