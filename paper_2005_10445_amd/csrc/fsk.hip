@@ -444,22 +444,27 @@ __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
     }
 }
 
-// One thread per tag: parts summed in order, re-maximisation of |w_c| over
-// +/-1 lag (one re-centring when it lands on the edge), parabola, results.
-__global__ void k_fsk_refine_final(FskRefineArgs a, int items) {
-    const int item = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
-    if (item >= items) return;
+// One wave per item: lane k < kFskSums adds sum k over the parts in order;
+// lane 0 re-maximises |w_c| over +/-1 lag (one re-centring when it lands on
+// the edge), fits the parabola and writes the result.
+__global__ __launch_bounds__(64) void k_fsk_refine_final(FskRefineArgs a) {
+    const int item = int(blockIdx.x);
     const FskItem fi = fsk_item(a, item);
     const int64_t lags = fi.tk.lags;
     const unsigned long long key = lags > 0 ? a.keys[item] : 0ull;
+    const int t = int(threadIdx.x);
     if (key == 0ull) {
-        a.found[item] = 0;
+        if (t == 0) a.found[item] = 0;
         return;
     }
-    double S[kFskSums];
-    for (int k = 0; k < kFskSums; ++k) S[k] = 0.0;
-    for (int p = 0; p < kFskParts; ++p)
-        for (int k = 0; k < kFskSums; ++k) S[k] += a.partial[(size_t(item) * kFskParts + p) * kFskSums + k];
+    __shared__ double S[kFskSums];
+    if (t < kFskSums) {
+        double v = 0.0;
+        for (int p = 0; p < kFskParts; ++p) v += a.partial[(size_t(item) * kFskParts + p) * kFskSums + t];
+        S[t] = v;
+    }
+    __syncthreads();
+    if (t != 0) return;
     const int64_t lam0 = int64_t(~unsigned(key & 0xffffffffull)) - kFskWin / 2;
     double A[kFskWin];
     for (int w = 0; w < kFskWin; ++w) {
@@ -1085,7 +1090,7 @@ int finish_fsk(acq_fsk_plan_s* p, int nblocks, bool track, int items, acq_fsk_de
         FskTimer kt(p, ACQ_FSK_KERNEL_REFINE);
         hipLaunchKernelGGL(acq::k_fsk_refine_sums, dim3(unsigned(items) * acq::kFskParts), dim3(256), 0, st, ra);
         FSK_HIP(hipGetLastError());
-        hipLaunchKernelGGL(acq::k_fsk_refine_final, dim3(unsigned((items + 63) / 64)), dim3(64), 0, st, ra, items);
+        hipLaunchKernelGGL(acq::k_fsk_refine_final, dim3(unsigned(items)), dim3(64), 0, st, ra);
         FSK_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(acq::k_fsk_compact, dim3(1), dim3(1024), 0, st, p->d_dets, p->d_found, items, p->d_out,
