@@ -6,7 +6,7 @@
 //                    each) combined by one radix-spc decimation-in-time step
 //   k_bank         : replica spectra conj(DFT_Msub(chip code)) / M, plan time
 //   k_correlate    : the hot loop, in correlate.hip
-//   k_refine       : FP64 re-correlation around each tag's peak, re-maximisation,
+//   k_refine_*     : FP64 re-correlation around each tag's peak, re-maximisation,
 //                    parabolic vertex, z and energy
 //   k_compact      : detections in tag order
 //
@@ -198,14 +198,15 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
 // ------------------------------------------------------------------ refine
 constexpr int kMaxWin = 2 * kMaxRefineRadius + 3;
 
-// FP64 refinement of each (block, tag) peak key, in two rounds of two
-// kernels.  Round 0 takes the window of W = 2R + 3 lags centred on the key's
-// lag; k_refine_sums adds, in kRefineParts workgroups per item, the re- and
-// im-sums of the mixed samples against the tag's replica and the sample
-// energy under it for every lag of the window; k_refine_decide (one thread
-// per item) adds the parts in order, re-maximises over the inner 2R+1 lags and
+// FP64 refinement of each (block, tag) peak key, in two passes of two
+// kernels.  The first pass takes the window of W = 2R + 3 lags centred on the
+// key's lag; k_refine_sums adds, in kRefineParts workgroups per item, the re-
+// and im-sums of the mixed samples against the tag's replica and the sample
+// energy under it for every lag of the window; k_refine_decide (one wave per
+// item) adds the parts in order, re-maximises over the inner 2R+1 lags and
 // either writes the detection or, when the maximum sits on the inner edge,
-// records a re-centred window for round 1, which repeats both steps once.
+// records a re-centred window for the second pass, which repeats both steps
+// once.
 // The mix exp(-j 2 pi m_k i / M) is an FP64 table entry at (m_k i) mod M (M a
 // power of two, so the reduction is exact), or the exact bin's FP64 phase.
 struct RefineItem {
@@ -228,7 +229,7 @@ __device__ __forceinline__ bool refine_item(const RefineArgs& a, int item, Refin
 constexpr int kRefineChipsLds = 4096;     // chips of one part staged in LDS (else read from global)
 
 template <int WMAX>
-__global__ __launch_bounds__(256) void k_refine_sums(RefineArgs a, int round) {
+__global__ __launch_bounds__(256) void k_refine_sums(RefineArgs a, int pass) {
     constexpr int NT = 256, NW = NT / 64;
     const int item = int(blockIdx.x) / kRefineParts, part = int(blockIdx.x) % kRefineParts;
     RefineItem it;
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(256) void k_refine_sums(RefineArgs a, int round) {
     if (key == 0ull) return;
     const unsigned idx = ~unsigned(key & 0xffffffffull);
     const int k = int(idx % unsigned(a.K));
-    const int64_t center = round == 0 ? int64_t(idx / unsigned(a.K)) : a.center[item];
+    const int64_t center = pass == 0 ? int64_t(idx / unsigned(a.K)) : a.center[item];
     if (center < 0) return;
     const int R = a.radius;
     const int W = 2 * R + 3;
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void k_refine_sums(RefineArgs a, int round) {
 // One wave per item: lane s < 3W adds sum s over the parts in order, lane 0
 // decides.
 template <int WMAX>
-__global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int round) {
+__global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int pass) {
     const int item = int(blockIdx.x);
     RefineItem it;
     if (!refine_item(a, item, &it)) return;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int round) {
     const int t = int(threadIdx.x);
     const unsigned long long key = d.lags > 0 ? a.keys[it.slot] : 0ull;
     if (key == 0ull) {                       // no valid lag was searched for this tag
-        if (round == 0 && t == 0) {
+        if (pass == 0 && t == 0) {
             a.found[it.slot] = 0;
             a.center[item] = -1;
         }
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int round) {
     }
     const unsigned idx = ~unsigned(key & 0xffffffffull);
     const int k = int(idx % unsigned(a.K));
-    const int64_t center = round == 0 ? int64_t(idx / unsigned(a.K)) : a.center[item];
+    const int64_t center = pass == 0 ? int64_t(idx / unsigned(a.K)) : a.center[item];
     if (center < 0) return;
     const int R = a.radius;
     const int W = 2 * R + 3;
@@ -356,9 +357,9 @@ __global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int round) {
         if (P[w] > P[wb] || (P[w] == P[wb] && w < wb)) wb = w;
     const int64_t lam = lam0 + wb;
     const bool hit = (wb == 1 && lam > 0) || (wb == W - 2 && lam < d.lags - 1);
-    if (round == 0) {
+    if (pass == 0) {
         a.center[item] = hit ? lam : -1;
-        if (hit) return;                     // round 1 re-centres on lam
+        if (hit) return;                     // the second pass re-centres on lam
     }
     unsigned flags = hit ? ACQ_DET_WINDOW_EDGE : 0u;
     const double p0 = P[wb];
@@ -538,13 +539,13 @@ hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
         return hipErrorInvalidValue;
     const int items = max_blocks * (a.track ? 1 : a.T);
     const dim3 sgrid(unsigned(items) * kRefineParts), dgrid{unsigned(items)};
-    for (int round = 0; round < 2; ++round) {
+    for (int pass = 0; pass < 2; ++pass) {
         if (a.radius <= 1) {
-            hipLaunchKernelGGL((k_refine_sums<5>), sgrid, dim3(256), 0, st, a, round);
-            hipLaunchKernelGGL((k_refine_decide<5>), dgrid, dim3(64), 0, st, a, round);
+            hipLaunchKernelGGL((k_refine_sums<5>), sgrid, dim3(256), 0, st, a, pass);
+            hipLaunchKernelGGL((k_refine_decide<5>), dgrid, dim3(64), 0, st, a, pass);
         } else {
-            hipLaunchKernelGGL((k_refine_sums<kMaxWin>), sgrid, dim3(256), 0, st, a, round);
-            hipLaunchKernelGGL((k_refine_decide<kMaxWin>), dgrid, dim3(64), 0, st, a, round);
+            hipLaunchKernelGGL((k_refine_sums<kMaxWin>), sgrid, dim3(256), 0, st, a, pass);
+            hipLaunchKernelGGL((k_refine_decide<kMaxWin>), dgrid, dim3(64), 0, st, a, pass);
         }
     }
     return hipGetLastError();
