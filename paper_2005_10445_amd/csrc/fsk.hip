@@ -389,6 +389,7 @@ __device__ __forceinline__ FskItem fsk_item(const FskRefineArgs& a, int item) {
 constexpr int kFskWin = 7;
 constexpr int kFskParts = 16;
 constexpr int kFskSums = 3 * kFskWin + 1;
+constexpr int kFskStage = 4608;     // d and u samples of one part staged in LDS (longer parts read global)
 
 __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
     constexpr int NT = 256, NW = NT / 64;
@@ -408,6 +409,21 @@ __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
     const float* ub = a.u + fi.tk.zoff;
     const int64_t ch = (a.nt + kFskParts - 1) / kFskParts;
     const int64_t i0 = int64_t(part) * ch, i1 = min(a.nt, i0 + ch);
+    // the part reads block samples k0 .. k0 + span - 1 (zero outside the block),
+    // each kFskWin times: stage them in LDS when they fit
+    __shared__ float s_d[kFskStage], s_u[kFskStage];
+    const int64_t k0 = lam0 + i0;
+    const int64_t span = i1 > i0 ? i1 - i0 + kFskWin - 1 : 0;
+    const bool staged = span <= kFskStage;
+    if (staged) {
+        for (int64_t q = t; q < span; q += NT) {
+            const int64_t k = k0 + q;
+            const bool in = k >= 0 && k < fi.tk.n;
+            s_d[q] = in ? db[k] : 0.f;
+            s_u[q] = in ? ub[k] : 0.f;
+        }
+    }
+    __syncthreads();
     double wv[kFskWin], pv[kFskWin], qv[kFskWin], ec = 0.0;
 #pragma unroll
     for (int w = 0; w < kFskWin; ++w) wv[w] = pv[w] = qv[w] = 0.0;
@@ -416,13 +432,20 @@ __global__ __launch_bounds__(256) void k_fsk_refine_sums(FskRefineArgs a) {
         ec += c * c;
 #pragma unroll
         for (int w = 0; w < kFskWin; ++w) {
-            const int64_t k = lam0 + w + i;
-            if (k >= 0 && k < fi.tk.n) {
-                const double zd = db[k], zu = ub[k];
-                wv[w] += c * zd;
-                pv[w] += c * zu;
-                qv[w] += zd * zd;
+            double zd = 0.0, zu = 0.0;
+            if (staged) {                           // zero outside the block, as staged
+                zd = s_d[i - i0 + w];
+                zu = s_u[i - i0 + w];
+            } else {
+                const int64_t k = lam0 + w + i;
+                if (k >= 0 && k < fi.tk.n) {
+                    zd = db[k];
+                    zu = ub[k];
+                }
             }
+            wv[w] += c * zd;
+            pv[w] += c * zu;
+            qv[w] += zd * zd;
         }
     }
 #pragma unroll
