@@ -84,7 +84,29 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_b
     }
 
 
-def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCES) -> str:
+def timed_dispatches(trace_dir: str, skip_steps: int, steps_total: int):
+    """{kernel: [duration ns]} of the dispatches of the timed steps: a kernel
+    launched c times over steps_total steps runs c // steps_total times per step,
+    so its first skip_steps * (c // steps_total) dispatches are the warm-up."""
+    with open(_find(trace_dir, "kernel_trace.csv")) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    calls = defaultdict(int)
+    for r in rows:
+        calls[r["Kernel_Name"]] += 1
+    out = defaultdict(list)
+    seen = defaultdict(int)
+    for r in rows:
+        name = r["Kernel_Name"]
+        if calls[name] < steps_total:
+            continue                                  # plan-time or occasional kernels
+        seen[name] += 1
+        if seen[name] > skip_steps * (calls[name] // steps_total):
+            out[name].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCES, skip: int = 0,
+                  steps_total: int = 0) -> str:
     path = _find(trace_dir, "kernel_stats.csv")
     with open(path) as f:
         rows = list(csv.DictReader(f))
@@ -97,6 +119,14 @@ def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCE
         lines.append(f"{name:60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
                      f"{float(r['Percentage']):6.2f}")
+    if skip > 0 and steps_total > skip:
+        timed = timed_dispatches(trace_dir, skip, steps_total)
+        lines += ["", f"# timed steps only: {steps_total - skip} of {steps_total} steps, the first {skip} "
+                      f"(warm-up) left out",
+                  f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}"]
+        for name, d in sorted(timed.items(), key=lambda kv: -sum(kv[1]))[:top]:
+            lines.append(f"{name.replace('void ', '')[:60]:60s} {len(d):6d} {sum(d) / len(d) / 1e3:10.2f} "
+                         f"{min(d) / 1e3:10.2f} {max(d) / 1e3:10.2f}")
     return "\n".join(lines) + "\n"
 
 
@@ -108,6 +138,8 @@ def main(argv=None):
     t.add_argument("out")
     t.add_argument("--cmd", required=True)
     t.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
+    t.add_argument("--warmup", type=int, default=0, help="warm-up steps of the profiled run")
+    t.add_argument("--steps-total", type=int, default=0, help="warm-up plus timed steps of the profiled run")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
@@ -121,7 +153,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "trace":
         with open(a.out, "w") as f:
-            f.write(trace_summary(a.trace_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES))
+            f.write(trace_summary(a.trace_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES,
+                                  skip=a.warmup, steps_total=a.steps_total))
     else:
         res = traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir, a.kernel,
                       a.copy_bytes, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES)
