@@ -95,8 +95,9 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     unsigned long long* keys = a.keys + size_t(bi) * a.T;
 
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
+    constexpr int NB = bank_stride(N);
     const __amdgpu_buffer_rsrc_t bank =
-        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag0) * N * St::BYTES, uint32_t(ntag) * N * St::BYTES);
+        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag0) * NB * St::BYTES, uint32_t(ntag) * NB * St::BYTES);
     // stored spectra carry 2^-x_exp (segments) and 2^bank_exp (bank): undo both in G
     float gscale = 1.0f;
     if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, a.exps[bi] - a.bank_exp);
@@ -118,12 +119,18 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     const int omin = eng.out_min(), omax = eng.out_max();   // wave-uniform
     const bool hi = omin + E::HI_OFF < ulim;               // any output of the upper half needed
 
-    const int voff = eng.in_index(0) * St::BYTES;   // bank element of register m: in_index(0) + m*NT
+    // bank element of register m: i = in_index(0) + m*NT, stored for i <= N/2;
+    // registers m >= 8 read the mirror N - i = (NT - in_index(0)) + (15-m)*NT
+    const int voff = eng.in_index(0) * St::BYTES;
+    const int voffm = (E::NT - eng.in_index(0)) * St::BYTES;
 
     for (int tt = 0; tt < ntag; ++tt) {
         float2 v[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = cmul(G[m], St::bload(bank, voff, (tt * N + m * E::NT) * St::BYTES));
+        for (int m = 0; m < 8; ++m) v[m] = cmul(G[m], St::bload(bank, voff, (tt * NB + m * E::NT) * St::BYTES));
+#pragma unroll
+        for (int m = 8; m < 16; ++m)
+            v[m] = cmulc(G[m], St::bload(bank, voffm, (tt * NB + (15 - m) * E::NT) * St::BYTES));
         eng.template transform<+1>(v, lds, b1, extra, hi);
         // per-register indices and masks are the same for every tag: keep the
         // optimiser from holding all of them across the loop (recomputing is cheap)
@@ -191,8 +198,9 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
     const int tag = d.tag;
 
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
+    constexpr int NB = bank_stride(E::N);
     const __amdgpu_buffer_rsrc_t bank =
-        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag) * E::N * St::BYTES, uint32_t(E::N) * St::BYTES);
+        make_rsrc(static_cast<const char*>(a.bank) + size_t(tag) * NB * St::BYTES, uint32_t(NB) * St::BYTES);
     float gscale = 1.0f;
     if constexpr (PREC != ACQ_FP32) gscale = ldexpf(1.0f, a.exps[bi] - a.bank_exp);
 
@@ -204,14 +212,17 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
     const int ob0 = eng.out_base();
     const int omin = eng.out_min(), omax = eng.out_max();
     const bool hi = omin + E::HI_OFF < ulim;
-    const int voff = eng.in_index(0) * St::BYTES;
+    const int voff = eng.in_index(0) * St::BYTES;              // half bank, as in correlate_item
+    const int voffm = (E::NT - eng.in_index(0)) * St::BYTES;
 
     unsigned long long best = 0ull;
     for (int k = k0; k < k1; ++k) {
         float2 v[16];
         first_step<E, PREC>(a, eng, g, k, rho, gscale, v);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = cmul(v[m], St::bload(bank, voff, (m * E::NT) * St::BYTES));
+        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], St::bload(bank, voff, (m * E::NT) * St::BYTES));
+#pragma unroll
+        for (int m = 8; m < 16; ++m) v[m] = cmulc(v[m], St::bload(bank, voffm, ((15 - m) * E::NT) * St::BYTES));
         eng.template transform<+1>(v, lds, b1, extra, hi);
         int ob = ob0;
         unsigned idx0 = unsigned((seg0 + rho) * a.K + k) + unsigned(ob0) * kstep;

@@ -179,7 +179,7 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     const int64_t sbytes = cfg->precision == ACQ_FP32 ? 8 : 4;
     bytes += G.max_total_segments * G.ncls * G.M * 8;  // forward spectra X[S][classes][M] (FP32)
     if (sbytes == 4) bytes += G.max_total_segments * G.ncls * G.M * 4;   // their 16-bit copy
-    bytes += T * G.Msub * sbytes;             // replica bank [T][M/spc]
+    bytes += T * (G.Msub / 2 + 64) * sbytes;  // replica bank [T][M/spc / 2 + 64] (half spectrum)
     bytes += G.M * 8 * (spc + 1) + G.Msub * 8;  // phase weights [spc][M], roots at M and M/spc
     bytes += T * C;                           // chips
     bytes += K * (4 + 8);                     // rotations, frequencies

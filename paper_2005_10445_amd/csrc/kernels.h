@@ -10,6 +10,11 @@ namespace acq {
 
 // Workgroups of the block-power partial sums, per block.
 constexpr int kPowerParts = 256;
+
+// The replica bank keeps half of each tag's Msub-point spectrum: the chip code
+// is real, so Chat[Msub - i] = conj(Chat[i]) and entries 0 .. Msub/2 suffice.
+// Per-tag stride in elements (padded).
+__host__ __device__ constexpr int bank_stride(int msub) { return msub / 2 + 64; }
 // Persistent correlation launch: work-item counters, one per XCD.
 constexpr int kXcds = 8;
 

@@ -190,9 +190,12 @@ __global__ __launch_bounds__(E::NT) void k_bank(const int8_t* __restrict__ chips
     eng.template transform<-1>(v, lds, b1, extra);
     const float s = ldexpf(1.0f, bank_exp) / float(M);   // exact: powers of two
     const int ob = eng.out_base();
-    typename St::T* out = reinterpret_cast<typename St::T*>(bank) + size_t(tag) * E::N;
+    typename St::T* out = reinterpret_cast<typename St::T*>(bank) + size_t(tag) * bank_stride(E::N);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) out[ob + E::out_off(m)] = St::pack(make_float2(v[m].x * s, -v[m].y * s));
+    for (int m = 0; m < 16; ++m) {
+        const int i = ob + E::out_off(m);
+        if (i <= E::N / 2) out[i] = St::pack(make_float2(v[m].x * s, -v[m].y * s));   // the rest is the mirror
+    }
 }
 
 // ------------------------------------------------------------------ refine

@@ -42,7 +42,7 @@ struct acq_plan_s {
     int32_t* d_cls = nullptr;           // [K] residual class of each bin
     double* d_cls_cyc = nullptr;        // [classes] residual offsets, cycles per sample
     double* d_cyc = nullptr;            // [K] f_k / Fs
-    void* d_bank = nullptr;             // [T][Msub] in the plan's storage format
+    void* d_bank = nullptr;             // [T][bank_stride(Msub)]: spectrum entries 0 .. Msub/2, storage format
     int bank_exp = 0;                   // power-of-two prescale of the stored bank
     float2* d_wts = nullptr;            // [spc][M] first-step weights of the split inverse transform
     float2* d_rootsM = nullptr;         // [M]
@@ -148,7 +148,7 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_cls, K));
     ACQ_HIP(dalloc(&p->d_cls_cyc, ncls));
     ACQ_HIP(dalloc(&p->d_cyc, K));
-    ACQ_HIP(hipMalloc(&p->d_bank, T * size_t(g.Msub) * (half ? 4 : 8)));
+    ACQ_HIP(hipMalloc(&p->d_bank, T * size_t(acq::bank_stride(int(g.Msub))) * (half ? 4 : 8)));
     // 16-bit banks are stored with rms magnitude near 1: 2^round(log2(M / sqrt(C)))
     p->bank_exp = half ? int(std::lrint(std::log2(double(g.M) / std::sqrt(double(C))))) : 0;
     ACQ_HIP(dalloc(&p->d_wts, size_t(g.M) * size_t(c.samples_per_chip)));
