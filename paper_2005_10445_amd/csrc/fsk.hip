@@ -49,7 +49,7 @@ namespace {
 
 constexpr int kFrontLog = 12;                 // composed filters applied on 4096-point segments
 constexpr int kFrontN = 1 << kFrontLog;
-constexpr int kFskMaxGrid = 512;              // workgroups (and scratch slots) of the correlation
+constexpr int kFskMaxGrid = 256;              // workgroups (and scratch slots) of the correlation: one per CU
 
 // One block of an FSK call: the searching window (tag -1: every template) or
 // one tracking task (its tag only).  Front-end segments and packed segment
@@ -175,19 +175,27 @@ __global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
 }
 
 // zp[s][i] = (d[2g V + i], d[(2g+1) V + i]) of slot s = slot0 + g of its
-// block, zero past the block or past its last segment; grid covers slots * M.
-__global__ void k_fsk_pack(FskTasks tt, const float* __restrict__ d, int64_t V, int64_t M, int nslots,
-                           float2* __restrict__ zp) {
-    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= int64_t(nslots) * M) return;
-    const int64_t s = k / M, i = k - s * M;
+// block, zero past the block or past its last segment.  256 threads per
+// workgroup, each workgroup kFskPackChunk consecutive i of one slot: the slot,
+// and so the block lookup, is uniform over the workgroup and done once.
+constexpr int kFskPackChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_fsk_pack(FskTasks tt, const float* __restrict__ d, int64_t V, int64_t M,
+                                                  float2* __restrict__ zp) {
+    const int64_t chunk = M < kFskPackChunk ? M : kFskPackChunk;
+    const int64_t per_slot = M / chunk;
+    const int64_t s = int64_t(blockIdx.x) / per_slot;
     const FskTask tk = tt.t[fsk_task_of<&FskTask::slot0>(tt, int(s))];
     const int64_t g = s - tk.slot0;
     const float* db = d + tk.zoff;
-    const int64_t p0 = 2 * g * V + i, p1 = (2 * g + 1) * V + i;
-    const float re = p0 < tk.n ? db[p0] : 0.f;
-    const float im = (2 * g + 1 < tk.nseg && p1 < tk.n) ? db[p1] : 0.f;
-    zp[k] = make_float2(re, im);
+    const bool second = 2 * g + 1 < tk.nseg;
+    const int64_t i0 = (int64_t(blockIdx.x) - s * per_slot) * chunk;
+    for (int64_t i = i0 + threadIdx.x; i < i0 + chunk; i += 256) {
+        const int64_t p0 = 2 * g * V + i, p1 = (2 * g + 1) * V + i;
+        const float re = p0 < tk.n ? db[p0] : 0.f;
+        const float im = (second && p1 < tk.n) ? db[p1] : 0.f;
+        zp[s * M + i] = make_float2(re, im);
+    }
 }
 
 // bank[t][i] = conj(X_t[i]) / M in place
@@ -300,14 +308,15 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
                 ulim[h] = vlim > rho ? (vlim - rho + PP - 1) / PP : 0;
             }
             const int ob0 = eng.out_base();
-            const int omin = eng.out_min(), omax = eng.out_max();
+            const int omin = eng.out_min();
             const bool hi = omin + E::HI_OFF < max(ulim[0], ulim[1]);
             float2 v[16];
 #pragma unroll
             for (int m = 0; m < 16; ++m) v[m] = G[rho * a.Msub + eng.in_index(m)];
             eng.template transform<+1>(v, lds, b1, extra, hi);
-            int ob = ob0;
-            asm volatile("" : "+v"(ob));
+            // output off of this lane is a valid lag of segment h when off < lim[h]
+            int lim[2] = {ulim[0] - ob0, ulim[1] - ob0};
+            asm volatile("" : "+v"(lim[0]), "+v"(lim[1]));
             // this lane's largest |c| of the phase: the first segment's lags
             // before the second's, each in increasing lag (strict comparison:
             // the smallest lag of a tie within the phase)
@@ -321,22 +330,21 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
                     const int off = E::out_off(r);
                     if (omin + off < ulim[h]) {
                         const float cv = h ? v[r].y : v[r].x;
-                        float pv = fabsf(cv);
+                        const float pv = fabsf(cv);
                         if constexpr (DUMP) {
-                            if (ob + off < ulim[h]) {
-                                const int64_t tau = sbeg[h] + int64_t(PP) * (ob + off) + rho;
+                            if (off < lim[h]) {
+                                const int64_t tau = sbeg[h] + int64_t(PP) * (ob0 + off) + rho;
                                 a.dump[size_t(tag) * size_t(tk.lags) + size_t(tau)] = cv;
                             }
                         }
-                        if (omax + off >= ulim[h] && ob + off >= ulim[h]) pv = -1.0f;
-                        const bool take = pv > bp;
+                        const bool take = pv > bp && off < lim[h];
                         boff = take ? off : boff;
                         bh = take ? h : bh;
                         bp = take ? pv : bp;
                     }
                 }
             }
-            const unsigned lag = unsigned(sbeg[bh] + rho) + unsigned(ob + boff) * unsigned(PP);
+            const unsigned lag = unsigned(sbeg[bh] + rho) + unsigned(ob0 + boff) * unsigned(PP);
             const unsigned long long key = bp >= 0.0f
                 ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) | static_cast<unsigned long long>(~lag)
                 : 0ull;
@@ -1051,9 +1059,9 @@ int enqueue_fsk(acq_fsk_plan_s* p, int nblocks, bool track, float* dump, int* it
         FskTimer kt(p, ACQ_FSK_KERNEL_FRONT);
         FSK_HIP(launch_front(p, tt, fsegs, false, nullptr));
     }
-    const int64_t packed = int64_t(slots) * g.M;
-    hipLaunchKernelGGL(acq::k_fsk_pack, dim3(unsigned((packed + 255) / 256)), dim3(256), 0, st, tt, p->d_d, g.V, g.M,
-                       slots, p->d_zp);
+    const int64_t packed = int64_t(slots) * g.M;      // M is a power of two >= 2^10
+    hipLaunchKernelGGL(acq::k_fsk_pack, dim3(unsigned(packed / std::min<int64_t>(g.M, acq::kFskPackChunk))), dim3(256),
+                       0, st, tt, p->d_d, g.V, g.M, p->d_zp);
     FSK_HIP(hipGetLastError());
     BlockTable bt{};
     bt.one.x = p->d_zp;

@@ -3,10 +3,16 @@
   python -m paper_2005_10445_amd.profiling trace  <trace_dir> <out.txt> --cmd "<command>"
   python -m paper_2005_10445_amd.profiling traffic <fetch_dir> <write_dir> <copy_fetch_dir>
          <copy_write_dir> <out.json> --kernel k_correlate --copy-bytes 268435456 --cmd "<command>"
+  python -m paper_2005_10445_amd.profiling issue <pmc_dir> <out.txt> --kernel k_correlate --cmd "<command>"
 
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
 counters read for a plain device copy of known size, so that the reported
 figure is HBM bytes per launch of the kernel.
+
+`issue` turns SQ instruction counts (wave instructions per dispatch) into the
+time the vector ALUs need to issue them: without packed FP32, a SIMD retires
+16 lanes of an FP32 operation per clock, so one wave-64 VALU instruction
+occupies its SIMD for 4 clocks; 256 CUs x 4 SIMDs at 2.4 GHz.
 """
 from __future__ import annotations
 
@@ -84,6 +90,27 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_b
     }
 
 
+NUM_SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_CLOCKS = 4
+
+
+def issue_summary(pmc_dir: str, kernel: str, cmd: str, sources=KERNEL_SOURCES) -> str:
+    t = counters(pmc_dir)
+    name = _pick(t, kernel)
+    means = {c: sum(v) / len(v) for c, v in sorted(t[name].items())}
+    n = len(next(iter(t[name].values())))
+    lines = ["# rocprofv3 instruction counts per dispatch", f"# command: {cmd}",
+             f"# kernel source hash: {kernel_source_hash(sources)} ({', '.join(sources)})",
+             f"# kernel: {name.replace('void ', '')[:100]}", f"# dispatches: {n}", ""]
+    lines += [f"{c:24s} {v:18.0f}" for c, v in means.items()]
+    if "SQ_INSTS_VALU" in means:
+        ms = means["SQ_INSTS_VALU"] * VALU_CLOCKS / (NUM_SIMDS * CLOCK_HZ) * 1e3
+        lines += ["", f"VALU issue time at {CLOCK_HZ / 1e9:.1f} GHz, {VALU_CLOCKS} clocks per wave instruction, "
+                      f"{NUM_SIMDS} SIMDs: {ms:.3f} ms per dispatch"]
+    return "\n".join(lines) + "\n"
+
+
 def timed_dispatches(trace_dir: str, skip_steps: int, steps_total: int):
     """{kernel: [duration ns]} of the dispatches of the timed steps: a kernel
     launched c times over steps_total steps runs c // steps_total times per step,
@@ -150,8 +177,17 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, default=256 << 20)
     c.add_argument("--cmd", required=True)
     c.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
+    i = sub.add_parser("issue")
+    i.add_argument("pmc_dir")
+    i.add_argument("out")
+    i.add_argument("--kernel", default="k_correlate")
+    i.add_argument("--cmd", required=True)
+    i.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
     a = ap.parse_args(argv)
-    if a.what == "trace":
+    if a.what == "issue":
+        with open(a.out, "w") as f:
+            f.write(issue_summary(a.pmc_dir, a.kernel, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES))
+    elif a.what == "trace":
         with open(a.out, "w") as f:
             f.write(trace_summary(a.trace_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES,
                                   skip=a.warmup, steps_total=a.steps_total))
