@@ -113,7 +113,8 @@ struct RefineArgs {
 // <= 1, else 2 * kMaxRefineRadius + 3).
 constexpr int kRefineParts = 16;
 
-hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st);
+// partial sums of |x|^2 of every block (blocks of at most max_len samples)
+hipError_t launch_block_power(const BlockTable& bt, int max_blocks, int64_t max_len, double* parts, hipStream_t st);
 // exps[b] = round(log2(sqrt(M * Pxhat_b))): the 16-bit storage prescale of block b
 hipError_t launch_block_exponent(const BlockTable& bt, int max_blocks, const double* parts, int M, int* exps,
                                  hipStream_t st);

@@ -25,30 +25,36 @@ using namespace kdev;
 namespace {
 
 // ------------------------------------------------------------------ block power
-// Partial sums of block b in parts[b][*]: item part * blocks + b sums
-// the part-th chunk of the block (chunks of at least kPowerMinChunk samples,
-// so short blocks use few parts and the rest hold zeros); workgroups stride
-// over the items of the batch, and every item is summed in the same order
-// whichever workgroup takes it, so the sums are deterministic.
+// Partial sums of block b in parts[b][*]: part p sums the p-th chunk of the
+// block (chunks of at least kPowerMinChunk samples, so a block of n samples
+// fills the first power_parts(n) <= kPowerParts parts and no more are read).
+// Item p * blocks + b, p < the parts of the longest block the plan takes;
+// workgroups stride over the items, and every item is summed in the same
+// order whichever workgroup takes it, so the sums are deterministic.
 constexpr int kPowerMaxGrid = 4096;
 constexpr int64_t kPowerMinChunk = 4096;
 
-__global__ __launch_bounds__(256) void k_block_power(BlockTable bt, double* __restrict__ parts) {
+__host__ __device__ __forceinline__ int64_t power_chunk(int64_t n) {
+    const int64_t c = (n + kPowerParts - 1) / kPowerParts;
+    return c > kPowerMinChunk ? c : kPowerMinChunk;
+}
+
+__host__ __device__ __forceinline__ int power_parts(int64_t n) {
+    return n > 0 ? int((n + power_chunk(n) - 1) / power_chunk(n)) : 0;
+}
+
+__global__ __launch_bounds__(256) void k_block_power(BlockTable bt, double* __restrict__ parts, int max_parts) {
     __shared__ double red[4];
     const int nb = bt.nblocks();
-    const int items = nb * kPowerParts;
-    // part-major order: the non-empty low parts of every block come first and
-    // spread over distinct workgroups
+    const int items = nb * max_parts;
+    // part-major order: the low parts of every block come first and spread
+    // over distinct workgroups
     for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
         const int b = it % nb, part = it / nb;
         const BlockDesc d = bt.get(b);
-        int64_t chunk = (d.n + kPowerParts - 1) / kPowerParts;
-        chunk = chunk > kPowerMinChunk ? chunk : kPowerMinChunk;
+        const int64_t chunk = power_chunk(d.n);
         const int64_t beg = int64_t(part) * chunk;
-        if (beg >= d.n) {                            // uniform: an empty part
-            if (threadIdx.x == 0) parts[size_t(b) * kPowerParts + part] = 0.0;
-            continue;
-        }
+        if (beg >= d.n) continue;                    // uniform: past this block's parts
         const int64_t end = beg + chunk < d.n ? beg + chunk : d.n;
         double acc = 0.0;
         for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
@@ -76,7 +82,8 @@ __global__ void k_fill_i32(int* p, int64_t count) {
 // mean block power from the fixed-order partial sums
 __device__ __forceinline__ double block_mean_power(const double* __restrict__ parts, int64_t n) {
     double s = 0.0;
-    for (int i = 0; i < kPowerParts; ++i) s += parts[i];
+    const int np = power_parts(n);
+    for (int i = 0; i < np; ++i) s += parts[i];
     return n > 0 ? s / double(n) : 0.0;
 }
 
@@ -446,9 +453,10 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(BlockTable bt, cons
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_block_power(const BlockTable& bt, int max_blocks, double* parts, hipStream_t st) {
-    const unsigned grid = unsigned(std::min<int64_t>(int64_t(max_blocks) * kPowerParts, kPowerMaxGrid));
-    hipLaunchKernelGGL(k_block_power, dim3(grid), dim3(256), 0, st, bt, parts);
+hipError_t launch_block_power(const BlockTable& bt, int max_blocks, int64_t max_len, double* parts, hipStream_t st) {
+    const int mp = std::max(power_parts(max_len), 1);
+    const unsigned grid = unsigned(std::min<int64_t>(int64_t(max_blocks) * mp, kPowerMaxGrid));
+    hipLaunchKernelGGL(k_block_power, dim3(grid), dim3(256), 0, st, bt, parts, mp);
     return hipGetLastError();
 }
 

@@ -243,7 +243,7 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     const int nb_grid = batch ? g.max_blocks : 1;
     {
         KernelTimer kt(p, ACQ_KERNEL_BLOCK_POWER);
-        ACQ_HIP(acq::launch_block_power(bt, nb_grid, p->d_parts, st));
+        ACQ_HIP(acq::launch_block_power(bt, nb_grid, c.max_block_len, p->d_parts, st));
     }
     if (c.precision != ACQ_FP32) ACQ_HIP(acq::launch_block_exponent(bt, nb_grid, p->d_parts, int(g.M), p->d_exps, st));
     ACQ_HIP(acq::launch_fill_u64(p->d_keys, int64_t(nb_grid) * c.num_tags, st));
