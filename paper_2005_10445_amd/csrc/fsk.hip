@@ -8,8 +8,9 @@
 //                     with the spectra of h_BP * h_1 and h_BP * h_0, two inverse
 //                     transforms, demodulation d = (|f1|-|f0|)/(|f1|+|f0|),
 //                     u = |f1|-|f0|.  Output d and u (block) or d (replica).
-//   k_fsk_pack      : overlap-save segments 2g and 2g+1 of d as the real and
-//                     imaginary parts of one complex M-point input (slot g)
+//   k_fsk_pack      : overlap-save segments 2s and 2s+1 of the call (numbered
+//                     over its blocks) as the real and imaginary parts of one
+//                     complex M-point input (slot s)
 //   (forward spectra of the slots and of the templates: launch_forward, the
 //    decimation-in-time transform of the acquisition path)
 //   k_fsk_correlate : the real cross-correlation of d with each template by
@@ -17,7 +18,12 @@
 //                     transform of Z_g conj(D^(c)) / M holds the correlation of
 //                     segment 2g in its real part and of segment 2g+1 in its
 //                     imaginary part: one complex transform per two segments.
-//                     The peak search uses |c|.  An M-point inverse
+//                     Two tracking segments with different templates share
+//                     a slot too: with Z the slot's spectrum, X_A = (Z[i] +
+//                     conj Z[-i]) / 2 and j X_B = (Z[i] - conj Z[-i]) / 2,
+//                     so the product is (Z[i] (B_a + B_b) + conj Z[-i]
+//                     (B_a - B_b)) / 2 for the conjugate spectra B of the two
+//                     templates.  The peak search uses |c|.  An M-point inverse
 //                     transform (M up to 2^17) runs as P = M / Msub phases of
 //                     an Msub-point transform: for output lag tau = P u + rho,
 //                       G_rho[i'] = exp(+j 2 pi i' rho / M)
@@ -50,10 +56,12 @@ namespace {
 constexpr int kFrontLog = 12;                 // composed filters applied on 4096-point segments
 constexpr int kFrontN = 1 << kFrontLog;
 constexpr int kFskMaxGrid = 256;              // workgroups (and scratch slots) of the correlation: one per CU
+constexpr int kFskSplitMaxGrid = 2048;        // workgroups of the one-phase-per-workgroup form (no scratch)
 
 // One block of an FSK call: the searching window (tag -1: every template) or
-// one tracking task (its tag only).  Front-end segments and packed segment
-// pairs are numbered globally over the call's blocks.
+// one tracking task (its tag only).  Front-end segments and correlation
+// segments are numbered globally over the call's blocks; slot s holds
+// correlation segments 2s and 2s+1, which may belong to different blocks.
 struct FskTask {
     const int16_t* iq;          // device [n][2]
     int64_t n;                  // samples
@@ -61,7 +69,7 @@ struct FskTask {
     int64_t zoff;               // offset of the block's d and u in the plan's arrays
     int32_t tag;                // -1 searching; else the tracked template
     int32_t fseg0, nfseg;       // front-end segments
-    int32_t slot0, nslots;      // packed segment pairs
+    int32_t unit0;              // first correlation segment (global number)
     int32_t nseg;               // overlap-save segments of the correlation
 };
 
@@ -71,7 +79,7 @@ struct FskTasks {
     int32_t track;              // 1: tracking tasks (one template each)
 };
 
-// block holding global index g of the field (fseg0 or slot0), by binary search
+// block holding global index g of the field (fseg0 or unit0), by binary search
 template <int32_t FskTask::*FIRST>
 __device__ __forceinline__ int fsk_task_of(const FskTasks& tt, int g) {
     int lo = 0, hi = tt.count - 1;
@@ -174,26 +182,29 @@ __global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
     }
 }
 
-// zp[s][i] = (d[2g V + i], d[(2g+1) V + i]) of slot s = slot0 + g of its
-// block, zero past the block or past its last segment.  256 threads per
+// zp[s][i] = (d_A[jA V + i], d_B[jB V + i]) for the correlation segments 2s
+// (segment jA of block A) and 2s+1 (segment jB of block B; zero if the call
+// has no such segment), zero past the end of a block.  256 threads per
 // workgroup, each workgroup kFskPackChunk consecutive i of one slot: the slot,
-// and so the block lookup, is uniform over the workgroup and done once.
+// and so the block lookups, are uniform over the workgroup and done once.
 constexpr int kFskPackChunk = 4096;
 
 __global__ __launch_bounds__(256) void k_fsk_pack(FskTasks tt, const float* __restrict__ d, int64_t V, int64_t M,
-                                                  float2* __restrict__ zp) {
+                                                  int units, float2* __restrict__ zp) {
     const int64_t chunk = M < kFskPackChunk ? M : kFskPackChunk;
     const int64_t per_slot = M / chunk;
     const int64_t s = int64_t(blockIdx.x) / per_slot;
-    const FskTask tk = tt.t[fsk_task_of<&FskTask::slot0>(tt, int(s))];
-    const int64_t g = s - tk.slot0;
-    const float* db = d + tk.zoff;
-    const bool second = 2 * g + 1 < tk.nseg;
+    const int ua = int(2 * s), ub = int(2 * s + 1);
+    const FskTask ta = tt.t[fsk_task_of<&FskTask::unit0>(tt, ua)];
+    const bool second = ub < units;
+    const FskTask tb = second ? tt.t[fsk_task_of<&FskTask::unit0>(tt, ub)] : ta;
+    const float* da = d + ta.zoff;
+    const float* dbb = d + tb.zoff;
+    const int64_t sa = int64_t(ua - ta.unit0) * V, sb = int64_t(ub - tb.unit0) * V;
     const int64_t i0 = (int64_t(blockIdx.x) - s * per_slot) * chunk;
     for (int64_t i = i0 + threadIdx.x; i < i0 + chunk; i += 256) {
-        const int64_t p0 = 2 * g * V + i, p1 = (2 * g + 1) * V + i;
-        const float re = p0 < tk.n ? db[p0] : 0.f;
-        const float im = (second && p1 < tk.n) ? db[p1] : 0.f;
+        const float re = sa + i < ta.n ? da[sa + i] : 0.f;
+        const float im = (second && sb + i < tb.n) ? dbb[sb + i] : 0.f;
         zp[s * M + i] = make_float2(re, im);
     }
 }
@@ -224,18 +235,24 @@ struct FskCorrArgs {
     FskTasks tasks;
     int64_t V;
     int32_t M, Msub, P, T, nslots;      // nslots: slots of the call
+    int32_t units;                      // correlation segments of the call
+    int32_t split;                      // 1: one phase per work item (set by the launcher)
 };
 
 // Work item (template t, slot s), taken with a stride of the grid: searching,
-// items t * nslots + s for every template; tracking, item s for its task's
-// template.  Slot s holds segments 2g (real part) and 2g+1 (imaginary part)
-// of its block, g = s - slot0.
+// items t * nslots + s for every template; tracking, item s with the
+// templates of its segments' tasks.  Slot s holds correlation segments 2s
+// (real part) and 2s+1 (imaginary part).
 //   first step, once per item: for each i' < Msub, the spectrum products
-//     Y_a = Z_g[i' + Msub a] conj(D_t[i' + Msub a]) / M, a < P, and
+//     Y_a = Z_s[i' + Msub a] B_t[i' + Msub a], a < P, B_t = conj(D_t) / M (or
+//     the two-template product when the segments' templates differ), and
 //     G_rho[i'] = exp(+j 2 pi i' rho / M) sum_a Y_a exp(+j 2 pi a rho / P),
 //     written to the workgroup's scratch (each input read once);
 //   then, per phase rho, the Msub-point inverse transform of G_rho (lag
-//   P u + rho) and the lane maximum of |c| over both segments and all phases.
+//   P u + rho) and each segment's lane maximum of |c| over all phases.
+// SPLIT (calls with fewer items than CUs, e.g. a few tracking tasks): work
+// item (item, rho) forms its G_rho in registers from the P products, reading
+// the spectra once per phase instead of going through the scratch.
 // exp(+j 2 pi k / 8), k < 8 (the values FP64 rounds to in FP32)
 __device__ __forceinline__ float2 root8(int k) {
     constexpr float h = 0.70710678118654752f;
@@ -251,79 +268,151 @@ __device__ __forceinline__ float2 root8(int k) {
     }
 }
 
-template <class E, int PP, bool DUMP>
+// exp(+j 2 pi k / 8) for a run-time k (selects, no table)
+__device__ __forceinline__ float2 root8_rt(int k) {
+    constexpr float h = 0.70710678118654752f;
+    auto c = [](int kk) {                    // cos(pi kk / 4), kk < 8
+        const float mag = (kk & 1) ? h : ((kk & 2) ? 0.0f : 1.0f);
+        return (kk >= 3 && kk <= 5) ? -mag : mag;
+    };
+    return make_float2(c(k & 7), c((k + 6) & 7));
+}
+
+// TRACK: tracking calls, whose slots may hold segments of two templates.
+template <class E, int PP, bool DUMP, bool SPLIT, bool TRACK>
 __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
     constexpr int NW = E::NT / 64;
     __shared__ float2 lds[E::LDS];
     __shared__ float2 extra[E::EXTRA];
-    __shared__ unsigned long long red[NW];
+    __shared__ unsigned long long red[2 * NW];
     E eng;
     eng.init(a.rootsSub, extra);
     const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     const int mmask = a.M - 1;
     float2* G = a.scratch + size_t(blockIdx.x) * size_t(a.M);
-    const int items = a.tasks.track ? a.nslots : a.T * a.nslots;
-    for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
+    const int items = (a.tasks.track ? a.nslots : a.T * a.nslots) * (SPLIT ? PP : 1);
+    for (int wi = int(blockIdx.x); wi < items; wi += int(gridDim.x)) {
+        const int it = SPLIT ? wi / PP : wi;
+        const int rho0 = SPLIT ? wi % PP : 0, rho1 = SPLIT ? rho0 + 1 : PP;
         const int slot = a.tasks.track ? it : it % a.nslots;
-        const int bi = fsk_task_of<&FskTask::slot0>(a.tasks, slot);
-        const FskTask tk = a.tasks.t[bi];
-        const int tag = a.tasks.track ? tk.tag : it / a.nslots;
-        const int kidx = a.tasks.track ? bi : tag;          // key of the result
-        const int j = slot - tk.slot0;
+        // the slot's two correlation segments: block, segment within it, template, key
+        int bk[2], jseg[2], tg[2], kidx[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int u = 2 * slot + h < a.units ? 2 * slot + h : 2 * slot;     // absent: as the first
+            bk[h] = fsk_task_of<&FskTask::unit0>(a.tasks, u);
+            jseg[h] = 2 * slot + h < a.units ? u - a.tasks.t[bk[h]].unit0 : -1;
+            tg[h] = a.tasks.track ? a.tasks.t[bk[h]].tag : it / a.nslots;
+            kidx[h] = a.tasks.track ? bk[h] : tg[h];
+        }
         const float2* Xj = a.X + size_t(slot) * size_t(a.M);
-        const float2* B = a.bank + size_t(tag) * size_t(a.M);
+        const float2* B = a.bank + size_t(tg[0]) * size_t(a.M);
+        const float2* Bb = a.bank + size_t(tg[1]) * size_t(a.M);
+        const bool two = TRACK && tg[1] != tg[0];              // uniform: tracking segments of two templates
         // first step: P outputs per i' from P products; the P-point DFT uses
         // constant eighth roots of unity, so each i' issues its 2P product
         // loads and P-1 twiddle loads together (one i' at a time keeps them in
         // registers without holding all 16)
-#pragma unroll 1
-        for (int m = 0; m < 16; ++m) {
-            const int ip = eng.in_index(m);
-            float2 y[PP], tw[PP];
+        // the P spectrum products of input index ip
+        auto products = [&](int ip, float2 (&y)[PP]) {
+            if (!two) {
 #pragma unroll
-            for (int q = 0; q < PP; ++q) y[q] = cmul(Xj[ip + q * a.Msub], B[ip + q * a.Msub]);
+                for (int q = 0; q < PP; ++q) y[q] = cmul(Xj[ip + q * a.Msub], B[ip + q * a.Msub]);
+            } else {
 #pragma unroll
-            for (int r = 1; r < PP; ++r) tw[r] = a.rootsM[(ip * r) & mmask];
+                for (int q = 0; q < PP; ++q) {
+                    const int i = ip + q * a.Msub;
+                    const float2 z = Xj[i], zm = Xj[(a.M - i) & mmask];
+                    const float2 ba = B[i], bb = Bb[i];
+                    const float2 s = cadd(ba, bb), d = make_float2(ba.x - bb.x, ba.y - bb.y);
+                    const float2 r = cadd(cmul(z, s), cmul(make_float2(zm.x, -zm.y), d));
+                    y[q] = make_float2(0.5f * r.x, 0.5f * r.y);
+                }
+            }
+        };
+        float2 gs[16];                            // SPLIT: G_rho0 of this thread's inputs
+        if constexpr (SPLIT) {
+            float2 w[PP];                         // exp(+j 2 pi q rho0 / P)
 #pragma unroll
-            for (int rho = 0; rho < PP; ++rho) {
+            for (int q = 0; q < PP; ++q) w[q] = root8_rt(q * rho0 * (8 / PP));
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                // opaque index: its address arithmetic is not hoisted out of
+                // the item loop for all 16 registers at once
+                int ip = eng.in_index(m);
+                asm volatile("" : "+v"(ip));
+                float2 y[PP];
+                products(ip, y);
                 float2 acc = y[0];
 #pragma unroll
-                for (int q = 1; q < PP; ++q) acc = cadd(acc, cmul(y[q], root8((q * rho * (8 / PP)) & 7)));
-                if (rho) acc = cmul(acc, tw[rho]);
-                G[rho * a.Msub + ip] = acc;
+                for (int q = 1; q < PP; ++q) acc = cadd(acc, cmul(y[q], w[q]));
+                gs[m] = rho0 ? cmul(acc, a.rootsM[(ip * rho0) & mmask]) : acc;
+                asm volatile("" ::: "memory");    // one input index at a time: no hoisting of later loads
+            }
+        } else {
+#pragma unroll 1
+            for (int m = 0; m < 16; ++m) {
+                const int ip = eng.in_index(m);
+                float2 y[PP], tw[PP];
+                products(ip, y);
+#pragma unroll
+                for (int r = 1; r < PP; ++r) tw[r] = a.rootsM[(ip * r) & mmask];
+#pragma unroll
+                for (int rho = 0; rho < PP; ++rho) {
+                    float2 acc = y[0];
+#pragma unroll
+                    for (int q = 1; q < PP; ++q) acc = cadd(acc, cmul(y[q], root8((q * rho * (8 / PP)) & 7)));
+                    if (rho) acc = cmul(acc, tw[rho]);
+                    G[rho * a.Msub + ip] = acc;
+                }
             }
         }
-        __threadfence_block();
-        __syncthreads();
+        if constexpr (!SPLIT) {
+            __threadfence_block();
+            __syncthreads();
+        }
         int ulim[2];
         int64_t sbeg[2];
-        unsigned long long best = 0ull;
-        for (int rho = 0; rho < PP; ++rho) {
+        unsigned long long best[2] = {0ull, 0ull};
+        int vlim[2];                                  // valid lags of each segment
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                sbeg[h] = int64_t(2 * j + h) * a.V;
-                const int64_t v64 = (2 * j + h < tk.nseg) ? (tk.lags - sbeg[h] < a.V ? tk.lags - sbeg[h] : a.V) : 0;
-                const int vlim = int(v64);
-                ulim[h] = vlim > rho ? (vlim - rho + PP - 1) / PP : 0;
-            }
+        for (int h = 0; h < 2; ++h) {
+            const int64_t lags = a.tasks.t[bk[h]].lags;
+            sbeg[h] = int64_t(jseg[h]) * a.V;
+            vlim[h] = jseg[h] >= 0 ? int(lags - sbeg[h] < a.V ? lags - sbeg[h] : a.V) : 0;
+        }
+        for (int rho = rho0; rho < rho1; ++rho) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) ulim[h] = vlim[h] > rho ? (vlim[h] - rho + PP - 1) / PP : 0;
             const int ob0 = eng.out_base();
             const int omin = eng.out_min();
             const bool hi = omin + E::HI_OFF < max(ulim[0], ulim[1]);
             float2 v[16];
 #pragma unroll
-            for (int m = 0; m < 16; ++m) v[m] = G[rho * a.Msub + eng.in_index(m)];
+            for (int m = 0; m < 16; ++m) {
+                if constexpr (SPLIT) v[m] = gs[m];
+                else v[m] = G[rho * a.Msub + eng.in_index(m)];
+            }
             eng.template transform<+1>(v, lds, b1, extra, hi);
             // output off of this lane is a valid lag of segment h when off < lim[h]
             int lim[2] = {ulim[0] - ob0, ulim[1] - ob0};
             asm volatile("" : "+v"(lim[0]), "+v"(lim[1]));
-            // this lane's largest |c| of the phase: the first segment's lags
-            // before the second's, each in increasing lag (strict comparison:
-            // the smallest lag of a tie within the phase)
-            float bp = -1.0f;
-            int boff = 0, bh = 0;
+            // this lane's largest |c| of the phase, in increasing lag (strict
+            // comparison: the smallest lag of a tie within the phase); one
+            // maximum per segment when tracking, else one over both segments
+            // (the first segment's lags come first)
+            constexpr int NR = TRACK ? 2 : 1;
+            float bp[NR];
+            int boff[NR], bh[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                bp[k] = -1.0f;
+                boff[k] = bh[k] = 0;
+            }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+                const int k = TRACK ? h : 0;
 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) {
                     const int r = E::visit(rr);
@@ -334,29 +423,41 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
                         if constexpr (DUMP) {
                             if (off < lim[h]) {
                                 const int64_t tau = sbeg[h] + int64_t(PP) * (ob0 + off) + rho;
-                                a.dump[size_t(tag) * size_t(tk.lags) + size_t(tau)] = cv;
+                                a.dump[size_t(tg[h]) * size_t(a.tasks.t[bk[h]].lags) + size_t(tau)] = cv;
                             }
                         }
-                        const bool take = pv > bp && off < lim[h];
-                        boff = take ? off : boff;
-                        bh = take ? h : bh;
-                        bp = take ? pv : bp;
+                        const bool take = pv > bp[k] && off < lim[h];
+                        boff[k] = take ? off : boff[k];
+                        bh[k] = take ? h : bh[k];
+                        bp[k] = take ? pv : bp[k];
                     }
                 }
             }
-            const unsigned lag = unsigned(sbeg[bh] + rho) + unsigned(ob0 + boff) * unsigned(PP);
-            const unsigned long long key = bp >= 0.0f
-                ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) | static_cast<unsigned long long>(~lag)
-                : 0ull;
-            best = key > best ? key : best;          // across phases the key order decides ties
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const unsigned lag = unsigned(sbeg[bh[k]] + rho) + unsigned(ob0 + boff[k]) * unsigned(PP);
+                const unsigned long long key = bp[k] >= 0.0f
+                    ? (static_cast<unsigned long long>(__float_as_uint(bp[k])) << 32) | static_cast<unsigned long long>(~lag)
+                    : 0ull;
+                best[k] = key > best[k] ? key : best[k];    // across phases the key order decides ties
+            }
         }
-        best = wave_max(best);
-        if (lane == 0) red[wave] = best;
+        // one key per result: the two segments' maxima combine when they
+        // belong to the same result (searching, or one tracking task)
+        const bool same = kidx[1] == kidx[0];
+        if (same) best[0] = best[1] > best[0] ? best[1] : best[0];
+        best[0] = wave_max(best[0]);
+        if (!same) best[1] = wave_max(best[1]);
+        if (lane == 0) {
+            red[wave] = best[0];
+            red[NW + wave] = best[1];
+        }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < (same ? 1 : 2)) {
+            const int h = int(threadIdx.x);
             unsigned long long m = 0ull;
-            for (int q = 0; q < NW; ++q) m = red[q] > m ? red[q] : m;
-            if (m) atomicMax(&a.keys[kidx], m);
+            for (int q = 0; q < NW; ++q) m = red[h * NW + q] > m ? red[h * NW + q] : m;
+            if (m) atomicMax(&a.keys[kidx[h]], m);
         }
         __syncthreads();                     // red[], scratch and LDS are reused by the next item
     }
@@ -572,10 +673,17 @@ __global__ __launch_bounds__(1024) void k_fsk_compact(const acq_fsk_detection* _
 
 template <class E, int PP>
 void launch_fsk_corr_ep(const FskCorrArgs& a, int grid, hipStream_t st) {
-    if (a.dump)
-        hipLaunchKernelGGL((k_fsk_correlate<E, PP, true>), dim3(grid), dim3(E::NT), 0, st, a);
+    const bool track = a.tasks.track != 0;
+    if (a.dump)                                          // searching only
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, true, false, false>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (PP > 1 && a.split && track)
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, PP != 1, true>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (PP > 1 && a.split)
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, PP != 1, false>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (track)
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, false, true>), dim3(grid), dim3(E::NT), 0, st, a);
     else
-        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false>), dim3(grid), dim3(E::NT), 0, st, a);
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, false, false>), dim3(grid), dim3(E::NT), 0, st, a);
 }
 
 // M <= 2^14 runs as one phase (P = 1) on the Stockham engine of that size;
@@ -645,8 +753,9 @@ int fsk_geometry(const acq_fsk_config* c, FskGeometry* g) {
     if (c->max_track_tasks < 0 || c->max_track_tasks > 65536)
         return fail(ACQ_ERR_INVALID_ARG, "max_track_tasks outside [0, 65536]");
     g->max_tasks = c->max_track_tasks > 0 ? c->max_track_tasks : 16;
-    // a searching window uses ceil(max_seg / 2) pairs; tracking blocks of total
-    // length <= max_block_len use at most max_block_len / (2V) + one per task
+    // a searching window uses ceil(max_seg / 2) slots; tracking blocks of total
+    // length <= max_block_len have at most max_block_len / V + one segment per
+    // task, two to a slot (the bound below keeps room for one slot per task)
     g->slots = (g->max_seg + 1) / 2 + g->max_tasks + 1;
     g->items = std::max<int>(c->num_tags, g->max_tasks);
     const int64_t T = c->num_tags;
@@ -1034,20 +1143,20 @@ int enqueue_fsk(acq_fsk_plan_s* p, int nblocks, bool track, float* dump, int* it
     const int T = p->cfg.num_tags;
     hipStream_t st = p->stream;
     int64_t zoff = 0;
-    int fsegs = 0, slots = 0;
+    int fsegs = 0, units = 0;
     for (int b = 0; b < nblocks; ++b) {
         acq::FskTask& tk = p->h_tasks[b];
         tk.lags = tk.n - g.nt + 1;
         tk.zoff = zoff;
         tk.nseg = tk.lags > 0 ? int((tk.lags + g.V - 1) / g.V) : 0;
-        tk.nslots = (tk.nseg + 1) / 2;
         tk.nfseg = tk.lags > 0 ? int((tk.n + g.vf - 1) / g.vf) : 0;
         tk.fseg0 = fsegs;
-        tk.slot0 = slots;
+        tk.unit0 = units;
         zoff += tk.n;
         fsegs += tk.nfseg;
-        slots += tk.nslots;
+        units += tk.nseg;
     }
+    const int slots = (units + 1) / 2;              // correlation segments 2s and 2s+1 share slot s
     if (zoff > p->cfg.max_block_len) return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "blocks longer than max_block_len in all");
     if (slots > g.slots) return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "blocks need more segments than the plan holds");
     *items = track ? nblocks : T;
@@ -1061,7 +1170,7 @@ int enqueue_fsk(acq_fsk_plan_s* p, int nblocks, bool track, float* dump, int* it
     }
     const int64_t packed = int64_t(slots) * g.M;      // M is a power of two >= 2^10
     hipLaunchKernelGGL(acq::k_fsk_pack, dim3(unsigned(packed / std::min<int64_t>(g.M, acq::kFskPackChunk))), dim3(256),
-                       0, st, tt, p->d_d, g.V, g.M, p->d_zp);
+                       0, st, tt, p->d_d, g.V, g.M, units, p->d_zp);
     FSK_HIP(hipGetLastError());
     BlockTable bt{};
     bt.one.x = p->d_zp;
@@ -1091,8 +1200,14 @@ int enqueue_fsk(acq_fsk_plan_s* p, int nblocks, bool track, float* dump, int* it
     ca.T = T;
     ca.scratch = p->d_scratch;
     ca.nslots = slots;
-    const int64_t work = track ? int64_t(slots) : int64_t(T) * slots;
-    const int grid = int(std::min<int64_t>(work, p->corr_grid));
+    ca.units = units;
+    int64_t work = track ? int64_t(slots) : int64_t(T) * slots;
+    int grid = int(std::min<int64_t>(work, p->corr_grid));
+    if (!dump && g.P > 1 && work < acq::kFskMaxGrid) {   // fewer items than CUs: one phase per workgroup
+        ca.split = 1;
+        work *= g.P;
+        grid = int(std::min<int64_t>(work, acq::kFskSplitMaxGrid));
+    }
     {
         FskTimer kt(p, ACQ_FSK_KERNEL_CORRELATE);
         FSK_HIP(acq::launch_fsk_correlate(ca, grid, g.log2_sub, st));

@@ -255,6 +255,43 @@ def test_tracking_tasks(dev):
         _check_peak(d, r, dd, uu, ss, tm[t], _template_front(case, bits[t], bp))
 
 
+def test_tracking_segments_share_slots_across_tasks(dev):
+    """Tracking tasks of 2, 1, 3 and 1 correlation segments: seven segments in
+    four slots, so one slot holds segments of two tasks with different
+    templates (separated through the mirror relation), one two segments of one
+    task, and the last slot one segment.  Every task equals the searching
+    result for its tag on the same block and the oracle."""
+    case = CASES[1]
+    name, T, nb, sps, ntaps, cut, f1, f0, lo, N, M, ntx = case
+    bits = siggen.make_fsk_bits(860, T, nb)
+    bp = siggen.fsk_bandpass(ntaps, cut, FS)
+    n_t = nb * sps + ntaps + sps - 2
+    V = M - n_t + 1
+    spec = [(2, 1, [1]), (1, 0, [0, 3]), (3, 2, [2]), (1, 1, [])]      # segments, tag, packets
+    blocks, tasks = [], []
+    for i, (nseg, tag, tags) in enumerate(spec):
+        n = n_t - 1 + (nseg - 1) * V + V // 2
+        iq, _ = siggen.make_fsk_block(861 + i, n, bits, sps, FS, f1, f0, lo, len(tags), snr_db=(-3.0, 3.0),
+                                      tags=tags, delays=[(k + 1) * (n - n_t) // (len(tags) + 1) for k in range(len(tags))])
+        assert -(-(n - n_t + 1) // V) == nseg
+        blocks.append(iq)
+        tasks.append((i, tag))
+    dev_blocks = [torch.from_numpy(b).to(dev) for b in blocks]
+    total = sum(len(b) for b in blocks)
+    from paper_2005_10445_amd.fsk import FskPlan
+    with FskPlan(bits, FS, lo, f1, f0, bp, sps, total, fft_len=M, max_track_tasks=4) as plan:
+        got = plan.track([(dev_blocks[b], t) for b, t in tasks])
+        searched = [plan.detect(x) for x in dev_blocks]
+    assert [d.block for d in got] == list(range(len(tasks)))
+    for d, (b, t) in zip(got, tasks):
+        s = searched[b][t]
+        assert (d.tag, d.lag, d.toa, d.xcorr, d.q, d.p, d.z) == (s.tag, s.lag, s.toa, s.xcorr, s.q, s.p, s.z)
+        dd, uu, ss = _oracle_front(case, blocks[b], bp)
+        tm = {t: ofsk.replica_template(bits[t], FS, bp, f1, f0, sps)}
+        r = ofsk.fsk_acquire(dd, uu, tm, tags=[t])[0]
+        _check_peak(d, r, dd, uu, ss, tm[t], _template_front(case, bits[t], bp))
+
+
 def test_tracking_errors(dev):
     from paper_2005_10445_amd import AcqError
     case = CASES[0]
