@@ -119,7 +119,19 @@ __global__ __launch_bounds__(E::NT) void k_forward_sub(FwdArgs a) {
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     const int per_seg = a.ncls * a.spc;
     const int items = a.blocks.total_seg() * per_seg;
-    for (int it = int(blockIdx.x); it < items; it += int(gridDim.x)) {
+    // the per_seg items of a segment read interleaved samples of one input
+    // range: with one item per workgroup, place them on one XCD (workgroups
+    // go to the XCDs in turn), so that its L2 fetches the range once.  Within
+    // each group of kXcds * per_seg workgroups, workgroup j takes item
+    // k = j / kXcds of segment j % kXcds of the group.
+    const int grp = kXcds * per_seg;
+    const bool xcd_map = int(gridDim.x) >= items && per_seg > 1;
+    for (int b = int(blockIdx.x); b < items; b += int(gridDim.x)) {
+        int it = b;
+        if (xcd_map && b < items / grp * grp) {
+            const int q = b / grp, j = b - q * grp;
+            it = (q * kXcds + j % kXcds) * per_seg + j / kXcds;
+        }
         const int g = it / per_seg, rem = it - g * per_seg, c = rem / a.spc, r = rem - c * a.spc;
         const int bi = a.blocks.block_of_segment(g);
         const BlockDesc d = a.blocks.get(bi);
