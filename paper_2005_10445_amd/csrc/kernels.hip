@@ -161,7 +161,10 @@ __global__ __launch_bounds__(E::NT) void k_forward_sub(FwdArgs a) {
 
 // 256 threads per workgroup, one i per thread; a workgroup's 256 i lie in one
 // slot (Msub is a multiple of 256).  Workgroups past the slots in use exit.
-template <int PREC>
+// SPC (= a.spc) is a template argument so the spc inputs stay in registers.
+// The twiddle of phase r is the r-th power of exp(-j 2 pi io / M): one table
+// load per output, then products (exact table values for spc <= 2).
+template <int PREC, int SPC>
 __global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
     using St = dev::Storage<PREC>;
     const int per_slot = a.Msub / 256;
@@ -171,13 +174,22 @@ __global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
     float2* X = a.X + size_t(g) * size_t(a.M);
     float xs = 1.0f;
     if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -a.exps[a.blocks.block_of_segment(g / a.ncls)]);
-    const int mmask = a.M - 1;
-    float2 F[8];
-    for (int r = 0; r < a.spc; ++r) F[r] = X[r * a.Msub + i];
-    for (int q = 0; q < a.spc; ++q) {
+    float2 F[SPC];
+#pragma unroll
+    for (int r = 0; r < SPC; ++r) F[r] = X[r * a.Msub + i];
+#pragma unroll
+    for (int q = 0; q < SPC; ++q) {
         const int io = i + q * a.Msub;
         float2 c = F[0];
-        for (int r = 1; r < a.spc; ++r) c = cadd(c, cmulc(F[r], a.rootsM[(int)((int64_t(io) * r) & mmask)]));
+        if constexpr (SPC > 1) {
+            const float2 w1 = a.rootsM[io];
+            float2 w = w1;
+#pragma unroll
+            for (int r = 1; r < SPC; ++r) {
+                c = cadd(c, cmulc(F[r], w));
+                if (r + 1 < SPC) w = cmul(w, w1);
+            }
+        }
         if constexpr (PREC == ACQ_FP32)
             X[io] = c;
         else
@@ -498,6 +510,22 @@ static hipError_t fwd_e(const FwdArgs& a, int grid, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int PREC>
+static hipError_t combine_p(const FwdArgs& a, dim3 grid, hipStream_t st) {
+    switch (a.spc) {
+        case 1: hipLaunchKernelGGL((k_forward_combine<PREC, 1>), grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_forward_combine<PREC, 2>), grid, dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_forward_combine<PREC, 3>), grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_forward_combine<PREC, 4>), grid, dim3(256), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_forward_combine<PREC, 5>), grid, dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_forward_combine<PREC, 6>), grid, dim3(256), 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_forward_combine<PREC, 7>), grid, dim3(256), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_forward_combine<PREC, 8>), grid, dim3(256), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_forward(const FwdArgs& a, int grid, int combine_slots, int log2_sub, int prec, hipStream_t st) {
     if (grid <= 0 || combine_slots <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub || a.Msub % 256 || a.spc < 1 || a.spc > 8) return hipErrorInvalidValue;
@@ -513,11 +541,12 @@ hipError_t launch_forward(const FwdArgs& a, int grid, int combine_slots, int log
     if (e != hipSuccess) return e;
     const dim3 cgrid(unsigned(combine_slots) * unsigned(a.Msub / 256));
     switch (prec) {
-        case ACQ_FP32: hipLaunchKernelGGL((k_forward_combine<ACQ_FP32>), cgrid, dim3(256), 0, st, a); break;
-        case ACQ_FP16: hipLaunchKernelGGL((k_forward_combine<ACQ_FP16>), cgrid, dim3(256), 0, st, a); break;
-        case ACQ_BF16: hipLaunchKernelGGL((k_forward_combine<ACQ_BF16>), cgrid, dim3(256), 0, st, a); break;
+        case ACQ_FP32: e = combine_p<ACQ_FP32>(a, cgrid, st); break;
+        case ACQ_FP16: e = combine_p<ACQ_FP16>(a, cgrid, st); break;
+        case ACQ_BF16: e = combine_p<ACQ_BF16>(a, cgrid, st); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
