@@ -161,8 +161,8 @@ def main():
                     help="copy: a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(the path runs on a single GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the library runs on a single GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -65,7 +65,7 @@ typedef enum acq_status {
     ACQ_ERR_DEVICE = -3,             /* a HIP call or kernel launch failed          */
     ACQ_ERR_TRUNCATED = -4,          /* more detections than capacity; see n_found */
     ACQ_ERR_BLOCK_TOO_LONG = -5,     /* n > max_block_len of the plan              */
-    ACQ_ERR_UNSUPPORTED = -7         /* valid request outside what this build does */
+    ACQ_ERR_UNSUPPORTED = -7         /* valid request outside what the library implements */
 } acq_status;
 
 typedef enum acq_precision {
