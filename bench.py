@@ -37,8 +37,12 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3
 # rocprofv3 HBM byte counts of the correlation kernel, per workload
 TRAFFIC_FILES = {"tagbank_fp32": os.path.join(ROOT, "profiles", "correlate_tagbank_traffic.json"),
+                 "tagbank_fp16": os.path.join(ROOT, "profiles", "correlate_tagbank_fp16_traffic.json"),
+                 "tagbank_bf16": os.path.join(ROOT, "profiles", "correlate_tagbank_bf16_traffic.json"),
+                 "batched_stream": os.path.join(ROOT, "profiles", "correlate_stream_traffic.json"),
                  "tracking": os.path.join(ROOT, "profiles", "correlate_tracking_traffic.json"),
-                 "fsk_search": os.path.join(ROOT, "profiles", "fsk_correlate_traffic.json")}
+                 "fsk_search": os.path.join(ROOT, "profiles", "fsk_correlate_traffic.json"),
+                 "fsk_tracking": os.path.join(ROOT, "profiles", "fsk_tracking_correlate_traffic.json")}
 
 
 def log(*a):

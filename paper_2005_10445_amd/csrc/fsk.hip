@@ -292,9 +292,21 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
     const int mmask = a.M - 1;
     float2* G = a.scratch + size_t(blockIdx.x) * size_t(a.M);
     const int items = (a.tasks.track ? a.nslots : a.T * a.nslots) * (SPLIT ? PP : 1);
+    // SPLIT with one work item per workgroup: the PP phases of an item read
+    // the same spectra, so they run on one XCD (workgroups go to the XCDs in
+    // turn) and share its L2.  Within each group of kXcds * PP workgroups,
+    // workgroup j takes phase j / kXcds of item j % kXcds of the group.
+    constexpr int grp = kXcds * PP;
+    const bool xcd_map = SPLIT && int(gridDim.x) >= items;
     for (int wi = int(blockIdx.x); wi < items; wi += int(gridDim.x)) {
-        const int it = SPLIT ? wi / PP : wi;
-        const int rho0 = SPLIT ? wi % PP : 0, rho1 = SPLIT ? rho0 + 1 : PP;
+        int it = SPLIT ? wi / PP : wi;
+        int rho0 = SPLIT ? wi % PP : 0;
+        if (xcd_map && wi < items / grp * grp) {
+            const int q = wi / grp, j = wi - q * grp;
+            it = q * kXcds + j % kXcds;
+            rho0 = j / kXcds;
+        }
+        const int rho1 = SPLIT ? rho0 + 1 : PP;
         const int slot = a.tasks.track ? it : it % a.nslots;
         // the slot's two correlation segments: block, segment within it, template, key
         int bk[2], jseg[2], tg[2], kidx[2];

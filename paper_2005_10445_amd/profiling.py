@@ -48,11 +48,12 @@ def _find(d: str, suffix: str) -> str:
 
 
 def counters(d: str):
-    """{kernel name: {counter: [value per dispatch]}} from a --pmc run."""
+    """{kernel name: {counter: [value per dispatch, in dispatch order]}} from a --pmc run."""
     out = defaultdict(lambda: defaultdict(list))
     with open(_find(d, "counter_collection.csv")) as f:
-        for r in csv.DictReader(f):
-            out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Dispatch_Id"]))
+    for r in rows:
+        out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
     return out
 
 
@@ -63,20 +64,25 @@ def _pick(table, substr):
     return names[0]
 
 
-def mean_counter(d: str, kernel_substr: str, counter: str) -> float:
+def mean_counter(d: str, kernel_substr: str, counter: str, last: int = 0) -> float:
+    """Mean of a counter over the kernel's dispatches (the last `last` ones if
+    > 0: the timed steps of a run whose plan-time tuning launched others)."""
     t = counters(d)
     vals = t[_pick(t, kernel_substr)][counter]
+    if last > 0:
+        vals = vals[-last:]
     return sum(vals) / len(vals)
 
 
-def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_bytes, cmd, sources=KERNEL_SOURCES):
+def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_bytes, cmd, sources=KERNEL_SOURCES,
+            last: int = 0):
     copy_name = "copyBuffer"
     f_copy = mean_counter(copy_fetch_dir, copy_name, "FETCH_SIZE")
     w_copy = mean_counter(copy_write_dir, copy_name, "WRITE_SIZE")
     f_scale = copy_bytes / f_copy          # bytes per counted KiB
     w_scale = copy_bytes / w_copy
-    f_k = mean_counter(fetch_dir, kernel, "FETCH_SIZE")
-    w_k = mean_counter(write_dir, kernel, "WRITE_SIZE")
+    f_k = mean_counter(fetch_dir, kernel, "FETCH_SIZE", last)
+    w_k = mean_counter(write_dir, kernel, "WRITE_SIZE", last)
     return {
         "kernel": kernel,
         "fetch_kib_counted": f_k, "write_kib_counted": w_k,
@@ -86,6 +92,7 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, kernel, copy_b
         "bytes_per_launch": f_k * f_scale + w_k * w_scale,
         "kernel_source_hash": kernel_source_hash(sources),
         "kernel_sources": list(sources),
+        "dispatches": f"last {last}" if last > 0 else "all",
         "command": cmd,
     }
 
@@ -177,6 +184,7 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, default=256 << 20)
     c.add_argument("--cmd", required=True)
     c.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
+    c.add_argument("--last", type=int, default=0, help="average only the kernel's last N dispatches")
     i = sub.add_parser("issue")
     i.add_argument("pmc_dir")
     i.add_argument("out")
@@ -193,7 +201,7 @@ def main(argv=None):
                                   skip=a.warmup, steps_total=a.steps_total))
     else:
         res = traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir, a.kernel,
-                      a.copy_bytes, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES)
+                      a.copy_bytes, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES, last=a.last)
         with open(a.out, "w") as f:
             json.dump(res, f, indent=1)
             f.write("\n")
