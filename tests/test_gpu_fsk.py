@@ -255,12 +255,12 @@ def test_tracking_tasks(dev):
         _check_peak(d, r, dd, uu, ss, tm[t], _template_front(case, bits[t], bp))
 
 
-@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=[CASES[1][0], CASES[3][0]])
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[2]], ids=[CASES[1][0], CASES[3][0], CASES[2][0]])
 def test_tracking_segments_share_slots_across_tasks(dev, case):
     """Tracking tasks of 2, 1, 3 and 1 correlation segments: seven segments in
     four slots, so one slot holds segments of two tasks with different
     templates (separated through the mirror relation), one two segments of one
-    task, and the last slot one segment; P = 2 and P = 4 phases, run one phase
+    task, and the last slot one segment; P = 2, 4 and 8 phases, run one phase
     per workgroup.  Every task equals the searching result for its tag on the
     same block and the oracle."""
     name, T, nb, sps, ntaps, cut, f1, f0, lo, N, M, ntx = case
