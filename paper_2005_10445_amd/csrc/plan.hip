@@ -300,12 +300,16 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     int grid;
     if (track) {
         // bins per work item: enough items to give every compute unit about
-        // eight, each amortising its launch over as many bins as that allows
+        // four, each amortising its setup over as many bins as that allows
+        // (256 tasks x 21 bins: 7 bins per item, 0.89 ms; eight per CU gave
+        // 5 bins per item and 0.97 ms).  The choice follows this batch's
+        // segments (for a captured graph, those of the batch it was captured
+        // on), while a captured graph sizes its grid for the plan's capacity.
         const int64_t segs = p->capturing ? int64_t(g.max_total_segments) : int64_t(total_seg_host);
         int bins = p->track_bins;
         if (bins <= 0) {
-            const int64_t per_bin = segs * c.samples_per_chip;
-            const int64_t want = int64_t(8) * p->cus;
+            const int64_t per_bin = int64_t(total_seg_host) * c.samples_per_chip;
+            const int64_t want = int64_t(4) * p->cus;
             bins = int(std::max<int64_t>(1, std::min<int64_t>(c.num_bins, per_bin * c.num_bins / want)));
             const int ntl = (c.num_bins + bins - 1) / bins;      // even tiles
             bins = (c.num_bins + ntl - 1) / ntl;
@@ -413,7 +417,9 @@ int launch_batch(acq_plan_s* p, int32_t seg, bool track) {
             if (e == hipSuccess)
                 e = hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice,
                                    p->cap_stream);
-            if (e == hipSuccess) rc = enqueue_search(p, bt, true, 0, nullptr, true, p->cap_stream, track);
+            // grids follow the plan's capacity while capturing; the capturing
+            // batch's segment count only guides the bins per tracking item
+            if (e == hipSuccess) rc = enqueue_search(p, bt, true, seg, nullptr, true, p->cap_stream, track);
             p->capturing = false;
             hipGraph_t graph = nullptr;
             const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
