@@ -264,10 +264,11 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     fa.Msub = int(g.Msub);
     {
         KernelTimer kt(p, ACQ_KERNEL_FORWARD);
-        // batches: a loop over items on a fixed grid and a combine step sized for
-        // the capacity when captured; single blocks: one workgroup per item
-        const int grid = batch ? p->cus : total_seg_host * g.ncls * c.samples_per_chip;
+        // one workgroup per item (so that a segment's items can share an XCD);
+        // a captured batch sizes both steps for the plan's capacity and the
+        // surplus workgroups exit
         const int slots = (batch && p->capturing ? int(g.max_total_segments) : total_seg_host) * g.ncls;
+        const int grid = slots * c.samples_per_chip;
         ACQ_HIP(acq::launch_forward(fa, grid, slots, g.log2_sub, c.precision, st));
     }
 
