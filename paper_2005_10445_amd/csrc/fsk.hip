@@ -298,7 +298,16 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
     // workgroup j takes phase j / kXcds of item j % kXcds of the group.
     constexpr int grp = kXcds * PP;
     const bool xcd_map = SPLIT && int(gridDim.x) >= items;
-    for (int wi = int(blockIdx.x); wi < items; wi += int(gridDim.x)) {
+    // Searching without SPLIT (a grid of whole-XCD multiples): XCD x takes the
+    // templates x, x + kXcds, ..., and its workgroups take the slots of one
+    // template side by side, so that template's spectrum is read once into
+    // the XCD's L2 instead of once per slot on different XCDs.
+    const bool tmap = !SPLIT && !TRACK && int(gridDim.x) % kXcds == 0;
+    const int xg = int(blockIdx.x) % kXcds, nw = int(gridDim.x) / kXcds;
+    const int nloop = tmap ? ((a.T - xg + kXcds - 1) / kXcds) * a.nslots : items;
+    for (int ci = tmap ? int(blockIdx.x) / kXcds : int(blockIdx.x); ci < nloop;
+         ci += tmap ? nw : int(gridDim.x)) {
+        const int wi = tmap ? (xg + kXcds * (ci / a.nslots)) * a.nslots + ci % a.nslots : ci;
         int it = SPLIT ? wi / PP : wi;
         int rho0 = SPLIT ? wi % PP : 0;
         if (xcd_map && wi < items / grp * grp) {
