@@ -157,3 +157,67 @@ def test_noisy_packet_found_and_acquire_methods_agree():
     assert a["lag"] == 1500 and b["lag"] == 1500
     for key in ("xcorr", "q", "p", "z", "toa"):
         assert a[key] == pytest.approx(b[key], rel=1e-12, abs=1e-12)
+
+
+def _brute_front_u(iq, lo, bp, f1, f0, mf):
+    """u = |f1| - |f0| of Section 3, steps 1-5, by explicit loops: the int16 pairs,
+    the mix by exp(-j 2 pi lo n / Fs), the band-pass filter, then each tone's
+    matched filter as its own sum (no composed filter)."""
+    x = [complex(int(i), int(q)) * complex(math.cos(2 * math.pi * lo * n / FS), -math.sin(2 * math.pi * lo * n / FS))
+         for n, (i, q) in enumerate(iq)]
+    y = _brute_fir(x, bp)
+    out = []
+    for n in range(len(y)):
+        acc = []
+        for f in (f1, f0):
+            s = 0j
+            for m in range(mf):                 # conj(tone[m]) y[n - mf + 1 + m]
+                idx = n - mf + 1 + m
+                if idx >= 0:
+                    s += complex(math.cos(2 * math.pi * f * m / FS), -math.sin(2 * math.pi * f * m / FS)) * y[idx]
+            acc.append(abs(s))
+        out.append(acc[0] - acc[1])
+    return np.array(out)
+
+
+def test_p_c_pinned_by_loops_identity_and_noise_free_replica():
+    """p_c (Section 3, step 8) is the sum over the replica span of d^(c)[i] times
+    u[i + j*].  Three pins, each failing for a swapped d/u or a shifted window:
+    (1) explicit loops over a brute-force u at the detected lag; (2) with u
+    replaced by d the same sum is the correlation peak w_c; (3) a noise-free
+    packet of amplitude A at delay D has u[D + i] = A u^(c)[i], u^(c) the
+    replica's own u, so p_c = A sum d^(c) u^(c) (int16 rounding aside)."""
+    g = np.random.default_rng(11)
+    bits = g.integers(0, 2, 24)
+    bp = np.exp(-0.5 * ((np.arange(15) - 7) / 3.0) ** 2) * np.exp(2j * np.pi * 0.02 * np.arange(15))
+    f1, f0, mf, lo, D, amp = 250e3, -250e3, 8, 1.2e6, 57, 9000.0
+    dc = fsk.replica_template(bits, FS, bp, f1, f0, mf)
+    n = dc.size
+    iq = _packet_block(bits, D, 400, lo, amp, bp, f1, f0, mf, noise=300.0, seed=12)
+    d, u = fsk.front_end(iq, FS, lo, bp, f1, f0, mf)
+    r = fsk.fsk_acquire(d, u, [dc])[0]
+    assert r["lag"] == D
+    # (1) loops over u from explicit filter sums
+    ub = _brute_front_u(iq, lo, bp, f1, f0, mf)
+    np.testing.assert_allclose(u, ub, rtol=0, atol=1e-8 * np.max(np.abs(ub)))
+    p_loop = 0.0
+    for i in range(n):
+        p_loop += dc[i] * ub[i + D]
+    assert r["p"] == pytest.approx(p_loop, rel=1e-10)
+    shifted = sum(dc[i] * ub[i + D + 1] for i in range(n))
+    assert abs(shifted - p_loop) > 1e-3 * abs(p_loop)        # the window offset matters
+    # (2) u -> d turns p_c into w_c
+    r_dd = fsk.fsk_acquire(d, d, [dc])[0]
+    assert r_dd["p"] == pytest.approx(r["xcorr"], rel=1e-12)
+    assert abs(r["p"] - r["xcorr"]) > 1.0                    # u and d differ in scale
+    # (3) noise-free packet: p_c = A * sum d^(c) u^(c)
+    iq0 = _packet_block(bits, D, 400, lo, amp, bp, f1, f0, mf)
+    d0, u0 = fsk.front_end(iq0, FS, lo, bp, f1, f0, mf)
+    r0 = fsk.fsk_acquire(d0, u0, [dc])[0]
+    rep = fsk.cpfsk(bits, mf, f1, f0, FS)
+    rep = np.concatenate((rep, np.zeros(len(bp) + mf - 2)))
+    g1 = fsk.compose(bp, fsk.tone_matched_filter(f1, mf, FS))
+    g0 = fsk.compose(bp, fsk.tone_matched_filter(f0, mf, FS))
+    _, uc = fsk.demod(fsk.fir(rep, g1), fsk.fir(rep, g0))
+    assert r0["lag"] == D
+    assert r0["p"] == pytest.approx(amp * float(np.dot(dc, uc)), rel=2e-3)
