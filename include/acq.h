@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define ACQ_API_VERSION 1
+#define ACQ_API_VERSION 2
 
 typedef enum acq_status {
     ACQ_OK = 0,
@@ -65,7 +65,11 @@ typedef enum acq_status {
     ACQ_ERR_DEVICE = -3,             /* a HIP call or kernel launch failed          */
     ACQ_ERR_TRUNCATED = -4,          /* more detections than capacity; see n_found */
     ACQ_ERR_BLOCK_TOO_LONG = -5,     /* n > max_block_len of the plan              */
-    ACQ_ERR_UNSUPPORTED = -7         /* valid request outside what the library implements */
+    ACQ_ERR_WORKSPACE_TOO_SMALL = -6,/* caller workspace smaller than acq_workspace_size */
+    ACQ_ERR_UNSUPPORTED = -7,        /* valid request outside what the library implements */
+    ACQ_ERR_NON_FINITE = -8          /* ACQ_FLAG_CHECK_FINITE: a block holds a NaN or infinite
+                                        sample; that block gave no detection, the others'
+                                        detections are delivered */
 } acq_status;
 
 typedef enum acq_precision {
@@ -82,6 +86,18 @@ typedef enum acq_precision {
                                       M-point spectrum plus a residual offset applied
                                       to the samples before the forward transform; one
                                       set of segment spectra per distinct residual. */
+#define ACQ_FLAG_ASYNC       0x4u  /* acq_detect, acq_detect_batch and acq_track_batch only
+                                      enqueue their kernels on the plan's stream and return:
+                                      no host synchronisation, no copy, so acq_detect can be
+                                      captured into a caller's hipGraph.  The detections and
+                                      their count stay in the plan's workspace
+                                      (acq_device_results), overwritten by the next search;
+                                      acq_collect copies them to the host.  The proposal
+                                      searches stay synchronous. */
+#define ACQ_FLAG_CHECK_FINITE 0x8u /* a block holding a non-finite sample gives no detection
+                                      and the call reports ACQ_ERR_NON_FINITE (tested on the
+                                      block power: any NaN or infinite sample makes it non-
+                                      finite, finite samples cannot) */
 
 /* acq_detection.flags */
 #define ACQ_DET_NEAR_EDGE    0x1u  /* peak at lag 0 or N-L: no parabola, delta = 0    */
@@ -123,7 +139,8 @@ typedef struct acq_geometry {
     double  freq_quantum_hz;     /* q = Fs / M_min                                 */
     double  bin_center_hz;       /* snapped centre                                  */
     double  bin_step_hz;         /* snapped step (0 when K == 1)                    */
-    int64_t device_bytes;        /* device memory a plan allocates                  */
+    int64_t device_bytes;        /* device memory of a plan, its workspace included */
+    int64_t workspace_bytes;     /* per-search buffers: acq_workspace_size          */
 } acq_geometry;
 
 /* One detection.  lag and bin identify the peak; values are FP64 re-correlations. */
@@ -141,6 +158,8 @@ typedef struct acq_detection {
     double   snr;           /* A^2 / sigma^2, sigma^2 = (E - P/L) / L; +inf if <= 0   */
     int32_t  block;         /* index of the block in a batch call, else 0            */
     uint32_t flags;         /* ACQ_DET_*                                             */
+    int64_t  crossings;     /* hypotheses (bin, lag) of this tag with z >= threshold,
+                               decided on the FP32 powers of the correlation pass    */
 } acq_detection;
 
 typedef struct acq_plan_s* acq_plan_t;
@@ -158,12 +177,25 @@ int acq_plan_geometry(const acq_config* cfg, acq_geometry* out);
 int acq_bin_frequencies(const acq_config* cfg, double* freqs_hz, int32_t n);
 
 /*
- * Create a plan: allocate the plan's device memory, build the replica spectra
- * (Section 4.2: computed once, kept for the plan's lifetime) and the transform
- * tables.  `stream` is a hipStream_t (NULL: the null stream).  Synchronises the
- * stream before returning.  On failure *out is NULL and nothing is leaked.
+ * Bytes of the per-search workspace of a plan for `cfg` (Section 4.2: every
+ * buffer a search writes is allocated once, not per block): segment spectra
+ * for the largest batch, peak keys, refinement sums, detections, batch
+ * descriptors.  No GPU call.
  */
-int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out);
+int acq_workspace_size(const acq_config* cfg, size_t* bytes);
+
+/*
+ * Create a plan: build the replica spectra (Section 4.2: computed once, kept
+ * for the plan's lifetime) and the transform tables in device memory the plan
+ * allocates, and bind the per-search workspace.  `workspace`: device memory
+ * of at least acq_workspace_size(cfg) bytes, 256-byte aligned, owned by the
+ * caller and kept alive until acq_release (searches write nothing else);
+ * NULL: the plan allocates and frees it.  A smaller `workspace_bytes` gives
+ * ACQ_ERR_WORKSPACE_TOO_SMALL.  `stream` is a hipStream_t (NULL: the null
+ * stream).  Synchronises the stream before returning.  On failure *out is
+ * NULL and nothing is leaked.
+ */
+int acq_plan(const acq_config* cfg, void* workspace, size_t workspace_bytes, void* stream, acq_plan_t* out);
 
 /*
  * Search one block.  `block`: device, n complex64 samples (interleaved re, im,
@@ -171,7 +203,11 @@ int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out);
  * go to host `out[0..capacity)`; *n_found receives the number of detections.
  * If that exceeds capacity, the first `capacity` are written and
  * ACQ_ERR_TRUNCATED is returned.  n < L is valid and yields 0 detections.
- * Synchronous: returns after the results are on the host.
+ * Synchronous: returns after the results are on the host.  With
+ * ACQ_FLAG_ASYNC the call only enqueues the search (out, capacity and n_found
+ * are not used and may be NULL/0): the results stay on the device, and no
+ * call it makes is illegal under stream capture, so a caller may capture it
+ * into a hipGraph (the block pointer and length are then fixed in the graph).
  */
 int acq_detect(acq_plan_t plan, const void* block, int64_t n,
                acq_detection* out, int32_t capacity, int32_t* n_found);
@@ -187,10 +223,14 @@ int acq_detect(acq_plan_t plan, const void* block, int64_t n,
  * ACQ_FLAG_GRAPH the launch sequence is captured once as a hipGraph (on a
  * private stream) and replayed on the plan's stream for every later call;
  * block descriptors travel through pinned memory that the graph copies.
- * Synchronous; capacity and truncation as in acq_detect.
+ * block_of (host [capacity], may be NULL) receives the block index of each
+ * delivered detection (the same value as its `block` field).
+ * Synchronous; capacity and truncation as in acq_detect.  With ACQ_FLAG_ASYNC
+ * the call returns once the search is enqueued (it waits only for the
+ * previous call's descriptor upload); results as for acq_detect.
  */
 int acq_detect_batch(acq_plan_t plan, const void* const* blocks, const int64_t* lens, int32_t nblocks,
-                     acq_detection* out, int32_t capacity, int32_t* n_found);
+                     acq_detection* out, int32_t capacity, int32_t* n_found, int32_t* block_of);
 
 /*
  * Tracking-mode tasks (Section 2: a task looks for one packet of one
@@ -219,6 +259,25 @@ typedef struct acq_track_task {
  */
 int acq_track_batch(acq_plan_t plan, const acq_track_task* tasks, int32_t ntasks,
                     acq_detection* out, int32_t capacity, int32_t* n_found);
+
+/*
+ * Results of the plan's last search, for ACQ_FLAG_ASYNC plans (any plan may
+ * call it): waits for the plan's stream, then copies the detections to host
+ * out[0..capacity) and their number to *n_found, with the statuses of
+ * acq_detect (ACQ_ERR_TRUNCATED, ACQ_ERR_NON_FINITE).  A plan that has not
+ * searched yet reports none.
+ */
+int acq_collect(acq_plan_t plan, acq_detection* out, int32_t capacity, int32_t* n_found);
+
+/*
+ * Device addresses of the last search's results in the plan's workspace, for
+ * consumers on the device: *records = detections (sorted, at most
+ * max_batch_blocks * num_tags), *counts = int32[2] {detections, blocks with a
+ * non-finite sample}.  Fixed for the plan's lifetime; valid once the search
+ * has run on the plan's stream.
+ */
+int acq_device_results(acq_plan_t plan, const acq_detection** records, const int32_t** counts);
+
 
 /*
  * Launch configuration of the correlation kernel.  engine: 0 = the default

@@ -27,6 +27,10 @@ What is computed, and where it comes from:
   centre = round(centre/q) q, f_k = centre + (k - (K-1)/2) step, K odd.
 * Default threshold (reading): theta = ln(T K (N-L+1) / 1e-3), a 1e-3
   expected false alarms per block under noise, where z ~ Exp(1).
+* Threshold crossings (reading: the detection test applied to every
+  hypothesis, not only to the peak): the number of (bin, lag) of a tag with
+  z >= theta.  Reported with a band, the counts at theta (1 +- CROSS_REL),
+  inside which an implementation deciding on FP32 powers must fall.
 """
 from __future__ import annotations
 
@@ -42,7 +46,7 @@ __all__ = [
     "build_library", "library_path", "rotation_grid", "snap_bins", "templates",
     "block_power", "corr_power", "corr_power_at", "corr_power_fft",
     "default_threshold", "argmax_detect", "parabola", "energy_at", "power_snr_estimates",
-    "acquire", "track", "NEAR_TIE_REL", "NEAR_THRESHOLD_REL", "num_threads",
+    "acquire", "track", "crossings", "NEAR_TIE_REL", "NEAR_THRESHOLD_REL", "CROSS_REL", "num_threads",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -52,6 +56,8 @@ _LIB = os.path.join(_HERE, "_direct.so")
 # Decisions this close to a tie (or to the threshold) are flagged, not pinned.
 NEAR_TIE_REL = 1e-5
 NEAR_THRESHOLD_REL = 1e-5
+# Relative band of the threshold-crossing count (FP32 powers err by <= 1e-4 P).
+CROSS_REL = 1e-4
 
 
 # --------------------------------------------------------------------------- C library
@@ -264,6 +270,17 @@ def power_snr_estimates(P0: float, E: float, L: int):
     return a2, (a2 / s2 if s2 > 0.0 else float("inf"))
 
 
+def crossings(Pt: np.ndarray, theta: float, template_len: int, px: float):
+    """(count, low, high): hypotheses of one tag's P[k][tau] with z = P / (L Pxhat) >= theta,
+    and the counts at theta (1 + CROSS_REL) and theta (1 - CROSS_REL).  None cross when
+    Pxhat is 0."""
+    if not px > 0.0:
+        return 0, 0, 0
+    thr = theta * float(template_len) * px
+    return (int(np.count_nonzero(Pt >= thr)), int(np.count_nonzero(Pt >= thr * (1.0 + CROSS_REL))),
+            int(np.count_nonzero(Pt >= thr * (1.0 - CROSS_REL))))
+
+
 def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, method: str = "direct",
             refine_window: int = 1, tags: Optional[Sequence[int]] = None):
     """Per-tag acquisition result (list of dicts) by the definitions above.
@@ -295,6 +312,7 @@ def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, metho
         raise ValueError(method)
     lags = N - L + 1
     for t, Pt in it:
+        cross = crossings(Pt, theta, L, Px)
         k, tau, P0, far, near = argmax_detect(Pt, window=refine_window)
         trip_taus = [tau - 1, tau, tau + 1]
         if method == "fft":
@@ -315,6 +333,7 @@ def acquire(x, chips, spc, freqs_hz, fs_hz, theta: Optional[float] = None, metho
             block_power=Px, freq_hz=float(f[k]), near_edge=bool(edge),
             near_tie=bool(far >= P0 * (1 - NEAR_TIE_REL) or near >= P0 * (1 - 1e-12)),
             near_threshold=bool(abs(z - theta) <= NEAR_THRESHOLD_REL * theta), theta=float(theta),
+            crossings=cross[0], crossings_band=(cross[1], cross[2]),
         ))
     return out
 

@@ -17,7 +17,7 @@ import numpy as np
 from . import _capi
 from ._capi import AcqConfig, AcqDetection, AcqGeometry, AcqError, check
 
-__all__ = ["Plan", "Detection", "geometry", "bin_frequencies", "AcqError", "make_config"]
+__all__ = ["Plan", "Detection", "geometry", "workspace_size", "bin_frequencies", "AcqError", "make_config"]
 
 _PRECISION = {"fp32": _capi.ACQ_FP32, "fp16": _capi.ACQ_FP16, "bf16": _capi.ACQ_BF16}
 
@@ -37,13 +37,20 @@ class Detection:
     flags: int
     power: float = 0.0          # relative power A^2 = P / L^2
     snr: float = 0.0            # A^2 / sigma^2, sigma^2 = (E - P/L) / L
+    crossings: int = 0          # (bin, lag) hypotheses of the tag with z >= threshold
+
+
+def _det(d) -> Detection:
+    return Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy, d.block_power,
+                     d.block, d.flags, d.power, d.snr, d.crossings)
 
 
 def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
                 bin_center_hz: float = 0.0, bin_step_hz: float = 0.0, max_block_len: int = 1 << 20,
                 fft_len: int = 0, threshold: float = 0.0, precision: str = "fp32",
                 refine_radius: int = 1, tag_tile: int = 0, max_batch_blocks: int = 0,
-                max_batch_samples: int = 0, graph: bool = False, exact_bins: bool = False):
+                max_batch_samples: int = 0, graph: bool = False, exact_bins: bool = False,
+                asynchronous: bool = False, check_finite: bool = False):
     """Build an AcqConfig; returns (config, chips array that must outlive the call)."""
     ch = np.ascontiguousarray(np.asarray(chips, dtype=np.int8))
     if ch.ndim != 2:
@@ -62,10 +69,19 @@ def make_config(chips: np.ndarray, spc: int, fs_hz: float, num_bins: int = 1,
     cfg.precision = _PRECISION[precision]
     cfg.refine_radius = int(refine_radius)
     cfg.tag_tile = int(tag_tile)
-    cfg.flags = (_capi.ACQ_FLAG_GRAPH if graph else 0) | (_capi.ACQ_FLAG_EXACT_BINS if exact_bins else 0)
+    cfg.flags = ((_capi.ACQ_FLAG_GRAPH if graph else 0) | (_capi.ACQ_FLAG_EXACT_BINS if exact_bins else 0) |
+                 (_capi.ACQ_FLAG_ASYNC if asynchronous else 0) | (_capi.ACQ_FLAG_CHECK_FINITE if check_finite else 0))
     cfg.max_batch_blocks = int(max_batch_blocks)
     cfg.max_batch_samples = int(max_batch_samples)
     return cfg, ch
+
+
+def workspace_size(**kw) -> int:
+    """acq_workspace_size for a configuration (no GPU involved)."""
+    cfg, _keep = make_config(**kw)
+    n = ctypes.c_size_t(0)
+    check(_capi.lib().acq_workspace_size(ctypes.byref(cfg), ctypes.byref(n)), "acq_workspace_size")
+    return int(n.value)
 
 
 def geometry(**kw) -> dict:
@@ -95,18 +111,25 @@ def _device_ptr(block):
 
 
 class Plan:
-    """An acquisition plan bound to one HIP stream (default: torch's current stream)."""
+    """An acquisition plan bound to one HIP stream (default: torch's current stream).
+
+    workspace: optional uint8 CUDA tensor of at least workspace_size(...) bytes that the
+    plan uses for every per-search buffer (kept referenced by the plan); None lets the
+    library allocate it.  asynchronous: searches only enqueue (results via collect() or
+    device_results()).  check_finite: blocks with NaN/inf samples raise AcqError."""
 
     def __init__(self, chips, spc: int, fs_hz: float, *, num_bins: int = 1, bin_center_hz: float = 0.0,
                  bin_step_hz: float = 0.0, max_block_len: int = 1 << 20, fft_len: int = 0,
                  threshold: float = 0.0, precision: str = "fp32", refine_radius: int = 1,
                  tag_tile: int = 0, max_batch_blocks: int = 0, max_batch_samples: int = 0,
-                 graph: bool = False, exact_bins: bool = False, stream=None):
+                 graph: bool = False, exact_bins: bool = False, stream=None, workspace=None,
+                 asynchronous: bool = False, check_finite: bool = False):
         import torch
         self._lib = _capi.lib()
         cfg, ch = make_config(chips, spc, fs_hz, num_bins, bin_center_hz, bin_step_hz, max_block_len,
                               fft_len, threshold, precision, refine_radius, tag_tile, max_batch_blocks,
-                              max_batch_samples, graph, exact_bins)
+                              max_batch_samples, graph, exact_bins, asynchronous, check_finite)
+        self.asynchronous = bool(asynchronous)
         self.max_batch_blocks = max(int(max_batch_blocks), 1)
         self.num_tags, self.num_chips = ch.shape
         self.precision = precision
@@ -125,7 +148,15 @@ class Plan:
                                             self.freqs_hz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             self.num_bins), "acq_bin_frequencies")
         self._h = ctypes.c_void_p()
-        check(self._lib.acq_plan(ctypes.byref(cfg), ctypes.c_void_p(handle), ctypes.byref(self._h)), "acq_plan")
+        self._workspace = workspace                 # the caller's memory must outlive the plan
+        if workspace is not None:
+            if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or not workspace.is_contiguous():
+                raise TypeError("workspace must be a contiguous CUDA tensor")
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        else:
+            ws_ptr, ws_bytes = None, 0
+        check(self._lib.acq_plan(ctypes.byref(cfg), ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes),
+                                 ctypes.c_void_p(handle), ctypes.byref(self._h)), "acq_plan")
         self._out = (AcqDetection * self.num_tags)()
 
     def detect(self, block) -> List[Detection]:
@@ -133,8 +164,31 @@ class Plan:
         nf = ctypes.c_int32(0)
         check(self._lib.acq_detect(self._h, ctypes.c_void_p(ptr), n, self._out, self.num_tags,
                                    ctypes.byref(nf)), "acq_detect")
-        return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags, d.power, d.snr) for d in self._out[:nf.value]]
+        if self.asynchronous:
+            return self.collect()
+        return [_det(d) for d in self._out[:nf.value]]
+
+    def enqueue(self, block):
+        """acq_detect on an asynchronous plan: enqueue the search and return at once
+        (capturable into a hipGraph on the plan's stream)."""
+        if not self.asynchronous:
+            raise RuntimeError("enqueue needs a plan made with asynchronous=True")
+        ptr, n = _device_ptr(block)
+        check(self._lib.acq_detect(self._h, ctypes.c_void_p(ptr), n, None, 0, None), "acq_detect")
+
+    def collect(self, capacity: Optional[int] = None) -> List[Detection]:
+        """acq_collect: wait for the plan's stream and return the last search's detections."""
+        cap = capacity if capacity is not None else self.max_batch_blocks * self.num_tags
+        out = (AcqDetection * max(cap, 1))()
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_collect(self._h, out, cap, ctypes.byref(nf)), "acq_collect")
+        return [_det(d) for d in out[:min(nf.value, cap)]]
+
+    def device_results(self):
+        """acq_device_results: (device address of the records, device address of the int32[2] counts)."""
+        rec, cnt = ctypes.c_void_p(), ctypes.c_void_p()
+        check(self._lib.acq_device_results(self._h, ctypes.byref(rec), ctypes.byref(cnt)), "acq_device_results")
+        return rec.value, cnt.value
 
     def detect_batch(self, blocks) -> List[Detection]:
         """acq_detect_batch over a list of 1-D complex64 device tensors of any lengths."""
@@ -147,9 +201,11 @@ class Plan:
         cap = n * self.num_tags
         out = (AcqDetection * cap)()
         nf = ctypes.c_int32(0)
-        check(self._lib.acq_detect_batch(self._h, ptrs, lens, n, out, cap, ctypes.byref(nf)), "acq_detect_batch")
-        return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
+        check(self._lib.acq_detect_batch(self._h, ptrs, lens, n, out, cap, ctypes.byref(nf), None),
+              "acq_detect_batch")
+        if self.asynchronous:
+            return self.collect(cap)
+        return [_det(d) for d in out[:nf.value]]
 
     def track(self, tasks) -> List[Detection]:
         """acq_track_batch over (1-D complex64 device tensor, tag) pairs: at most one
@@ -159,8 +215,9 @@ class Plan:
         out = (AcqDetection * n)()
         nf = ctypes.c_int32(0)
         check(self._lib.acq_track_batch(self._h, arr, n, out, n, ctypes.byref(nf)), "acq_track_batch")
-        return [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
+        if self.asynchronous:
+            return self.collect(n)
+        return [_det(d) for d in out[:nf.value]]
 
     @staticmethod
     def task_array(tasks):
@@ -245,6 +302,7 @@ class Plan:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.acq_release(self._h)
             self._h = ctypes.c_void_p()
+            self._workspace = None
 
     def __del__(self):
         try:

@@ -18,17 +18,22 @@ ACQ_ERR_OOM = -2
 ACQ_ERR_DEVICE = -3
 ACQ_ERR_TRUNCATED = -4
 ACQ_ERR_BLOCK_TOO_LONG = -5
+ACQ_ERR_WORKSPACE_TOO_SMALL = -6
 ACQ_ERR_UNSUPPORTED = -7
+ACQ_ERR_NON_FINITE = -8
 
 ACQ_FP32, ACQ_FP16, ACQ_BF16 = 0, 1, 2
 ACQ_DET_NEAR_EDGE = 0x1
 ACQ_DET_WINDOW_EDGE = 0x2
 ACQ_FLAG_GRAPH = 0x1
 ACQ_FLAG_EXACT_BINS = 0x2
+ACQ_FLAG_ASYNC = 0x4
+ACQ_FLAG_CHECK_FINITE = 0x8
 
 # every symbol include/acq.h declares
-EXPORTED = ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
-            "acq_track_batch", "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
+EXPORTED = ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "acq_plan", "acq_detect",
+            "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results",
+            "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
             "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
@@ -75,6 +80,7 @@ class AcqGeometry(ctypes.Structure):
         ("bin_center_hz", ctypes.c_double),
         ("bin_step_hz", ctypes.c_double),
         ("device_bytes", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
     ]
 
 
@@ -93,6 +99,7 @@ class AcqDetection(ctypes.Structure):
         ("snr", ctypes.c_double),
         ("block", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("crossings", ctypes.c_int64),
     ]
 
 
@@ -205,12 +212,15 @@ def lib(path: str = LIB_PATH):
     P = ctypes.POINTER
     L.acq_plan_geometry.argtypes = [P(AcqConfig), P(AcqGeometry)]
     L.acq_bin_frequencies.argtypes = [P(AcqConfig), P(ctypes.c_double), ctypes.c_int32]
-    L.acq_plan.argtypes = [P(AcqConfig), ctypes.c_void_p, P(ctypes.c_void_p)]
+    L.acq_workspace_size.argtypes = [P(AcqConfig), P(ctypes.c_size_t)]
+    L.acq_plan.argtypes = [P(AcqConfig), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, P(ctypes.c_void_p)]
     L.acq_detect.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, P(AcqDetection),
                              ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_correlate_power.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     L.acq_detect_batch.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_int64), ctypes.c_int32,
-                                   P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32)]
+                                   P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.acq_collect.argtypes = [ctypes.c_void_p, P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32)]
+    L.acq_device_results.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_void_p)]
     L.acq_track_batch.argtypes = [ctypes.c_void_p, P(AcqTrackTask), ctypes.c_int32, P(AcqDetection),
                                   ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_get_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
@@ -252,12 +262,13 @@ def lib(path: str = LIB_PATH):
                  "acq_fsk_xcorr", "acq_fsk_detect", "acq_fsk_track", "acq_fsk_set_profiling",
                  "acq_fsk_last_kernel_times"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("acq_plan_geometry", "acq_bin_frequencies", "acq_plan", "acq_detect", "acq_detect_batch",
-                 "acq_track_batch", "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_release",
-                 "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create", "acq_cnn_release",
-                 "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
-                 "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
-                 "acq_detect_learned", "acq_detect_batch_learned"):
+    for name in ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "acq_plan", "acq_detect",
+                 "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results",
+                 "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power",
+                 "acq_release", "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create",
+                 "acq_cnn_release", "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward",
+                 "acq_cnn_gradients", "acq_cnn_adam_step", "acq_power_map", "acq_synth_block",
+                 "acq_cnn_train_synthetic", "acq_detect_learned", "acq_detect_batch_learned"):
         getattr(L, name).restype = ctypes.c_int
     L.acq_strerror.argtypes = [ctypes.c_int]
     L.acq_strerror.restype = ctypes.c_char_p

@@ -27,7 +27,9 @@
 // key = float_bits(P) << 32 | ~(tau*K + k), so the largest key is the largest
 // power with ties going to the smaller lag and then the smaller bin (the
 // argmax of Section 3, step 8).  P >= 0, so its bit pattern orders like its
-// value.
+// value.  Each tag also counts its threshold crossings, the (bin, lag) with
+// P >= theta * L * Pxhat; a wave takes that count only when one of its lanes'
+// largest powers crosses, which is rare, so the common path pays one compare.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -70,11 +72,29 @@ __device__ __forceinline__ void first_step(const CorrArgs& a, const E& eng, int 
     }
 }
 
+// Threshold crossings of one transform's outputs in this wave: valid outputs
+// with power >= pth (wave-uniform count).
+template <class E>
+__device__ __forceinline__ unsigned wave_crossings(const float2 (&v)[16], int ob, int omin, int ulim, float pth) {
+    unsigned c = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int off = E::out_off(r);
+        if (omin + off < ulim) {
+            const float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
+            const bool ok = ob + off < ulim && p >= pth;
+            c += unsigned(__builtin_popcountll(__builtin_amdgcn_ballot_w64(ok)));
+        }
+    }
+    return c;
+}
+
 // One work item: (tile of tags, global segment g, bin k, phase rho), item index
 // wi = ((tile * segments + g) * K + k) * spc + rho.
 template <class E, int PREC, bool DUMP>
 __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, int wi, int total_seg,
-                                               float2* lds, const float2* extra, unsigned long long* red) {
+                                               float2* lds, const float2* extra, unsigned long long* red,
+                                               unsigned* cred) {
     using St = dev::Storage<PREC>;
     constexpr int N = E::N;
     constexpr int NW = E::NT / 64;
@@ -93,6 +113,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
     const int ntag = d.tag >= 0 ? 1 : min(a.tile, a.T - tag0);
     const int j = a.blocks.segment(g, d);
     unsigned long long* keys = a.keys + size_t(bi) * a.T;
+    const float pth = a.pthr[bi];
 
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     constexpr int NB = bank_stride(N);
@@ -162,14 +183,25 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
             ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) |
                   static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
             : 0ull;
+        // threshold crossings: counted only by waves where some lane's largest power crosses
+        unsigned cross = 0;
+        if (__builtin_amdgcn_ballot_w64(bp >= pth)) cross = wave_crossings<E>(v, ob, omin, ulim, pth);
         best = wave_max(best);
-        if (lane == 0) red[tt * NW + wave] = best;
+        if (lane == 0) {
+            red[tt * NW + wave] = best;
+            cred[tt * NW + wave] = cross;
+        }
     }
     __syncthreads();
     for (int i = int(threadIdx.x); i < ntag; i += E::NT) {
         unsigned long long m = 0ull;
-        for (int q = 0; q < NW; ++q) m = red[i * NW + q] > m ? red[i * NW + q] : m;
+        unsigned c = 0;
+        for (int q = 0; q < NW; ++q) {
+            m = red[i * NW + q] > m ? red[i * NW + q] : m;
+            c += cred[i * NW + q];
+        }
         if (m) atomicMax(&keys[tag0 + i], m);
+        if (c) atomicAdd(&a.cross[size_t(bi) * a.T + tag0 + i], c);
     }
     __syncthreads();                             // red[] is rewritten by the next item
 }
@@ -181,7 +213,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
 // wave reduction and one atomic per item remain.
 template <class E, int PREC>
 __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int wi, float2* lds,
-                                           const float2* extra, unsigned long long* red) {
+                                           const float2* extra, unsigned long long* red, unsigned* cred) {
     using St = dev::Storage<PREC>;
     constexpr int NW = E::NT / 64;
     const int ntl = (a.K + a.tile - 1) / a.tile;
@@ -196,6 +228,7 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
     const BlockDesc d = a.blocks.get(bi);
     const int j = a.blocks.segment(g, d);
     const int tag = d.tag;
+    const float pth = a.pthr[bi];
 
     const __amdgpu_buffer_rsrc_t b1 = make_rsrc(a.b1tab, E::B1_TABLE * 8);
     constexpr int NB = bank_stride(E::N);
@@ -216,6 +249,7 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
     const int voffm = (E::NT - eng.in_index(0)) * St::BYTES;
 
     unsigned long long best = 0ull;
+    unsigned cross = 0;
     for (int k = k0; k < k1; ++k) {
         float2 v[16];
         first_step<E, PREC>(a, eng, g, k, rho, gscale, v);
@@ -245,14 +279,23 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
                   static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
             : 0ull;
         best = key > best ? key : best;
+        if (__builtin_amdgcn_ballot_w64(bp >= pth)) cross += wave_crossings<E>(v, ob, omin, ulim, pth);
     }
     best = wave_max(best);
-    if (lane == 0) red[wave] = best;
+    if (lane == 0) {
+        red[wave] = best;
+        cred[wave] = cross;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = 0ull;
-        for (int q = 0; q < NW; ++q) m = red[q] > m ? red[q] : m;
+        unsigned c = 0;
+        for (int q = 0; q < NW; ++q) {
+            m = red[q] > m ? red[q] : m;
+            c += cred[q];
+        }
         if (m) atomicMax(&a.keys[size_t(bi) * a.T + tag], m);
+        if (c) atomicAdd(&a.cross[size_t(bi) * a.T + tag], c);
     }
     __syncthreads();
 }
@@ -268,6 +311,7 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
     __shared__ float2 lds[E::LDS];
     __shared__ float2 extra[E::EXTRA];
     __shared__ unsigned long long red[kMaxTagTile * NW];
+    __shared__ unsigned cred[kMaxTagTile * NW];
     __shared__ int s_item;
     const int total_seg = a.blocks.total_seg();
     const int total = MODE == kCorrTrack ? total_seg * ((a.K + a.tile - 1) / a.tile) * a.spc
@@ -289,7 +333,7 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
             const int it = begin + __builtin_amdgcn_readfirstlane(s_item);
             __syncthreads();
             if (it >= end) break;
-            correlate_item<E, PREC, false>(a, eng, it, total_seg, lds, extra, red);
+            correlate_item<E, PREC, false>(a, eng, it, total_seg, lds, extra, red, cred);
         }
     } else {
         // one item per workgroup; the grid may exceed the work (a batch captured
@@ -301,9 +345,9 @@ __global__ __launch_bounds__(E::NT) void k_correlate(CorrArgs a) {
         if (q >= per || wi >= total) return;
         eng.init(a.rootsSub, extra);
         if constexpr (MODE == kCorrTrack)
-            track_item<E, PREC>(a, eng, wi, lds, extra, red);
+            track_item<E, PREC>(a, eng, wi, lds, extra, red, cred);
         else
-            correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red);
+            correlate_item<E, PREC, DUMP>(a, eng, wi, total_seg, lds, extra, red, cred);
     }
 }
 

@@ -67,7 +67,8 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     if (cfg->refine_radius < 0 || cfg->refine_radius > kMaxRefineRadius)
         return fail(ACQ_ERR_INVALID_ARG, "refine_radius must be in [0, 8]");
     if (cfg->tag_tile < 0) return fail(ACQ_ERR_INVALID_ARG, "tag_tile must be >= 0");
-    if ((cfg->flags & ~(ACQ_FLAG_GRAPH | ACQ_FLAG_EXACT_BINS)) != 0) return fail(ACQ_ERR_INVALID_ARG, "unknown flags");
+    if ((cfg->flags & ~(ACQ_FLAG_GRAPH | ACQ_FLAG_EXACT_BINS | ACQ_FLAG_ASYNC | ACQ_FLAG_CHECK_FINITE)) != 0)
+        return fail(ACQ_ERR_INVALID_ARG, "unknown flags");
     if (cfg->max_batch_blocks < 0 || cfg->max_batch_samples < 0)
         return fail(ACQ_ERR_INVALID_ARG, "negative batch capacity");
 

@@ -69,6 +69,8 @@ struct CorrArgs {
     const int32_t* rot;         // [K] rotation of bin k, in [0, M)
     const int32_t* cls;         // [K] residual class of bin k (spectra slot g * ncls + cls[k])
     unsigned long long* keys;   // [block][T] packed (power bits, ~(lag*K + k)), max-reduced
+    const float* pthr;          // [block] power threshold theta * L * Pxhat (+inf: none)
+    unsigned* cross;            // [block][T] count of (bin, lag) with P >= pthr, added to
     float* dump;                // optional [T][K][lags] power (single-block calls)
     int* counters;              // [kXcds] work-item counters (persistent launches)
     int64_t V;                  // valid lags per segment
@@ -99,11 +101,14 @@ struct RefineArgs {
     const double* cyc;          // [K] f_k / Fs (exact bins)
     const unsigned long long* keys;   // [block][T]
     const double* parts;        // [block][kPowerParts]
+    const int32_t* bad;         // [block] 1: the block holds a non-finite sample
+    const unsigned* cross;      // [block][T] threshold crossings of the correlation pass
     acq_detection* dets;        // [block][T]
     int32_t* found;             // [block][T] 1 if detected
     int64_t L;
     int32_t T, C, K, spc, log2_spc, M, radius, exact;
     int32_t track;              // 1: one candidate per block, the block's own tag
+    int32_t check_finite;       // 1: no detection in a block with a non-finite sample
     double* partial;            // [items][kRefineParts][3 * window] FP64 partial sums
     int64_t* center;            // [items] window centre of the second round (-1: none)
 };
@@ -115,9 +120,13 @@ constexpr int kRefineParts = 16;
 
 // partial sums of |x|^2 of every block (blocks of at most max_len samples)
 hipError_t launch_block_power(const BlockTable& bt, int max_blocks, int64_t max_len, double* parts, hipStream_t st);
-// exps[b] = round(log2(sqrt(M * Pxhat_b))): the 16-bit storage prescale of block b
-hipError_t launch_block_exponent(const BlockTable& bt, int max_blocks, const double* parts, int M, int* exps,
-                                 hipStream_t st);
+// Per-block quantities derived from the block power, for every block of the
+// table: exps[b] = round(log2(sqrt(M * Pxhat_b))) (the 16-bit storage
+// prescale), pthr[b] = theta_b * L * Pxhat_b (+inf when Pxhat_b is 0 or not
+// finite), bad[b] = 1 when Pxhat_b is not finite (some sample is NaN or
+// infinite); nbad[0] receives the number of such blocks.  One workgroup.
+hipError_t launch_block_stats(const BlockTable& bt, const double* parts, int M, int64_t L, int* exps, float* pthr,
+                              int32_t* bad, int32_t* nbad, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, hipStream_t st);
 // grid: workgroups of the sub-transforms (items = segments * spc); combine_slots:
@@ -130,7 +139,8 @@ hipError_t launch_bank(const int8_t* chips, int T, int C, void* bank, const floa
 hipError_t launch_correlate(const CorrArgs& a, int grid, int log2_sub, int prec, int engine, hipStream_t st);
 hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st);
 // track: one candidate per block (its tag), else T per block
+// capacity: records written to out (the rest are counted only)
 hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T, int track,
-                          acq_detection* out, int32_t* count, hipStream_t st);
+                          acq_detection* out, int32_t capacity, int32_t* count, hipStream_t st);
 
 }  // namespace acq

@@ -87,18 +87,39 @@ __device__ __forceinline__ double block_mean_power(const double* __restrict__ pa
     return n > 0 ? s / double(n) : 0.0;
 }
 
-// ------------------------------------------------------------------ forward spectra
-// Power-of-two prescale of the stored segment spectra for 16-bit storage:
-// 2^-e with e = round(log2(sqrt(M * Pxhat))), so typical |X| is near 1.  One
-// value per block, computed once after the block power (grid = max_blocks).
-__global__ void k_block_exponent(BlockTable bt, const double* __restrict__ parts, int M, int* __restrict__ exps) {
-    const int b = int(blockIdx.x);
-    if (threadIdx.x != 0 || b >= bt.nblocks()) return;
-    const BlockDesc d = bt.get(b);
-    const double px = block_mean_power(parts + size_t(b) * kPowerParts, d.n);
-    exps[b] = px > 0.0 ? int(rint(0.5 * log2(double(M) * px))) : 0;
+// ------------------------------------------------------------------ per-block statistics
+// From the block power, for every block b of the table: the power-of-two
+// prescale of 16-bit storage, 2^-e with e = round(log2(sqrt(M * Pxhat))) (so
+// typical |X| is near 1); the power at the detection threshold, theta * L *
+// Pxhat (the z >= theta test on FP32 powers); and whether the block holds a
+// non-finite sample (then Pxhat is not finite: |x|^2 of a finite complex64
+// value cannot overflow FP64 and every term is >= 0, so no cancellation).
+// One workgroup strides over the blocks and counts the non-finite ones.
+constexpr int kStatsThreads = 256;
+
+__global__ __launch_bounds__(kStatsThreads) void k_block_stats(BlockTable bt, const double* __restrict__ parts, int M,
+                                                               int64_t L, int* __restrict__ exps,
+                                                               float* __restrict__ pthr, int32_t* __restrict__ bad,
+                                                               int32_t* __restrict__ nbad) {
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const int nb = bt.nblocks();
+    for (int b = int(threadIdx.x); b < nb; b += kStatsThreads) {
+        const BlockDesc d = bt.get(b);
+        const double px = block_mean_power(parts + size_t(b) * kPowerParts, d.n);
+        const bool fin = isfinite(px);
+        exps[b] = fin && px > 0.0 ? int(rint(0.5 * log2(double(M) * px))) : 0;
+        const double th = d.theta * double(L) * px;
+        pthr[b] = fin && px > 0.0 && th <= 3.0e38 ? float(th) : __builtin_huge_valf();
+        bad[b] = fin ? 0 : 1;
+        if (!fin) atomicAdd(&s_bad, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) nbad[0] = s_bad;
 }
 
+// ------------------------------------------------------------------ forward spectra
 // One workgroup per global segment g (looping when the grid is smaller):
 // X_g = DFT_M of the segment held in slot g (segment g - seg0 of its block, or
 // the listed segment when only some segments are searched), in two kernels:
@@ -411,6 +432,7 @@ __global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int pass) {
     }
     const double px = block_mean_power(a.parts + size_t(it.bi) * kPowerParts, d.n);
     const double z = px > 0.0 ? p0 / (double(a.L) * px) : 0.0;
+    const bool suppressed = a.check_finite && a.bad[it.bi];
     acq_detection r;
     r.tag = it.tag;
     r.bin = k;
@@ -428,8 +450,9 @@ __global__ __launch_bounds__(64) void k_refine_decide(RefineArgs a, int pass) {
     r.snr = s2 > 0.0 ? r.power / s2 : __builtin_huge_val();
     r.block = it.bi;
     r.flags = flags;
+    r.crossings = int64_t(a.cross[it.slot]);
     a.dets[it.slot] = r;
-    a.found[it.slot] = z >= d.theta ? 1 : 0;
+    a.found[it.slot] = z >= d.theta && !suppressed ? 1 : 0;
 }
 
 // Detections in (block, tag) order.  One workgroup: each thread takes a
@@ -440,7 +463,7 @@ constexpr int kCompactThreads = 1024;
 
 __global__ __launch_bounds__(kCompactThreads) void k_compact(BlockTable bt, const acq_detection* __restrict__ dets,
                                                              const int32_t* __restrict__ found, int T, int track,
-                                                             acq_detection* __restrict__ out,
+                                                             acq_detection* __restrict__ out, int32_t capacity,
                                                              int32_t* __restrict__ count) {
     __shared__ int scan[kCompactThreads];
     const int t = int(threadIdx.x);
@@ -467,7 +490,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(BlockTable bt, cons
         __syncthreads();
     }
     int o = scan[t] - c;
-    for (int64_t e = e0; e < e1; ++e) {
+    for (int64_t e = e0; e < e1 && o < capacity; ++e) {
         const int64_t s = slot(e);
         if (s >= 0 && found[s]) out[o++] = dets[s];
     }
@@ -484,9 +507,9 @@ hipError_t launch_block_power(const BlockTable& bt, int max_blocks, int64_t max_
     return hipGetLastError();
 }
 
-hipError_t launch_block_exponent(const BlockTable& bt, int max_blocks, const double* parts, int M, int* exps,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL(k_block_exponent, dim3(unsigned(max_blocks)), dim3(64), 0, st, bt, parts, M, exps);
+hipError_t launch_block_stats(const BlockTable& bt, const double* parts, int M, int64_t L, int* exps, float* pthr,
+                              int32_t* bad, int32_t* nbad, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_stats, dim3(1), dim3(kStatsThreads), 0, st, bt, parts, M, L, exps, pthr, bad, nbad);
     return hipGetLastError();
 }
 
@@ -604,8 +627,9 @@ hipError_t launch_refine(const RefineArgs& a, int max_blocks, hipStream_t st) {
 }
 
 hipError_t launch_compact(const BlockTable& bt, const acq_detection* dets, const int32_t* found, int T, int track,
-                          acq_detection* out, int32_t* count, hipStream_t st) {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, bt, dets, found, T, track, out, count);
+                          acq_detection* out, int32_t capacity, int32_t* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, bt, dets, found, T, track, out, capacity,
+                       count);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "acq.h"
@@ -25,6 +26,30 @@
 using acq::BlockDesc;
 using acq::BlockTable;
 using acq::Geometry;
+
+// Per-search device buffers: everything a search writes, sized for the
+// plan's batch capacity.  They live in one region, the plan's workspace
+// (caller-owned, or allocated by acq_plan when the caller passes none).
+struct Scratch {
+    float2* X = nullptr;                // [segments][classes][M] FP32 segment spectra
+    void* Xh = nullptr;                 // [segments][classes][M] 16-bit segment spectra (FP16/BF16 plans)
+    unsigned long long* keys = nullptr; // [blocks][T] peak keys
+    unsigned* cross = nullptr;          // [blocks][T] threshold crossings
+    double* parts = nullptr;            // [blocks][kPowerParts] block-power partial sums
+    int* exps = nullptr;                // [blocks] 16-bit storage prescale exponents
+    float* pthr = nullptr;              // [blocks] power at the detection threshold
+    int32_t* bad = nullptr;             // [blocks] 1: a non-finite sample
+    acq_detection* dets = nullptr;      // [blocks][T] candidates
+    acq_detection* out = nullptr;       // [blocks][T] detections, compacted
+    int32_t* found = nullptr;           // [blocks][T]
+    double* refpart = nullptr;          // refinement partial sums [blocks * T][parts][3 * window]
+    int64_t* refcenter = nullptr;       // [blocks * T] refinement re-centring
+    int32_t* count = nullptr;           // [2]: detections, blocks holding a non-finite sample
+    int* counters = nullptr;            // [kXcds] persistent-launch work counters
+    BlockDesc* descs = nullptr;         // [blocks]
+    int32_t* counts = nullptr;          // [2] = {blocks, segments} of a batch
+    int32_t* seglist = nullptr;         // segments searched by a proposal search
+};
 
 struct acq_plan_s {
     acq_config cfg{};
@@ -37,8 +62,8 @@ struct acq_plan_s {
     int batch_launch = ACQ_BATCH_GRID;  // acq_tuning.batch_launch
     int track_bins = 0;                 // acq_tuning.track_bins (0: chosen per launch)
 
-    float2* d_X = nullptr;              // [segments][classes][M] FP32 segment spectra
-    void* d_Xh = nullptr;               // [segments][classes][M] 16-bit segment spectra (FP16/BF16 plans)
+    Scratch ws;                         // per-search buffers in the workspace
+    void* own_ws = nullptr;             // the workspace when acq_plan allocated it
     int32_t* d_cls = nullptr;           // [K] residual class of each bin
     double* d_cls_cyc = nullptr;        // [classes] residual offsets, cycles per sample
     double* d_cyc = nullptr;            // [K] f_k / Fs
@@ -53,28 +78,17 @@ struct acq_plan_s {
     int32_t* d_rot = nullptr;           // [K]
     int64_t* d_rot_signed = nullptr;    // [K]
     double* d_freqs = nullptr;          // [K]
-    unsigned long long* d_keys = nullptr;   // [blocks][T]
-    double* d_parts = nullptr;          // [blocks][kPowerParts]
-    int* d_exps = nullptr;              // [blocks] 16-bit storage prescale exponents
-    acq_detection* d_dets = nullptr;    // [blocks][T]
-    acq_detection* d_out = nullptr;     // [blocks][T]
-    int32_t* d_found = nullptr;         // [blocks][T]
-    double* d_refpart = nullptr;        // refinement partial sums [blocks * T][parts][3 * window]
-    int64_t* d_refcenter = nullptr;     // [blocks * T] refinement re-centring
-    int32_t* d_count = nullptr;         // [1]
-    int* d_counters = nullptr;          // [kXcds]
-    BlockDesc* d_descs = nullptr;       // [blocks]
-    int32_t* d_counts = nullptr;        // [2]
     acq_detection* h_out = nullptr;     // pinned [blocks][T]
-    int32_t* h_count = nullptr;         // pinned [1]
+    int32_t* h_count = nullptr;         // pinned [2]
     BlockDesc* h_descs = nullptr;       // pinned [blocks]
     int32_t* h_counts = nullptr;        // pinned [2]
-    int32_t* d_seglist = nullptr;       // [max(max_segments, max_total_segments)] segments searched by a
-                                        // learned search (per block, concatenated for batches)
     int32_t* h_iota = nullptr;          // pinned [max_segments] 0, 1, 2, ... (full-search lists)
+    hipEvent_t desc_ev = nullptr;       // after the last upload of h_descs / h_counts
+    bool desc_pending = false;
 
     bool profiling = false;
-    bool capturing = false;
+    bool capturing = false;             // capturing the plan's own batch graph
+    bool ext_capture = false;           // the plan's stream is being captured by the caller
     hipEvent_t ev[ACQ_NUM_KERNELS][2] = {};
     bool ev_used[ACQ_NUM_KERNELS] = {};
 
@@ -119,10 +133,8 @@ void drop_graph(acq_plan_s* p) {
 void free_plan(acq_plan_s* p) {
     if (!p) return;
     drop_graph(p);
-    void* dev[] = {p->d_X, p->d_Xh, p->d_cls, p->d_cls_cyc, p->d_cyc, p->d_bank, p->d_wts, p->d_rootsM, p->d_rootsSub, p->d_roots64, p->d_b1tab,
-                   p->d_chips,
-                   p->d_rot, p->d_rot_signed, p->d_freqs, p->d_keys, p->d_parts, p->d_exps, p->d_dets,
-                   p->d_out, p->d_found, p->d_refpart, p->d_refcenter, p->d_count, p->d_counters, p->d_descs, p->d_counts, p->d_seglist};
+    void* dev[] = {p->own_ws, p->d_cls, p->d_cls_cyc, p->d_cyc, p->d_bank, p->d_wts, p->d_rootsM, p->d_rootsSub,
+                   p->d_roots64, p->d_b1tab, p->d_chips, p->d_rot, p->d_rot_signed, p->d_freqs};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     void* host[] = {p->h_out, p->h_count, p->h_descs, p->h_counts, p->h_iota};
@@ -131,20 +143,84 @@ void free_plan(acq_plan_s* p) {
     for (auto& pair : p->ev)
         for (hipEvent_t e : pair)
             if (e) (void)hipEventDestroy(e);
+    if (p->desc_ev) (void)hipEventDestroy(p->desc_ev);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
 }
 
-int build_plan(acq_plan_s* p) {
+constexpr size_t kWsAlign = 256;
+
+// Carve the per-search buffers of `blocks` blocks and `segments` segment
+// spectra (and a proposal list of `seglist` entries) out of `base`, each
+// aligned to kWsAlign bytes.  Returns the bytes used; with base == nullptr
+// only the size is computed.
+size_t layout_scratch(const Geometry& g, const acq_config& c, int64_t blocks, int64_t segments, int64_t seglist,
+                      char* base, Scratch* s) {
+    size_t off = 0;
+    auto take = [&](auto*& ptr, size_t bytes) {
+        using P = std::remove_reference_t<decltype(ptr)>;
+        ptr = base ? reinterpret_cast<P>(base + off) : nullptr;
+        off += (std::max<size_t>(bytes, 1) + kWsAlign - 1) / kWsAlign * kWsAlign;
+    };
+    const size_t T = size_t(c.num_tags), B = size_t(blocks), S = size_t(std::max<int64_t>(segments, 1));
+    const size_t spectra = S * size_t(g.ncls) * size_t(g.M);
+    const size_t wmax = c.refine_radius <= 1 ? 5 : size_t(2 * acq::kMaxRefineRadius + 3);
+    take(s->X, spectra * sizeof(float2));
+    if (c.precision != ACQ_FP32) take(s->Xh, spectra * 4);
+    else s->Xh = nullptr;
+    take(s->keys, B * T * sizeof(unsigned long long));
+    take(s->cross, B * T * sizeof(unsigned));
+    take(s->parts, B * size_t(acq::kPowerParts) * sizeof(double));
+    take(s->exps, B * sizeof(int));
+    take(s->pthr, B * sizeof(float));
+    take(s->bad, B * sizeof(int32_t));
+    take(s->dets, B * T * sizeof(acq_detection));
+    take(s->out, B * T * sizeof(acq_detection));
+    take(s->found, B * T * sizeof(int32_t));
+    take(s->refpart, B * T * size_t(acq::kRefineParts) * 3 * wmax * sizeof(double));
+    take(s->refcenter, B * T * sizeof(int64_t));
+    take(s->count, 2 * sizeof(int32_t));
+    take(s->counters, size_t(acq::kXcds) * sizeof(int));
+    take(s->descs, B * sizeof(BlockDesc));
+    take(s->counts, 2 * sizeof(int32_t));
+    take(s->seglist, size_t(std::max<int64_t>(seglist, 1)) * sizeof(int32_t));
+    return off;
+}
+
+size_t workspace_bytes(const Geometry& g, const acq_config& c) {
+    Scratch s;
+    return layout_scratch(g, c, g.max_blocks, std::max<int64_t>(g.max_total_segments, 1),
+                          std::max<int64_t>({g.max_segments, g.max_total_segments, 1}), nullptr, &s);
+}
+
+// Device memory a plan holds besides its workspace: replica bank and tables.
+size_t own_bytes(const Geometry& g, const acq_config& c) {
+    const size_t T = size_t(c.num_tags), K = size_t(c.num_bins);
+    const size_t half = c.precision != ACQ_FP32 ? 4 : 8;
+    size_t b = T * size_t(acq::bank_stride(int(g.Msub))) * half;
+    b += size_t(g.M) * size_t(c.samples_per_chip) * 8 + size_t(g.M) * 8 + size_t(g.Msub) * 8 + size_t(g.M) * 16;
+    b += (g.log2_sub == 14 ? size_t(16 * 16 * 64) : 1) * 8;
+    b += T * size_t(c.num_chips) + K * (4 + 8 + 8 + 8 + 4) + size_t(g.ncls) * 8;
+    return b;
+}
+
+int build_plan(acq_plan_s* p, void* workspace, size_t ws_bytes) {
     const Geometry& g = p->g;
     const acq_config& c = p->cfg;
     const size_t T = size_t(c.num_tags), C = size_t(c.num_chips), K = size_t(c.num_bins);
     const size_t B = size_t(g.max_blocks);
-    const size_t S = size_t(g.max_total_segments > 0 ? g.max_total_segments : 1);
     const bool half = c.precision != ACQ_FP32;
     const size_t ncls = size_t(g.ncls);
-    ACQ_HIP(dalloc(&p->d_X, S * ncls * size_t(g.M)));
-    if (half) ACQ_HIP(hipMalloc(&p->d_Xh, S * ncls * size_t(g.M) * 4));
+    const size_t need = workspace_bytes(g, c);
+    char* base = static_cast<char*>(workspace);
+    if (!base) {
+        ACQ_HIP(hipMalloc(&p->own_ws, need));
+        base = static_cast<char*>(p->own_ws);
+    } else if (ws_bytes < need) {
+        return acq::fail(ACQ_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than acq_workspace_size");
+    }
+    layout_scratch(g, c, g.max_blocks, std::max<int64_t>(g.max_total_segments, 1),
+                   std::max<int64_t>({g.max_segments, g.max_total_segments, 1}), base, &p->ws);
     ACQ_HIP(dalloc(&p->d_cls, K));
     ACQ_HIP(dalloc(&p->d_cls_cyc, ncls));
     ACQ_HIP(dalloc(&p->d_cyc, K));
@@ -161,33 +237,21 @@ int build_plan(acq_plan_s* p) {
     ACQ_HIP(dalloc(&p->d_rot, K));
     ACQ_HIP(dalloc(&p->d_rot_signed, K));
     ACQ_HIP(dalloc(&p->d_freqs, K));
-    ACQ_HIP(dalloc(&p->d_keys, B * T));
-    ACQ_HIP(dalloc(&p->d_parts, B * size_t(acq::kPowerParts)));
-    ACQ_HIP(dalloc(&p->d_exps, B));
-    ACQ_HIP(dalloc(&p->d_dets, B * T));
-    ACQ_HIP(dalloc(&p->d_out, B * T));
-    ACQ_HIP(dalloc(&p->d_found, B * T));
-    const size_t wmax = c.refine_radius <= 1 ? 5 : size_t(2 * acq::kMaxRefineRadius + 3);
-    ACQ_HIP(dalloc(&p->d_refpart, B * T * size_t(acq::kRefineParts) * 3 * wmax));
-    ACQ_HIP(dalloc(&p->d_refcenter, B * T));
-    ACQ_HIP(dalloc(&p->d_count, 1));
-    ACQ_HIP(dalloc(&p->d_counters, size_t(acq::kXcds)));
-    ACQ_HIP(dalloc(&p->d_descs, B));
-    ACQ_HIP(dalloc(&p->d_counts, 2));
-    const size_t seglist = size_t(std::max<int64_t>({g.max_segments, g.max_total_segments, 1}));
-    ACQ_HIP(dalloc(&p->d_seglist, seglist));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_iota), sizeof(int32_t) * size_t(std::max<int64_t>(g.max_segments, 1))));
     for (int64_t j = 0; j < g.max_segments; ++j) p->h_iota[j] = int32_t(j);
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_out), sizeof(acq_detection) * B * T));
-    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t)));
+    ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_count), sizeof(int32_t) * 2));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_descs), sizeof(BlockDesc) * B));
     ACQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->h_counts), sizeof(int32_t) * 2));
+    ACQ_HIP(hipEventCreateWithFlags(&p->desc_ev, hipEventDisableTiming));
 
     const std::vector<float> rootsM = acq::unit_roots(g.M);
     const std::vector<float> rootsSub = acq::unit_roots(g.Msub);
     const std::vector<double> roots64 = acq::unit_roots64(g.M);
     const std::vector<float> wts = acq::phase_weights(g.M, c.samples_per_chip);
     hipStream_t st = p->stream;
+    // nothing has been searched yet: results read before the first search are empty
+    ACQ_HIP(acq::launch_fill_i32(p->ws.count, 2, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rootsM, rootsM.data(), rootsM.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_rootsSub, rootsSub.data(), rootsSub.size() * sizeof(float), hipMemcpyHostToDevice, st));
     ACQ_HIP(hipMemcpyAsync(p->d_roots64, roots64.data(), roots64.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -211,7 +275,8 @@ struct KernelTimer {
     acq_plan_s* p;
     int id;
     bool on;
-    KernelTimer(acq_plan_s* plan, int kernel) : p(plan), id(kernel), on(plan->profiling && !plan->capturing) {
+    KernelTimer(acq_plan_s* plan, int kernel)
+        : p(plan), id(kernel), on(plan->profiling && !plan->capturing && !plan->ext_capture) {
         if (on) {
             (void)hipEventRecord(p->ev[id][0], p->stream);
             p->ev_used[id] = true;
@@ -231,28 +296,44 @@ double threshold_for(const acq_plan_s* p, int64_t n) {
     return c.threshold > 0.0 ? c.threshold : acq::default_threshold(c.num_tags, c.num_bins, n, p->g.L);
 }
 
-// Launch sequence of a search on stream st.  `bt` holds one inline block
-// (single-block calls: plain grids sized on the host) or the plan's device
-// block table (batches: persistent grids that do not depend on the batch, so
-// the sequence can be captured once and replayed).  track: every block is a
-// tracking task searched for its own tag only.
-int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_seg_host, float* dump,
-                   bool refine, hipStream_t st, bool track = false) {
+// Where a search leaves its results: the compacted detections (at most
+// `capacity` records) and their count, in device memory, optionally copied to
+// the plan's pinned staging.
+struct ResultDest {
+    acq_detection* out;
+    int32_t capacity;
+    int32_t* count;             // [1]
+    bool to_host;
+};
+
+ResultDest workspace_dest(const acq_plan_s* p, bool to_host) {
+    return ResultDest{p->ws.out, int32_t(std::min<int64_t>(int64_t(p->g.max_blocks) * p->cfg.num_tags, INT32_MAX)),
+                      p->ws.count, to_host};
+}
+
+// Launch sequence of a search on stream st, in the buffers of `w`.  `bt`
+// holds one inline block (single-block calls: plain grids sized on the host)
+// or the plan's device block table (batches: persistent grids that do not
+// depend on the batch, so the sequence can be captured once and replayed).
+// track: every block is a tracking task searched for its own tag only.
+int enqueue_search(acq_plan_s* p, const Scratch& w, const BlockTable& bt, bool batch, int total_seg_host, float* dump,
+                   bool refine, hipStream_t st, bool track, const ResultDest& dst) {
     const Geometry& g = p->g;
     const acq_config& c = p->cfg;
     const int nb_grid = batch ? g.max_blocks : 1;
     {
         KernelTimer kt(p, ACQ_KERNEL_BLOCK_POWER);
-        ACQ_HIP(acq::launch_block_power(bt, nb_grid, c.max_block_len, p->d_parts, st));
+        ACQ_HIP(acq::launch_block_power(bt, nb_grid, c.max_block_len, w.parts, st));
     }
-    if (c.precision != ACQ_FP32) ACQ_HIP(acq::launch_block_exponent(bt, nb_grid, p->d_parts, int(g.M), p->d_exps, st));
-    ACQ_HIP(acq::launch_fill_u64(p->d_keys, int64_t(nb_grid) * c.num_tags, st));
+    ACQ_HIP(acq::launch_block_stats(bt, w.parts, int(g.M), g.L, w.exps, w.pthr, w.bad, w.count + 1, st));
+    ACQ_HIP(acq::launch_fill_u64(w.keys, int64_t(nb_grid) * c.num_tags, st));
+    ACQ_HIP(acq::launch_fill_i32(reinterpret_cast<int*>(w.cross), int64_t(nb_grid) * c.num_tags, st));
 
     acq::FwdArgs fa{};
     fa.blocks = bt;
-    fa.X = p->d_X;
-    fa.Xh = p->d_Xh;
-    fa.exps = p->d_exps;
+    fa.X = w.X;
+    fa.Xh = w.Xh;
+    fa.exps = w.exps;
     fa.cls_cyc = p->d_cls_cyc;
     fa.ncls = g.ncls;
     fa.rootsM = p->d_rootsM;
@@ -274,9 +355,9 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
 
     acq::CorrArgs ca{};
     ca.blocks = bt;
-    ca.X = c.precision == ACQ_FP32 ? static_cast<const void*>(p->d_X) : p->d_Xh;
+    ca.X = c.precision == ACQ_FP32 ? static_cast<const void*>(w.X) : w.Xh;
     ca.bank = p->d_bank;
-    ca.exps = p->d_exps;
+    ca.exps = w.exps;
     ca.wts = p->d_wts;
     ca.rootsM = p->d_rootsM;
     ca.rootsSub = p->d_rootsSub;
@@ -284,9 +365,11 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ca.rot = p->d_rot;
     ca.cls = p->d_cls;
     ca.ncls = g.ncls;
-    ca.keys = p->d_keys;
+    ca.keys = w.keys;
+    ca.pthr = w.pthr;
+    ca.cross = w.cross;
     ca.dump = dump;
-    ca.counters = p->d_counters;
+    ca.counters = w.counters;
     ca.V = g.V;
     ca.K = c.num_bins;
     ca.spc = c.samples_per_chip;
@@ -322,7 +405,7 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
         if (nwork >= (int64_t(1) << 31) - 8) return acq::fail(ACQ_ERR_UNSUPPORTED, "too many work items");
         grid = int((nwork + acq::kXcds - 1) / acq::kXcds) * acq::kXcds;
     } else if (ca.persistent) {
-        ACQ_HIP(acq::launch_fill_i32(p->d_counters, acq::kXcds, st));
+        ACQ_HIP(acq::launch_fill_i32(w.counters, acq::kXcds, st));
         grid = p->cus;
     } else {
         // batches captured into a graph size the grid for the plan's capacity;
@@ -343,10 +426,13 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ra.chips = p->d_chips;
     ra.rot_signed = p->d_rot_signed;
     ra.freqs = p->d_freqs;
-    ra.keys = p->d_keys;
-    ra.parts = p->d_parts;
-    ra.dets = p->d_dets;
-    ra.found = p->d_found;
+    ra.keys = w.keys;
+    ra.parts = w.parts;
+    ra.bad = w.bad;
+    ra.cross = w.cross;
+    ra.check_finite = (c.flags & ACQ_FLAG_CHECK_FINITE) ? 1 : 0;
+    ra.dets = w.dets;
+    ra.found = w.found;
     ra.L = g.L;
     ra.T = c.num_tags;
     ra.C = c.num_chips;
@@ -359,20 +445,22 @@ int enqueue_search(acq_plan_s* p, const BlockTable& bt, bool batch, int total_se
     ra.M = int(g.M);
     ra.radius = c.refine_radius > 0 ? c.refine_radius : 1;
     ra.track = track ? 1 : 0;
-    ra.partial = p->d_refpart;
-    ra.center = p->d_refcenter;
+    ra.partial = w.refpart;
+    ra.center = w.refcenter;
     {
         KernelTimer kt(p, ACQ_KERNEL_REFINE);
         ACQ_HIP(acq::launch_refine(ra, nb_grid, st));
     }
     {
         KernelTimer kt(p, ACQ_KERNEL_COMPACT);
-        ACQ_HIP(acq::launch_compact(bt, p->d_dets, p->d_found, c.num_tags, track ? 1 : 0, p->d_out, p->d_count, st));
+        ACQ_HIP(acq::launch_compact(bt, w.dets, w.found, c.num_tags, track ? 1 : 0, dst.out, dst.capacity, dst.count,
+                                    st));
     }
-    ACQ_HIP(hipMemcpyAsync(p->h_count, p->d_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (!dst.to_host) return ACQ_OK;
+    ACQ_HIP(hipMemcpyAsync(p->h_count, w.count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     // at most one detection per (block, tag), per task when tracking
     const size_t most = size_t(nb_grid) * size_t(track ? 1 : c.num_tags);
-    ACQ_HIP(hipMemcpyAsync(p->h_out, p->d_out, sizeof(acq_detection) * most, hipMemcpyDeviceToHost, st));
+    ACQ_HIP(hipMemcpyAsync(p->h_out, w.out, sizeof(acq_detection) * most, hipMemcpyDeviceToHost, st));
     return ACQ_OK;
 }
 
@@ -398,14 +486,27 @@ BlockDesc single_desc(const acq_plan_s* p, const void* block, int64_t n) {
     return d;
 }
 
+bool async_mode(const acq_plan_s* p) { return (p->cfg.flags & ACQ_FLAG_ASYNC) != 0; }
+
+// The host-side descriptor staging may be rewritten once the previous upload
+// from it has run (asynchronous plans return before their searches run).
+int wait_descriptors(acq_plan_s* p) {
+    if (p->desc_pending) {
+        ACQ_HIP(hipEventSynchronize(p->desc_ev));
+        p->desc_pending = false;
+    }
+    return ACQ_OK;
+}
+
 // Copies the staged descriptors and runs a batch search: eagerly, or by
 // replaying the plan's captured graph for this kind of batch (captured on
 // first use with grids sized for the plan's capacity).
 int launch_batch(acq_plan_s* p, int32_t seg, bool track) {
     BlockTable bt{};
-    bt.descs = p->d_descs;
-    bt.counts = p->d_counts;
+    bt.descs = p->ws.descs;
+    bt.counts = p->ws.counts;
     const size_t desc_bytes = sizeof(BlockDesc) * size_t(p->g.max_blocks);
+    const ResultDest dst = workspace_dest(p, !async_mode(p));
     if (p->cfg.flags & ACQ_FLAG_GRAPH) {
         hipGraph_t& graph_ref = track ? p->tgraph : p->graph;
         hipGraphExec_t& exec_ref = track ? p->tgexec : p->gexec;
@@ -414,13 +515,14 @@ int launch_batch(acq_plan_s* p, int32_t seg, bool track) {
             ACQ_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
             p->capturing = true;
             int rc = ACQ_OK;
-            hipError_t e = hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->cap_stream);
+            hipError_t e = hipMemcpyAsync(p->ws.descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->cap_stream);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice,
+                e = hipMemcpyAsync(p->ws.counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice,
                                    p->cap_stream);
             // grids follow the plan's capacity while capturing; the capturing
             // batch's segment count only guides the bins per tracking item
-            if (e == hipSuccess) rc = enqueue_search(p, bt, true, seg, nullptr, true, p->cap_stream, track);
+            if (e == hipSuccess)
+                rc = enqueue_search(p, p->ws, bt, true, seg, nullptr, true, p->cap_stream, track, dst);
             p->capturing = false;
             hipGraph_t graph = nullptr;
             const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
@@ -433,21 +535,72 @@ int launch_batch(acq_plan_s* p, int32_t seg, bool track) {
             ACQ_HIP(hipGraphInstantiate(&exec_ref, graph_ref, nullptr, nullptr, 0));
         }
         ACQ_HIP(hipGraphLaunch(exec_ref, p->stream));
+        ACQ_HIP(hipEventRecord(p->desc_ev, p->stream));
+        p->desc_pending = true;
     } else {
-        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->stream));
-        ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
-        const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream, track);
+        ACQ_HIP(hipMemcpyAsync(p->ws.descs, p->h_descs, desc_bytes, hipMemcpyHostToDevice, p->stream));
+        ACQ_HIP(hipMemcpyAsync(p->ws.counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+        ACQ_HIP(hipEventRecord(p->desc_ev, p->stream));
+        p->desc_pending = true;
+        const int rc = enqueue_search(p, p->ws, bt, true, seg, nullptr, true, p->stream, track, dst);
         if (rc != ACQ_OK) return rc;
     }
     return ACQ_OK;
 }
 
-int deliver(acq_plan_s* p, acq_detection* out, int32_t capacity, int32_t* n_found) {
-    const int32_t found = *p->h_count;
+// Detections staged on the host after a synchronous search (or read back by
+// acq_collect): copied to out, then the status.  Blocks holding non-finite
+// samples (ACQ_FLAG_CHECK_FINITE) take precedence over truncation.
+int deliver(acq_plan_s* p, acq_detection* out, int32_t capacity, int32_t* n_found, int32_t* block_of = nullptr) {
+    const int32_t found = p->h_count[0];
+    const int32_t nbad = p->h_count[1];
     *n_found = found;
     const int32_t ncopy = found < capacity ? found : capacity;
     if (ncopy > 0) std::memcpy(out, p->h_out, sizeof(acq_detection) * size_t(ncopy));
+    if (block_of)
+        for (int32_t i = 0; i < ncopy; ++i) block_of[i] = out[i].block;
+    if ((p->cfg.flags & ACQ_FLAG_CHECK_FINITE) && nbad > 0)
+        return acq::fail(ACQ_ERR_NON_FINITE, std::to_string(nbad) + " block(s) hold non-finite samples");
     if (found > capacity) return acq::fail(ACQ_ERR_TRUNCATED, "more detections than capacity");
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+// Output arguments of a result-returning call: required unless the plan is
+// asynchronous (its results stay on the device).
+int check_outputs(const acq_plan_s* p, const acq_detection* out, int32_t capacity, const int32_t* n_found) {
+    if (async_mode(p)) return ACQ_OK;
+    if (!n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null n_found");
+    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    return ACQ_OK;
+}
+
+// Note whether the caller is capturing the plan's stream into a graph (the
+// plan's kernel timers stay off then).
+int note_capture(acq_plan_s* p) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    ACQ_HIP(hipStreamIsCapturing(p->stream, &cs));
+    p->ext_capture = cs != hipStreamCaptureStatusNone;
+    return ACQ_OK;
+}
+
+// End of a result-returning search: synchronous plans wait and deliver,
+// asynchronous ones leave the results on the device.
+int finish(acq_plan_s* p, acq_detection* out, int32_t capacity, int32_t* n_found, int32_t* block_of = nullptr) {
+    if (async_mode(p)) {
+        if (n_found) *n_found = 0;
+        acq::clear_error();
+        return ACQ_OK;
+    }
+    ACQ_HIP(hipStreamSynchronize(p->stream));
+    return deliver(p, out, capacity, n_found, block_of);
+}
+
+// A call with nothing to search: the results are empty (device too, so that a
+// later acq_collect or device read sees them).
+int finish_empty(acq_plan_s* p, int32_t* n_found) {
+    if (n_found) *n_found = 0;
+    if (async_mode(p)) ACQ_HIP(acq::launch_fill_i32(p->ws.count, 2, p->stream));
     acq::clear_error();
     return ACQ_OK;
 }
@@ -470,7 +623,17 @@ int acq_plan_geometry(const acq_config* cfg, acq_geometry* out) {
     out->freq_quantum_hz = g.q;
     out->bin_center_hz = double(g.centre_q) * g.q;
     out->bin_step_hz = double(g.step_q) * g.q;
-    out->device_bytes = g.device_bytes;
+    out->workspace_bytes = int64_t(workspace_bytes(g, *cfg));
+    out->device_bytes = int64_t(own_bytes(g, *cfg)) + out->workspace_bytes;
+    return ACQ_OK;
+}
+
+int acq_workspace_size(const acq_config* cfg, size_t* bytes) {
+    if (!bytes) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
+    Geometry g;
+    const int rc = acq::derive_geometry(cfg, &g);
+    if (rc != ACQ_OK) return rc;
+    *bytes = workspace_bytes(g, *cfg);
     return ACQ_OK;
 }
 
@@ -484,12 +647,18 @@ int acq_bin_frequencies(const acq_config* cfg, double* freqs_hz, int32_t n) {
     return ACQ_OK;
 }
 
-int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out) {
+int acq_plan(const acq_config* cfg, void* workspace, size_t workspace_bytes_, void* stream, acq_plan_t* out) {
     if (!out) return acq::fail(ACQ_ERR_INVALID_ARG, "null output");
     *out = nullptr;
+    if (workspace && reinterpret_cast<uintptr_t>(workspace) % kWsAlign != 0)
+        return acq::fail(ACQ_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     Geometry g;
     int rc = acq::derive_geometry(cfg, &g);
     if (rc != ACQ_OK) return rc;
+    if (workspace && workspace_bytes_ < workspace_bytes(g, *cfg))
+        return acq::fail(ACQ_ERR_WORKSPACE_TOO_SMALL, "workspace of " + std::to_string(workspace_bytes_) +
+                                                          " bytes, the plan needs " +
+                                                          std::to_string(workspace_bytes(g, *cfg)));
     acq_plan_s* p = new (std::nothrow) acq_plan_s();
     if (!p) return acq::fail(ACQ_ERR_OOM, "host allocation failed");
     p->cfg = *cfg;                   // chips are read by build_plan only
@@ -503,7 +672,7 @@ int acq_plan(const acq_config* cfg, void* stream, acq_plan_t* out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus >= 8)
         p->cus = cus / acq::kXcds * acq::kXcds;
-    rc = build_plan(p);
+    rc = build_plan(p, workspace, workspace_bytes_);
     p->cfg.chips = nullptr;          // copied to the device; the caller keeps its buffer
     if (rc != ACQ_OK) {
         free_plan(p);
@@ -518,38 +687,40 @@ int acq_detect(acq_plan_t p, const void* block, int64_t n, acq_detection* out, i
                int32_t* n_found) {
     int rc = check_block(p, block, n);
     if (rc != ACQ_OK) return rc;
-    if (!n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null n_found");
-    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
-    *n_found = 0;
-    if (n < p->g.L) {
-        acq::clear_error();
-        return ACQ_OK;
-    }
+    rc = check_outputs(p, out, capacity, n_found);
+    if (rc != ACQ_OK) return rc;
+    if (n_found) *n_found = 0;
+    if (n < p->g.L) return finish_empty(p, n_found);
+    rc = note_capture(p);
+    if (rc != ACQ_OK) return rc;
     reset_timers(p);
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
-    rc = enqueue_search(p, bt, false, bt.one.nseg, nullptr, true, p->stream);
+    rc = enqueue_search(p, p->ws, bt, false, bt.one.nseg, nullptr, true, p->stream, false,
+                        workspace_dest(p, !async_mode(p)));
     if (rc != ACQ_OK) return rc;
-    ACQ_HIP(hipStreamSynchronize(p->stream));
-    return deliver(p, out, capacity, n_found);
+    return finish(p, out, capacity, n_found);
 }
 
 int acq_detect_batch(acq_plan_t p, const void* const* blocks, const int64_t* lens, int32_t nblocks,
-                     acq_detection* out, int32_t capacity, int32_t* n_found) {
+                     acq_detection* out, int32_t capacity, int32_t* n_found, int32_t* block_of) {
     if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
-    if (!blocks || !lens || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
-    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (!blocks || !lens) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    int rc = check_outputs(p, out, capacity, n_found);
+    if (rc != ACQ_OK) return rc;
     if (nblocks < 1 || nblocks > p->g.max_blocks)
         return acq::fail(ACQ_ERR_INVALID_ARG, "nblocks outside [1, max_batch_blocks]");
     int64_t total = 0;
     for (int32_t b = 0; b < nblocks; ++b) {
-        const int rc = check_block(p, blocks[b], lens[b]);
+        rc = check_block(p, blocks[b], lens[b]);
         if (rc != ACQ_OK) return rc;
         total += lens[b];
     }
     if (total > p->g.max_batch_samples)
         return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "batch longer than max_batch_samples");
-    *n_found = 0;
+    if (n_found) *n_found = 0;
+    rc = wait_descriptors(p);
+    if (rc != ACQ_OK) return rc;
     int32_t seg = 0;
     for (int32_t b = 0; b < nblocks; ++b) {
         BlockDesc d = single_desc(p, blocks[b], lens[b]);
@@ -559,24 +730,25 @@ int acq_detect_batch(acq_plan_t p, const void* const* blocks, const int64_t* len
     }
     p->h_counts[0] = nblocks;
     p->h_counts[1] = seg;
+    p->ext_capture = false;
     reset_timers(p);
 
-    const int rc = launch_batch(p, seg, false);
+    rc = launch_batch(p, seg, false);
     if (rc != ACQ_OK) return rc;
-    ACQ_HIP(hipStreamSynchronize(p->stream));
-    return deliver(p, out, capacity, n_found);
+    return finish(p, out, capacity, n_found, block_of);
 }
 
 int acq_track_batch(acq_plan_t p, const acq_track_task* tasks, int32_t ntasks, acq_detection* out,
                     int32_t capacity, int32_t* n_found) {
     if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
-    if (!tasks || !n_found) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
-    if (capacity < 0 || (capacity > 0 && !out)) return acq::fail(ACQ_ERR_INVALID_ARG, "bad output buffer");
+    if (!tasks) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    int rc = check_outputs(p, out, capacity, n_found);
+    if (rc != ACQ_OK) return rc;
     if (ntasks < 1 || ntasks > p->g.max_blocks)
         return acq::fail(ACQ_ERR_INVALID_ARG, "ntasks outside [1, max_batch_blocks]");
     int64_t total = 0;
     for (int32_t b = 0; b < ntasks; ++b) {
-        const int rc = check_block(p, tasks[b].block, tasks[b].n);
+        rc = check_block(p, tasks[b].block, tasks[b].n);
         if (rc != ACQ_OK) return rc;
         if (tasks[b].tag < 0 || tasks[b].tag >= p->cfg.num_tags)
             return acq::fail(ACQ_ERR_INVALID_ARG, "task tag outside [0, num_tags)");
@@ -584,7 +756,9 @@ int acq_track_batch(acq_plan_t p, const acq_track_task* tasks, int32_t ntasks, a
     }
     if (total > p->g.max_batch_samples)
         return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "batch longer than max_batch_samples");
-    *n_found = 0;
+    if (n_found) *n_found = 0;
+    rc = wait_descriptors(p);
+    if (rc != ACQ_OK) return rc;
     const acq_config& c = p->cfg;
     int32_t seg = 0;
     for (int32_t b = 0; b < ntasks; ++b) {
@@ -598,12 +772,35 @@ int acq_track_batch(acq_plan_t p, const acq_track_task* tasks, int32_t ntasks, a
     }
     p->h_counts[0] = ntasks;
     p->h_counts[1] = seg;
+    p->ext_capture = false;
     reset_timers(p);
-    const int rc = launch_batch(p, seg, true);
+    rc = launch_batch(p, seg, true);
     if (rc != ACQ_OK) return rc;
+    return finish(p, out, capacity, n_found);
+}
+
+int acq_collect(acq_plan_t p, acq_detection* out, int32_t capacity, int32_t* n_found) {
+    if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (!n_found || capacity < 0 || (capacity > 0 && !out))
+        return acq::fail(ACQ_ERR_INVALID_ARG, "bad output arguments");
     ACQ_HIP(hipStreamSynchronize(p->stream));
+    ACQ_HIP(hipMemcpy(p->h_count, p->ws.count, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int32_t found = p->h_count[0];
+    const int32_t ncopy = std::max(0, std::min(found, capacity));
+    if (ncopy > 0) ACQ_HIP(hipMemcpy(p->h_out, p->ws.out, sizeof(acq_detection) * size_t(ncopy), hipMemcpyDeviceToHost));
     return deliver(p, out, capacity, n_found);
 }
+
+int acq_device_results(acq_plan_t p, const acq_detection** records, const int32_t** counts) {
+    if (!p || !records || !counts) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    *records = p->ws.out;
+    *counts = p->ws.count;
+    return ACQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
 
 // Proposals of one block (n >= L) written to d_segs; on a fallback the full
 // list 0 .. nseg-1 instead.  Fills the report and the searched segment count.
@@ -637,6 +834,10 @@ int propose_block(acq_plan_s* p, acq_cnn_t cnn, const void* block, int64_t n, co
     return ACQ_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n, const acq_learned_params* lp,
                        acq_detection* out, int32_t capacity, int32_t* n_found, acq_learned_report* report) {
     int rc = check_block(p, block, n);
@@ -658,7 +859,7 @@ int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
     int32_t nseg = 0;
-    rc = propose_block(p, cnn, block, n, lp, p->d_seglist, &rep, &nseg);
+    rc = propose_block(p, cnn, block, n, lp, p->ws.seglist, &rep, &nseg);
     if (rc != ACQ_OK) return rc;
     if (report) *report = rep;
     if (nseg == 0) {
@@ -666,8 +867,9 @@ int acq_detect_learned(acq_plan_t p, acq_cnn_t cnn, const void* block, int64_t n
         return ACQ_OK;
     }
     bt.one.nseg = nseg;
-    bt.seg_of = p->d_seglist;
-    rc = enqueue_search(p, bt, false, nseg, nullptr, true, p->stream);
+    bt.seg_of = p->ws.seglist;
+    p->ext_capture = false;
+    rc = enqueue_search(p, p->ws, bt, false, nseg, nullptr, true, p->stream, false, workspace_dest(p, true));
     if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
     return deliver(p, out, capacity, n_found);
@@ -691,6 +893,8 @@ int acq_detect_batch_learned(acq_plan_t p, acq_cnn_t cnn, const void* const* blo
     if (total > p->g.max_batch_samples)
         return acq::fail(ACQ_ERR_BLOCK_TOO_LONG, "batch longer than max_batch_samples");
     *n_found = 0;
+    const int wrc = wait_descriptors(p);
+    if (wrc != ACQ_OK) return wrc;
     reset_timers(p);
     int32_t seg = 0;
     for (int32_t b = 0; b < nblocks; ++b) {
@@ -698,7 +902,7 @@ int acq_detect_batch_learned(acq_plan_t p, acq_cnn_t cnn, const void* const* blo
         acq_learned_report rep{};
         int32_t nseg = 0;
         if (lens[b] >= p->g.L) {
-            const int rc = propose_block(p, cnn, blocks[b], lens[b], lp, p->d_seglist + seg, &rep, &nseg);
+            const int rc = propose_block(p, cnn, blocks[b], lens[b], lp, p->ws.seglist + seg, &rep, &nseg);
             if (rc != ACQ_OK) return rc;
         } else {
             double floor = 0.0;
@@ -718,13 +922,14 @@ int acq_detect_batch_learned(acq_plan_t p, acq_cnn_t cnn, const void* const* blo
     p->h_counts[0] = nblocks;
     p->h_counts[1] = seg;
     BlockTable bt{};
-    bt.descs = p->d_descs;
-    bt.counts = p->d_counts;
-    bt.seg_of = p->d_seglist;
-    ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(BlockDesc) * size_t(nblocks), hipMemcpyHostToDevice,
+    bt.descs = p->ws.descs;
+    bt.counts = p->ws.counts;
+    bt.seg_of = p->ws.seglist;
+    ACQ_HIP(hipMemcpyAsync(p->ws.descs, p->h_descs, sizeof(BlockDesc) * size_t(nblocks), hipMemcpyHostToDevice,
                            p->stream));
-    ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
-    const int rc = enqueue_search(p, bt, true, seg, nullptr, true, p->stream);
+    ACQ_HIP(hipMemcpyAsync(p->ws.counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+    p->ext_capture = false;
+    const int rc = enqueue_search(p, p->ws, bt, true, seg, nullptr, true, p->stream, false, workspace_dest(p, true));
     if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
     return deliver(p, out, capacity, n_found);
@@ -741,7 +946,9 @@ int acq_correlate_power(acq_plan_t p, const void* block, int64_t n, float* power
     reset_timers(p);
     BlockTable bt{};
     bt.one = single_desc(p, block, n);
-    rc = enqueue_search(p, bt, false, bt.one.nseg, power, false, p->stream);
+    rc = note_capture(p);
+    if (rc != ACQ_OK) return rc;
+    rc = enqueue_search(p, p->ws, bt, false, bt.one.nseg, power, false, p->stream, false, workspace_dest(p, false));
     if (rc != ACQ_OK) return rc;
     ACQ_HIP(hipStreamSynchronize(p->stream));
     acq::clear_error();
@@ -801,11 +1008,14 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
     // the same block repeated as a batch (device descriptor table): as many
     // copies as the plan's batch capacity holds, at most 16
     BlockTable bbt{};
-    bbt.descs = p->d_descs;
-    bbt.counts = p->d_counts;
+    bbt.descs = p->ws.descs;
+    bbt.counts = p->ws.counts;
     const int64_t copies = std::min<int64_t>({int64_t(p->g.max_blocks), p->g.max_batch_samples / n, 16});
     const bool batch_ok = copies >= 1;
     int32_t batch_seg = 0;
+    rc = wait_descriptors(p);
+    if (rc != ACQ_OK) return rc;
+    p->ext_capture = false;
     if (batch_ok) {
         for (int64_t b = 0; b < copies; ++b) {
             p->h_descs[b] = bt.one;
@@ -814,17 +1024,17 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
         }
         p->h_counts[0] = int32_t(copies);
         p->h_counts[1] = batch_seg;
-        ACQ_HIP(hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(BlockDesc) * size_t(copies), hipMemcpyHostToDevice,
+        ACQ_HIP(hipMemcpyAsync(p->ws.descs, p->h_descs, sizeof(BlockDesc) * size_t(copies), hipMemcpyHostToDevice,
                                p->stream));
-        ACQ_HIP(hipMemcpyAsync(p->d_counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+        ACQ_HIP(hipMemcpyAsync(p->ws.counts, p->h_counts, 2 * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
     }
     auto time_one = [&](const acq_tuning& t, bool batch, double* mean_ms) -> int {
         acq_set_tuning(p, &t);
         double total = 0.0;
         for (int r = 0; r <= reps; ++r) {           // one warm-up run
             reset_timers(p);
-            const int rc2 = enqueue_search(p, batch ? bbt : bt, batch, batch ? batch_seg : bt.one.nseg, nullptr, false,
-                                           p->stream);
+            const int rc2 = enqueue_search(p, p->ws, batch ? bbt : bt, batch, batch ? batch_seg : bt.one.nseg, nullptr,
+                                           false, p->stream, false, workspace_dest(p, false));
             if (rc2 != ACQ_OK) return rc2;
             ACQ_HIP(hipStreamSynchronize(p->stream));
             float ms = 0.f;
@@ -909,7 +1119,9 @@ const char* acq_strerror(int status) {
         case ACQ_ERR_DEVICE: return "device error";
         case ACQ_ERR_TRUNCATED: return "output truncated";
         case ACQ_ERR_BLOCK_TOO_LONG: return "block too long";
+        case ACQ_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
         case ACQ_ERR_UNSUPPORTED: return "unsupported";
+        case ACQ_ERR_NON_FINITE: return "non-finite samples";
         default: return "unknown status";
     }
 }

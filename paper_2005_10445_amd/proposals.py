@@ -164,7 +164,7 @@ class Network:
 
     def detect(self, plan, block, params: LearnedParams):
         """acq_detect_learned: (detections, LearnedReport)."""
-        from . import Detection
+        from . import _det
         n = block.numel()
         out = (_capi.AcqDetection * plan.num_tags)()
         nf = ctypes.c_int32(0)
@@ -173,14 +173,13 @@ class Network:
         check(self._lib.acq_detect_learned(plan._h, self._h, ctypes.c_void_p(_dev(block, "block")), n,
                                            ctypes.byref(lp), out, plan.num_tags, ctypes.byref(nf),
                                            ctypes.byref(rep)), "acq_detect_learned")
-        dets = [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
+        dets = [_det(d) for d in out[:nf.value]]
         return dets, LearnedReport(rep.proposals, rep.segments, rep.total_segments, rep.fallback, rep.median,
                                    rep.floor)
 
     def detect_batch(self, plan, blocks, params: LearnedParams):
         """acq_detect_batch_learned over a list of device blocks: (detections, [LearnedReport])."""
-        from . import Detection
+        from . import _det
         n = len(blocks)
         ptrs = (ctypes.c_void_p * n)()
         lens = (ctypes.c_int64 * n)()
@@ -193,8 +192,7 @@ class Network:
         lp = _capi.AcqLearnedParams(float(params.kappa), float(params.max_fraction), float(params.floor_db))
         check(self._lib.acq_detect_batch_learned(plan._h, self._h, ptrs, lens, n, ctypes.byref(lp), out, cap,
                                                  ctypes.byref(nf), reps), "acq_detect_batch_learned")
-        dets = [Detection(d.tag, d.bin, d.lag, d.toa_samples, d.freq_hz, d.peak_power, d.z, d.energy,
-                          d.block_power, d.block, d.flags, d.power, d.snr) for d in out[:nf.value]]
+        dets = [_det(d) for d in out[:nf.value]]
         return dets, [LearnedReport(r.proposals, r.segments, r.total_segments, r.fallback, r.median, r.floor)
                       for r in reps]
 

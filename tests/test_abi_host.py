@@ -108,9 +108,55 @@ def test_null_handles_rejected_without_gpu(capi):
     assert L.acq_detect(None, None, 10, out, 1, ctypes.byref(n)) == -1
     assert L.acq_correlate_power(None, None, 10, None) == -1
     assert L.acq_release(None) == 0
-    assert L.acq_plan(None, None, None) == -1
+    assert L.acq_plan(None, None, 0, None, None) == -1
+    assert L.acq_collect(None, out, 1, ctypes.byref(n)) == -1
+    rec, cnt = ctypes.c_void_p(), ctypes.c_void_p()
+    assert L.acq_device_results(None, ctypes.byref(rec), ctypes.byref(cnt)) == -1
+    assert L.acq_detect_batch(None, None, None, 1, out, 1, ctypes.byref(n), None) == -1
     assert L.acq_strerror(-4) == b"output truncated"
+    assert L.acq_strerror(-6) == b"workspace too small"
+    assert L.acq_strerror(-8) == b"non-finite samples"
     assert L.acq_strerror(0) == b"ok"
+
+
+def test_detection_record_layout(capi):
+    # tag, bin, lag, 8 doubles (toa .. snr), block, flags, crossings
+    assert ctypes.sizeof(capi.AcqDetection) == 4 + 4 + 8 + 8 * 8 + 4 + 4 + 8
+    assert capi.AcqDetection.crossings.offset == 88
+
+
+def test_workspace_size_and_caller_workspace_checked_before_the_gpu(capi):
+    """The per-search workspace (Section 4.2: buffers allocated once): its size is
+    the same from acq_workspace_size and the geometry, grows with the batch
+    capacity, and a caller workspace that is too small or misaligned is refused
+    before any device call."""
+    L = capi.lib()
+    cfg, keep = _cfg(capi)
+    need = ctypes.c_size_t(0)
+    assert L.acq_workspace_size(ctypes.byref(cfg), ctypes.byref(need)) == 0
+    rc, g = _status(capi, cfg)
+    assert rc == 0 and g.workspace_bytes == need.value and g.device_bytes > g.workspace_bytes
+    # 63 segment spectra of 2^15 FP32 complex values dominate
+    assert 63 * (1 << 15) * 8 <= need.value <= 63 * (1 << 15) * 8 + (4 << 20)
+    big, keep2 = _cfg(capi, max_batch_blocks=4)
+    need4 = ctypes.c_size_t(0)
+    assert L.acq_workspace_size(ctypes.byref(big), ctypes.byref(need4)) == 0 and need4.value > need.value
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)                  # never dereferenced: the size check comes first
+    assert L.acq_plan(ctypes.byref(cfg), fake, need.value - 1, None, ctypes.byref(h)) == capi.ACQ_ERR_WORKSPACE_TOO_SMALL
+    assert not h.value and b"workspace" in L.acq_last_error()
+    assert L.acq_plan(ctypes.byref(cfg), ctypes.c_void_p((1 << 20) + 8), need.value, None,
+                      ctypes.byref(h)) == capi.ACQ_ERR_INVALID_ARG
+    assert L.acq_workspace_size(None, ctypes.byref(need)) == -1
+
+
+def test_async_and_finite_flags_accepted_unknown_flags_refused(capi):
+    from paper_2005_10445_amd import geometry
+    kw = dict(chips=siggen.make_codes(1, 2, 1000), spc=2, fs_hz=8e6, max_block_len=50000)
+    assert geometry(asynchronous=True, check_finite=True, **kw)["fft_len"] > 0
+    cfg, keep = _cfg(capi)
+    cfg.flags = 0x10
+    assert _status(capi, cfg)[0] == -1
 
 
 def test_oracle_is_not_imported_by_the_product():

@@ -1,6 +1,9 @@
 """Batched search (many uneven blocks, one persistent correlation launch,
 optional hipGraph replay) and tuning: identical to single-block searches, and
 to the FP64 oracle."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -116,13 +119,21 @@ def test_tuning_candidates_give_identical_results(dev):
                 assert np.max(np.abs(P - base_P) / np.maximum(base_P, L * Px)) <= 1e-5, e
 
 
+GOLDEN_STREAM = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "stream_seed4000_shortest2.json")
+
+
 @pytest.mark.timeout(600)
 def test_stream_workload_full_size(dev):
     """256 tags x 21 bins over +/-10 kHz, 64 blocks of uneven length (log-uniform
     in [2^18, 2^21]) from 8 receivers, 0-20 transmissions per block, one graph-
-    captured batch: per-block identity with single-block searches (sampled
-    blocks), injected transmissions found, FP64 peak values against the direct
-    definition, detections outside the injected set confirmed by the oracle."""
+    captured batch at M = 2^15 (the launch configuration the benchmark times):
+    per-block identity with single-block searches (sampled blocks), injected
+    transmissions found, and the complete detection sets of the two shortest
+    blocks (every tag and bin) equal to the oracle's, stored by
+    tests/golden/make_stream_golden.py: same tags, (bin, lag) exact unless the
+    oracle flags a near tie, ToA within 1e-3, FP64 values within 1e-9, threshold
+    crossings inside the oracle's band."""
+    from test_gpu_parity import _compare_detections
     w = siggen.workload("batched_stream")
     T, C, spc, K = w["num_tags"], w["num_chips"], w["spc"], w["num_bins"]
     L = C * spc
@@ -141,8 +152,8 @@ def test_stream_workload_full_size(dev):
         order = np.argsort([x.numel() for x in xs])
         for b in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
             single = plan.detect(xs[b])
-            assert [(d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in single] == \
-                   [(d.tag, d.bin, d.lag, d.toa, d.peak_power) for d in dets if d.block == b], b
+            assert [(d.tag, d.bin, d.lag, d.toa, d.peak_power, d.crossings) for d in single] == \
+                   [(d.tag, d.bin, d.lag, d.toa, d.peak_power, d.crossings) for d in dets if d.block == b], b
     by_block = {}
     for d in dets:
         by_block.setdefault(d.block, {})[d.tag] = d
@@ -153,25 +164,23 @@ def test_stream_workload_full_size(dev):
             if tx.snr_db > -12.0:
                 d = by_block.get(b, {}).get(tx.tag)
                 assert d is not None and d.bin == tx.bin and abs(d.toa - tx.toa) < 0.35, (b, tx)
-    # Detections of tags not injected into their block: the statistic is
-    # normalised by the whole block's mean power, and where several strong
-    # transmissions overlap the local interference is well above that mean, so
-    # dense blocks raise threshold crossings.  Each must still be the oracle's
-    # own detection (sampled: FFT-identity search of that tag over the block).
-    truth = {(b, tx.tag) for b, (_, txs) in enumerate(blocks) for tx in txs}
-    extra = [d for d in dets if (d.block, d.tag) not in truth]
-    print(f"[stream] detections {len(dets)} of {injected} injected, outside the injected set {len(extra)}", flush=True)
-    for d in extra[:3]:
-        x = blocks[d.block][0]
-        r = oracle.acquire(x, chips, spc, freqs, w["fs_hz"], method="fft", tags=[d.tag])[0]
-        assert r["detected"] or r["near_threshold"], (d, r)
-        if r["detected"] and not r["near_tie"]:
-            assert (d.bin, d.lag) == (r["bin"], r["lag"]) and abs(d.toa - r["toa"]) <= 1e-3, (d, r)
-    # FP64 values of the detections of two blocks against the definition
-    for b in (0, 1):
-        x = blocks[b][0]
-        for d in by_block.get(b, {}).values():
-            taus = [t for t in (d.lag - 1, d.lag, d.lag + 1) if 0 <= t <= x.size - L]
-            ref = oracle.corr_power_at(x, chips, spc, freqs, w["fs_hz"], [d.tag] * len(taus), [d.bin] * len(taus), taus)
-            p0 = ref[taus.index(d.lag)]
-            assert abs(d.peak_power - p0) <= 1e-9 * p0
+    print(f"[stream] detections {len(dets)} of {injected} injected", flush=True)
+    # complete detection sets of the two shortest blocks against the stored oracle results
+    with open(GOLDEN_STREAM) as f:
+        gold = json.load(f)
+    assert gold["seed"] == seed
+    toa_err = []
+    for key, gb in gold["blocks"].items():
+        b = int(key)
+        assert blocks[b][0].size == gb["n"]
+        ref = []
+        for r in gb["results"]:
+            r = dict(r)
+            r["crossings_band"] = tuple(r["crossings_band"])
+            ref.append(r)
+        got = [d for d in dets if d.block == b]
+        _compare_detections(got, ref, L)
+        want = {r["tag"]: r for r in ref if r["detected"]}
+        toa_err += [abs(d.toa - want[d.tag]["toa"]) for d in got if d.tag in want]
+        print(f"[stream] block {b}: {len(got)} detections equal the oracle's {len(want)}", flush=True)
+    print(f"[stream] max |ToA - oracle| over {len(toa_err)} detections: {max(toa_err):.2e} samples", flush=True)

@@ -131,6 +131,21 @@ def _check_peak(got, r, d, u, s, dc, sc):
         return float(np.dot(np.abs(dc), e[j:j + n]) + np.dot(np.abs(d[j:j + n]), ec_err)) + 1e-9
 
     j = r["lag"]
+    if got.lag != j and not r["near_tie"]:
+        # several lags are correct when their |xcorr| lie within the FP32 front
+        # end's error of the maximum: accept the GPU's lag if it is one of them,
+        # then compare the step-8 values at that lag
+        a_got = abs(float(np.dot(dc, d[got.lag:got.lag + n])))
+        assert a_got >= abs(r["xcorr"]) - (bw(j) + bw(got.lag)), (got, r)
+        j = got.lag
+        w = float(np.dot(dc, d[j:j + n]))
+        q = float(np.dot(d[j:j + n], d[j:j + n]))
+        lags = d.size - n + 1
+        a = [abs(float(np.dot(dc, d[k:k + n]))) if 0 <= k < lags else 0.0 for k in (j - 1, j, j + 1)]
+        from oracle.reference import parabola
+        delta = parabola(a[0], a[1], a[2], at_edge=j == 0 or j == lags - 1)
+        r = dict(r, lag=j, xcorr=w, q=q, p=float(np.dot(dc, u[j:j + n])), z=w * w / (q * ec), toa=j + delta,
+                 near_tie=True)
     bq = float(np.dot(2 * np.abs(d[j:j + n]) + e[j:j + n], e[j:j + n])) + 1e-9
     bp = float(np.dot(np.abs(dc), 2e-5 * s.max() * np.ones(n)) + np.dot(np.abs(u[j:j + n]), ec_err)) + 1e-9
     bec = float(np.dot(2 * np.abs(dc) + ec_err, ec_err))
@@ -194,13 +209,15 @@ def test_threshold_edges_and_errors(dev):
         assert plan.detect(torch.zeros((N, 2), dtype=torch.int16, device=dev)) == []   # z = 0
 
 
+@pytest.mark.timeout(600)
 def test_paper_shaped_window(dev):
-    """The paper's searching task: 100 ms at 8 Msps, 8192-bit packets at 8
-    samples per bit, a 200-tap band-pass, here 8 codes (6 packets at -10..0 dB):
-    every packet found at its delay, two tags compared with the oracle (FFT
-    identity for the argmax, exact sums at the peak)."""
+    """The paper's searching task at full size: 100 ms at 8 Msps, 128 codes of
+    8192 bits at 8 samples per bit, a 200-tap band-pass, six packets at
+    -10..0 dB: every packet found at its delay, and every code's peak compared
+    with the oracle (FFT identity for the argmax, exact sums at the peak)."""
     w = siggen.workload("fsk_search")
-    T = 8
+    T = w["num_tags"]
+    assert T == 128
     bits = siggen.make_fsk_bits(w["seeds"][0], T, w["num_bits"])
     bp = siggen.fsk_bandpass(w["bp_taps"], w["bp_cutoff_hz"], FS)
     iq, txs = siggen.make_fsk_block(w["seeds"][0] + 1, w["block_len"], bits, w["sps"], FS, w["f1_hz"], w["f0_hz"],
@@ -209,16 +226,19 @@ def test_paper_shaped_window(dev):
     with FskPlan(bits, FS, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], w["block_len"]) as plan:
         assert plan.geometry["fft_len"] == 1 << 17
         dets = plan.detect(torch.from_numpy(iq).to(dev))
+    assert len(dets) == T
     for tag, D, snr in txs:
         assert abs(dets[tag].lag - D) <= 1 and dets[tag].z > 0.02, (tag, D, snr, dets[tag])
     case = ("paper", T, w["num_bits"], w["sps"], w["bp_taps"], w["bp_cutoff_hz"], w["f1_hz"], w["f0_hz"],
             w["lo_hz"], w["block_len"], 0, w["n_tx"])
     d, u, s = _oracle_front(case, iq, bp)
-    check = [txs[0][0]] + [t for t in range(T) if t not in {x[0] for x in txs}][:1]
-    tm = {t: ofsk.replica_template(bits[t], FS, bp, w["f1_hz"], w["f0_hz"], w["sps"]) for t in check}
-    for t in check:
+    print(f"[fsk] comparing {T} codes with the oracle", flush=True)
+    for t in range(T):
+        tm = {t: ofsk.replica_template(bits[t], FS, bp, w["f1_hz"], w["f0_hz"], w["sps"])}
         r = ofsk.fsk_acquire(d, u, tm, method="fft", tags=[t])[0]
         _check_peak(dets[t], r, d, u, s, tm[t], _template_front(case, bits[t], bp))
+        if (t + 1) % 32 == 0:
+            print(f"[fsk] {t + 1}/{T} codes match", flush=True)
 
 
 def test_tracking_tasks(dev):

@@ -5,7 +5,9 @@ Tolerances (stated by the acquisition contract):
   * detections: same tags, same (bin, lag) unless the oracle flags a near-tie
     or a near-threshold decision; ToA within 1e-3 samples;
   * reported peak power / z / energy are FP64 re-correlations on both sides:
-    relative 1e-9.
+    relative 1e-9;
+  * threshold crossings (hypotheses with z >= theta, decided on FP32 powers):
+    within the oracle's counts at theta (1 -+ 1e-4).
 """
 import math
 import os
@@ -77,6 +79,8 @@ def _compare_detections(dets, ref, L):
             assert abs(d.snr - r["snr"]) <= 1e-8 * (floor / (L * L) + r["energy"] / L) / s2 * (1 + r["snr"])
         assert d.freq_hz == r["freq_hz"]
         assert bool(d.flags & 1) == r["near_edge"]
+        lo, hi = r["crossings_band"]
+        assert lo <= d.crossings <= hi, (t, d.crossings, r["crossings_band"])
     return got, want
 
 

@@ -389,3 +389,43 @@ def test_tracking_task_exact_recovery(oracle_lib):
     s0 = oracle.templates(chips, spc)[0]
     cross = float(np.dot(s2[100:], s0[:L - 100]))
     assert r["peak_power"] == (L + cross) ** 2
+
+
+def test_crossing_count_pins(oracle_lib):
+    """The threshold-crossing count of `acquire` against brute force (explicit
+    loops over the triple-loop powers), the limits theta -> 0 (every hypothesis
+    crosses: K (N-L+1) per tag) and theta above the peak z (none), the
+    exponential law under noise (e^-theta of the hypotheses cross), and the
+    band around theta."""
+    x, chips = _tiny_case(seed=21, N=80)
+    fs = 8e6
+    freqs = [-250e3, 0.0, 375e3]
+    s = [[float(chips[t][n // 2]) for n in range(8)] for t in range(2)]
+    B = _brute_power(x, s, freqs, fs)
+    px = sum(abs(complex(v)) ** 2 for v in x) / len(x)
+    theta = 1.5
+    res = oracle.acquire(x, chips, 2, freqs, fs, theta=theta)
+    for t in range(2):
+        brute = 0
+        for k in range(3):
+            for tau in range(B.shape[2]):
+                brute += B[t, k, tau] / (8 * px) >= theta
+        assert res[t]["crossings"] == brute
+        lo, hi = res[t]["crossings_band"]
+        assert lo <= brute <= hi
+    for r in oracle.acquire(x, chips, 2, freqs, fs, theta=1e-300):
+        assert r["crossings"] == 3 * (80 - 8 + 1)
+    for r in oracle.acquire(x, chips, 2, freqs, fs, theta=1e6):
+        assert r["crossings"] == 0
+    # noise only: about e^-theta of K (N-L+1) hypotheses per tag cross
+    C, spc, N = 64, 2, 20000
+    L = C * spc
+    chips = siggen.make_codes(5, 3, C)
+    total = tests = 0
+    for seed in range(3):
+        xn, _ = siggen.make_block(300 + seed, N, chips, spc, 1e6, [0.0], 0)
+        for r in oracle.acquire(xn, chips, spc, [0.0, 1e6 / 256], 1e6, theta=3.0):
+            total += r["crossings"]
+            tests += 2 * (N - L + 1)
+    expect = math.exp(-3.0) * tests
+    assert abs(total - expect) < 0.1 * expect
