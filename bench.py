@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 # rocprofv3 HBM byte counts of the correlation kernel, per workload
 TRAFFIC_FILES = {"tagbank_fp32": os.path.join(ROOT, "profiles", "correlate_tagbank_traffic.json"),
                  "tagbank_fp16": os.path.join(ROOT, "profiles", "correlate_tagbank_fp16_traffic.json"),
@@ -89,6 +90,20 @@ def cpu_baseline(x, chips, spc, freqs, fs, budget_s: float):
     return {"value": done * N / dt / 1e6, "unit": "tag*freq*Msample/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"{done} (tag, bin) pairs x {N} samples, direct FP64 correlation, {dt:.1f} s"}
+
+
+def cpu_baseline_one_core(x, chips, spc, freqs, fs, budget_s: float):
+    """The same oracle restricted to one thread (the paper's CPU baseline is one core):
+    whole (tag, bin) pairs of the block until the budget is used."""
+    import oracle
+    oracle.build_library(force=False)
+    cores = oracle.set_threads(1)
+    try:
+        out = cpu_baseline(x, chips, spc, freqs, fs, budget_s)
+    finally:
+        oracle.set_threads(0)
+    out["cores"] = cores
+    return out
 
 
 def cpu_baseline_tasks(tasks, chips, spc, freqs, fs, budget_s: float):
@@ -160,7 +175,13 @@ def main():
                     help="skip the plan-time autotuner (by default every launch configuration is timed once "
                          "before the timed steps and the fastest kept)")
     ap.add_argument("--graph", action="store_true", help="batched workloads: replay one captured hipGraph per step")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time (0: skip)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle time on all host cores, and half of it on one core (0: skip)")
+    ap.add_argument("--legs", default="stream,learned",
+                    help="tag-bank workload only: comma-separated extra legs reported in the same line "
+                         "(stream: the 64-block batched stream, eager and graph-replayed; learned: the "
+                         "trained proposal network on that stream against the exhaustive search; none)")
+    ap.add_argument("--leg-steps", type=int, default=3, help="timed batches per extra leg")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -300,11 +321,13 @@ def main():
                    "tags_per_block": T_eff,
                    "template_len": L, "fft_len": M, "segments": S, "precision": prec, "tuning": plan.tuning,
                    "graph": bool((batched or tracking) and args.graph), "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None,
-                     "traffic": traffic_per_launch(args.workload),
-                     "kernel": "k_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},
+        "roofline": roofline(achieved, corr_avg, flops, traffic_per_launch(args.workload)),
     }
+    plan.close()
+    if args.workload == "tagbank_fp32":
+        legs = [l for l in args.legs.split(",") if l and l != "none"]
+        if legs:
+            out.update(bench_stream_legs(args, legs, dev))
     if args.cpu_budget > 0:
         log("[bench] cpu baseline ...")
         if tracking:
@@ -312,8 +335,138 @@ def main():
                                                      args.cpu_budget)
         else:
             out["cpu_baseline"] = cpu_baseline(x, chips, spc, freqs, fs, args.cpu_budget)
-    plan.close()
+            log("[bench] cpu baseline, one core ...")
+            out["cpu_baseline"]["one_core"] = cpu_baseline_one_core(x, chips, spc, freqs, fs, 0.5 * args.cpu_budget)
     print(json.dumps(out), flush=True)
+
+
+def roofline(achieved, kernel_ms, flops, traffic):
+    """Roofline record of the correlation kernel: FP32 vector peak, plus the fraction of
+    the rate the kernel's unpacked FP32 arithmetic can reach (one FMA per lane per cycle,
+    half the packed peak) and the HBM fraction of its counted traffic."""
+    hbm = traffic / (kernel_ms * 1e-3) / 1e9 if traffic and kernel_ms else None
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": traffic,
+            "kernel": "k_correlate", "kernel_ms": kernel_ms, "flops_per_launch": flops,
+            "frac_unpacked_peak": achieved / (0.5 * PEAK_FP32_TFLOPS) if achieved else None,
+            "hbm_gbs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS if hbm else None}
+
+
+def _gpu_ms(fn, steps):
+    """Mean wall time (ms) of fn over `steps` calls after one untimed call, each call
+    bracketed by device synchronisations; returns (ms, last result)."""
+    import torch
+    r = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, r
+
+
+def bench_stream_legs(args, legs, dev):
+    """Extra legs on the batched stream (64 resident blocks of log-uniform length in
+    [2^18, 2^21], 256 tags x 21 bins, 0-20 transmissions each): the exhaustive batch
+    search eagerly (per-kernel events) and as a replayed hipGraph, and the trained
+    proposal network's batch search on the same blocks against it."""
+    import numpy as np
+    import torch
+    import siggen
+    from paper_2005_10445_amd import Plan, bin_frequencies
+    w = siggen.workload("batched_stream")
+    T, C, spc, K, fs = w["num_tags"], w["num_chips"], w["spc"], w["num_bins"], w["fs_hz"]
+    seed = w["seeds"][0]
+    chips = siggen.make_codes(seed, T, C)
+    bins = dict(num_bins=K, bin_center_hz=w["bin_center_hz"], bin_step_hz=w["bin_step_hz"])
+    fft_len = args.fft_len or w["fft_len"] or (1 << 15)
+    freqs = bin_frequencies(chips=chips, spc=spc, fs_hz=fs, max_block_len=1 << 21, fft_len=fft_len, **bins)
+    log(f"[bench] stream leg: generating {w['num_blocks']} blocks")
+    blocks = siggen.make_stream_batch(seed, chips, spc, fs, freqs, w["num_blocks"], w["block_len_log2"],
+                                      w["receivers"], w["n_tx"], w["snr_db"])
+    lens = [x.size for x, _ in blocks]
+    xds = [torch.from_numpy(x).to(dev) for x, _ in blocks]
+    samples = sum(lens)
+    kw = dict(max_block_len=max(lens), fft_len=fft_len, max_batch_blocks=len(lens), max_batch_samples=samples,
+              **bins)
+    out = {}
+    eager = Plan(chips, spc, fs, **kw)
+    table = eager.tune(xds[int(np.argmax(lens))], reps=2)
+    tuning = eager.tuning
+    log(f"[bench] stream tuning {table} -> {tuning}")
+    g = eager.geometry
+    L, M, V = C * spc, g["fft_len"], g["valid_per_segment"]
+    S = sum(-(-(n - L + 1) // V) for n in lens if n >= L)
+    eager.detect_batch(xds)
+    eager.set_profiling(True)
+    corr = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.leg_steps):
+        full = eager.detect_batch(xds)
+        corr.append(eager.last_kernel_times()["correlate"])
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.leg_steps
+    eager.set_profiling(False)
+    flops = correlate_flops(T, K, S, M, V)
+    corr_ms = float(np.mean(corr))
+    with Plan(chips, spc, fs, graph=True, **kw) as gp:
+        gp.set_tuning(**tuning)
+        ms_graph, gdets = _gpu_ms(lambda: gp.detect_batch(xds), args.leg_steps)
+    key = lambda d: (d.block, d.tag, d.bin, d.lag, d.toa, d.peak_power)   # noqa: E731
+    assert sorted(map(key, gdets)) == sorted(map(key, full)), "graph replay differs from the eager batch"
+    if "stream" in legs:
+        out["stream"] = {
+            "workload": "batched_stream", "tags": T, "bins": K, "blocks": len(lens), "samples": samples,
+            "fft_len": M, "segments": S, "tuning": tuning,
+            "ms_per_batch_eager": ms_eager, "ms_per_batch_graph": ms_graph,
+            "value_graph": T * K * samples / (ms_graph * 1e-3) / 1e6,
+            "value_eager": T * K * samples / (ms_eager * 1e-3) / 1e6, "unit": "tag*freq*Msample/s",
+            "detections": len(full),
+            "roofline": roofline(flops / (corr_ms * 1e-3) / 1e12, corr_ms, flops,
+                                 traffic_per_launch("batched_stream")),
+        }
+        log(f"[bench] stream: eager {ms_eager:.1f} ms, graph {ms_graph:.1f} ms per batch, "
+            f"correlate {corr_ms:.1f} ms, {len(full)} detections")
+    if "learned" in legs:
+        out["learned"] = learned_leg(args, eager, xds, blocks, full, ms_eager)
+    eager.close()
+    return out
+
+
+def learned_leg(args, plan, xds, blocks, full, ms_exhaustive):
+    """The committed trained network and its calibrated kappa on the stream batch:
+    detections must be a subset of the exhaustive ones; recall is over the exhaustive
+    detections of injected transmissions and over all of them."""
+    import numpy as np
+    from paper_2005_10445_amd.proposals import LearnedParams, Network, num_params
+    wdir = os.path.join(ROOT, "paper_2005_10445_amd", "weights")
+    params = np.load(os.path.join(wdir, "proposal_cnn.npy"), allow_pickle=False)
+    with open(os.path.join(wdir, "proposal_cnn.json")) as f:
+        kappa = float(json.load(f)["kappa"])
+    assert params.size == num_params(256)
+    lp = LearnedParams(kappa=kappa, max_fraction=0.5, floor_db=1.0)
+    with Network("bf16", 256, max_rows=1 << 15, max_block_len=1 << 21) as net:
+        net.set_params(params)
+        ms, (dets, reps) = _gpu_ms(lambda: net.detect_batch(plan, xds, lp), args.leg_steps)
+    key = lambda d: (d.block, d.tag, d.bin, d.lag, d.toa, d.peak_power, d.z)   # noqa: E731
+    fk, lk = {key(d) for d in full}, {key(d) for d in dets}
+
+    def injected(d):
+        return any(d.tag == t.tag and d.bin == t.bin and abs(d.lag - t.delay) <= 2 for t in blocks[d.block][1])
+    inj = [key(d) for d in full if injected(d)]
+    out = {"workload": "batched_stream + proposals", "network": "4 conv1d x 64 channels, k=5, bf16",
+           "kappa": kappa, "ms_per_batch_learned": ms, "ms_per_batch_exhaustive": ms_exhaustive,
+           "speedup": ms_exhaustive / ms,
+           "recall_injected": sum(k in lk for k in inj) / max(len(inj), 1), "injected_detections": len(inj),
+           "recall_all": len(lk & fk) / max(len(fk), 1), "exhaustive_detections": len(fk),
+           "not_in_exhaustive": len(lk - fk),
+           "segments_searched": sum(r.segments for r in reps) / max(sum(r.total_segments for r in reps), 1),
+           "fallbacks": sum(r.fallback != 0 for r in reps), "blocks": len(reps)}
+    log(f"[bench] learned: {ms:.1f} ms vs {ms_exhaustive:.1f} ms exhaustive, recall {out['recall_injected']:.4f} "
+        f"(injected) {out['recall_all']:.4f} (all), segments {out['segments_searched']:.3f}, "
+        f"fallbacks {out['fallbacks']}/{len(reps)}")
+    return out
 
 
 def bench_fsk(args, w):
@@ -409,9 +562,8 @@ def bench_fsk(args, w):
                    "window_samples": N, "template_len": n_t, "fft_len": M, "segments": S,
                    "tasks": len(tasks) if tracking else None,
                    "codes_realtime_half_duty": None if tracking else codes_rt, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_per_launch(args.workload),
-                     "kernel": "k_fsk_correlate", "kernel_ms": corr_avg, "flops_per_launch": flops},
+        "roofline": dict(roofline(achieved, corr_avg, flops, traffic_per_launch(args.workload)),
+                         kernel="k_fsk_correlate"),
     }
     if args.cpu_budget > 0 and not tracking:
         log("[bench] cpu baseline ...")

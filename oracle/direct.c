@@ -118,3 +118,18 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the following calls (timing the oracle on fewer cores);
+ * n < 1 restores the runtime's default.  Returns the count now in effect. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    static int dflt = 0;
+    if (dflt == 0) dflt = omp_get_max_threads();
+    omp_set_num_threads(n >= 1 ? n : dflt);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -47,6 +47,7 @@ __all__ = [
     "block_power", "corr_power", "corr_power_at", "corr_power_fft",
     "default_threshold", "argmax_detect", "parabola", "energy_at", "power_snr_estimates",
     "acquire", "track", "crossings", "NEAR_TIE_REL", "NEAR_THRESHOLD_REL", "CROSS_REL", "num_threads",
+    "set_threads",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -99,12 +100,20 @@ def _lib():
         lib.oracle_corr_power_at.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         _lib_handle = lib
     return _lib_handle
 
 
 def num_threads() -> int:
     return int(_lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads used by the C library's following calls (n < 1: the default).
+    Returns the count now in effect."""
+    return int(_lib().oracle_set_threads(int(n)))
 
 
 def _ptr(a, ctype):
