@@ -278,6 +278,29 @@ int acq_collect(acq_plan_t plan, acq_detection* out, int32_t capacity, int32_t* 
  */
 int acq_device_results(acq_plan_t plan, const acq_detection** records, const int32_t** counts);
 
+/*
+ * For callers that cannot allocate memory (code under hipGraph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): acq_detect of one block
+ * whose per-search buffers (segment spectra, peak keys, refinement sums,
+ * candidate records) live in a static device array of the library, 64 MiB on
+ * every GPU the library runs on, instead of the plan's workspace.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine) and
+ * only enqueues work on the plan's stream: `out` (device, capacity records)
+ * receives the detections sorted by tag, the first `capacity` of them, and
+ * `count` (device, int32[1]) their total number; both are valid once the
+ * stream has run the search.  Results equal acq_detect's for the same plan
+ * and block.  A block whose search needs more than the static array holds
+ * (about 64 MiB / (fft_len * 8) segments: 4.1 M samples at fft_len 2^15) is
+ * rejected with ACQ_ERR_WORKSPACE_TOO_SMALL before anything is enqueued.
+ * All calls on one GPU share its array, which keeps the last call's contents
+ * (every buffer a search reads is rewritten by that search first): calls that
+ * overlap on one GPU, from any plans or streams, race and must be ordered by
+ * the caller.  ACQ_ERR_DEVICE if the array's address could not be resolved
+ * when the plan was made.
+ */
+int acq_detect_noalloc(acq_plan_t plan, const void* block, int64_t n, acq_detection* out, int32_t capacity,
+                       int32_t* count);
+
 
 /*
  * Launch configuration of the correlation kernel.  engine: 0 = the default

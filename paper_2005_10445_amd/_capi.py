@@ -32,7 +32,7 @@ ACQ_FLAG_CHECK_FINITE = 0x8
 
 # every symbol include/acq.h declares
 EXPORTED = ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "acq_plan", "acq_detect",
-            "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results",
+            "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results", "acq_detect_noalloc",
             "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
@@ -221,6 +221,8 @@ def lib(path: str = LIB_PATH):
                                    P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
     L.acq_collect.argtypes = [ctypes.c_void_p, P(AcqDetection), ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_device_results.argtypes = [ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_void_p)]
+    L.acq_detect_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_void_p]
     L.acq_track_batch.argtypes = [ctypes.c_void_p, P(AcqTrackTask), ctypes.c_int32, P(AcqDetection),
                                   ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_get_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
@@ -263,7 +265,7 @@ def lib(path: str = LIB_PATH):
                  "acq_fsk_last_kernel_times"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "acq_plan", "acq_detect",
-                 "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results",
+                 "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results", "acq_detect_noalloc",
                  "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power",
                  "acq_release", "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create",
                  "acq_cnn_release", "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward",

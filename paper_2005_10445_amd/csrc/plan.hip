@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -92,6 +93,9 @@ struct acq_plan_s {
     hipEvent_t ev[ACQ_NUM_KERNELS][2] = {};
     bool ev_used[ACQ_NUM_KERNELS] = {};
 
+    void* scratch = nullptr;            // this device's address of the static search scratch
+                                        // (acq_detect_noalloc), resolved by acq_plan
+
     hipStream_t cap_stream = nullptr;   // private stream the batch graphs are captured on
     hipGraph_t graph = nullptr;         // searching batch
     hipGraphExec_t gexec = nullptr;
@@ -99,7 +103,33 @@ struct acq_plan_s {
     hipGraphExec_t tgexec = nullptr;
 };
 
+// Per-search buffers of acq_detect_noalloc, which may allocate nothing: one
+// array in the library's code object, so every GPU the library runs on holds
+// its own copy (for the life of the process).  In host code the name stands
+// for no device address; its device address comes from hipGetSymbolAddress.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;          // per device, once resolved
+
+// Device address of `scratch` on `device` (the current device), resolved once
+// per device.
+hipError_t static_scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if (size_t(device) >= g_scratch_addr.size()) g_scratch_addr.resize(size_t(device) + 1, nullptr);
+    if (!g_scratch_addr[size_t(device)]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[size_t(device)] = ptr;
+    }
+    *out = g_scratch_addr[size_t(device)];
+    return hipSuccess;
+}
 
 std::string hip_msg(const char* what, hipError_t e) {
     return std::string(what) + ": " + hipGetErrorString(e);
@@ -678,6 +708,12 @@ int acq_plan(const acq_config* cfg, void* workspace, size_t workspace_bytes_, vo
         free_plan(p);
         return rc;
     }
+    // the static scratch of acq_detect_noalloc on this device; a failure here
+    // only disables that entry point, which then reports it
+    if (static_scratch_address(p->device, &p->scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        p->scratch = nullptr;
+    }
     *out = p;
     acq::clear_error();
     return ACQ_OK;
@@ -789,6 +825,38 @@ int acq_collect(acq_plan_t p, acq_detection* out, int32_t capacity, int32_t* n_f
     const int32_t ncopy = std::max(0, std::min(found, capacity));
     if (ncopy > 0) ACQ_HIP(hipMemcpy(p->h_out, p->ws.out, sizeof(acq_detection) * size_t(ncopy), hipMemcpyDeviceToHost));
     return deliver(p, out, capacity, n_found);
+}
+
+int acq_detect_noalloc(acq_plan_t p, const void* block, int64_t n, acq_detection* out, int32_t capacity,
+                       int32_t* count) {
+    int rc = check_block(p, block, n);
+    if (rc != ACQ_OK) return rc;
+    if (!count || capacity < 0 || (capacity > 0 && !out))
+        return acq::fail(ACQ_ERR_INVALID_ARG, "bad output arguments");
+    if (!p->scratch) return acq::fail(ACQ_ERR_DEVICE, "the static scratch has no address on this device");
+    if (n < p->g.L) {
+        ACQ_HIP(acq::launch_fill_i32(count, 1, p->stream));
+        acq::clear_error();
+        return ACQ_OK;
+    }
+    BlockTable bt{};
+    bt.one = single_desc(p, block, n);
+    Scratch w;
+    const size_t need = layout_scratch(p->g, p->cfg, 1, bt.one.nseg, 1, nullptr, &w);
+    if (need > kStaticScratchBytes)
+        return acq::fail(ACQ_ERR_WORKSPACE_TOO_SMALL,
+                         "acq_detect_noalloc: a block of " + std::to_string(n) + " samples needs " +
+                             std::to_string(need) + " bytes of search memory, the static scratch holds " +
+                             std::to_string(kStaticScratchBytes));
+    layout_scratch(p->g, p->cfg, 1, bt.one.nseg, 1, static_cast<char*>(p->scratch), &w);
+    rc = note_capture(p);
+    if (rc != ACQ_OK) return rc;
+    reset_timers(p);
+    rc = enqueue_search(p, w, bt, false, bt.one.nseg, nullptr, true, p->stream, false,
+                        ResultDest{out, capacity, count, false});
+    if (rc != ACQ_OK) return rc;
+    acq::clear_error();
+    return ACQ_OK;
 }
 
 int acq_device_results(acq_plan_t p, const acq_detection** records, const int32_t** counts) {
