@@ -326,7 +326,10 @@ typedef struct acq_tuning {
 
 typedef struct acq_tune_entry {
     acq_tuning tuning;
-    double     ms;              /* mean correlation-kernel time over the repetitions */
+    int32_t    fft_len;         /* the plan's overlap-save segment length M */
+    int32_t    reserved;
+    double     ms;              /* acq_tune: mean correlation-kernel time over the repetitions;
+                                   acq_tune_fft_len: mean time of the whole search */
 } acq_tune_entry;
 
 int acq_get_tuning(acq_plan_t plan, acq_tuning* out);
@@ -344,6 +347,25 @@ int acq_set_tuning(acq_plan_t plan, const acq_tuning* tuning);
  */
 int acq_tune(acq_plan_t plan, const void* block, int64_t n, int32_t reps,
              acq_tune_entry* out, int32_t capacity, int32_t* n_out);
+
+/*
+ * Segment-length autotuning (Section 4.2: the transform sizes are chosen when
+ * the plan is made, by measurement).  For every overlap-save length M this
+ * library can run for `cfg` -- powers of two from the smallest M >= L + 1 up
+ * to four of them, each with a per-phase transform M / samples_per_chip of at
+ * most 2^14 points (the largest transform one workgroup keeps in LDS, and
+ * with the tag-independent first step in registers, in its register file) --
+ * a plan with fft_len = M is made on `stream` (hipStream_t), tuned by
+ * acq_tune on the device block `block`, and its whole search of the block
+ * (every kernel, HIP events) timed `reps` times.  One entry per M goes to host
+ * out[0..capacity) (*n_out = count), with the tuning acq_tune kept; the M of
+ * the fastest search goes to *best_fft_len.  cfg->fft_len is ignored; every
+ * candidate plan is released before returning.  Results of a search do not
+ * depend on M (up to FP32 rounding of the correlation; the FP64 refinement
+ * decides the reported values).
+ */
+int acq_tune_fft_len(const acq_config* cfg, const void* block, int64_t n, int32_t reps, void* stream,
+                     acq_tune_entry* out, int32_t capacity, int32_t* n_out, int32_t* best_fft_len);
 
 /*
  * Test hook: the FFT-path power P[t][k][tau] for every valid lag, written to

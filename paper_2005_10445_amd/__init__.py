@@ -17,7 +17,8 @@ import numpy as np
 from . import _capi
 from ._capi import AcqConfig, AcqDetection, AcqGeometry, AcqError, check
 
-__all__ = ["Plan", "Detection", "geometry", "workspace_size", "bin_frequencies", "AcqError", "make_config"]
+__all__ = ["Plan", "Detection", "geometry", "workspace_size", "bin_frequencies", "tune_fft_len", "AcqError",
+           "make_config"]
 
 _PRECISION = {"fp32": _capi.ACQ_FP32, "fp16": _capi.ACQ_FP16, "bf16": _capi.ACQ_BF16}
 
@@ -99,6 +100,24 @@ def bin_frequencies(**kw) -> np.ndarray:
                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                           cfg.num_bins), "acq_bin_frequencies")
     return out
+
+
+def tune_fft_len(block, reps: int = 2, stream=None, **kw):
+    """acq_tune_fft_len: time every segment length the library can run for this
+    configuration (make_config's keywords) on a device block; returns (best M,
+    table of {fft_len, engine, tag_tile, batch_launch, ms})."""
+    import torch
+    cfg, _keep = make_config(**kw)
+    ptr, n = _device_ptr(block)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    out = (_capi.AcqTuneEntry * 8)()
+    cnt, best = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(_capi.lib().acq_tune_fft_len(ctypes.byref(cfg), ctypes.c_void_p(ptr), n, int(reps), ctypes.c_void_p(handle),
+                                       out, 8, ctypes.byref(cnt), ctypes.byref(best)), "acq_tune_fft_len")
+    return best.value, [{"fft_len": e.fft_len, "engine": e.tuning.engine, "tag_tile": e.tuning.tag_tile,
+                         "batch_launch": e.tuning.batch_launch, "ms": e.ms} for e in out[:cnt.value]]
 
 
 def _device_ptr(block):
@@ -265,7 +284,7 @@ class Plan:
         check(self._lib.acq_tune(self._h, ctypes.c_void_p(ptr), n, int(reps), out, 32, ctypes.byref(cnt)),
               "acq_tune")
         return [{"engine": e.tuning.engine, "tag_tile": e.tuning.tag_tile, "batch_launch": e.tuning.batch_launch,
-                 "ms": e.ms} for e in out[:cnt.value]]
+                 "fft_len": e.fft_len, "ms": e.ms} for e in out[:cnt.value]]
 
     def detect_raw(self, block) -> int:
         """acq_detect without building Python records (for timing); returns the count."""

@@ -33,7 +33,8 @@ ACQ_FLAG_CHECK_FINITE = 0x8
 # every symbol include/acq.h declares
 EXPORTED = ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "acq_plan", "acq_detect",
             "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results", "acq_detect_noalloc",
-            "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power", "acq_set_profiling",
+            "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_tune_fft_len", "acq_correlate_power",
+            "acq_set_profiling",
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
             "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
@@ -112,7 +113,8 @@ ACQ_BATCH_GRID, ACQ_BATCH_PERSISTENT = 0, 1
 
 
 class AcqTuneEntry(ctypes.Structure):
-    _fields_ = [("tuning", AcqTuning), ("ms", ctypes.c_double)]
+    _fields_ = [("tuning", AcqTuning), ("fft_len", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class AcqCnnConfig(ctypes.Structure):
@@ -227,6 +229,8 @@ def lib(path: str = LIB_PATH):
                                   ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_get_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
     L.acq_set_tuning.argtypes = [ctypes.c_void_p, P(AcqTuning)]
+    L.acq_tune_fft_len.argtypes = [P(AcqConfig), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                   P(AcqTuneEntry), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
     L.acq_tune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, P(AcqTuneEntry),
                            ctypes.c_int32, P(ctypes.c_int32)]
     L.acq_release.argtypes = [ctypes.c_void_p]
@@ -266,7 +270,7 @@ def lib(path: str = LIB_PATH):
         getattr(L, name).restype = ctypes.c_int
     for name in ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "acq_plan", "acq_detect",
                  "acq_detect_batch", "acq_track_batch", "acq_collect", "acq_device_results", "acq_detect_noalloc",
-                 "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_correlate_power",
+                 "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_tune_fft_len", "acq_correlate_power",
                  "acq_release", "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create",
                  "acq_cnn_release", "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward",
                  "acq_cnn_gradients", "acq_cnn_adam_step", "acq_power_map", "acq_synth_block",

@@ -43,27 +43,72 @@ using namespace kdev;
 namespace {
 
 // ------------------------------------------------------------------ correlation
+// cos and sin of pi m / 16, m = 0 .. 8 (FP64 values rounded to FP32)
+__device__ constexpr float kCos16[9] = {1.0f, 0.98078528040323044913f, 0.92387953251128675613f,
+                                         0.83146961230254523708f, 0.70710678118654752440f, 0.55557023301960222474f,
+                                         0.38268343236508977173f, 0.19509032201612826785f, 0.0f};
+
+// exp(+j pi m / 16) for a register index m < 16 (a compile-time constant)
+__device__ __forceinline__ float2 root32(int m) {
+    return m <= 8 ? make_float2(kCos16[m], kCos16[8 - m]) : make_float2(-kCos16[16 - m], kCos16[m - 8]);
+}
+
 // First step of the split inverse transform for (global segment slot g, bin k,
 // phase rho): G[m] = sum_q X_g[(i + m_k) mod M] W_rho[i], i = in_index(m) +
-// q Msub, for the 16 inputs this thread holds.  The q loop is outside the
-// unrolled m loop so each pass issues its 32 loads back to back.
+// q Msub, for the 16 inputs this thread holds.  The spectra are padded, so
+// the rotated element is position xpad + i + r_k of the slot (r_k the bin's
+// rotation reduced to (-M/2, M/2]); every load is a buffer load whose
+// register offset is the same for all 16 registers.  For spc = 2 the weights
+// have a closed form: with e = exp(+j 2 pi i / M) (i = in_index(m)), the two
+// inputs Xa = X[i + m_k], Xb = X[i + Msub + m_k], S = Xa + Xb, D = Xa - Xb,
+//   W_0 = 1 + e, 1 - e   ->  G_0 = S + e D
+//   W_1 = e + e^2, e^2 - e  ->  G_1 = e (D + e S)
+// and e = exp(+j 2 pi in_index(0) / M) exp(+j pi m / 16) (in_index(m) =
+// in_index(0) + m Msub / 16); other spc read W from the table.
 template <class E, int PREC>
 __device__ __forceinline__ void first_step(const CorrArgs& a, const E& eng, int g, int k, int rho, float gscale,
                                            float2 (&G)[16]) {
     using St = dev::Storage<PREC>;
-    const typename St::T* Xj =
-        static_cast<const typename St::T*>(a.X) + (size_t(g) * size_t(a.ncls) + size_t(a.cls[k])) * size_t(a.M);
-    const float2* W = a.wts + size_t(rho) * size_t(a.M);
+    constexpr int NT = E::N / 16;
+    const size_t slot = size_t(g) * size_t(a.ncls) + size_t(a.cls[k]);
+    const __amdgpu_buffer_rsrc_t xr = make_rsrc(static_cast<const char*>(a.X) + slot * size_t(a.xstride) * St::BYTES,
+                                                uint32_t(a.xstride) * St::BYTES);
     const int rot = a.rot[k];
-    const int mmask = a.M - 1;
-#pragma unroll
-    for (int m = 0; m < 16; ++m) G[m] = make_float2(0.f, 0.f);
-    for (int q = 0; q < a.spc; ++q) {
-        const int base = q * a.Msub;
+    const int rs = rot <= (a.M >> 1) ? rot : rot - a.M;          // |rs| <= xpad
+    const int i0 = eng.in_index(0);
+    const int xoff = (a.xpad + i0 + rs) * St::BYTES;
+    if (a.spc == 2) {
+        const float2 e0 = a.rootsM[i0];
+        float2 xa[16], xb[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
-            const int i = eng.in_index(m) + base;
-            G[m] = cadd(G[m], cmul(St::unpack(Xj[(i + rot) & mmask]), W[i]));
+            xa[m] = St::bload(xr, xoff, m * NT * St::BYTES);
+            xb[m] = St::bload(xr, xoff, (m * NT + a.Msub) * St::BYTES);
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const float2 e = m ? cmul(e0, root32(m)) : e0;
+            const float2 S = cadd(xa[m], xb[m]);
+            const float2 D = make_float2(xa[m].x - xb[m].x, xa[m].y - xb[m].y);
+            if (rho == 0) {
+                G[m] = cadd(S, cmul(e, D));
+            } else {
+                G[m] = cmul(e, cadd(D, cmul(e, S)));
+            }
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t wr =
+            make_rsrc(a.wts + size_t(rho) * size_t(a.M), uint32_t(a.M) * 8u);
+        const int woff = i0 * 8;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) G[m] = make_float2(0.f, 0.f);
+        for (int q = 0; q < a.spc; ++q) {
+            const int base = q * a.Msub;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int i = m * NT + base;
+                G[m] = cadd(G[m], cmul(St::bload(xr, xoff, i * St::BYTES), bload(wr, woff, i * 8)));
+            }
         }
     }
     if constexpr (PREC != ACQ_FP32) {
@@ -250,13 +295,19 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
 
     unsigned long long best = 0ull;
     unsigned cross = 0;
+    // the task's replica spectrum is the same for every bin: read it once
+    float2 bk[16];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) bk[m] = St::bload(bank, voff, (m * E::NT) * St::BYTES);
+#pragma unroll
+    for (int m = 8; m < 16; ++m) bk[m] = St::bload(bank, voffm, ((15 - m) * E::NT) * St::BYTES);
     for (int k = k0; k < k1; ++k) {
         float2 v[16];
         first_step<E, PREC>(a, eng, g, k, rho, gscale, v);
 #pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], St::bload(bank, voff, (m * E::NT) * St::BYTES));
+        for (int m = 0; m < 8; ++m) v[m] = cmul(v[m], bk[m]);
 #pragma unroll
-        for (int m = 8; m < 16; ++m) v[m] = cmulc(v[m], St::bload(bank, voffm, ((15 - m) * E::NT) * St::BYTES));
+        for (int m = 8; m < 16; ++m) v[m] = cmulc(v[m], bk[m]);
         eng.template transform<+1>(v, lds, b1, extra, hi);
         int ob = ob0;
         unsigned idx0 = unsigned((seg0 + rho) * a.K + k) + unsigned(ob0) * kstep;

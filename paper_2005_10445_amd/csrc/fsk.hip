@@ -956,6 +956,8 @@ acq::FwdArgs fwd_args(acq_fsk_plan_s* p, const BlockTable& bt, float2* X, int64_
     fa.rootsSub = p->d_rootsSub;
     fa.b1tab = p->d_b1tab;
     fa.V = V;
+    fa.xstride = p->g.M;             // unpadded [slots][M]
+    fa.xpad = 0;
     fa.spc = p->g.P;
     fa.M = int(p->g.M);
     fa.Msub = int(p->g.Msub);

@@ -1,6 +1,7 @@
 // Host-side checks and derived quantities of an acquisition plan (no GPU calls).
 #include "host_logic.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <limits>
@@ -160,6 +161,13 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
         G.rot[size_t(k)] = int32_t(r);
     }
     G.ncls = int(G.cls_cyc.size());
+    G.xpad = 0;
+    for (int64_t k = 0; k < K; ++k) {
+        const int64_t r = G.rot[size_t(k)];
+        const int64_t rs = r <= G.M / 2 ? r : r - G.M;
+        G.xpad = std::max<int64_t>(G.xpad, rs < 0 ? -rs : rs);
+    }
+    G.xstride = (G.M + 2 * G.xpad + 63) / 64 * 64;
 
     // batch capacity: segments of a batch are bounded by sum(n_b)/V + blocks
     G.max_blocks = cfg->max_batch_blocks > 0 ? cfg->max_batch_blocks : 1;
@@ -178,8 +186,8 @@ int derive_geometry(const acq_config* cfg, Geometry* g) {
     // device memory: spectra of segments, replica bank, tables, small buffers
     int64_t bytes = 0;
     const int64_t sbytes = cfg->precision == ACQ_FP32 ? 8 : 4;
-    bytes += G.max_total_segments * G.ncls * G.M * 8;  // forward spectra X[S][classes][M] (FP32)
-    if (sbytes == 4) bytes += G.max_total_segments * G.ncls * G.M * 4;   // their 16-bit copy
+    bytes += G.max_total_segments * G.ncls * G.xstride * 8;  // forward spectra X[S][classes][xstride] (FP32)
+    if (sbytes == 4) bytes += G.max_total_segments * G.ncls * G.xstride * 4;   // their 16-bit copy
     bytes += T * (G.Msub / 2 + 64) * sbytes;  // replica bank [T][M/spc / 2 + 64] (half spectrum)
     bytes += G.M * 8 * (spc + 1) + G.Msub * 8;  // phase weights [spc][M], roots at M and M/spc
     bytes += T * C;                           // chips

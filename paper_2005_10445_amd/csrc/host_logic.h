@@ -35,6 +35,12 @@ struct Geometry {
     std::vector<double>  freqs_hz;   // K bin frequencies (snapped unless exact)
     std::vector<int32_t> rot;        // per-bin rotation of the M-point spectrum, in [0, M)
     std::vector<int64_t> rot_signed; // per-bin signed rotation at M
+    // Segment spectra are stored padded: a slot of xstride elements holds
+    // X[(i - xpad) mod M] at position i, i < M + 2 xpad, so that the rotated
+    // read X[(i + r) mod M] of any bin (|r| <= xpad, r the rotation reduced to
+    // (-M/2, M/2]) is position xpad + i + r, with no wrap-around.
+    int64_t xpad = 0;
+    int64_t xstride = 0;             // M + 2 xpad rounded up to 64 elements
     bool exact = false;              // ACQ_FLAG_EXACT_BINS
     int ncls = 1;                    // distinct residual offsets (sets of segment spectra)
     std::vector<int32_t> cls;        // per-bin residual class

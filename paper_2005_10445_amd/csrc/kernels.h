@@ -59,10 +59,12 @@ struct BlockTable {
 
 struct CorrArgs {
     BlockTable blocks;
-    const void* X;              // [segments][ncls][M] spectra (storage format)
+    const void* X;              // [segments][ncls][xstride] padded spectra (storage format): slot
+                                // position xpad + i holds X[i mod M] for -xpad <= i < M + xpad
     const void* bank;           // [T][Msub] 2^bank_exp conj(DFT_Msub(chips)) / M (storage format)
     const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
     const float2* wts;          // [spc][M] W_rho[i] = sum_{r<spc} exp(+j 2 pi i (r + rho) / M)
+                                // (read for spc != 2; spc = 2 forms them in closed form)
     const float2* rootsM;       // [M] exp(+j 2 pi m / M)
     const float2* rootsSub;     // [Msub] exp(+j 2 pi m / Msub)
     const float2* b1tab;        // 2^14-point engine twiddle table (else unused)
@@ -74,6 +76,8 @@ struct CorrArgs {
     float* dump;                // optional [T][K][lags] power (single-block calls)
     int* counters;              // [kXcds] work-item counters (persistent launches)
     int64_t V;                  // valid lags per segment
+    int64_t xstride;            // elements per spectra slot
+    int32_t xpad;               // wrap-around copies before and after each spectrum
     int32_t K, spc, M, Msub, T, tile, ntiles, bank_exp, ncls;
     int32_t persistent;         // 1: loop over work items from the counters
     int32_t track;              // 1: tracking tasks; `tile` then counts bins per work item
@@ -81,14 +85,17 @@ struct CorrArgs {
 
 struct FwdArgs {
     BlockTable blocks;
-    float2* X;                  // [segments][ncls][M] FP32 spectra (sub-transforms, then the result)
-    void* Xh;                   // [segments][M] 16-bit copy (FP16/BF16 plans only)
+    float2* X;                  // [segments][ncls][xstride] FP32 spectra (sub-transforms, then the
+                                // result), at offset xpad of each slot with wrap-around copies
+    void* Xh;                   // [segments][ncls][xstride] 16-bit copy (FP16/BF16 plans only)
     const int* exps;            // [block] 16-bit storage prescale exponents (16-bit plans)
     const float2* rootsM;
     const float2* rootsSub;
     const float2* b1tab;
     const double* cls_cyc;      // [ncls] residual offset of each class, cycles per sample
     int64_t V;
+    int64_t xstride;            // elements per slot (M when unpadded)
+    int32_t xpad;               // wrap-around copies before and after each spectrum (0: none)
     int32_t spc, M, Msub, ncls;
 };
 

@@ -130,7 +130,15 @@ __global__ __launch_bounds__(kStatsThreads) void k_block_stats(BlockTable bt, co
 // k_forward_combine: the radix-spc decimation-in-time step, in place per i:
 //   X_g[i + q*Msub] = F_0[i] + sum_{r>=1} exp(-j 2 pi (i + q*Msub) r / M) F_r[i],
 //   accumulated in FP32 in increasing r; 16-bit plans store the result scaled
-//   and packed in the 16-bit copy instead.
+//   and packed in the 16-bit copy instead.  Each spectrum sits at offset xpad
+//   of its slot, with its last xpad entries copied before it and its first
+//   xpad after it (rotated reads need no wrap-around).
+// LDS position of transform output i for the natural-order staging: bits 0-3
+// XOR-ed with a function of bits 4-7 and 10-11, so that both the engine-order
+// writes and the lane-consecutive reads hit 16 distinct 8-byte banks per
+// 16 lanes (a permutation of [0, N)).
+__device__ __forceinline__ int out_swizzle(int i) { return i ^ (((i >> 4) + 4 * (i >> 10)) & 15); }
+
 template <class E>
 __global__ __launch_bounds__(E::NT) void k_forward_sub(FwdArgs a) {
     __shared__ float2 lds[E::LDS];
@@ -172,10 +180,20 @@ __global__ __launch_bounds__(E::NT) void k_forward_sub(FwdArgs a) {
             }
         }
         eng.template transform<-1>(v, lds, b1, extra);
-        float2* F = a.X + (size_t(g) * size_t(a.ncls) + size_t(c)) * size_t(a.M) + size_t(r) * size_t(a.Msub);
+        float2* F = a.X + (size_t(g) * size_t(a.ncls) + size_t(c)) * size_t(a.xstride) + size_t(a.xpad) +
+                    size_t(r) * size_t(a.Msub);
+        // outputs leave in the engine's order: put them in natural order in LDS
+        // (XOR-swizzled, conflict-free both ways), then store whole lines
         const int ob = eng.out_base();
+        __syncthreads();                 // every wave is done with the transform's LDS
 #pragma unroll
-        for (int m = 0; m < 16; ++m) F[ob + E::out_off(m)] = v[m];
+        for (int m = 0; m < 16; ++m) lds[out_swizzle(ob + E::out_off(m))] = v[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int i = eng.in_index(m);
+            F[i] = lds[out_swizzle(i)];
+        }
         __syncthreads();                 // LDS is reused by the next item
     }
 }
@@ -192,7 +210,7 @@ __global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
     const int g = int(blockIdx.x) / per_slot;           // spectra slot: segment * ncls + class
     if (g >= a.blocks.total_seg() * a.ncls) return;
     const int i = (int(blockIdx.x) - g * per_slot) * 256 + int(threadIdx.x);
-    float2* X = a.X + size_t(g) * size_t(a.M);
+    float2* X = a.X + size_t(g) * size_t(a.xstride) + size_t(a.xpad);
     float xs = 1.0f;
     if constexpr (PREC != ACQ_FP32) xs = ldexpf(1.0f, -a.exps[a.blocks.block_of_segment(g / a.ncls)]);
     float2 F[SPC];
@@ -211,11 +229,19 @@ __global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
                 if (r + 1 < SPC) w = cmul(w, w1);
             }
         }
-        if constexpr (PREC == ACQ_FP32)
+        // the spectrum, and its wrap-around copy when io is within xpad of an end
+        if constexpr (PREC == ACQ_FP32) {
             X[io] = c;
-        else
-            reinterpret_cast<typename St::T*>(a.Xh)[size_t(g) * size_t(a.M) + io] =
-                St::pack(make_float2(c.x * xs, c.y * xs));
+            if (io < a.xpad) X[a.M + io] = c;
+            if (io >= a.M - a.xpad) X[io - a.M] = c;
+        } else {
+            typename St::T* Xh = reinterpret_cast<typename St::T*>(a.Xh) + size_t(g) * size_t(a.xstride) +
+                                 size_t(a.xpad);
+            const typename St::T h = St::pack(make_float2(c.x * xs, c.y * xs));
+            Xh[io] = h;
+            if (io < a.xpad) Xh[a.M + io] = h;
+            if (io >= a.M - a.xpad) Xh[io - a.M] = h;
+        }
     }
 }
 
@@ -552,6 +578,7 @@ static hipError_t combine_p(const FwdArgs& a, dim3 grid, hipStream_t st) {
 hipError_t launch_forward(const FwdArgs& a, int grid, int combine_slots, int log2_sub, int prec, hipStream_t st) {
     if (grid <= 0 || combine_slots <= 0) return hipSuccess;
     if ((1 << log2_sub) != a.Msub || a.Msub % 256 || a.spc < 1 || a.spc > 8) return hipErrorInvalidValue;
+    if (a.xpad < 0 || a.xpad > a.M / 2 || a.xstride < int64_t(a.M) + 2 * int64_t(a.xpad)) return hipErrorInvalidValue;
     hipError_t e;
     switch (log2_sub) {
         case 10: e = fwd_e<StockhamEngine<10>>(a, grid, st); break;

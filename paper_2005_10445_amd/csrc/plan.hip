@@ -193,7 +193,7 @@ size_t layout_scratch(const Geometry& g, const acq_config& c, int64_t blocks, in
         off += (std::max<size_t>(bytes, 1) + kWsAlign - 1) / kWsAlign * kWsAlign;
     };
     const size_t T = size_t(c.num_tags), B = size_t(blocks), S = size_t(std::max<int64_t>(segments, 1));
-    const size_t spectra = S * size_t(g.ncls) * size_t(g.M);
+    const size_t spectra = S * size_t(g.ncls) * size_t(g.xstride);
     const size_t wmax = c.refine_radius <= 1 ? 5 : size_t(2 * acq::kMaxRefineRadius + 3);
     take(s->X, spectra * sizeof(float2));
     if (c.precision != ACQ_FP32) take(s->Xh, spectra * 4);
@@ -370,6 +370,8 @@ int enqueue_search(acq_plan_s* p, const Scratch& w, const BlockTable& bt, bool b
     fa.rootsSub = p->d_rootsSub;
     fa.b1tab = p->d_b1tab;
     fa.V = g.V;
+    fa.xstride = g.xstride;
+    fa.xpad = int(g.xpad);
     fa.spc = c.samples_per_chip;
     fa.M = int(g.M);
     fa.Msub = int(g.Msub);
@@ -401,6 +403,8 @@ int enqueue_search(acq_plan_s* p, const Scratch& w, const BlockTable& bt, bool b
     ca.dump = dump;
     ca.counters = w.counters;
     ca.V = g.V;
+    ca.xstride = g.xstride;
+    ca.xpad = int(g.xpad);
     ca.K = c.num_bins;
     ca.spc = c.samples_per_chip;
     ca.M = int(g.M);
@@ -1068,6 +1072,7 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
             acq_tune_entry c{};
             c.tuning.engine = e;
             c.tuning.tag_tile = tile;
+            c.fft_len = int32_t(p->g.M);
             cand.push_back(c);
         }
     const acq_tuning before{p->engine, p->tile, p->batch_launch, p->track_bins};
@@ -1127,6 +1132,7 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
             acq_tune_entry c{};
             c.tuning = cand[best].tuning;
             c.tuning.batch_launch = form;
+            c.fft_len = int32_t(p->g.M);
             rc = time_one(c.tuning, true, &c.ms);
             if (rc != ACQ_OK) break;
             if (form == ACQ_BATCH_GRID || c.ms < best_ms) {
@@ -1145,6 +1151,70 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
     acq_set_profiling(p, was_profiling ? 1 : 0);
     *n_out = int32_t(cand.size());
     for (size_t i = 0; i < cand.size() && int32_t(i) < capacity; ++i) out[i] = cand[i];
+    acq::clear_error();
+    return ACQ_OK;
+}
+
+int acq_tune_fft_len(const acq_config* cfg, const void* block, int64_t n, int32_t reps, void* stream,
+                     acq_tune_entry* out, int32_t capacity, int32_t* n_out, int32_t* best_fft_len) {
+    if (!cfg || !n_out || !best_fft_len || reps < 1 || capacity < 0 || (capacity > 0 && !out))
+        return acq::fail(ACQ_ERR_INVALID_ARG, "bad arguments");
+    acq_config base = *cfg;
+    base.fft_len = 0;
+    Geometry g0;
+    int rc = acq::derive_geometry(&base, &g0);
+    if (rc != ACQ_OK) return rc;
+    if (n < g0.L) return acq::fail(ACQ_ERR_INVALID_ARG, "block shorter than a template");
+    const int64_t spc = cfg->samples_per_chip;
+    std::vector<acq_tune_entry> table;
+    for (int64_t M = g0.m_min; table.size() < 4 && M / spc <= (int64_t(1) << 14); M *= 2) {
+        acq_config c = base;
+        c.fft_len = int32_t(M);
+        Geometry gm;
+        if (acq::derive_geometry(&c, &gm) != ACQ_OK) continue;      // e.g. M / spc below 2^10
+        acq_plan_t p = nullptr;
+        rc = acq_plan(&c, nullptr, 0, stream, &p);
+        if (rc != ACQ_OK) return rc;
+        acq_tune_entry e{};
+        std::vector<acq_tune_entry> inner(32);
+        int32_t ni = 0;
+        rc = acq_tune(p, block, n, reps, inner.data(), int32_t(inner.size()), &ni);
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (rc == ACQ_OK && (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess))
+            rc = acq::fail(ACQ_ERR_DEVICE, "hipEventCreate failed");
+        double total = 0.0;
+        BlockTable bt{};
+        bt.one = single_desc(p, block, n);
+        for (int r = 0; r <= reps && rc == ACQ_OK; ++r) {       // one warm-up run
+            if (hipEventRecord(t0, p->stream) != hipSuccess) rc = acq::fail(ACQ_ERR_DEVICE, "hipEventRecord");
+            if (rc == ACQ_OK)
+                rc = enqueue_search(p, p->ws, bt, false, bt.one.nseg, nullptr, true, p->stream, false,
+                                    workspace_dest(p, false));
+            float ms = 0.f;
+            if (rc == ACQ_OK && (hipEventRecord(t1, p->stream) != hipSuccess ||
+                                 hipEventSynchronize(t1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, t0, t1) != hipSuccess))
+                rc = acq::fail(ACQ_ERR_DEVICE, "timing the search failed");
+            if (r > 0) total += ms;
+        }
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        if (rc == ACQ_OK) {
+            e.tuning = acq_tuning{p->engine, p->tile, p->batch_launch, p->track_bins};
+            e.fft_len = int32_t(M);
+            e.ms = total / reps;
+            table.push_back(e);
+        }
+        acq_release(p);
+        if (rc != ACQ_OK) return rc;
+    }
+    if (table.empty()) return acq::fail(ACQ_ERR_UNSUPPORTED, "no segment length available");
+    size_t best = 0;
+    for (size_t i = 1; i < table.size(); ++i)
+        if (table[i].ms < table[best].ms) best = i;
+    *best_fft_len = table[best].fft_len;
+    *n_out = int32_t(table.size());
+    for (size_t i = 0; i < table.size() && int32_t(i) < capacity; ++i) out[i] = table[i];
     acq::clear_error();
     return ACQ_OK;
 }
