@@ -28,8 +28,8 @@
 // power with ties going to the smaller lag and then the smaller bin (the
 // argmax of Section 3, step 8).  P >= 0, so its bit pattern orders like its
 // value.  Each tag also counts its threshold crossings, the (bin, lag) with
-// P >= theta * L * Pxhat; a wave takes that count only when one of its lanes'
-// largest powers crosses, which is rare, so the common path pays one compare.
+// P >= theta * L * Pxhat: each lane counts its own (invalid lags carry
+// P = -1), and the wave adds the lanes' counts only when some lane has one.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -117,21 +117,10 @@ __device__ __forceinline__ void first_step(const CorrArgs& a, const E& eng, int 
     }
 }
 
-// Threshold crossings of one transform's outputs in this wave: valid outputs
-// with power >= pth (wave-uniform count).
-template <class E>
-__device__ __forceinline__ unsigned wave_crossings(const float2 (&v)[16], int ob, int omin, int ulim, float pth) {
-    unsigned c = 0;
+__device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int off = E::out_off(r);
-        if (omin + off < ulim) {
-            const float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
-            const bool ok = ob + off < ulim && p >= pth;
-            c += unsigned(__builtin_popcountll(__builtin_amdgcn_ballot_w64(ok)));
-        }
-    }
-    return c;
+    for (int off = 32; off > 0; off >>= 1) v += unsigned(__shfl_xor(int(v), off, 64));
+    return v;
 }
 
 // One work item: (tile of tags, global segment g, bin k, phase rho), item index
@@ -207,6 +196,7 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
         // output index, so the strict comparison keeps the smallest lag of a tie
         float bp = -1.0f;
         int boff = 0;
+        unsigned lc = 0;                           // this lane's crossings
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int r = E::visit(rr);
@@ -220,17 +210,17 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
                     }
                 }
                 if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
+                lc += p >= pth ? 1u : 0u;
                 boff = p > bp ? off : boff;
                 bp = p > bp ? p : bp;
             }
         }
+        unsigned cross = 0;
+        if (__builtin_amdgcn_ballot_w64(lc != 0)) cross = wave_sum_u32(lc);
         unsigned long long best = bp >= 0.0f
             ? (static_cast<unsigned long long>(__float_as_uint(bp)) << 32) |
                   static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
             : 0ull;
-        // threshold crossings: counted only by waves where some lane's largest power crosses
-        unsigned cross = 0;
-        if (__builtin_amdgcn_ballot_w64(bp >= pth)) cross = wave_crossings<E>(v, ob, omin, ulim, pth);
         best = wave_max(best);
         if (lane == 0) {
             red[tt * NW + wave] = best;
@@ -294,7 +284,7 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
     const int voffm = (E::NT - eng.in_index(0)) * St::BYTES;
 
     unsigned long long best = 0ull;
-    unsigned cross = 0;
+    unsigned lc = 0;                               // this lane's crossings over the item's bins
     // the task's replica spectrum is the same for every bin: read it once
     float2 bk[16];
 #pragma unroll
@@ -321,6 +311,7 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
             if (omin + off < ulim) {
                 float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
                 if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
+                lc += p >= pth ? 1u : 0u;
                 boff = p > bp ? off : boff;
                 bp = p > bp ? p : bp;
             }
@@ -330,9 +321,10 @@ __device__ __forceinline__ void track_item(const CorrArgs& a, const E& eng, int 
                   static_cast<unsigned long long>(~(idx0 + unsigned(boff) * kstep))
             : 0ull;
         best = key > best ? key : best;
-        if (__builtin_amdgcn_ballot_w64(bp >= pth)) cross += wave_crossings<E>(v, ob, omin, ulim, pth);
     }
     best = wave_max(best);
+    unsigned cross = 0;
+    if (__builtin_amdgcn_ballot_w64(lc != 0)) cross = wave_sum_u32(lc);
     if (lane == 0) {
         red[wave] = best;
         cred[wave] = cross;
