@@ -490,6 +490,12 @@ typedef struct acq_synth_batch {
  * out[block_len].  Synchronous. */
 int acq_synth_block(acq_cnn_t cnn, const acq_synth_batch* batch, void* out);
 
+/* Test hook: the training labels of the batch's frames, device FP32
+ * labels[nblocks * frames] (block-major): 1 where at least half of the
+ * frame's 256 samples lie inside some transmission [delay, delay + L),
+ * L = num_chips * samples_per_chip, else 0.  Synchronous. */
+int acq_synth_labels(acq_cnn_t cnn, const acq_synth_batch* batch, float* labels);
+
 /* One training step on a generated batch: samples, power maps, frame labels,
  * forward, loss, backward and Adam, all on the device (no sample is written to
  * memory).  *loss (host) is the batch's mean loss before the update. */

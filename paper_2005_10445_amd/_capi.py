@@ -37,7 +37,7 @@ EXPORTED = ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "a
             "acq_set_profiling",
             "acq_last_kernel_times", "acq_release", "acq_cnn_num_params", "acq_cnn_create", "acq_cnn_release",
             "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward", "acq_cnn_gradients",
-            "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_cnn_train_synthetic",
+            "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_synth_labels", "acq_cnn_train_synthetic",
             "acq_detect_learned", "acq_detect_batch_learned", "acq_fsk_plan_geometry", "acq_fsk_plan",
             "acq_fsk_release", "acq_fsk_demod", "acq_fsk_template", "acq_fsk_xcorr", "acq_fsk_detect",
             "acq_fsk_track", "acq_fsk_set_profiling", "acq_fsk_last_kernel_times", "acq_strerror",
@@ -249,6 +249,7 @@ def lib(path: str = LIB_PATH):
     L.acq_cnn_adam_step.argtypes = [vp, f32]
     L.acq_power_map.argtypes = [vp, vp, i64, vp, P(ctypes.c_float)]
     L.acq_synth_block.argtypes = [vp, P(AcqSynthBatch), vp]
+    L.acq_synth_labels.argtypes = [vp, P(AcqSynthBatch), vp]
     L.acq_cnn_train_synthetic.argtypes = [vp, P(AcqSynthBatch), f32, f32, P(ctypes.c_float)]
     L.acq_detect_learned.argtypes = [vp, vp, vp, i64, P(AcqLearnedParams), P(AcqDetection), i32, P(i32),
                                      P(AcqLearnedReport)]
@@ -273,7 +274,7 @@ def lib(path: str = LIB_PATH):
                  "acq_get_tuning", "acq_set_tuning", "acq_tune", "acq_tune_fft_len", "acq_correlate_power",
                  "acq_release", "acq_set_profiling", "acq_last_kernel_times", "acq_cnn_create",
                  "acq_cnn_release", "acq_cnn_set_params", "acq_cnn_get_params", "acq_cnn_forward",
-                 "acq_cnn_gradients", "acq_cnn_adam_step", "acq_power_map", "acq_synth_block",
+                 "acq_cnn_gradients", "acq_cnn_adam_step", "acq_power_map", "acq_synth_block", "acq_synth_labels",
                  "acq_cnn_train_synthetic", "acq_detect_learned", "acq_detect_batch_learned"):
         getattr(L, name).restype = ctypes.c_int
     L.acq_strerror.argtypes = [ctypes.c_int]

@@ -408,6 +408,18 @@ int acq_synth_block(acq_cnn_t c, const acq_synth_batch* batch, void* out) {
     return ACQ_OK;
 }
 
+int acq_synth_labels(acq_cnn_t c, const acq_synth_batch* batch, float* labels) {
+    if (!c || !labels) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
+    BlockSource src{};
+    int rc = synth_source(c, batch, &src);
+    if (rc != ACQ_OK) return rc;
+    CNN_HIP(launch_labels(c->d_tx, c->d_ntx, batch->nblocks, num_frames(batch->block_len), src.chip_len, labels,
+                          c->stream));
+    CNN_HIP(hipStreamSynchronize(c->stream));
+    acq::clear_error();
+    return ACQ_OK;
+}
+
 int acq_cnn_train_synthetic(acq_cnn_t c, const acq_synth_batch* batch, float pos_weight, float lr, float* loss) {
     if (!c || !loss) return acq::fail(ACQ_ERR_INVALID_ARG, "null argument");
     if (c->cfg.in_channels != kWin) return acq::fail(ACQ_ERR_INVALID_ARG, "power-map training needs 256 inputs");

@@ -258,7 +258,8 @@ __global__ void k_synth(BlockSource src, int64_t n, float2* __restrict__ out) {
     if (i < n) out[i] = synth_sample(src, 0, i);
 }
 
-// 1 when at least half of the frame lies inside some transmission.
+// 1 when at least half of the frame lies inside some transmission: the frame's
+// samples covered by the union of the transmissions, as a 256-bit mask.
 __global__ void k_labels(const SynthTx* __restrict__ tx, const int32_t* __restrict__ ntx, int64_t rows, int64_t F,
                          int L, float* __restrict__ labels) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -266,16 +267,25 @@ __global__ void k_labels(const SynthTx* __restrict__ tx, const int32_t* __restri
     const int b = int(r / F);
     const int64_t f0 = (r - int64_t(b) * F) * kHop;
     const int nt = ntx[b];
-    int covered = 0;
-    for (int j = 0; j < kWin; ++j) {
-        const int64_t n = f0 + j;
-        bool in = false;
-        for (int t = 0; t < nt && !in; ++t) {
-            const int64_t d = tx[int64_t(b) * kMaxTx + t].delay;
-            in = n >= d && n < d + L;
+    constexpr int kWords = kWin / 32;
+    uint32_t cov[kWords];
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) cov[w] = 0u;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t d = tx[int64_t(b) * kMaxTx + t].delay;
+        const int64_t lo = (d > f0 ? d : f0) - f0;                               // [lo, hi) of the frame
+        const int64_t hi = (d + L < f0 + kWin ? d + L : f0 + kWin) - f0;
+        if (lo >= hi) continue;
+#pragma unroll
+        for (int w = 0; w < kWords; ++w) {
+            const int a = int(lo - 32 * w > 0 ? lo - 32 * w : 0);
+            const int e = int(hi - 32 * w < 32 ? hi - 32 * w : 32);
+            if (a < e) cov[w] |= (e - a == 32 ? 0xffffffffu : ((1u << (e - a)) - 1u) << a);
         }
-        covered += in;
     }
+    int covered = 0;
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) covered += __popc(cov[w]);
     labels[r] = covered >= kWin / 2 ? 1.0f : 0.0f;
 }
 
@@ -463,13 +473,17 @@ __global__ void k_conv_dw_ref(const float* __restrict__ in, int cin, const float
 }
 
 // db[o] += sum_r dA[r][o] (bf16 activations)
+// Column sums of dH where the layer output is positive (the bias gradient):
+// 64 rows per workgroup, one atomic per column per workgroup.
+constexpr int kColsumRows = 64;
+
 __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dH, const uint16_t* __restrict__ H,
                                                 float* __restrict__ db, int64_t rows) {
     __shared__ float s[256];
     const int t = int(threadIdx.x), o = t & 63, part = t >> 6;
     float acc = 0.0f;
-    const int64_t r0 = int64_t(blockIdx.x) * 1024;
-    for (int64_t r = r0 + part; r < r0 + 1024 && r < rows; r += 4) {
+    const int64_t r0 = int64_t(blockIdx.x) * kColsumRows;
+    for (int64_t r = r0 + part; r < r0 + kColsumRows && r < rows; r += 4) {
         const uint16_t hv = H[r * kCh + o];
         if (hv && !(hv & 0x8000u)) acc += dH[r * kCh + o];
     }
@@ -711,8 +725,8 @@ hipError_t launch_conv_dweight(const void* in, int cin, const float* dH, const v
         if (cin % 64) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_conv_dw_mfma, dim3(blocks_for(rows, kDwRows), unsigned(kTaps * (cin / 64))), dim3(256),
                            0, st, (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, rows, F, d);
-        hipLaunchKernelGGL(k_colsum, dim3(blocks_for(rows, 1024)), dim3(256), 0, st, dH, (const uint16_t*)H, db,
-                           rows);
+        hipLaunchKernelGGL(k_colsum, dim3(blocks_for(rows, kColsumRows)), dim3(256), 0, st, dH, (const uint16_t*)H,
+                           db, rows);
     } else {
         hipLaunchKernelGGL(k_conv_dw_ref, dim3(blocks_for(int64_t(kTaps) * cin * kCh, 256)), dim3(256), 0, st,
                            (const float*)in, cin, dH, (const float*)H, dW, db, rows, F, d);

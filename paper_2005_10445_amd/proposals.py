@@ -153,6 +153,16 @@ class Network:
               "acq_synth_block")
         return out
 
+    def synth_labels(self, seed: int, first_block: int, block_len: int, num_chips: int, spc: int,
+                     txs: Sequence[Sequence[SynthTransmission]]):
+        """Training labels (device FP32 [len(txs) * frames]) of a generated batch."""
+        import torch
+        batch, keep = self._batch(seed, first_block, block_len, num_chips, spc, txs)
+        out = torch.empty(len(txs) * num_frames(int(block_len)), dtype=torch.float32, device="cuda")
+        check(self._lib.acq_synth_labels(self._h, ctypes.byref(batch), ctypes.c_void_p(out.data_ptr())),
+              "acq_synth_labels")
+        return out
+
     def train_synthetic(self, seed: int, first_block: int, block_len: int, num_chips: int, spc: int,
                         txs: Sequence[Sequence[SynthTransmission]], pos_weight: float, lr: float) -> float:
         """One generated batch (len(txs) blocks): map, labels, forward, backward, Adam.  Mean loss."""

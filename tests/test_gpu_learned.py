@@ -236,6 +236,38 @@ def test_synthetic_generator_statistics(dev):
     assert abs(chips.mean()) < 0.05                         # balanced +/-1
 
 
+def test_training_labels_match_the_oracle(dev):
+    """Frame labels of generated batches, bit for bit against the oracle and a
+    brute-force count: overlapping transmissions (a union, not a sum), one cut
+    by the block's end, frames exactly half covered, a block without
+    transmissions, and a template shorter than a frame."""
+    from paper_2005_10445_amd.proposals import SynthTransmission
+    g = np.random.default_rng(12)
+    n = 1 << 16
+    for C, spc in ((8192, 2), (50, 2)):
+        L = C * spc
+        delays = [
+            [0, 5000, 5100, n - L // 2],                       # block start, an overlap, the end
+            [],
+            [int(d) for d in g.integers(0, n, 20)],            # many, overlapping
+            [128 * 40 + 128, 128 * 90 - 1, 128 * 300 + 127],   # boundaries of half-covered frames
+        ]
+        txs = [[SynthTransmission(delay=d, freq_over_fs=0.0, amp=1.0, phase0=0.0, code=i) for i, d in enumerate(b)]
+               for b in delays]
+        with _net("bf16", max_rows=1 << 12) as net:
+            got = net.synth_labels(3, 0, n, C, spc, txs).cpu().numpy().reshape(len(txs), -1)
+        for b, ds in enumerate(delays):
+            want = ol.frame_labels(n, ds, L)
+            cover = np.zeros(n, dtype=bool)
+            for d in ds:
+                cover[d:min(d + L, n)] = True
+            brute = np.array([cover[128 * f:128 * f + 256].sum() >= 128 for f in range(want.size)], dtype=np.float64)
+            assert np.array_equal(want, brute), (C, b)
+            assert np.array_equal(got[b].astype(np.float64), want), (C, b)
+            if ds and L >= 256:
+                assert 0 < want.sum() < want.size, (C, b)
+
+
 def test_training_reduces_loss(dev):
     from paper_2005_10445_amd.proposals import SynthTransmission
     g = np.random.default_rng(8)
