@@ -18,6 +18,8 @@
 //   k_window/k_propose window scores, frames at or above the threshold and the
 //                     segment list
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <cfloat>
 
 #include "device_fft.h"
@@ -290,80 +292,146 @@ __global__ void k_labels(const SynthTx* __restrict__ tx, const int32_t* __restri
 }
 
 // ------------------------------------------------------------------ conv (MFMA)
-// v_mfma_f32_16x16x16_bf16 operand layout, lane l: A[row l%16][k 4(l/16)+e],
-// B[k 4(l/16)+e][col l%16], D[row 4(l/16)+e][col l%16], e < 4.
-//
-// Forward / input gradient share one shape: out[r][n] (n < 64) =
-// sum_i sum_k A(r, i, k) Bt[i][n][k], A(r, i, k) = src[r + sgn d (i-2)][k] (zero
-// outside r's block).  A workgroup computes 64 rows x 64 columns; wave w rows
-// 16w .. 16w+15 as four 16x16 tiles.
+// Forward / input gradient as a tiled GEMM on v_mfma_f32_16x16x32_bf16
+// (lane l: A[row l%16][k 8(l/16)+e], B[k 8(l/16)+e][col l%16], e < 8;
+// D[row 4(l/16)+e][col l%16], e < 4).  A workgroup computes 128 rows x 64
+// columns.  The rows it needs for all five taps -- its 128 plus 2d above and
+// below -- are staged once in LDS as bf16 ([row][K + 8], the pad spreading
+// the 16-byte reads of a wave over the banks); for the input gradient the
+// staging applies the ReLU mask to dH and rounds it once.  Each wave takes
+// 32 rows (two 16-row tiles) by the 64 columns (four 16-column tiles); the
+// weights of the next 32-deep k step are loaded while the current step's
+// eight MFMAs run.  A tap row outside its output row's block is zero.
+constexpr int kTileRows = 128;
+
+using bf16x8 = __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
 template <bool FWD>
-__global__ __launch_bounds__(256) void k_conv_mfma(const void* __restrict__ src, const uint16_t* __restrict__ H,
+__global__ __launch_bounds__(256) void k_conv_tile(const void* __restrict__ src, const uint16_t* __restrict__ H,
                                                    int K, const uint16_t* __restrict__ Bt,
                                                    const float* __restrict__ bias, void* __restrict__ out,
                                                    int64_t rows, int64_t F, int d) {
-    const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
-    const int64_t r0 = int64_t(blockIdx.x) * 64 + wave * 16;
-    const int64_t ar = r0 + (lane & 15);
-    const int kq = 4 * (lane >> 4);
-    const int sgn = FWD ? 1 : -1;
-    const int64_t blk = ar / F, f = ar - blk * F;
-    f32x4 acc[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int i = 0; i < kTaps; ++i) {
-        const int64_t fs = f + int64_t(sgn) * d * (i - 2);
-        const bool ok = ar < rows && fs >= 0 && fs < F;
-        const int64_t srow = blk * F + fs;
-        const uint16_t* brow = Bt + (int64_t(i) * kCh + (lane & 15)) * K;
-        for (int kc = 0; kc < K; kc += 16) {
-            bf16x4 a = bf16x4{0, 0, 0, 0};
-            if (ok) {
-                if constexpr (FWD) {
-                    a = *reinterpret_cast<const bf16x4*>(static_cast<const uint16_t*>(src) + srow * K + kc + kq);
-                } else {
-                    const float4 g = *reinterpret_cast<const float4*>(static_cast<const float*>(src) + srow * kCh + kc + kq);
-                    const uint2 hb = *reinterpret_cast<const uint2*>(H + srow * kCh + kc + kq);
-                    // dA = dH where the layer output is positive
-                    const float g0 = (hb.x & 0x7fffu) && !(hb.x & 0x8000u) ? g.x : 0.f;
-                    const float g1 = (hb.x & 0x7fff0000u) && !(hb.x & 0x80000000u) ? g.y : 0.f;
-                    const float g2 = (hb.y & 0x7fffu) && !(hb.y & 0x8000u) ? g.z : 0.f;
-                    const float g3 = (hb.y & 0x7fff0000u) && !(hb.y & 0x80000000u) ? g.w : 0.f;
-                    a = bf16x4{short(to_bf16(g0)), short(to_bf16(g1)), short(to_bf16(g2)), short(to_bf16(g3))};
-                }
+    extern __shared__ __align__(16) uint16_t sA[];
+    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    const int pitch = K + 8, halo = 2 * d, srows = kTileRows + 2 * halo;
+    const int64_t r0 = int64_t(blockIdx.x) * kTileRows;
+    if constexpr (FWD) {
+        const int cpr = K / 8;                           // 16-byte chunks per row
+        for (int idx = tid; idx < srows * cpr; idx += 256) {
+            const int sr = idx / cpr, ch = idx - sr * cpr;
+            const int64_t g = r0 - halo + sr;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (g >= 0 && g < rows) v = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(src) + g * K + ch * 8);
+            *reinterpret_cast<uint4*>(&sA[sr * pitch + ch * 8]) = v;
+        }
+    } else {
+        const int cpr = K / 4;                           // 4 values per thread and step
+        for (int idx = tid; idx < srows * cpr; idx += 256) {
+            const int sr = idx / cpr, ch = idx - sr * cpr;
+            const int64_t g = r0 - halo + sr;
+            uint2 o = {0u, 0u};
+            if (g >= 0 && g < rows) {
+                const float4 gv = *reinterpret_cast<const float4*>(static_cast<const float*>(src) + g * K + ch * 4);
+                const uint2 hb = *reinterpret_cast<const uint2*>(H + g * K + ch * 4);
+                // dA = dH where the layer output is positive
+                const float g0 = (hb.x & 0x7fffu) && !(hb.x & 0x8000u) ? gv.x : 0.f;
+                const float g1 = (hb.x & 0x7fff0000u) && !(hb.x & 0x80000000u) ? gv.y : 0.f;
+                const float g2 = (hb.y & 0x7fffu) && !(hb.y & 0x8000u) ? gv.z : 0.f;
+                const float g3 = (hb.y & 0x7fff0000u) && !(hb.y & 0x80000000u) ? gv.w : 0.f;
+                o.x = uint32_t(to_bf16(g0)) | (uint32_t(to_bf16(g1)) << 16);
+                o.y = uint32_t(to_bf16(g2)) | (uint32_t(to_bf16(g3)) << 16);
             }
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const bf16x4 bb = *reinterpret_cast<const bf16x4*>(brow + int64_t(nt) * 16 * K + kc + kq);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[nt], 0, 0, 0);
-            }
+            *reinterpret_cast<uint2*>(&sA[sr * pitch + ch * 4]) = o;
         }
     }
+    __syncthreads();
+
+    const int ra = lane & 15, kq = 8 * (lane >> 4);
+    int64_t frame[2];
+    bool live[2];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const int n = nt * 16 + (lane & 15);
-        const float bn = FWD ? bias[n] : 0.0f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t row = r0 + 4 * (lane >> 4) + e;
-            if (row >= rows) continue;
-            if constexpr (FWD)
-                static_cast<uint16_t*>(out)[row * kCh + n] = to_bf16(fmaxf(acc[nt][e] + bn, 0.0f));
-            else
-                static_cast<float*>(out)[row * kCh + n] = acc[nt][e];
-        }
+    for (int rt = 0; rt < 2; ++rt) {
+        const int64_t orow = r0 + 32 * wave + 16 * rt + ra;
+        live[rt] = orow < rows;
+        frame[rt] = orow - (orow / F) * F;
     }
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[rt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int ksteps = K / 32, steps = kTaps * ksteps;
+    auto bptr = [&](int step, int nt) {
+        const int i = step / ksteps, kc = (step - i * ksteps) * 32;
+        return Bt + (int64_t(i) * kCh + nt * 16 + ra) * K + kc + kq;
+    };
+    uint4 bcur[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) bcur[nt] = *reinterpret_cast<const uint4*>(bptr(0, nt));
+    for (int step = 0; step < steps; ++step) {
+        uint4 bnext[4];
+        const int sn = step + 1 < steps ? step + 1 : step;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) bnext[nt] = *reinterpret_cast<const uint4*>(bptr(sn, nt));
+        const int i = step / ksteps, kc = (step - i * ksteps) * 32;
+        const int delta = (FWD ? 1 : -1) * d * (i - 2);
+        bf16x8 a[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int arow = 32 * wave + 16 * rt + ra + halo + delta;
+            const uint4 v = *reinterpret_cast<const uint4*>(&sA[arow * pitch + kc + kq]);
+            const bool ok = live[rt] && frame[rt] + delta >= 0 && frame[rt] + delta < F;
+            a[rt] = as_bf16x8(ok ? v : uint4{0u, 0u, 0u, 0u});
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[rt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], as_bf16x8(bcur[nt]), acc[rt][nt], 0, 0, 0);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) bcur[nt] = bnext[nt];
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int n = nt * 16 + ra;
+            const float bn = FWD ? bias[n] : 0.0f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = r0 + 32 * wave + 16 * rt + 4 * (lane >> 4) + e;
+                if (row >= rows) continue;
+                if constexpr (FWD)
+                    static_cast<uint16_t*>(out)[row * kCh + n] = to_bf16(fmaxf(acc[rt][nt][e] + bn, 0.0f));
+                else
+                    static_cast<float*>(out)[row * kCh + n] = acc[rt][nt][e];
+            }
+        }
 }
 
-// Weight gradient of one tap and 64 input channels over 256 rows:
-// dW[i][c][o] += sum_r in[r + d(i-2)][c] dA[r][o].  The row chunk is staged in
-// LDS transposed ([channel][row]) so both MFMA operands are 8-byte reads.
-constexpr int kDwRows = 256;
+__host__ __device__ constexpr size_t conv_tile_lds(int K, int d) {
+    return size_t(kTileRows + 4 * d) * size_t(K + 8) * sizeof(uint16_t);
+}
+constexpr size_t kMaxConvLds = size_t(160) << 10;   // LDS of a gfx950 compute unit
+
+// Weight gradient on v_mfma_f32_16x16x16_bf16 (lane l: A[row l%16][k 4(l/16)+e],
+// B[k 4(l/16)+e][col l%16], D[row 4(l/16)+e][col l%16], e < 4), one tap and 64
+// input channels over a chunk of rows
+// (`chunk`, a multiple of 64): dW[i][c][o] += sum_r in[r + d(i-2)][c] dA[r][o].
+// Each 64-row piece is staged in LDS transposed ([channel][row]) so both MFMA
+// operands are 8-byte reads; the sums stay in registers over the chunk and are
+// added to dW once.  Short chunks keep many workgroups resident per CU, which
+// hides the staging loads (2048-row chunks with 4x fewer atomics were slower).
+constexpr int kDwRows = 64;
+constexpr int kDwChunk = 256;  // rows per workgroup
 constexpr int kDwPitch = 72;   // 64 rows + 8 pad (bf16)
 
 __global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict__ in, int cin,
                                                       const float* __restrict__ dH, const uint16_t* __restrict__ H,
-                                                      float* __restrict__ dW, int64_t rows, int64_t F, int d) {
+                                                      float* __restrict__ dW, int64_t rows, int64_t F, int d,
+                                                      int chunk) {
     __shared__ __align__(16) uint16_t sA[64 * kDwPitch];
     __shared__ __align__(16) uint16_t sD[64 * kDwPitch];
     const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
@@ -372,22 +440,29 @@ __global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict
     f32x4 acc[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int sub = 0; sub < kDwRows; sub += 64) {
-        const int64_t rbase = int64_t(blockIdx.x) * kDwRows + sub;
+    const int delta = d * (i - 2);
+    const int F32 = int(F);
+    for (int sub = 0; sub < chunk; sub += kDwRows) {
+        const int64_t rbase = int64_t(blockIdx.x) * chunk + sub;
+        if (rbase >= rows) break;                // uniform
+        // frame of this thread's first row (rows rbase + 4e + wave, e < 16), then stepped
+        int f = int(rbase % F) + wave;
+        while (f >= F32) f -= F32;
 #pragma unroll 4
         for (int e = 0; e < 16; ++e) {
-            const int idx = e * 256 + tid;
-            const int rr = idx >> 6, c = idx & 63;
+            const int rr = 4 * e + wave, c = lane;
             const int64_t r = rbase + rr;
             uint16_t av = 0, dv = 0;
             if (r < rows) {
-                const int64_t blk = r / F, f = r - blk * F, fs = f + int64_t(d) * (i - 2);
-                if (fs >= 0 && fs < F) av = in[(blk * F + fs) * cin + c0 + c];
+                // the tap row r + delta is in r's block when its frame is in [0, F)
+                if (f + delta >= 0 && f + delta < F32) av = in[(r + delta) * cin + c0 + c];
                 const uint16_t hv = H[r * kCh + c];
                 if (hv && !(hv & 0x8000u)) dv = to_bf16(dH[r * kCh + c]);
             }
             sA[c * kDwPitch + rr] = av;
             sD[c * kDwPitch + rr] = dv;
+            f += 4;
+            while (f >= F32) f -= F32;
         }
         __syncthreads();
 #pragma unroll
@@ -495,59 +570,82 @@ __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dH, co
 // ------------------------------------------------------------------ head and loss
 __device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
 
+// Head and loss.  Sixteen lanes share a row, each holding four of its 64
+// channels (coalesced reads of the layer output and writes of dH4): the
+// logit is a 16-lane sum; the head-weight gradient is kept per lane over the
+// workgroup's rows and added over its 16 row slots in LDS at the end.
+constexpr int kHeadRows = 256;          // rows per workgroup
+
 template <bool BF>
 __global__ __launch_bounds__(256) void k_head(const void* __restrict__ h4, const float* __restrict__ theta,
                                               int64_t wh_off, float* __restrict__ y, const float* __restrict__ labels,
                                               float pw, float inv_rows, float* __restrict__ dH4,
                                               float* __restrict__ grad, float* __restrict__ loss_sum, int64_t rows) {
-    __shared__ float swh[kCh];
-    __shared__ float sdw[kCh];
-    __shared__ float sred[2][256];
-    const int t = int(threadIdx.x);
-    if (t < kCh) {
-        swh[t] = theta[wh_off + t];
-        sdw[t] = 0.0f;
-    }
-    __syncthreads();
-    const int64_t r = int64_t(blockIdx.x) * 256 + t;
-    const bool ok = r < rows;
-    float h[kCh];
-    float z = theta[wh_off + kCh];
+    __shared__ float sdw[16][kCh + 1];
+    __shared__ float sred[2][16];
+    const int t = int(threadIdx.x), j = t & 15, slot = t >> 4;
+    float w[4];
 #pragma unroll
-    for (int o = 0; o < kCh; ++o) {
-        if constexpr (BF)
-            h[o] = ok ? from_bf16(static_cast<const uint16_t*>(h4)[r * kCh + o]) : 0.0f;
-        else
-            h[o] = ok ? static_cast<const float*>(h4)[r * kCh + o] : 0.0f;
-        z = fmaf(h[o], swh[o], z);
-    }
-    if (ok) y[r] = z;
-    if (!labels) return;   // uniform: inference
-    float dz = 0.0f, loss = 0.0f;
-    if (ok) {
-        const float lab = labels[r];
-        const float s = 1.0f / (1.0f + expf(-z));
-        loss = pw * lab * softplus(-z) + (1.0f - lab) * softplus(z);
-        dz = (pw * lab * (s - 1.0f) + (1.0f - lab) * s) * inv_rows;
-#pragma unroll
-        for (int o = 0; o < kCh; ++o) dH4[r * kCh + o] = dz * swh[o];
-#pragma unroll
-        for (int o = 0; o < kCh; ++o) atomicAdd(&sdw[o], dz * h[o]);
-    }
-    sred[0][t] = dz;
-    sred[1][t] = loss;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-            sred[0][t] += sred[0][t + off];
-            sred[1][t] += sred[1][t + off];
+    for (int c = 0; c < 4; ++c) w[c] = theta[wh_off + 4 * j + c];
+    const float bias = theta[wh_off + kCh];
+    float dw[4] = {0.f, 0.f, 0.f, 0.f};
+    float dzs = 0.0f, ls = 0.0f;
+    const int64_t rbase = int64_t(blockIdx.x) * kHeadRows;
+    for (int rr = 0; rr < kHeadRows; rr += 16) {
+        const int64_t r = rbase + rr + slot;
+        const bool ok = r < rows;
+        float h[4] = {0.f, 0.f, 0.f, 0.f};
+        if (ok) {
+            if constexpr (BF) {
+                const uint2 v = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(h4) + r * kCh + 4 * j);
+                h[0] = __uint_as_float(v.x << 16);
+                h[1] = __uint_as_float(v.x & 0xffff0000u);
+                h[2] = __uint_as_float(v.y << 16);
+                h[3] = __uint_as_float(v.y & 0xffff0000u);
+            } else {
+                const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(h4) + r * kCh + 4 * j);
+                h[0] = v.x; h[1] = v.y; h[2] = v.z; h[3] = v.w;
+            }
         }
-        __syncthreads();
+        float z = fmaf(h[3], w[3], fmaf(h[2], w[2], fmaf(h[1], w[1], h[0] * w[0])));
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) z += __shfl_xor(z, off, 16);
+        z += bias;
+        if (ok && j == 0) y[r] = z;
+        if (!labels) continue;     // uniform: inference
+        if (ok) {
+            const float lab = labels[r];
+            const float sg = 1.0f / (1.0f + expf(-z));
+            const float dz = (pw * lab * (sg - 1.0f) + (1.0f - lab) * sg) * inv_rows;
+            *reinterpret_cast<float4*>(dH4 + r * kCh + 4 * j) = make_float4(dz * w[0], dz * w[1], dz * w[2], dz * w[3]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dw[c] = fmaf(dz, h[c], dw[c]);
+            if (j == 0) {
+                dzs += dz;
+                ls += pw * lab * softplus(-z) + (1.0f - lab) * softplus(z);
+            }
+        }
     }
-    if (t < kCh) atomicAdd(&grad[wh_off + t], sdw[t]);
-    if (t == 0) {
-        atomicAdd(&grad[wh_off + kCh], sred[0][0]);
-        atomicAdd(loss_sum, sred[1][0]);
+    if (!labels) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sdw[slot][4 * j + c] = dw[c];
+    if (j == 0) {
+        sred[0][slot] = dzs;
+        sred[1][slot] = ls;
+    }
+    __syncthreads();
+    if (t < kCh) {
+        float a = 0.0f;
+        for (int q = 0; q < 16; ++q) a += sdw[q][t];
+        atomicAdd(&grad[wh_off + t], a);
+    } else if (t == kCh) {
+        float a = 0.0f, b = 0.0f;
+        for (int q = 0; q < 16; ++q) {
+            a += sred[0][q];
+            b += sred[1][q];
+        }
+        atomicAdd(&grad[wh_off + kCh], a);
+        atomicAdd(loss_sum, b);
     }
 }
 
@@ -695,8 +793,13 @@ hipError_t launch_conv_forward(const void* in, int cin, const void* w, const flo
                                int64_t F, int d, bool bf16, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     if (bf16) {
-        if (cin % 16) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_conv_mfma<true>, dim3(blocks_for(rows, 64)), dim3(256), 0, st, in,
+        if (cin % 32 || d < 1) return hipErrorInvalidValue;
+        const size_t lds = conv_tile_lds(cin, d);
+        if (lds > kMaxConvLds) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv_tile<true>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_conv_tile<true>, dim3(blocks_for(rows, kTileRows)), dim3(256), lds, st, in,
                            (const uint16_t*)nullptr, cin, (const uint16_t*)w, bias, out, rows, F, d);
     } else {
         hipLaunchKernelGGL(k_conv_fwd_ref, dim3(blocks_for(rows * kCh, 256)), dim3(256), 0, st, (const float*)in,
@@ -708,11 +811,17 @@ hipError_t launch_conv_forward(const void* in, int cin, const void* w, const flo
 hipError_t launch_conv_dinput(const float* dH, const void* H, const void* w, float* dprev, int64_t rows, int64_t F,
                               int d, bool bf16, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
-    if (bf16)
-        hipLaunchKernelGGL(k_conv_mfma<false>, dim3(blocks_for(rows, 64)), dim3(256), 0, st, (const void*)dH,
+    if (bf16) {
+        if (d < 1) return hipErrorInvalidValue;
+        const size_t lds = conv_tile_lds(kCh, d);
+        if (lds > kMaxConvLds) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_conv_tile<false>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_conv_tile<false>, dim3(blocks_for(rows, kTileRows)), dim3(256), lds, st, (const void*)dH,
                            (const uint16_t*)H, kCh, (const uint16_t*)w, (const float*)nullptr, (void*)dprev, rows,
                            F, d);
-    else
+    } else
         hipLaunchKernelGGL(k_conv_dinput_ref, dim3(blocks_for(rows * kCh, 256)), dim3(256), 0, st, dH,
                            (const float*)H, (const float*)w, dprev, rows, F, d);
     return hipGetLastError();
@@ -722,9 +831,11 @@ hipError_t launch_conv_dweight(const void* in, int cin, const float* dH, const v
                                int64_t rows, int64_t F, int d, bool bf16, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     if (bf16) {
-        if (cin % 64) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_conv_dw_mfma, dim3(blocks_for(rows, kDwRows), unsigned(kTaps * (cin / 64))), dim3(256),
-                           0, st, (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, rows, F, d);
+        if (cin % 64 || rows >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+        const int64_t tasks = int64_t(kTaps) * (cin / 64);
+        const int chunk = kDwChunk;
+        hipLaunchKernelGGL(k_conv_dw_mfma, dim3(blocks_for(rows, chunk), unsigned(tasks)), dim3(256), 0, st,
+                           (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, rows, F, d, chunk);
         hipLaunchKernelGGL(k_colsum, dim3(blocks_for(rows, kColsumRows)), dim3(256), 0, st, dH, (const uint16_t*)H,
                            db, rows);
     } else {
@@ -739,10 +850,10 @@ hipError_t launch_head(const void* h4, const float* theta, int64_t wh_off, float
                        bool bf16, hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     if (bf16)
-        hipLaunchKernelGGL(k_head<true>, dim3(blocks_for(rows, 256)), dim3(256), 0, st, h4, theta, wh_off, y, labels,
-                           pos_weight, inv_rows, dH4, grad, loss_sum, rows);
+        hipLaunchKernelGGL(k_head<true>, dim3(blocks_for(rows, kHeadRows)), dim3(256), 0, st, h4, theta, wh_off, y,
+                           labels, pos_weight, inv_rows, dH4, grad, loss_sum, rows);
     else
-        hipLaunchKernelGGL(k_head<false>, dim3(blocks_for(rows, 256)), dim3(256), 0, st, h4, theta, wh_off, y,
+        hipLaunchKernelGGL(k_head<false>, dim3(blocks_for(rows, kHeadRows)), dim3(256), 0, st, h4, theta, wh_off, y,
                            labels, pos_weight, inv_rows, dH4, grad, loss_sum, rows);
     return hipGetLastError();
 }
