@@ -426,12 +426,13 @@ constexpr size_t kMaxConvLds = size_t(160) << 10;   // LDS of a gfx950 compute u
 // hides the staging loads (2048-row chunks with 4x fewer atomics were slower).
 constexpr int kDwRows = 64;
 constexpr int kDwChunk = 256;  // rows per workgroup
-constexpr int kDwPitch = 72;   // 64 rows + 8 pad (bf16)
+constexpr int kDwPitch = 68;   // 64 rows + 4 pad (bf16): 34 dwords, so the transposed stores of a
+                               // wave's 64 channels spread over 16 banks, and rows stay 8-byte aligned
 
 __global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict__ in, int cin,
                                                       const float* __restrict__ dH, const uint16_t* __restrict__ H,
-                                                      float* __restrict__ dW, int64_t rows, int64_t F, int d,
-                                                      int chunk) {
+                                                      float* __restrict__ dW, float* __restrict__ db, int64_t rows,
+                                                      int64_t F, int d, int chunk) {
     __shared__ __align__(16) uint16_t sA[64 * kDwPitch];
     __shared__ __align__(16) uint16_t sD[64 * kDwPitch];
     const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
@@ -442,6 +443,9 @@ __global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict
     for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int delta = d * (i - 2);
     const int F32 = int(F);
+    // the bias gradient (column sums of dA, FP32) comes with the centre tap of the first channel group
+    const bool bias = db && i == 2 && c0 == 0;
+    float dbs = 0.0f;                            // output channel `lane`, this thread's rows
     for (int sub = 0; sub < chunk; sub += kDwRows) {
         const int64_t rbase = int64_t(blockIdx.x) * chunk + sub;
         if (rbase >= rows) break;                // uniform
@@ -457,7 +461,11 @@ __global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict
                 // the tap row r + delta is in r's block when its frame is in [0, F)
                 if (f + delta >= 0 && f + delta < F32) av = in[(r + delta) * cin + c0 + c];
                 const uint16_t hv = H[r * kCh + c];
-                if (hv && !(hv & 0x8000u)) dv = to_bf16(dH[r * kCh + c]);
+                if (hv && !(hv & 0x8000u)) {
+                    const float g = dH[r * kCh + c];
+                    dv = to_bf16(g);
+                    dbs += g;
+                }
             }
             sA[c * kDwPitch + rr] = av;
             sD[c * kDwPitch + rr] = dv;
@@ -483,6 +491,12 @@ __global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict
             const int c = c0 + wave * 16 + 4 * (lane >> 4) + e;
             atomicAdd(&dW[(int64_t(i) * cin + c) * kCh + nt * 16 + (lane & 15)], acc[nt][e]);
         }
+    if (bias) {                                  // uniform over the workgroup
+        __shared__ float sdb[4][64];
+        sdb[wave][lane] = dbs;
+        __syncthreads();
+        if (tid < 64) atomicAdd(&db[tid], sdb[0][tid] + sdb[1][tid] + sdb[2][tid] + sdb[3][tid]);
+    }
 }
 
 // ------------------------------------------------------------------ conv (FP32 reference)
@@ -548,24 +562,6 @@ __global__ void k_conv_dw_ref(const float* __restrict__ in, int cin, const float
 }
 
 // db[o] += sum_r dA[r][o] (bf16 activations)
-// Column sums of dH where the layer output is positive (the bias gradient):
-// 64 rows per workgroup, one atomic per column per workgroup.
-constexpr int kColsumRows = 64;
-
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ dH, const uint16_t* __restrict__ H,
-                                                float* __restrict__ db, int64_t rows) {
-    __shared__ float s[256];
-    const int t = int(threadIdx.x), o = t & 63, part = t >> 6;
-    float acc = 0.0f;
-    const int64_t r0 = int64_t(blockIdx.x) * kColsumRows;
-    for (int64_t r = r0 + part; r < r0 + kColsumRows && r < rows; r += 4) {
-        const uint16_t hv = H[r * kCh + o];
-        if (hv && !(hv & 0x8000u)) acc += dH[r * kCh + o];
-    }
-    s[t] = acc;
-    __syncthreads();
-    if (t < 64) atomicAdd(&db[o], s[t] + s[t + 64] + s[t + 128] + s[t + 192]);
-}
 
 // ------------------------------------------------------------------ head and loss
 __device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
@@ -835,9 +831,7 @@ hipError_t launch_conv_dweight(const void* in, int cin, const float* dH, const v
         const int64_t tasks = int64_t(kTaps) * (cin / 64);
         const int chunk = kDwChunk;
         hipLaunchKernelGGL(k_conv_dw_mfma, dim3(blocks_for(rows, chunk), unsigned(tasks)), dim3(256), 0, st,
-                           (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, rows, F, d, chunk);
-        hipLaunchKernelGGL(k_colsum, dim3(blocks_for(rows, kColsumRows)), dim3(256), 0, st, dH, (const uint16_t*)H,
-                           db, rows);
+                           (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, db, rows, F, d, chunk);
     } else {
         hipLaunchKernelGGL(k_conv_dw_ref, dim3(blocks_for(int64_t(kTaps) * cin * kCh, 256)), dim3(256), 0, st,
                            (const float*)in, cin, dH, (const float*)H, dW, db, rows, F, d);

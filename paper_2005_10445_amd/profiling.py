@@ -164,6 +164,51 @@ def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCE
     return "\n".join(lines) + "\n"
 
 
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP32_VALU_TFLOPS = 157.3
+
+
+def learned_summary(trace_dir: str, cmd: str, batch: int, block_len: int, steps_total: int, warmup: int) -> str:
+    """Per-step kernel times of proposal-network training steps (the timed steps
+    after `warmup`) with algorithmic FLOP rates: convolutions (4 layers, 5 taps,
+    256 -> 64 -> 64 -> 64 -> 64 channels) against the bf16 MFMA peak, the STFT
+    (256-point transform per frame, 5 N log2 N) against the FP32 vector peak."""
+    frames = (block_len - 256) // 128 + 1
+    rows = batch * frames
+    conv_macs = rows * 64 * 5 * (256 + 3 * 64)          # all layers, forward
+    flops = {
+        "k_conv_tile<true>": (2.0 * conv_macs, PEAK_BF16_MFMA_TFLOPS, "forward, 4 layers"),
+        "k_conv_tile<false>": (2.0 * rows * 64 * 5 * 64 * 3, PEAK_BF16_MFMA_TFLOPS, "input gradient, layers 1-3"),
+        "k_conv_dw_mfma": (2.0 * conv_macs, PEAK_BF16_MFMA_TFLOPS, "weight gradient, 4 layers"),
+        "k_head": (6.0 * rows * 64, PEAK_FP32_VALU_TFLOPS, "head forward + backward"),
+        "k_stft": (rows * (5.0 * 256 * 8 + 8.0 * 256), PEAK_FP32_VALU_TFLOPS, "generator + window + 256-point FFT + |X|^2"),
+    }
+    timed = timed_dispatches(trace_dir, warmup, steps_total)
+    steps = steps_total - warmup
+    per_step = {name: sum(d) / steps / 1e3 for name, d in timed.items()}       # microseconds
+    total = sum(per_step.values())
+    lines = ["# rocprofv3 kernel trace of proposal-network training (per step, timed steps only)",
+             f"# command: {cmd}",
+             f"# kernel source hash: {kernel_source_hash(('learned_kernels.hip', 'learned.h', 'cnn.hip'))} "
+             f"(learned_kernels.hip, learned.h, cnn.hip)",
+             f"# batch {batch} blocks of {block_len} samples: {frames} frames each, {rows} rows per step; "
+             f"{steps} timed steps after {warmup} warm-up",
+             "", f"{'kernel':44s} {'calls/step':>10s} {'us/step':>9s} {'share':>6s} {'GFLOP':>8s} {'TFLOP/s':>8s} "
+             f"{'of peak':>8s}  work"]
+    for name, us in sorted(per_step.items(), key=lambda kv: -kv[1]):
+        short = name.replace("void ", "").replace("(anonymous namespace)::", "").split("(")[0].split("::")[-1]
+        calls = len(timed[name]) / steps
+        f = next((v for k, v in flops.items() if short.startswith(k)), None)
+        if f:
+            tf = f[0] / (us * 1e-6) / 1e12
+            lines.append(f"{short:44s} {calls:10.0f} {us:9.1f} {us / total:6.1%} {f[0] / 1e9:8.2f} "
+                         f"{tf:8.1f} {tf / f[1]:8.2%}  {f[2]} (peak {f[1]:.0f} TFLOP/s)")
+        else:
+            lines.append(f"{short:44s} {calls:10.0f} {us:9.1f} {us / total:6.1%}")
+    lines.append(f"{'total':44s} {'':10s} {total:9.1f}")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -191,7 +236,20 @@ def main(argv=None):
     i.add_argument("--kernel", default="k_correlate")
     i.add_argument("--cmd", required=True)
     i.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
+    ls = sub.add_parser("learned")
+    ls.add_argument("trace_dir")
+    ls.add_argument("out")
+    ls.add_argument("--cmd", required=True)
+    ls.add_argument("--batch", type=int, default=8)
+    ls.add_argument("--block-len", type=int, default=1 << 20)
+    ls.add_argument("--warmup", type=int, default=10)
+    ls.add_argument("--steps-total", type=int, default=100)
     a = ap.parse_args(argv)
+    if a.what == "learned":
+        with open(a.out, "w") as f:
+            f.write(learned_summary(a.trace_dir, a.cmd, a.batch, a.block_len, a.steps_total, a.warmup))
+        print(open(a.out).read())
+        return
     if a.what == "issue":
         with open(a.out, "w") as f:
             f.write(issue_summary(a.pmc_dir, a.kernel, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES))
