@@ -372,20 +372,32 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
                 asm volatile("" ::: "memory");    // one input index at a time: no hoisting of later loads
             }
         } else {
+            // two input indices per pass, so that their 4P loads are in flight
+            // together; the P-point DFT over q is a radix-P butterfly, and the
+            // twiddle of phase rho is the rho-th power of exp(+j 2 pi i' / M)
 #pragma unroll 1
-            for (int m = 0; m < 16; ++m) {
-                const int ip = eng.in_index(m);
-                float2 y[PP], tw[PP];
-                products(ip, y);
+            for (int m = 0; m < 16; m += 2) {
+                float2 y[2][PP];
+                int ipv[2];
 #pragma unroll
-                for (int r = 1; r < PP; ++r) tw[r] = a.rootsM[(ip * r) & mmask];
+                for (int h = 0; h < 2; ++h) {
+                    ipv[h] = eng.in_index(m + h);
+                    products(ipv[h], y[h]);
+                }
 #pragma unroll
-                for (int rho = 0; rho < PP; ++rho) {
-                    float2 acc = y[0];
+                for (int h = 0; h < 2; ++h) {
+                    const int ip = ipv[h];
+                    if constexpr (PP > 1) dev::dft_r<PP, +1>(y[h]);
+                    G[ip] = y[h][0];
+                    if constexpr (PP > 1) {
+                        const float2 w1 = a.rootsM[ip];
+                        float2 tw = w1;
 #pragma unroll
-                    for (int q = 1; q < PP; ++q) acc = cadd(acc, cmul(y[q], root8((q * rho * (8 / PP)) & 7)));
-                    if (rho) acc = cmul(acc, tw[rho]);
-                    G[rho * a.Msub + ip] = acc;
+                        for (int rho = 1; rho < PP; ++rho) {
+                            G[rho * a.Msub + ip] = cmul(y[h][rho], tw);
+                            if (rho + 1 < PP) tw = cmul(tw, w1);
+                        }
+                    }
                 }
             }
         }
