@@ -123,6 +123,24 @@ __device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
     return v;
 }
 
+// Powers of this lane's valid outputs (ob + out_off < ulim) that reach the
+// threshold pth.  Only a lane whose largest power bp reaches it has any, so
+// the others skip the count; the powers are formed again exactly as in the
+// maximum, and the per-lane test alone decides validity (no wave-uniform
+// branches, which would hold a scalar mask per register).
+template <class E>
+__device__ __forceinline__ unsigned lane_crossings(const float2 (&v)[16], float bp, float pth, int ob, int ulim) {
+    unsigned lc = 0;
+    if (bp >= pth) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float p = fmaf(v[r].x, v[r].x, v[r].y * v[r].y);
+            lc += (ob + E::out_off(r) < ulim && p >= pth) ? 1u : 0u;
+        }
+    }
+    return lc;
+}
+
 // One work item: (tile of tags, global segment g, bin k, phase rho), item index
 // wi = ((tile * segments + g) * K + k) * spc + rho.
 template <class E, int PREC, bool DUMP>
@@ -196,7 +214,6 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
         // output index, so the strict comparison keeps the smallest lag of a tie
         float bp = -1.0f;
         int boff = 0;
-        unsigned lc = 0;                           // this lane's crossings
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             const int r = E::visit(rr);
@@ -210,11 +227,11 @@ __device__ __forceinline__ void correlate_item(const CorrArgs& a, const E& eng, 
                     }
                 }
                 if (omax + off >= ulim && ob + off >= ulim) p = -1.0f;
-                lc += p >= pth ? 1u : 0u;
                 boff = p > bp ? off : boff;
                 bp = p > bp ? p : bp;
             }
         }
+        const unsigned lc = lane_crossings<E>(v, bp, pth, ob, ulim);
         unsigned cross = 0;
         if (__builtin_amdgcn_ballot_w64(lc != 0)) cross = wave_sum_u32(lc);
         unsigned long long best = bp >= 0.0f

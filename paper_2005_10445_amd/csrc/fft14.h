@@ -67,7 +67,11 @@ struct Fft14 {
     static constexpr int ROW = 68;                  // 64 + 4 pad
     static constexpr int SLICE = 16 * ROW;
     static constexpr int LDS = 16 * SLICE;          // complex elements
-    static constexpr int EXTRA = 256;               // exp(+j 2 pi x / 256) table
+    // B2 twiddles [q][kb1] = exp(+j 2 pi q kb1 / 64) in rows of 17 entries: a
+    // lane reads its row from one base register with immediate offsets, and
+    // the four rows of a lane quad start on distinct LDS banks (rows of 16
+    // put q = 0, 2 and q = 1, 3 on the same banks)
+    static constexpr int EXTRA = 4 * 17;
     // B1 twiddle table entries: [w][k2a][l] = exp(+j 2 pi l (w + 16 k2a) / N)
     static constexpr int B1_TABLE = 16 * 16 * 64;
 
@@ -81,7 +85,7 @@ struct Fft14 {
         l = int(threadIdx.x) & 63;
 #pragma unroll
         for (int m = 0; m < 16; ++m) wu[m] = roots[(w * m * 64) & (N - 1)];
-        if (threadIdx.x < EXTRA) extra[threadIdx.x] = roots[threadIdx.x * (N / EXTRA)];
+        if (threadIdx.x < EXTRA) extra[threadIdx.x] = roots[(((threadIdx.x / 17) * (threadIdx.x % 17)) & 63) * (N / 64)];
     }
 
     // index of the element in input register m
@@ -111,11 +115,18 @@ struct Fft14 {
 #pragma unroll
         for (int k2a = 0; k2a < PRE; ++k2a) tb[k2a] = bload(b1tab, tboff, k2a * 512);
         __syncthreads();                        // every wave is done with the previous transform's slices
-        // X1 write: element (t, k1) -> slice k1, row w, column l
+        // X1 write: element (t, k1) -> slice k1, row w, column l.  Slices 8..15
+        // lie beyond the 64 KiB reach of a DS immediate offset, so they get a
+        // base register of their own (else every store there needs an add).
         {
             float2* p = lds + w * ROW + ln;
+            int hi8 = 8 * SLICE;
+            asm("" : "+s"(hi8));
+            float2* p8 = p + hi8;
 #pragma unroll
-            for (int k1 = 0; k1 < 16; ++k1) p[k1 * SLICE] = v[k1];
+            for (int k1 = 0; k1 < 8; ++k1) p[k1 * SLICE] = v[k1];
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) p8[k1 * SLICE] = v[k1 + 8];
         }
         __syncthreads();
         float2* sl = lds + w * SLICE;
@@ -150,8 +161,13 @@ struct Fft14 {
         }
         // B2
         dft16<S>(v);
+        {
+            int qrow = 17 * q;
+            asm("" : "+v"(qrow));                   // keep the row base in one register
+            const float2* tq = extra + qrow;
 #pragma unroll
-        for (int kb1 = 1; kb1 < 16; ++kb1) v[kb1] = cmul(v[kb1], tw_sign<S>(extra[((q * kb1) & 63) * 4]));
+            for (int kb1 = 1; kb1 < 16; ++kb1) v[kb1] = cmul(v[kb1], tw_sign<S>(tq[kb1]));
+        }
         // X3: (q, kb1) -> column 4 kb1 + ((q + kb1/4) & 3); lane (k2a, p) reads kb1 = 4 p + j
         wave_lds_order();
 #pragma unroll
