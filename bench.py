@@ -182,6 +182,10 @@ def main():
                          "(stream: the 64-block batched stream, eager and graph-replayed; learned: the "
                          "trained proposal network on that stream against the exhaustive search; none)")
     ap.add_argument("--leg-steps", type=int, default=3, help="timed batches per extra leg")
+    ap.add_argument("--max-fraction", type=float, default=0.5,
+                    help="learned leg: full search of a block whose proposals cover more than this fraction")
+    ap.add_argument("--floor-db", type=float, default=1.0,
+                    help="learned leg: full search when the map median leaves the noise floor by more (dB)")
     ap.add_argument("--mode", choices=("bench", "copy"), default="bench",
                     help="copy: a plain 256 MiB device copy, the reference for HBM byte counters")
     args = ap.parse_args()
@@ -445,7 +449,7 @@ def learned_leg(args, plan, xds, blocks, full, ms_exhaustive):
     with open(os.path.join(wdir, "proposal_cnn.json")) as f:
         kappa = float(json.load(f)["kappa"])
     assert params.size == num_params(256)
-    lp = LearnedParams(kappa=kappa, max_fraction=0.5, floor_db=1.0)
+    lp = LearnedParams(kappa=kappa, max_fraction=args.max_fraction, floor_db=args.floor_db)
     with Network("bf16", 256, max_rows=1 << 15, max_block_len=1 << 21) as net:
         net.set_params(params)
         ms, (dets, reps) = _gpu_ms(lambda: net.detect_batch(plan, xds, lp), args.leg_steps)
@@ -456,7 +460,8 @@ def learned_leg(args, plan, xds, blocks, full, ms_exhaustive):
         return any(d.tag == t.tag and d.bin == t.bin and abs(d.lag - t.delay) <= 2 for t in blocks[d.block][1])
     inj = [key(d) for d in full if injected(d)]
     out = {"workload": "batched_stream + proposals", "network": "4 conv1d x 64 channels, k=5, bf16",
-           "kappa": kappa, "ms_per_batch_learned": ms, "ms_per_batch_exhaustive": ms_exhaustive,
+           "kappa": kappa, "max_fraction": args.max_fraction, "floor_db": args.floor_db,
+           "ms_per_batch_learned": ms, "ms_per_batch_exhaustive": ms_exhaustive,
            "speedup": ms_exhaustive / ms,
            "recall_injected": sum(k in lk for k in inj) / max(len(inj), 1), "injected_detections": len(inj),
            "recall_all": len(lk & fk) / max(len(fk), 1), "exhaustive_detections": len(fk),
