@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-  python -m paper_2005_10445_amd.profiling trace  <trace_dir> <out.txt> --cmd "<command>"
+  python -m paper_2005_10445_amd.profiling trace  <trace_dir> <out.txt> --cmd "<command>" [--last N]
   python -m paper_2005_10445_amd.profiling traffic <fetch_dir> <write_dir> <copy_fetch_dir>
          <copy_write_dir> <out.json> --kernel k_correlate --copy-bytes 268435456 --cmd "<command>"
   python -m paper_2005_10445_amd.profiling issue <pmc_dir> <out.txt> --kernel k_correlate --cmd "<command>"
@@ -139,8 +139,20 @@ def timed_dispatches(trace_dir: str, skip_steps: int, steps_total: int):
     return out
 
 
+def last_dispatches(trace_dir: str, n: int):
+    """{kernel: [duration ns]} of each kernel's last n dispatches (kernels
+    launched at least n times): the timed steps of a run whose plan-time tuning
+    launched the same kernels before them."""
+    with open(_find(trace_dir, "kernel_trace.csv")) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    per = defaultdict(list)
+    for r in rows:
+        per[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return {k: d[-n:] for k, d in per.items() if len(d) >= n}
+
+
 def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCES, skip: int = 0,
-                  steps_total: int = 0) -> str:
+                  steps_total: int = 0, last: int = 0) -> str:
     path = _find(trace_dir, "kernel_stats.csv")
     with open(path) as f:
         rows = list(csv.DictReader(f))
@@ -153,7 +165,15 @@ def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCE
         lines.append(f"{name:60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
                      f"{float(r['Percentage']):6.2f}")
-    if skip > 0 and steps_total > skip:
+    if last > 0:
+        timed = last_dispatches(trace_dir, last)
+        lines += ["", f"# timed steps only: the last {last} dispatches of each kernel launched at least "
+                      f"{last} times",
+                  f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}"]
+        for name, d in sorted(timed.items(), key=lambda kv: -sum(kv[1]))[:top]:
+            lines.append(f"{name.replace('void ', '')[:60]:60s} {len(d):6d} {sum(d) / len(d) / 1e3:10.2f} "
+                         f"{min(d) / 1e3:10.2f} {max(d) / 1e3:10.2f}")
+    elif skip > 0 and steps_total > skip:
         timed = timed_dispatches(trace_dir, skip, steps_total)
         lines += ["", f"# timed steps only: {steps_total - skip} of {steps_total} steps, the first {skip} "
                       f"(warm-up) left out",
@@ -219,6 +239,8 @@ def main(argv=None):
     t.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
     t.add_argument("--warmup", type=int, default=0, help="warm-up steps of the profiled run")
     t.add_argument("--steps-total", type=int, default=0, help="warm-up plus timed steps of the profiled run")
+    t.add_argument("--last", type=int, default=0, help="also list each kernel's last N dispatches (timed steps "
+                                                       "after plan-time tuning)")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
@@ -256,7 +278,7 @@ def main(argv=None):
     elif a.what == "trace":
         with open(a.out, "w") as f:
             f.write(trace_summary(a.trace_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES,
-                                  skip=a.warmup, steps_total=a.steps_total))
+                                  skip=a.warmup, steps_total=a.steps_total, last=a.last))
     else:
         res = traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir, a.kernel,
                       a.copy_bytes, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES, last=a.last)
