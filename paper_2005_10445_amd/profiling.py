@@ -102,14 +102,16 @@ CLOCK_HZ = 2.4e9
 VALU_CLOCKS = 4
 
 
-def issue_summary(pmc_dir: str, kernel: str, cmd: str, sources=KERNEL_SOURCES) -> str:
+def issue_summary(pmc_dir: str, kernel: str, cmd: str, sources=KERNEL_SOURCES, last: int = 0) -> str:
     t = counters(pmc_dir)
     name = _pick(t, kernel)
-    means = {c: sum(v) / len(v) for c, v in sorted(t[name].items())}
-    n = len(next(iter(t[name].values())))
+    series = {c: (v[-last:] if last > 0 else v) for c, v in sorted(t[name].items())}
+    means = {c: sum(v) / len(v) for c, v in series.items()}
+    n = len(next(iter(series.values())))
     lines = ["# rocprofv3 instruction counts per dispatch", f"# command: {cmd}",
              f"# kernel source hash: {kernel_source_hash(sources)} ({', '.join(sources)})",
-             f"# kernel: {name.replace('void ', '')[:100]}", f"# dispatches: {n}", ""]
+             f"# kernel: {name.replace('void ', '')[:100]}",
+             f"# dispatches: {n}" + (f" (the last {last})" if last > 0 else ""), ""]
     lines += [f"{c:24s} {v:18.0f}" for c, v in means.items()]
     if "SQ_INSTS_VALU" in means:
         ms = means["SQ_INSTS_VALU"] * VALU_CLOCKS / (NUM_SIMDS * CLOCK_HZ) * 1e3
@@ -139,16 +141,30 @@ def timed_dispatches(trace_dir: str, skip_steps: int, steps_total: int):
     return out
 
 
-def last_dispatches(trace_dir: str, n: int):
-    """{kernel: [duration ns]} of each kernel's last n dispatches (kernels
-    launched at least n times): the timed steps of a run whose plan-time tuning
-    launched the same kernels before them."""
+def last_dispatches(trace_dir: str, n: int, anchor: str = "k_correlate"):
+    """{kernel: [duration ns]} of the dispatches in the timed steps of a run
+    whose plan-time tuning launched the same kernels before them: the window
+    opens at the n-th last dispatch of the anchor kernel (of the kernels whose
+    name contains `anchor`, the one launched last) and runs to the end."""
     with open(_find(trace_dir, "kernel_trace.csv")) as f:
         rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
-    per = defaultdict(list)
+    starts = defaultdict(list)
     for r in rows:
-        per[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    return {k: d[-n:] for k, d in per.items() if len(d) >= n}
+        starts[r["Kernel_Name"]].append(int(r["Start_Timestamp"]))
+    cands = [k for k in starts if anchor in k and len(starts[k]) >= n]
+    if not cands:
+        raise KeyError(anchor)
+    key = max(cands, key=lambda k: starts[k][-1])
+    t0 = starts[key][-n]
+    out = defaultdict(list)
+    for r in rows:
+        if int(r["Start_Timestamp"]) >= t0:
+            out[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def _short(name: str) -> str:
+    return name.replace("void ", "").replace("acq::(anonymous namespace)::", "").replace("acq::", "")
 
 
 def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCES, skip: int = 0,
@@ -161,17 +177,16 @@ def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCE
              f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'pct':>6s}"]
     rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
     for r in rows[:top]:
-        name = r["Name"].replace("void ", "")[:60]
+        name = _short(r["Name"])[:60]
         lines.append(f"{name:60s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
                      f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
                      f"{float(r['Percentage']):6.2f}")
     if last > 0:
         timed = last_dispatches(trace_dir, last)
-        lines += ["", f"# timed steps only: the last {last} dispatches of each kernel launched at least "
-                      f"{last} times",
+        lines += ["", f"# timed steps only: from the {last}-th last dispatch of the correlation kernel on",
                   f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}"]
         for name, d in sorted(timed.items(), key=lambda kv: -sum(kv[1]))[:top]:
-            lines.append(f"{name.replace('void ', '')[:60]:60s} {len(d):6d} {sum(d) / len(d) / 1e3:10.2f} "
+            lines.append(f"{_short(name)[:60]:60s} {len(d):6d} {sum(d) / len(d) / 1e3:10.2f} "
                          f"{min(d) / 1e3:10.2f} {max(d) / 1e3:10.2f}")
     elif skip > 0 and steps_total > skip:
         timed = timed_dispatches(trace_dir, skip, steps_total)
@@ -179,7 +194,7 @@ def trace_summary(trace_dir: str, cmd: str, top: int = 12, sources=KERNEL_SOURCE
                       f"(warm-up) left out",
                   f"{'kernel':60s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}"]
         for name, d in sorted(timed.items(), key=lambda kv: -sum(kv[1]))[:top]:
-            lines.append(f"{name.replace('void ', '')[:60]:60s} {len(d):6d} {sum(d) / len(d) / 1e3:10.2f} "
+            lines.append(f"{_short(name)[:60]:60s} {len(d):6d} {sum(d) / len(d) / 1e3:10.2f} "
                          f"{min(d) / 1e3:10.2f} {max(d) / 1e3:10.2f}")
     return "\n".join(lines) + "\n"
 
@@ -258,6 +273,7 @@ def main(argv=None):
     i.add_argument("--kernel", default="k_correlate")
     i.add_argument("--cmd", required=True)
     i.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
+    i.add_argument("--last", type=int, default=0, help="average only the kernel's last N dispatches")
     ls = sub.add_parser("learned")
     ls.add_argument("trace_dir")
     ls.add_argument("out")
@@ -274,7 +290,8 @@ def main(argv=None):
         return
     if a.what == "issue":
         with open(a.out, "w") as f:
-            f.write(issue_summary(a.pmc_dir, a.kernel, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES))
+            f.write(issue_summary(a.pmc_dir, a.kernel, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES,
+                                  last=a.last))
     elif a.what == "trace":
         with open(a.out, "w") as f:
             f.write(trace_summary(a.trace_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES,
