@@ -81,9 +81,20 @@ __global__ void k_fill_i32(int* p, int64_t count) {
 
 // mean block power from the fixed-order partial sums
 __device__ __forceinline__ double block_mean_power(const double* __restrict__ parts, int64_t n) {
+    // the parts are added in index order; loads go out 32 at a time so that a
+    // single thread does not wait for each one in turn
+    constexpr int kBatch = 32;
     double s = 0.0;
     const int np = power_parts(n);
-    for (int i = 0; i < np; ++i) s += parts[i];
+    int i = 0;
+    for (; i + kBatch <= np; i += kBatch) {
+        double v[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) v[j] = parts[i + j];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) s += v[j];
+    }
+    for (; i < np; ++i) s += parts[i];
     return n > 0 ? s / double(n) : 0.0;
 }
 
