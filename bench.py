@@ -20,7 +20,12 @@ Prints one JSON line on stdout.  Reported beside the throughput:
                  events recorded on the plan's stream during the timed steps,
                  against the FP32 vector peak;
   cpu_baseline : the FP64 CPU oracle (direct definition) on a bounded sample
-                 of tag x bin pairs of the same block, on this host's cores.
+                 of tag x bin pairs of the same block, on this host's cores
+                 (all of them, and one);
+and, for the default workload, the extra legs of --legs: mixed (the block
+with FP16 and with BF16 storage against the FP32 detections), stream (the
+64-block batched stream, eager and graph-replayed) and learned (the trained
+proposal network on that stream against its exhaustive search).
 """
 from __future__ import annotations
 
@@ -177,10 +182,11 @@ def main():
     ap.add_argument("--graph", action="store_true", help="batched workloads: replay one captured hipGraph per step")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time on all host cores, and half of it on one core (0: skip)")
-    ap.add_argument("--legs", default="stream,learned",
+    ap.add_argument("--legs", default="mixed,stream,learned",
                     help="tag-bank workload only: comma-separated extra legs reported in the same line "
-                         "(stream: the 64-block batched stream, eager and graph-replayed; learned: the "
-                         "trained proposal network on that stream against the exhaustive search; none)")
+                         "(mixed: the same block with FP16 and with BF16 storage; stream: the 64-block "
+                         "batched stream, eager and graph-replayed; learned: the trained proposal network "
+                         "on that stream against the exhaustive search; none)")
     ap.add_argument("--leg-steps", type=int, default=3, help="timed batches per extra leg")
     ap.add_argument("--max-fraction", type=float, default=0.5,
                     help="learned leg: full search of a block whose proposals cover more than this fraction")
@@ -327,9 +333,13 @@ def main():
                    "graph": bool((batched or tracking) and args.graph), "parallelism": "single GPU"},
         "roofline": roofline(achieved, corr_avg, flops, traffic_per_launch(args.workload)),
     }
+    ref_dets = plan.detect(xd) if args.workload == "tagbank_fp32" else None
     plan.close()
     if args.workload == "tagbank_fp32":
         legs = [l for l in args.legs.split(",") if l and l != "none"]
+        if "mixed" in legs:
+            out["mixed"] = mixed_leg(args, dev, xd, chips, ref_dets)
+        legs = [l for l in legs if l != "mixed"]
         if legs:
             out.update(bench_stream_legs(args, legs, dev))
     if args.cpu_budget > 0:
@@ -367,6 +377,60 @@ def _gpu_ms(fn, steps):
         r = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps, r
+
+
+def mixed_leg(args, dev, xd, chips, ref_dets):
+    """The tag-bank block with spectra and replicas stored in FP16 and in BF16 (FP32
+    arithmetic, FP64 refinement over +/-8 lags): time per step, the correlation
+    kernel's rate, and the detections against those of the FP32 plan."""
+    import numpy as np
+    import siggen
+    from paper_2005_10445_amd import Plan
+    res = {}
+    for name in ("tagbank_fp16", "tagbank_bf16"):
+        w = siggen.workload(name)
+        bins = dict(num_bins=w["num_bins"], bin_center_hz=w["bin_center_hz"], bin_step_hz=w["bin_step_hz"])
+        N, M = w["block_len"], w["fft_len"]
+        L = w["num_chips"] * w["spc"]
+        with Plan(chips, w["spc"], w["fs_hz"], max_block_len=N, fft_len=M, precision=w["precision"],
+                  refine_radius=w["refine_radius"], **bins) as plan:
+            plan.tune(xd, reps=3)
+            for _ in range(args.warmup):
+                plan.detect_raw(xd)
+            plan.set_profiling(True)
+            corr = []
+            torch_sync()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.detect_raw(xd)
+                corr.append(plan.last_kernel_times()["correlate"])
+            torch_sync()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            plan.set_profiling(False)
+            dets = plan.detect(xd)
+            g = plan.geometry
+        V = g["valid_per_segment"]
+        S = -(-(N - L + 1) // V)
+        T, K = chips.shape[0], w["num_bins"]
+        flops = correlate_flops(T, K, S, M, V)
+        corr_ms = float(np.mean(corr))
+        same = [(d.tag, d.bin, d.lag) for d in dets] == [(d.tag, d.bin, d.lag) for d in ref_dets]
+        res[w["precision"]] = {
+            "ms_per_step": ms, "value": T * K * N / (ms * 1e-3) / 1e6, "unit": "tag*freq*Msample/s",
+            "refine_radius": w["refine_radius"],
+            "roofline": roofline(flops / (corr_ms * 1e-3) / 1e12, corr_ms, flops, traffic_per_launch(name)),
+            "detections": len(dets), "same_detections_as_fp32": same,
+            "max_toa_diff_vs_fp32": (max(abs(a.toa - b.toa) for a, b in zip(dets, ref_dets)) if same and dets
+                                     else None),
+        }
+        log(f"[bench] {w['precision']}: {ms:.3f} ms/step, correlate {corr_ms:.3f} ms, {len(dets)} detections, "
+            f"same as FP32: {same}")
+    return res
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
 
 
 def bench_stream_legs(args, legs, dev):
