@@ -379,8 +379,15 @@ int acq_correlate_power(acq_plan_t plan, const void* block, int64_t n, float* po
  * HIP events on the plan's stream around each kernel they launch; after the
  * call, acq_last_kernel_times writes the durations (milliseconds) in the order
  * ACQ_KERNEL_* below to host `ms[0..n)` and the number of kernels to *count.
- * Kernels a call did not launch report 0.  Off by default.
+ * Kernels a call did not launch, or did not time, report 0.  `on` is
+ * ACQ_PROFILE_OFF (the default), ACQ_PROFILE_ALL (every kernel) or
+ * ACQ_PROFILE_CORRELATE (the correlation kernel only: two events per call,
+ * so the timed calls run closest to unprofiled ones); other values return
+ * ACQ_ERR_INVALID_ARG.
  */
+#define ACQ_PROFILE_OFF        0
+#define ACQ_PROFILE_ALL        1
+#define ACQ_PROFILE_CORRELATE  2
 #define ACQ_KERNEL_BLOCK_POWER 0
 #define ACQ_KERNEL_FORWARD     1
 #define ACQ_KERNEL_CORRELATE   2

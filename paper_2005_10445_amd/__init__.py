@@ -306,8 +306,11 @@ class Plan:
                                                 ctypes.c_void_p(out.data_ptr())), "acq_correlate_power")
         return out
 
-    def set_profiling(self, on: bool = True):
-        check(self._lib.acq_set_profiling(self._h, 1 if on else 0), "acq_set_profiling")
+    def set_profiling(self, on: bool = True, correlate_only: bool = False):
+        """Time the kernels of each call with HIP events on the plan's stream (every
+        kernel, or with correlate_only the correlation kernel alone)."""
+        mode = (_capi.PROFILE_CORRELATE if correlate_only else _capi.PROFILE_ALL) if on else _capi.PROFILE_OFF
+        check(self._lib.acq_set_profiling(self._h, mode), "acq_set_profiling")
 
     def last_kernel_times(self) -> dict:
         """Durations (ms) of the kernels of the last call, from HIP events on the plan's stream."""

@@ -45,6 +45,7 @@ EXPORTED = ("acq_plan_geometry", "acq_workspace_size", "acq_bin_frequencies", "a
 ACQ_SYNTH_MAX_TX = 32
 ACQ_FALLBACK_NONE, ACQ_FALLBACK_FRACTION, ACQ_FALLBACK_FLOOR = 0, 1, 2
 KERNELS = ("block_power", "forward", "correlate", "refine", "compact")
+PROFILE_OFF, PROFILE_ALL, PROFILE_CORRELATE = 0, 1, 2
 
 
 class AcqConfig(ctypes.Structure):

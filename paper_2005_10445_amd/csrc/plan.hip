@@ -88,6 +88,8 @@ struct acq_plan_s {
     bool desc_pending = false;
 
     bool profiling = false;
+    int profile_mode = ACQ_PROFILE_OFF;
+    unsigned profile_mask = 0;            // bit k: time kernel ACQ_KERNEL_k
     bool capturing = false;             // capturing the plan's own batch graph
     bool ext_capture = false;           // the plan's stream is being captured by the caller
     hipEvent_t ev[ACQ_NUM_KERNELS][2] = {};
@@ -306,7 +308,8 @@ struct KernelTimer {
     int id;
     bool on;
     KernelTimer(acq_plan_s* plan, int kernel)
-        : p(plan), id(kernel), on(plan->profiling && !plan->capturing && !plan->ext_capture) {
+        : p(plan), id(kernel),
+          on(plan->profiling && ((plan->profile_mask >> kernel) & 1u) && !plan->capturing && !plan->ext_capture) {
         if (on) {
             (void)hipEventRecord(p->ev[id][0], p->stream);
             p->ev_used[id] = true;
@@ -1061,8 +1064,8 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
     if (!n_out || reps < 1 || capacity < 0 || (capacity > 0 && !out))
         return acq::fail(ACQ_ERR_INVALID_ARG, "bad arguments");
     if (n < p->g.L) return acq::fail(ACQ_ERR_INVALID_ARG, "block shorter than a template");
-    const bool was_profiling = p->profiling;
-    rc = acq_set_profiling(p, 1);
+    const int was_profiling = p->profile_mode;
+    rc = acq_set_profiling(p, ACQ_PROFILE_CORRELATE);          // the tuner times the correlation kernel
     if (rc != ACQ_OK) return rc;
     std::vector<acq_tune_entry> cand;
     const int engines = p->g.log2_sub == 14 ? 2 : 1;
@@ -1144,11 +1147,11 @@ int acq_tune(acq_plan_t p, const void* block, int64_t n, int32_t reps, acq_tune_
     }
     if (rc != ACQ_OK) {
         acq_set_tuning(p, &before);
-        acq_set_profiling(p, was_profiling ? 1 : 0);
+        acq_set_profiling(p, was_profiling);
         return rc;
     }
     acq_set_tuning(p, &chosen);
-    acq_set_profiling(p, was_profiling ? 1 : 0);
+    acq_set_profiling(p, was_profiling);
     *n_out = int32_t(cand.size());
     for (size_t i = 0; i < cand.size() && int32_t(i) < capacity; ++i) out[i] = cand[i];
     acq::clear_error();
@@ -1221,12 +1224,18 @@ int acq_tune_fft_len(const acq_config* cfg, const void* block, int64_t n, int32_
 
 int acq_set_profiling(acq_plan_t p, int on) {
     if (!p) return acq::fail(ACQ_ERR_INVALID_ARG, "null plan");
+    if (on < ACQ_PROFILE_OFF || on > ACQ_PROFILE_CORRELATE)
+        return acq::fail(ACQ_ERR_INVALID_ARG, "profiling mode must be ACQ_PROFILE_OFF, _ALL or _CORRELATE");
     if (on && !p->ev[0][0]) {
         for (auto& pair : p->ev)
             for (hipEvent_t& e : pair) ACQ_HIP(hipEventCreate(&e));
     }
-    p->profiling = on != 0;
+    p->profiling = on != ACQ_PROFILE_OFF;
+    p->profile_mode = on;
+    p->profile_mask = on == ACQ_PROFILE_ALL ? (1u << ACQ_NUM_KERNELS) - 1u
+                      : on == ACQ_PROFILE_CORRELATE ? 1u << ACQ_KERNEL_CORRELATE : 0u;
     reset_timers(p);
+    acq::clear_error();
     return ACQ_OK;
 }
 

@@ -36,6 +36,20 @@ def test_header_symbols_exported(capi):
         assert hasattr(L, name), name
 
 
+def test_header_constants_mirrored(capi):
+    """The binding's copies of the header's constants: profiling modes, kernel
+    timer order, proposal fallbacks."""
+    src = open(os.path.join(ROOT, "include", "acq.h")).read()
+    defs = {k: int(v) for k, v in re.findall(r"^#define\s+ACQ_(\w+)\s+\(?(-?\d+)\)?\s*$", src, flags=re.M)}
+    assert (defs["PROFILE_OFF"], defs["PROFILE_ALL"], defs["PROFILE_CORRELATE"]) == \
+        (capi.PROFILE_OFF, capi.PROFILE_ALL, capi.PROFILE_CORRELATE)
+    assert defs["NUM_KERNELS"] == len(capi.KERNELS)
+    for i, name in enumerate(capi.KERNELS):
+        assert defs["KERNEL_" + name.upper()] == i
+    assert (defs["FALLBACK_NONE"], defs["FALLBACK_FRACTION"], defs["FALLBACK_FLOOR"]) == \
+        (capi.ACQ_FALLBACK_NONE, capi.ACQ_FALLBACK_FRACTION, capi.ACQ_FALLBACK_FLOOR)
+
+
 def _cfg(capi, **over):
     from paper_2005_10445_amd import make_config
     kw = dict(chips=siggen.make_codes(1, 4, 8192), spc=2, fs_hz=8e6, num_bins=11, bin_step_hz=1000.0,

@@ -197,3 +197,27 @@ def test_crossing_counts_match_the_oracle(dev):
             for d in dets:
                 lo, hi = ref[d.tag]["crossings_band"]
                 assert lo <= d.crossings <= hi and d.crossings >= 1, (d.tag, d.crossings, lo, hi)
+
+
+def test_profiling_modes(dev):
+    """Every kernel timed, the correlation kernel alone, or none; the results do
+    not depend on the mode, and modes outside the three are rejected."""
+    from paper_2005_10445_amd import _capi
+    chips, freqs, blocks = _setup(5)
+    x = torch.from_numpy(blocks[0][0]).to(dev)
+    with _plan(chips) as p:
+        ref = [_key(d) for d in p.detect(x)]
+        p.set_profiling(True)
+        assert [_key(d) for d in p.detect(x)] == ref
+        kt = p.last_kernel_times()
+        assert all(kt[k] > 0.0 for k in ("block_power", "forward", "correlate", "refine", "compact")), kt
+        p.set_profiling(True, correlate_only=True)
+        assert [_key(d) for d in p.detect(x)] == ref
+        kt = p.last_kernel_times()
+        assert kt["correlate"] > 0.0
+        assert all(v == 0.0 for k, v in kt.items() if k != "correlate"), kt
+        p.set_profiling(False)
+        assert [_key(d) for d in p.detect(x)] == ref
+        assert all(v == 0.0 for v in p.last_kernel_times().values())
+        for bad in (-1, 3):
+            assert p._lib.acq_set_profiling(p._h, bad) == _capi.ACQ_ERR_INVALID_ARG
