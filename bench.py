@@ -336,7 +336,11 @@ def main():
                    "template_len": L, "fft_len": M, "segments": S, "precision": prec, "tuning": plan.tuning,
                    "graph": bool((batched or tracking) and args.graph), "parallelism": "single GPU"},
         "roofline": roofline(achieved, corr_avg, flops, traffic_per_launch(args.workload)),
+        "device": device_info(),
     }
+    if corr_ms:
+        out["roofline"]["kernel_ms_stats"] = {"min": float(np.min(corr_ms)), "median": float(np.median(corr_ms)),
+                                              "max": float(np.max(corr_ms)), "launches": len(corr_ms)}
     ref_dets = plan.detect(xd) if args.workload == "tagbank_fp32" else None
     plan.close()
     if args.workload == "tagbank_fp32":
@@ -368,6 +372,15 @@ def roofline(achieved, kernel_ms, flops, traffic):
             "kernel": "k_correlate", "kernel_ms": kernel_ms, "flops_per_launch": flops,
             "frac_unpacked_peak": achieved / (0.5 * PEAK_FP32_TFLOPS) if achieved else None,
             "hbm_gbs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS if hbm else None}
+
+
+def device_info():
+    """The GPU and the ROCm build the numbers were taken on."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return {"name": torch.cuda.get_device_name(0), "arch": getattr(props, "gcnArchName", None),
+            "compute_units": props.multi_processor_count, "hbm_gib": round(props.total_memory / 2**30, 1),
+            "hip": torch.version.hip, "torch": torch.__version__}
 
 
 def _gpu_ms(fn, steps):
@@ -637,6 +650,7 @@ def bench_fsk(args, w):
                    "codes_realtime_half_duty": None if tracking else codes_rt, "parallelism": "single GPU"},
         "roofline": dict(roofline(achieved, corr_avg, flops, traffic_per_launch(args.workload)),
                          kernel="k_fsk_correlate"),
+        "device": device_info(),
     }
     if args.cpu_budget > 0 and not tracking:
         log("[bench] cpu baseline ...")
