@@ -102,6 +102,7 @@ struct FrontArgs {
     float* out_u;               // block: u at the block's zoff
     int64_t n_in, n_out, out_stride;     // replica mode
     double lo_cyc;              // f_LO / Fs
+    float2 lo_step[16];         // exp(-j 2 pi (f_LO / Fs) (NT m)), m < 16 (FP64, rounded once)
     double f1_cyc, f0_cyc;      // tones, cycles per sample
     int32_t nbits, sps, lg, vf, nseg, replica;   // nseg: segments per replica
 };
@@ -130,27 +131,42 @@ __global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
     }
     const int64_t base = int64_t(s) * a.vf - (a.lg - 1);
     float2 x[16];
+    if (a.replica) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int64_t p = base + eng.in_index(m);
-        float2 v = make_float2(0.f, 0.f);
-        if (p >= 0 && p < n_in) {
-            double cyc;
-            if (a.replica) {
+        for (int m = 0; m < 16; ++m) {
+            const int64_t p = base + eng.in_index(m);
+            float2 v = make_float2(0.f, 0.f);
+            if (p >= 0 && p < n_in) {
                 const int64_t b = p / a.sps;
                 const size_t bi = size_t(tag) * size_t(a.nbits) + size_t(b);
-                cyc = a.bit_cyc[bi] + (a.bits[bi] ? a.f1_cyc : a.f0_cyc) * double(p - b * a.sps);
-                v = make_float2(1.f, 0.f);
-            } else {
-                v = make_float2(float(iq[2 * p]), float(iq[2 * p + 1]));
-                cyc = -a.lo_cyc * double(p);
+                double cyc = a.bit_cyc[bi] + (a.bits[bi] ? a.f1_cyc : a.f0_cyc) * double(p - b * a.sps);
+                cyc -= floor(cyc);                          // exact phase reduction in FP64
+                float sn, cs;
+                sincospif(2.0f * float(cyc), &sn, &cs);
+                v = make_float2(cs, sn);
             }
-            cyc -= floor(cyc);                              // exact phase reduction in FP64
-            float sn, cs;
-            sincospif(2.0f * float(cyc), &sn, &cs);
-            v = make_float2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+            x[m] = v;
         }
-        x[m] = v;
+    } else {
+        // LO mix exp(-j 2 pi f_LO p / Fs) at p = p0 + NT m: the phase of p0 is
+        // reduced exactly in FP64 once per thread, and register m rotates it
+        // by the constant lo_step[m]
+        const int64_t p0 = base + eng.in_index(0);
+        double cyc = -a.lo_cyc * double(p0);
+        cyc -= floor(cyc);
+        float sn0, cs0;
+        sincospif(2.0f * float(cyc), &sn0, &cs0);
+        const float2 e0 = make_float2(cs0, sn0);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int64_t p = base + eng.in_index(m);
+            float2 v = make_float2(0.f, 0.f);
+            if (p >= 0 && p < n_in) {
+                const float2 e = m ? cmul(e0, a.lo_step[m]) : e0;
+                v = cmul(make_float2(float(iq[2 * p]), float(iq[2 * p + 1])), e);
+            }
+            x[m] = v;
+        }
     }
     const __amdgpu_buffer_rsrc_t dummy = make_rsrc(a.roots, 8);   // unused by the Stockham engine
     eng.template transform<-1>(x, lds, dummy, nullptr);
@@ -942,6 +958,14 @@ hipError_t launch_front(acq_fsk_plan_s* p, const acq::FskTasks& tasks, int fsegs
     a.n_out = p->g.nt;
     a.out_stride = p->g.M;
     a.lo_cyc = c.lo_hz / c.sample_rate_hz;
+    {
+        using E = acq::kdev::StockhamEngine<acq::kFrontLog>;
+        for (int m = 0; m < 16; ++m) {
+            double cyc = -a.lo_cyc * double(int64_t(E::NT) * m);
+            cyc -= std::floor(cyc);
+            a.lo_step[m] = make_float2(float(std::cos(2.0 * M_PI * cyc)), float(std::sin(2.0 * M_PI * cyc)));
+        }
+    }
     a.f1_cyc = c.f1_hz / c.sample_rate_hz;
     a.f0_cyc = c.f0_hz / c.sample_rate_hz;
     a.nbits = c.num_bits;
