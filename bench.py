@@ -580,7 +580,8 @@ def bench_fsk(args, w):
         iq = None
         plan = FskPlan(bits, fs, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], N * len(tasks),
                        max_track_tasks=len(tasks))
-        run = lambda: len(plan.track(tasks))          # noqa: E731
+        task_arr = plan.task_array(tasks)
+        run = lambda: plan.track_raw(task_arr)         # noqa: E731
         total_samples = N * len(tasks)
     else:
         iq, txs = siggen.make_fsk_block(seed + 1, N, bits, w["sps"], fs, w["f1_hz"], w["f0_hz"], w["lo_hz"],

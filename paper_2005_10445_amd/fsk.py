@@ -126,12 +126,28 @@ class FskPlan:
         return [FskDetection(d.tag, d.lag, d.toa_samples, d.xcorr, d.q, d.p, d.z, d.flags, d.block)
                 for d in self._out[:nf.value]]
 
-    def track(self, tasks) -> List[FskDetection]:
-        """acq_fsk_track over (int16 [n, 2] device tensor, tag) pairs; detection.block = task index."""
+    @staticmethod
+    def task_array(tasks):
+        """acq_fsk_task array of (int16 [n, 2] device tensor, tag) pairs (the tensors must stay alive)."""
         arr = (_capi.AcqFskTask * len(tasks))()
         for i, (iq, tag) in enumerate(tasks):
             ptr, n = _iq_ptr(iq)
             arr[i] = _capi.AcqFskTask(ptr, n, int(tag), 0)
+        return arr
+
+    def track_raw(self, arr) -> int:
+        """acq_fsk_track on a prebuilt task_array, without building Python records (for
+        timing); returns the count."""
+        n = len(arr)
+        if getattr(self, "_track_out", None) is None or len(self._track_out) < n:
+            self._track_out = (_capi.AcqFskDetection * n)()
+        nf = ctypes.c_int32(0)
+        check(self._lib.acq_fsk_track(self._h, arr, n, self._track_out, n, ctypes.byref(nf)), "acq_fsk_track")
+        return nf.value
+
+    def track(self, tasks) -> List[FskDetection]:
+        """acq_fsk_track over (int16 [n, 2] device tensor, tag) pairs; detection.block = task index."""
+        arr = self.task_array(tasks)
         out = (_capi.AcqFskDetection * len(tasks))()
         nf = ctypes.c_int32(0)
         check(self._lib.acq_fsk_track(self._h, arr, len(tasks), out, len(tasks), ctypes.byref(nf)), "acq_fsk_track")

@@ -265,6 +265,10 @@ def test_tracking_tasks(dev):
     with _plan(case, bits, bp, max_track_tasks=8) as plan:
         got = plan.track([(dev_blocks[b], t) for b, t in tasks])
         searched = [plan.detect(x) for x in dev_blocks[:-1]]
+        # the same call on a prebuilt task array leaves the same records
+        n_raw = plan.track_raw(plan.task_array([(dev_blocks[b], t) for b, t in tasks]))
+        raw = [(r.block, r.tag, r.lag, r.toa_samples, r.xcorr) for r in plan._track_out[:n_raw]]
+    assert raw == [(d.block, d.tag, d.lag, d.toa, d.xcorr) for d in got]
     assert [d.block for d in got] == list(range(len(tasks) - 1))       # the short block yields nothing
     for d, (b, t) in zip(got, tasks):
         s = searched[b][t]
