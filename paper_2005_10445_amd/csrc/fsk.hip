@@ -109,8 +109,10 @@ struct FrontArgs {
 
 // One workgroup per (template, segment) of the replicas or per global segment
 // of the blocks: outputs s*vf .. s*vf + vf - 1 of the causal convolution with
-// the composed filters, from inputs s*vf - (lg-1) ..
-__global__ __launch_bounds__(256) void k_fsk_front(FrontArgs a) {
+// the composed filters, from inputs s*vf - (lg-1) ..  Three workgroups per CU
+// (at most 168 VGPRs: the forward spectrum stays in registers through the
+// first inverse transform; at 128 it spills and runs slower).
+__global__ __launch_bounds__(256, 3) void k_fsk_front(FrontArgs a) {
     using E = StockhamEngine<kFrontLog>;
     __shared__ float2 lds[E::LDS];
     E eng;
