@@ -131,9 +131,12 @@ hipError_t launch_block_power(const BlockTable& bt, int max_blocks, int64_t max_
 // table: exps[b] = round(log2(sqrt(M * Pxhat_b))) (the 16-bit storage
 // prescale), pthr[b] = theta_b * L * Pxhat_b (+inf when Pxhat_b is 0 or not
 // finite), bad[b] = 1 when Pxhat_b is not finite (some sample is NaN or
-// infinite); nbad[0] receives the number of such blocks.  One workgroup.
+// infinite); nbad[0] receives the number of such blocks (workgroup 0).  The
+// same launch also clears the search's per-(block, tag) peak keys and
+// crossing counts, nclear of each (two launches fewer per search).
 hipError_t launch_block_stats(const BlockTable& bt, const double* parts, int M, int64_t L, int* exps, float* pthr,
-                              int32_t* bad, int32_t* nbad, hipStream_t st);
+                              int32_t* bad, int32_t* nbad, unsigned long long* keys, unsigned* cross,
+                              int64_t nclear, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, hipStream_t st);
 // grid: workgroups of the sub-transforms (items = segments * spc); combine_slots:

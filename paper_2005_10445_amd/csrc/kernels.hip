@@ -105,14 +105,24 @@ __device__ __forceinline__ double block_mean_power(const double* __restrict__ pa
 // Pxhat (the z >= theta test on FP32 powers); and whether the block holds a
 // non-finite sample (then Pxhat is not finite: |x|^2 of a finite complex64
 // value cannot overflow FP64 and every term is >= 0, so no cancellation).
-// One workgroup strides over the blocks and counts the non-finite ones.
+// Workgroup 0 strides over the blocks and counts the non-finite ones; every
+// workgroup of the launch also clears a share of the search's peak keys and
+// crossing counts.
 constexpr int kStatsThreads = 256;
 
 __global__ __launch_bounds__(kStatsThreads) void k_block_stats(BlockTable bt, const double* __restrict__ parts, int M,
                                                                int64_t L, int* __restrict__ exps,
                                                                float* __restrict__ pthr, int32_t* __restrict__ bad,
-                                                               int32_t* __restrict__ nbad) {
+                                                               int32_t* __restrict__ nbad,
+                                                               unsigned long long* __restrict__ keys,
+                                                               unsigned* __restrict__ cross, int64_t nclear) {
     __shared__ int s_bad;
+    for (int64_t i = int64_t(blockIdx.x) * kStatsThreads + threadIdx.x; i < nclear;
+         i += int64_t(gridDim.x) * kStatsThreads) {
+        keys[i] = 0ull;
+        cross[i] = 0u;
+    }
+    if (blockIdx.x != 0) return;             // workgroup 0 forms the statistics
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const int nb = bt.nblocks();
@@ -545,8 +555,12 @@ hipError_t launch_block_power(const BlockTable& bt, int max_blocks, int64_t max_
 }
 
 hipError_t launch_block_stats(const BlockTable& bt, const double* parts, int M, int64_t L, int* exps, float* pthr,
-                              int32_t* bad, int32_t* nbad, hipStream_t st) {
-    hipLaunchKernelGGL(k_block_stats, dim3(1), dim3(kStatsThreads), 0, st, bt, parts, M, L, exps, pthr, bad, nbad);
+                              int32_t* bad, int32_t* nbad, unsigned long long* keys, unsigned* cross,
+                              int64_t nclear, hipStream_t st) {
+    // workgroup 0 forms the statistics; all of them clear, 2048 entries each
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(256, (nclear + 2047) / 2048));
+    hipLaunchKernelGGL(k_block_stats, dim3(unsigned(grid)), dim3(kStatsThreads), 0, st, bt, parts, M, L, exps, pthr,
+                       bad, nbad, keys, cross, nclear);
     return hipGetLastError();
 }
 

@@ -358,9 +358,9 @@ int enqueue_search(acq_plan_s* p, const Scratch& w, const BlockTable& bt, bool b
         KernelTimer kt(p, ACQ_KERNEL_BLOCK_POWER);
         ACQ_HIP(acq::launch_block_power(bt, nb_grid, c.max_block_len, w.parts, st));
     }
-    ACQ_HIP(acq::launch_block_stats(bt, w.parts, int(g.M), g.L, w.exps, w.pthr, w.bad, w.count + 1, st));
-    ACQ_HIP(acq::launch_fill_u64(w.keys, int64_t(nb_grid) * c.num_tags, st));
-    ACQ_HIP(acq::launch_fill_i32(reinterpret_cast<int*>(w.cross), int64_t(nb_grid) * c.num_tags, st));
+    // block statistics; the same launch clears the peak keys and crossing counts
+    ACQ_HIP(acq::launch_block_stats(bt, w.parts, int(g.M), g.L, w.exps, w.pthr, w.bad, w.count + 1, w.keys, w.cross,
+                                    int64_t(nb_grid) * c.num_tags, st));
 
     acq::FwdArgs fa{};
     fa.blocks = bt;
