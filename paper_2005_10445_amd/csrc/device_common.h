@@ -17,10 +17,32 @@ using dev::cmulc;
 using dev::Fft;
 using dev::dft16;
 
+// One step of a wave sum: each lane adds the value DPP control CTRL routes to
+// it (lanes with no source, or in rows outside ROW_MASK, add +0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add_step(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, ROW_MASK, 0xf, true);
+    return v + __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(unsigned(hi)) << 32) |
+                                                          unsigned(lo)));
+}
+
+// Sum over the wave in a fixed order (uniform result, no LDS): row_shr 1, 2,
+// 4, 8 leave each 16-lane row's sum in its lane 15; row_bcast 15 (into rows 1
+// and 3) and row_bcast 31 (into rows 2 and 3) carry the total to lane 63, each
+// lane's value counted once.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = dpp_add_step<0x111, 0xf>(v);
+    v = dpp_add_step<0x112, 0xf>(v);
+    v = dpp_add_step<0x114, 0xf>(v);
+    v = dpp_add_step<0x118, 0xf>(v);
+    v = dpp_add_step<0x142, 0xa>(v);
+    v = dpp_add_step<0x143, 0xc>(v);
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(b)), 63));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(b >> 32)), 63));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
 // One step of a wave maximum: each lane takes the larger of its value and the
