@@ -284,9 +284,14 @@ def main():
 
     for _ in range(args.warmup):
         run()
-    # the timed steps record events around the correlation kernel only (two per
-    # step); one more step with every kernel timed gives the rest for the log
+    # one untimed step with every kernel timed gives the per-kernel figures for
+    # the log; the timed steps record events around the correlation kernel
+    # only (two per step)
     profiled = not ((batched or tracking) and args.graph)
+    if profiled:
+        plan.set_profiling(True)
+        run()
+        kt_all = plan.last_kernel_times()
     plan.set_profiling(profiled, correlate_only=True)
     corr_ms = []
     torch.cuda.synchronize()
@@ -298,10 +303,6 @@ def main():
             corr_ms.append(plan.last_kernel_times()["correlate"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if profiled:
-        plan.set_profiling(True)
-        run()
-        kt_all = plan.last_kernel_times()
     plan.set_profiling(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = T_eff * K * samples / (ms_per_step * 1e-3) / 1e6

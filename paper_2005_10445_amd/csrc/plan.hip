@@ -421,16 +421,17 @@ int enqueue_search(acq_plan_s* p, const Scratch& w, const BlockTable& bt, bool b
     int grid;
     if (track) {
         // bins per work item: enough items to give every compute unit about
-        // four, each amortising its setup over as many bins as that allows
-        // (256 tasks x 21 bins: 7 bins per item, 0.89 ms; eight per CU gave
-        // 5 bins per item and 0.97 ms).  The choice follows this batch's
+        // two, each amortising its setup (the task's replica spectrum, the
+        // item's addressing) over as many bins as that allows (256 tasks x 21
+        // bins: all 21 bins per item, 0.421 ms; four items per CU gave 7 bins
+        // per item and 0.430 ms, 11 bins 0.437 ms).  The choice follows this batch's
         // segments (for a captured graph, those of the batch it was captured
         // on), while a captured graph sizes its grid for the plan's capacity.
         const int64_t segs = p->capturing ? int64_t(g.max_total_segments) : int64_t(total_seg_host);
         int bins = p->track_bins;
         if (bins <= 0) {
             const int64_t per_bin = int64_t(total_seg_host) * c.samples_per_chip;
-            const int64_t want = int64_t(4) * p->cus;
+            const int64_t want = int64_t(2) * p->cus;
             bins = int(std::max<int64_t>(1, std::min<int64_t>(c.num_bins, per_bin * c.num_bins / want)));
             const int ntl = (c.num_bins + bins - 1) / bins;      // even tiles
             bins = (c.num_bins + ntl - 1) / ntl;
