@@ -172,7 +172,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before the timed ones (default 50; 1 for the batched stream, whose "
+                         "steps take a second): short steps need that many before the GPU's clocks settle")
     ap.add_argument("--workload", default="tagbank_fp32")
     ap.add_argument("--fft-len", type=int, default=0, help="override the workload's segment length")
     ap.add_argument("--tag-tile", type=int, default=0)
@@ -216,6 +218,8 @@ def main():
     from paper_2005_10445_amd import Plan, bin_frequencies
 
     w = siggen.workload(args.workload)
+    if args.warmup is None:
+        args.warmup = 1 if "num_blocks" in w else 50
     if "num_bits" in w:
         return bench_fsk(args, w)
     batched = "num_blocks" in w
