@@ -59,6 +59,8 @@ struct acq_cnn_s {
 
     void* act[kLayers + 1] = {};    // act[0]: map [rows][cin]; act[l]: layer l output [rows][64]
     float* dH[2] = {};              // [rows][64] FP32 gradients (ping-pong)
+    float* dw_part = nullptr;       // [dw_part_elems] weight-gradient chunk sums
+    int64_t dw_part_elems = 0;
     float* y = nullptr;             // [rows] logits
     float* labels = nullptr;        // [rows]
     float* P = nullptr;             // [rows][256] STFT powers
@@ -87,8 +89,8 @@ namespace {
 void free_cnn(acq_cnn_s* c) {
     if (!c) return;
     void* dev[] = {c->theta, c->grad, c->m, c->v, c->w_bf, c->wt_bf, c->act[0], c->act[1], c->act[2], c->act[3],
-                   c->act[4], c->dH[0], c->dH[1], c->y, c->labels, c->P, c->hist, c->mstate, c->med, c->hann,
-                   c->tw, c->loss, c->d_tx, c->d_ntx, c->wscore, c->d_info};
+                   c->act[4], c->dH[0], c->dH[1], c->dw_part, c->y, c->labels, c->P, c->hist, c->mstate, c->med,
+                   c->hann, c->tw, c->loss, c->d_tx, c->d_ntx, c->wscore, c->d_info};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     void* host[] = {c->h_tx, c->h_ntx, c->h_info, c->h_scalar};
@@ -113,6 +115,10 @@ int build_cnn(acq_cnn_s* c) {
     for (int l = 1; l <= kLayers; ++l) CNN_HIP(hipMalloc(&c->act[l], rows * kCh * es));
     CNN_HIP(dalloc(&c->dH[0], rows * kCh));
     CNN_HIP(dalloc(&c->dH[1], rows * kCh));
+    if (c->bf) {
+        c->dw_part_elems = std::max(dweight_part_elems(c->cfg.in_channels), dweight_part_elems(kCh));
+        CNN_HIP(dalloc(&c->dw_part, size_t(c->dw_part_elems)));
+    }
     CNN_HIP(dalloc(&c->y, rows));
     CNN_HIP(dalloc(&c->labels, rows));
     CNN_HIP(dalloc(&c->P, rows * kWin));
@@ -185,7 +191,8 @@ int run_backward(acq_cnn_s* c, const void* in, int32_t nblocks, int64_t F, const
     for (int l = kLayers - 1; l >= 0; --l) {
         const void* x = l == 0 ? in : c->act[l];
         CNN_HIP(launch_conv_dweight(x, c->lay.cin[l], c->dH[cur], c->act[l + 1], c->grad + c->lay.w_off[l],
-                                    c->grad + c->lay.b_off[l], rows, F, kDilation[l], c->bf, st));
+                                    c->grad + c->lay.b_off[l], c->dw_part, c->dw_part_elems, rows, F,
+                                    kDilation[l], c->bf, st));
         if (l > 0) {
             const void* w = c->bf ? static_cast<const void*>(c->w_bf + c->lay.bf_off[l])
                                   : static_cast<const void*>(c->theta + c->lay.w_off[l]);

@@ -85,9 +85,13 @@ hipError_t launch_conv_forward(const void* in, int cin, const void* wt, const fl
 hipError_t launch_conv_dinput(const float* dH, const void* H, const void* w, float* dprev, int64_t rows,
                               int64_t F, int d, bool bf16, hipStream_t st);
 // Weight and bias gradients (accumulated): dW[i][c][o] += sum_r in[r + d(i-2)][c] dA[r][o],
-// db[o] += sum_r dA[r][o].
+// db[o] += sum_r dA[r][o].  The bf16 form sums row chunks into `part` (FP32, at least
+// dweight_part_elems(cin) values; unused by the FP32 form) and adds the chunk sums
+// to dW and db in a fixed order.
+int64_t dweight_part_elems(int cin);
 hipError_t launch_conv_dweight(const void* in, int cin, const float* dH, const void* H, float* dW, float* db,
-                               int64_t rows, int64_t F, int d, bool bf16, hipStream_t st);
+                               float* part, int64_t part_elems, int64_t rows, int64_t F, int d, bool bf16,
+                               hipStream_t st);
 // Head logits y[r] = bh + h4[r] . wh; with labels also the loss terms and
 // dH4 = dy wh^T, dwh += h4^T dy, dbh += sum dy, loss_sum += sum of losses.
 hipError_t launch_head(const void* h4, const float* theta, int64_t wh_off, float* y, const float* labels,

@@ -7,9 +7,11 @@
 //   k_hist/k_select   exact lower median of a block's F*256 powers: radix
 //                     selection over the FP32 bit patterns (11 + 10 + 10 bits)
 //   k_map             ln(P / median), stored bf16 (or FP32)
-//   k_conv_*_mfma     dilated conv layers as implicit GEMMs on bf16 MFMA
-//                     (v_mfma_f32_16x16x16_bf16, FP32 accumulation): forward,
-//                     input gradient, weight gradient
+//   k_conv_tile       dilated conv layers as implicit GEMMs on bf16 MFMA
+//                     (v_mfma_f32_16x16x32_bf16, FP32 accumulation): forward and
+//                     input gradient
+//   k_conv_dw_taps    weight gradient, all taps of a channel group per workgroup,
+//                     on the same MFMA; k_dw_reduce adds the row-chunk sums
 //   k_conv_*_ref      the same products in FP32 FMA, one output per thread
 //                     (reference arithmetic for tests)
 //   k_head            1x1 head, weighted BCE with logits and its gradient
@@ -416,86 +418,263 @@ __host__ __device__ constexpr size_t conv_tile_lds(int K, int d) {
 }
 constexpr size_t kMaxConvLds = size_t(160) << 10;   // LDS of a gfx950 compute unit
 
-// Weight gradient on v_mfma_f32_16x16x16_bf16 (lane l: A[row l%16][k 4(l/16)+e],
-// B[k 4(l/16)+e][col l%16], D[row 4(l/16)+e][col l%16], e < 4), one tap and 64
-// input channels over a chunk of rows
-// (`chunk`, a multiple of 64): dW[i][c][o] += sum_r in[r + d(i-2)][c] dA[r][o].
-// Each 64-row piece is staged in LDS transposed ([channel][row]) so both MFMA
-// operands are 8-byte reads; the sums stay in registers over the chunk and are
-// added to dW once.  Short chunks keep many workgroups resident per CU, which
-// hides the staging loads (2048-row chunks with 4x fewer atomics were slower).
+// Weight gradient dW[i][c][o] += sum_r in[r + d(i-2)][c] dA[r][o] (dA = dH where the
+// layer output is positive) on v_mfma_f32_16x16x32_bf16 (lane l: A[row l%16][k
+// 8(l/16)+e], B[k 8(l/16)+e][col l%16], e < 8; D[row 4(l/16)+e][col l%16], e < 4),
+// all five taps of 64 input channels in one workgroup.  Rows come in 64-row
+// pieces: the piece's dA rows and the input rows it reaches (2D before, 2D after)
+// are staged once in LDS, transposed to [channel][row] so that an operand's 8
+// consecutive rows are one read, and every tap reads the input tile at its own
+// row shift D*i.  Wave w holds the 16 channels 16w.. of every tap and output
+// channel (20 accumulator tiles); the sums stay in registers over the chunk and
+// are stored once as the chunk's sums, which k_dw_reduce adds up in a fixed
+// order (atomic adds of every chunk's sums cost more than the products).  A pair (r, r + D(i-2)) whose rows lie in different
+// blocks contributes nothing: pieces with no block start near them need no
+// test, the others clear those operand rows tap by tap.
 constexpr int kDwRows = 64;
-constexpr int kDwChunk = 256;  // rows per workgroup
-constexpr int kDwPitch = 68;   // 64 rows + 4 pad (bf16): 34 dwords, so the transposed stores of a
-                               // wave's 64 channels spread over 16 banks, and rows stay 8-byte aligned
+constexpr int kDwPitchD = 72;    // dA tile row: 64 rows + 8 pad (bf16), 36 dwords = 4 x odd
+constexpr int kDwPitchI = 104;   // input tile row: 64 + 4 * 8 rows + 8 pad, 52 dwords = 4 x odd, so
+                                 // the 16 channels of an operand read fall on distinct banks
+constexpr int kDwXcds = 8;       // workgroups go to the XCDs in turn
+constexpr int kDwWgs = 256;      // workgroups per call (one per CU): sets the rows per workgroup
+constexpr int kDwBlock = kTaps * 64 * kCh;   // sums of one chunk and 64-channel group
 
-__global__ __launch_bounds__(256) void k_conv_dw_mfma(const uint16_t* __restrict__ in, int cin,
-                                                      const float* __restrict__ dH, const uint16_t* __restrict__ H,
-                                                      float* __restrict__ dW, float* __restrict__ db, int64_t rows,
-                                                      int64_t F, int d, int chunk) {
-    __shared__ __align__(16) uint16_t sA[64 * kDwPitch];
-    __shared__ __align__(16) uint16_t sD[64 * kDwPitch];
-    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
-    const int i = int(blockIdx.y) % kTaps, c0 = (int(blockIdx.y) / kTaps) * 64;
-    const int kq = 4 * (lane >> 4);
-    f32x4 acc[4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int delta = d * (i - 2);
-    const int F32 = int(F);
-    // the bias gradient (column sums of dA, FP32) comes with the centre tap of the first channel group
-    const bool bias = db && i == 2 && c0 == 0;
-    float dbs = 0.0f;                            // output channel `lane`, this thread's rows
-    for (int sub = 0; sub < chunk; sub += kDwRows) {
-        const int64_t rbase = int64_t(blockIdx.x) * chunk + sub;
-        if (rbase >= rows) break;                // uniform
-        // frame of this thread's first row (rows rbase + 4e + wave, e < 16), then stepped
-        int f = int(rbase % F) + wave;
-        while (f >= F32) f -= F32;
-#pragma unroll 4
-        for (int e = 0; e < 16; ++e) {
-            const int rr = 4 * e + wave, c = lane;
-            const int64_t r = rbase + rr;
-            uint16_t av = 0, dv = 0;
-            if (r < rows) {
-                // the tap row r + delta is in r's block when its frame is in [0, F)
-                if (f + delta >= 0 && f + delta < F32) av = in[(r + delta) * cin + c0 + c];
-                const uint16_t hv = H[r * kCh + c];
-                if (hv && !(hv & 0x8000u)) {
-                    const float g = dH[r * kCh + c];
-                    dv = to_bf16(g);
-                    dbs += g;
-                }
-            }
-            sA[c * kDwPitch + rr] = av;
-            sD[c * kDwPitch + rr] = dv;
-            f += 4;
-            while (f >= F32) f -= F32;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < 64; ks += 16) {
-            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&sA[(wave * 16 + (lane & 15)) * kDwPitch + ks + kq]);
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sD[(nt * 16 + (lane & 15)) * kDwPitch + ks + kq]);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
-            }
-        }
-        __syncthreads();
+// 8 bf16 of LDS row `p` starting SHIFT elements past a 16-byte boundary
+template <int SHIFT>
+__device__ __forceinline__ uint4 lds_row8(const uint16_t* p) {
+    p += (SHIFT / 8) * 8;
+    constexpr int s = SHIFT % 8;
+    if constexpr (s == 0) {
+        return *reinterpret_cast<const uint4*>(p);
+    } else if constexpr (s % 4 == 0) {
+        const uint2* q = reinterpret_cast<const uint2*>(p) + s / 4;
+        const uint2 a = q[0], b = q[1];
+        return uint4{a.x, a.y, b.x, b.y};
+    } else if constexpr (s % 2 == 0) {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(p) + s / 2;
+        return uint4{q[0], q[1], q[2], q[3]};
+    } else {                                     // odd: five dwords, each pair funnel-shifted by 16 bits
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(p) + s / 2;
+        const uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3], w4 = q[4];
+        return uint4{__builtin_amdgcn_alignbit(w1, w0, 16), __builtin_amdgcn_alignbit(w2, w1, 16),
+                     __builtin_amdgcn_alignbit(w3, w2, 16), __builtin_amdgcn_alignbit(w4, w3, 16)};
     }
+}
+
+template <int D>
+__global__ __launch_bounds__(256, 2) void k_conv_dw_taps(const uint16_t* __restrict__ in, int cin,
+                                                      const float* __restrict__ dH, const uint16_t* __restrict__ H,
+                                                      float* __restrict__ part, float* __restrict__ pdb, int64_t rows,
+                                                      int64_t F, int chunk, int nchunks) {
+    static_assert(64 + 4 * D + 8 <= kDwPitchI, "input tile row too short for the dilation");
+    __shared__ __align__(16) uint16_t sD[64 * kDwPitchD];
+    __shared__ __align__(16) uint16_t sI[64 * kDwPitchI];
+    __shared__ float sdb[16][64];
+    const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+    // workgroup -> (chunk, channel group); the groups of one chunk share an XCD and its L2
+    const int ngroups = cin / 64;
+    const int wg = int(blockIdx.x), s = wg / kDwXcds;
+    const int ck = (s / ngroups) * kDwXcds + wg % kDwXcds, c0 = (s % ngroups) * 64;
+    if (ck >= nchunks) return;                   // uniform: padding of the grid
+    const bool bias = pdb && c0 == 0;
+    // staging: thread -> 4 consecutive rows (j) x 4 consecutive channels (q)
+    const int j = tid >> 4, q = tid & 15;
+    float dbs[4] = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[kTaps][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int i = 0; i < kTaps; ++i)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int F32 = int(F);
+    const int64_t rend = min(rows, int64_t(ck + 1) * chunk);
+    // one piece's staging loads, held in registers so that the next piece's are
+    // in flight while this one's products run: dA rows rb + 4j + e, channels 4q..;
+    // input row groups j and j + 16 (rows rb - 2D + 4jj + e; zero outside [0, rows))
+    float4 pg[4];
+    uint2 ph[4], px[2][4];
+    auto fetch = [&](int64_t rb) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int c = c0 + wave * 16 + 4 * (lane >> 4) + e;
-            atomicAdd(&dW[(int64_t(i) * cin + c) * kCh + nt * 16 + (lane & 15)], acc[nt][e]);
+            const int64_t r = rb + 4 * j + e;
+            pg[e] = float4{0.f, 0.f, 0.f, 0.f};
+            ph[e] = uint2{0u, 0u};
+            if (r < rend) {
+                pg[e] = *reinterpret_cast<const float4*>(dH + r * kCh + 4 * q);
+                ph[e] = *reinterpret_cast<const uint2*>(H + r * kCh + 4 * q);
+            }
         }
-    if (bias) {                                  // uniform over the workgroup
-        __shared__ float sdb[4][64];
-        sdb[wave][lane] = dbs;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int jj = j + 16 * h;
+                const int64_t g = rb - 2 * D + 4 * jj + e;
+                px[h][e] = uint2{0u, 0u};
+                if (jj < 16 + D && g >= 0 && g < rows)
+                    px[h][e] = *reinterpret_cast<const uint2*>(in + g * cin + c0 + 4 * q);
+            }
+    };
+    // dA = dH where the layer output is positive, to bf16, as sD[channel][row];
+    // the input as sI[channel][row - (rb - 2D)]
+    auto stage = [&]() {
+        uint16_t v[4][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float4 g = pg[e];
+            const uint2 hb = ph[e];
+            const float g0 = (hb.x & 0x7fffu) && !(hb.x & 0x8000u) ? g.x : 0.f;
+            const float g1 = (hb.x & 0x7fff0000u) && !(hb.x & 0x80000000u) ? g.y : 0.f;
+            const float g2 = (hb.y & 0x7fffu) && !(hb.y & 0x8000u) ? g.z : 0.f;
+            const float g3 = (hb.y & 0x7fff0000u) && !(hb.y & 0x80000000u) ? g.w : 0.f;
+            dbs[0] += g0;
+            dbs[1] += g1;
+            dbs[2] += g2;
+            dbs[3] += g3;
+            v[0][e] = to_bf16(g0);
+            v[1][e] = to_bf16(g1);
+            v[2][e] = to_bf16(g2);
+            v[3][e] = to_bf16(g3);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            *reinterpret_cast<uint2*>(&sD[(4 * q + k) * kDwPitchD + 4 * j]) =
+                uint2{uint32_t(v[k][0]) | (uint32_t(v[k][1]) << 16), uint32_t(v[k][2]) | (uint32_t(v[k][3]) << 16)};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int jj = j + 16 * h;
+            if (jj >= 16 + D) break;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int sh = 16 * (k & 1), w = k >> 1;
+                auto half = [&](int e) { return ((w ? px[h][e].y : px[h][e].x) >> sh) & 0xffffu; };
+                *reinterpret_cast<uint2*>(&sI[(4 * q + k) * kDwPitchI + 4 * jj]) =
+                    uint2{half(0) | (half(1) << 16), half(2) | (half(3) << 16)};
+            }
+        }
+    };
+    int64_t rbase = int64_t(ck) * chunk;
+    if (rbase < rend) fetch(rbase);
+    for (; rbase < rend; rbase += kDwRows) {
+        stage();
         __syncthreads();
-        if (tid < 64) atomicAdd(&db[tid], sdb[0][tid] + sdb[1][tid] + sdb[2][tid] + sdb[3][tid]);
+        if (rbase + kDwRows < rend) fetch(rbase + kDwRows);
+        // no block start in (rbase - 2D, rbase + 64 + 2D): every pair of the piece is in one block
+        const int f0 = int(rbase % F);
+        const bool clean = f0 >= 2 * D && F32 - f0 >= kDwRows + 2 * D;
+        const uint16_t* arow = &sI[(16 * wave + (lane & 15)) * kDwPitchI + 8 * (lane >> 4)];
+        const uint16_t* brow = &sD[(lane & 15) * kDwPitchD + 8 * (lane >> 4)];
+#pragma unroll
+        for (int ks = 0; ks < kDwRows; ks += 32) {
+            bf16x8 b[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                b[nt] = as_bf16x8(*reinterpret_cast<const uint4*>(brow + 16 * nt * kDwPitchD + ks));
+            uint4 a[kTaps];
+            a[0] = lds_row8<0 * D>(arow + ks);
+            a[1] = lds_row8<1 * D>(arow + ks);
+            a[2] = lds_row8<2 * D>(arow + ks);
+            a[3] = lds_row8<3 * D>(arow + ks);
+            a[4] = lds_row8<4 * D>(arow + ks);
+            if (!clean) {
+                // clear the rows r of this lane (ks + 8(l/16) + e) whose tap row is in another block
+                int fr = f0 + ks + 8 * (lane >> 4);
+                while (fr >= F32) fr -= F32;
+                int frs[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    frs[e] = fr;
+                    fr = fr + 1 == F32 ? 0 : fr + 1;
+                }
+#pragma unroll
+                for (int i = 0; i < kTaps; ++i) {
+                    uint32_t m[4];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int t0 = frs[2 * h] + D * (i - 2), t1 = frs[2 * h + 1] + D * (i - 2);
+                        m[h] = (t0 >= 0 && t0 < F32 ? 0x0000ffffu : 0u) | (t1 >= 0 && t1 < F32 ? 0xffff0000u : 0u);
+                    }
+                    a[i].x &= m[0];
+                    a[i].y &= m[1];
+                    a[i].z &= m[2];
+                    a[i].w &= m[3];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kTaps; ++i)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[i]), b[nt], acc[i][nt], 0, 0, 0);
+        }
+        __syncthreads();                         // the tiles are restaged by the next piece
+    }
+    // this chunk's sums: [tap][channel of the group][output channel]
+    float* P = part + (int64_t(ck) * ngroups + c0 / 64) * kDwBlock;
+#pragma unroll
+    for (int i = 0; i < kTaps; ++i)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = 16 * wave + 4 * (lane >> 4) + e;
+                P[(i * 64 + c) * kCh + 16 * nt + (lane & 15)] = acc[i][nt][e];
+            }
+    if (bias) {                                  // uniform over the workgroup
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sdb[j][4 * q + k] = dbs[k];
+        __syncthreads();
+        if (tid < 64) {
+            float t = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) t += sdb[jj][tid];
+            pdb[int64_t(ck) * kCh + tid] = t;
+        }
+    }
+}
+
+// dW[i][c][o] += sum over chunks of their sums, and db[o] likewise (the last
+// workgroup): workgroup (i, c) takes the 64 outputs of one row, thread (s, o4) the
+// chunks s, s + 16, ... of 4 outputs, then the 16 partial sums are added in order.
+__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, const float* __restrict__ pdb,
+                                                   float* __restrict__ dW, float* __restrict__ db, int cin,
+                                                   int nchunks) {
+    __shared__ float4 red[16][16];
+    const int tid = int(threadIdx.x), s = tid >> 4, o4 = tid & 15;
+    const int row = int(blockIdx.x);             // i * cin + c, or the bias row after them
+    const int ngroups = cin / 64;
+    const bool brow = row == kTaps * cin;
+    const float* src;
+    int64_t stride;
+    if (brow) {
+        src = pdb + 4 * o4;
+        stride = kCh;
+    } else {
+        const int i = row / cin, c = row - i * cin;
+        src = part + int64_t(c / 64) * kDwBlock + (i * 64 + c % 64) * kCh + 4 * o4;
+        stride = int64_t(ngroups) * kDwBlock;
+    }
+    float4 t = {0.f, 0.f, 0.f, 0.f};
+    for (int k = s; k < nchunks; k += 16) {
+        const float4 v = *reinterpret_cast<const float4*>(src + k * stride);
+        t.x += v.x;
+        t.y += v.y;
+        t.z += v.z;
+        t.w += v.w;
+    }
+    red[s][o4] = t;
+    __syncthreads();
+    if (tid < 16) {
+        float4 u = red[0][tid];
+        for (int k = 1; k < 16; ++k) {
+            u.x += red[k][tid].x;
+            u.y += red[k][tid].y;
+            u.z += red[k][tid].z;
+            u.w += red[k][tid].w;
+        }
+        float* dst = brow ? db + 4 * tid : dW + int64_t(row) * kCh + 4 * tid;
+        dst[0] += u.x;
+        dst[1] += u.y;
+        dst[2] += u.z;
+        dst[3] += u.w;
     }
 }
 
@@ -823,15 +1002,37 @@ hipError_t launch_conv_dinput(const float* dH, const void* H, const void* w, flo
     return hipGetLastError();
 }
 
+// chunks x groups <= (pieces / k + 1) * groups <= kDwWgs + groups for k = ceil(pieces * groups / kDwWgs)
+int64_t dweight_part_elems(int cin) {
+    const int64_t ngroups = std::max(cin / 64, 1);
+    return (kDwWgs + ngroups) * (kDwBlock + kCh);
+}
+
 hipError_t launch_conv_dweight(const void* in, int cin, const float* dH, const void* H, float* dW, float* db,
-                               int64_t rows, int64_t F, int d, bool bf16, hipStream_t st) {
+                               float* part, int64_t part_elems, int64_t rows, int64_t F, int d, bool bf16,
+                               hipStream_t st) {
     if (rows <= 0) return hipSuccess;
     if (bf16) {
-        if (cin % 64 || rows >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-        const int64_t tasks = int64_t(kTaps) * (cin / 64);
-        const int chunk = kDwChunk;
-        hipLaunchKernelGGL(k_conv_dw_mfma, dim3(blocks_for(rows, chunk), unsigned(tasks)), dim3(256), 0, st,
-                           (const uint16_t*)in, cin, dH, (const uint16_t*)H, dW, db, rows, F, d, chunk);
+        if (cin % 64 || cin <= 0 || rows >= (int64_t(1) << 31) || !part) return hipErrorInvalidValue;
+        const int64_t ngroups = cin / 64, pieces = (rows + kDwRows - 1) / kDwRows;
+        const int64_t chunk = kDwRows * std::max<int64_t>(1, (pieces * ngroups + kDwWgs - 1) / kDwWgs);
+        const int nchunks = int((rows + chunk - 1) / chunk);
+        if ((nchunks * ngroups) * (kDwBlock + kCh) > part_elems) return hipErrorInvalidValue;
+        float* pdb = db ? part + nchunks * ngroups * kDwBlock : nullptr;
+        const unsigned grid = unsigned((nchunks + kDwXcds - 1) / kDwXcds * kDwXcds * ngroups);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, (const uint16_t*)in, cin, dH,
+                               (const uint16_t*)H, part, pdb, rows, F, int(chunk), nchunks);
+        };
+        switch (d) {
+        case 1: go(k_conv_dw_taps<1>); break;
+        case 2: go(k_conv_dw_taps<2>); break;
+        case 4: go(k_conv_dw_taps<4>); break;
+        case 8: go(k_conv_dw_taps<8>); break;
+        default: return hipErrorInvalidValue;    // the network's dilations only
+        }
+        hipLaunchKernelGGL(k_dw_reduce, dim3(unsigned(kTaps * cin + (db ? 1 : 0))), dim3(256), 0, st,
+                           (const float*)part, (const float*)pdb, dW, db, cin, nchunks);
     } else {
         hipLaunchKernelGGL(k_conv_dw_ref, dim3(blocks_for(int64_t(kTaps) * cin * kCh, 256)), dim3(256), 0, st,
                            (const float*)in, cin, dH, (const float*)H, dW, db, rows, F, d);

@@ -214,7 +214,10 @@ def learned_summary(trace_dir: str, cmd: str, batch: int, block_len: int, steps_
     flops = {
         "k_conv_tile<true>": (2.0 * conv_macs, PEAK_BF16_MFMA_TFLOPS, "forward, 4 layers"),
         "k_conv_tile<false>": (2.0 * rows * 64 * 5 * 64 * 3, PEAK_BF16_MFMA_TFLOPS, "input gradient, layers 1-3"),
-        "k_conv_dw_mfma": (2.0 * conv_macs, PEAK_BF16_MFMA_TFLOPS, "weight gradient, 4 layers"),
+        "k_conv_dw_taps<1>": (2.0 * rows * 64 * 5 * 256, PEAK_BF16_MFMA_TFLOPS, "weight gradient, layer 0 (d = 1)"),
+        "k_conv_dw_taps<2>": (2.0 * rows * 64 * 5 * 64, PEAK_BF16_MFMA_TFLOPS, "weight gradient, layer 1 (d = 2)"),
+        "k_conv_dw_taps<4>": (2.0 * rows * 64 * 5 * 64, PEAK_BF16_MFMA_TFLOPS, "weight gradient, layer 2 (d = 4)"),
+        "k_conv_dw_taps<8>": (2.0 * rows * 64 * 5 * 64, PEAK_BF16_MFMA_TFLOPS, "weight gradient, layer 3 (d = 8)"),
         "k_head": (6.0 * rows * 64, PEAK_FP32_VALU_TFLOPS, "head forward + backward"),
         "k_stft": (rows * (5.0 * 256 * 8 + 8.0 * 256), PEAK_FP32_VALU_TFLOPS, "generator + window + 256-point FFT + |X|^2"),
     }
