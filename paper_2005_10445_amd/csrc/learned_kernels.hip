@@ -98,8 +98,8 @@ __device__ float2 synth_sample(const BlockSource& s, int b, int64_t n) {
         const SynthTx tx = s.tx[int64_t(b) * kMaxTx + t];
         const int64_t m = n - tx.delay;
         if (m < 0 || m >= s.chip_len) continue;
-        const int64_t c = m / s.spc;
-        const P4 q = philox10(P4{uint32_t(c >> 7), tx.code, uint32_t(blk), 0x43484950u}, s.seed_lo, s.seed_hi);
+        const uint32_t c = uint32_t(m) / uint32_t(s.spc);     // 0 <= m < chip_len < 2^31
+        const P4 q = philox10(P4{c >> 7, tx.code, uint32_t(blk), 0x43484950u}, s.seed_lo, s.seed_hi);
         const int w = int(c & 127);
         const uint32_t word = w < 32 ? q.a : w < 64 ? q.b : w < 96 ? q.c : q.d;
         const float chip = ((word >> (w & 31)) & 1u) ? 1.0f : -1.0f;
@@ -121,15 +121,25 @@ __device__ float2 synth_sample(const BlockSource& s, int b, int64_t n) {
 // (j / Ns) 4 Ns + (j mod Ns) + r Ns).
 __global__ __launch_bounds__(256) void k_stft(BlockSource src, int nblocks, int64_t F, const float* __restrict__ hann,
                                               const float2* __restrict__ tw, float* __restrict__ P) {
+    constexpr int kShared = 3 * kHop + kWin;   // samples of the workgroup's 4 frames
     __shared__ float2 buf[4][kWin];
     __shared__ float2 stw[kWin];
     __shared__ float swin[kWin];
+    __shared__ float2 smp[kShared];
     const int tid = int(threadIdx.x), lane = tid & 63, wave = tid >> 6;
     stw[tid] = tw[tid];
     swin[tid] = hann[tid];
-    __syncthreads();
     const int64_t total = int64_t(nblocks) * F;
-    const int64_t row = int64_t(blockIdx.x) * 4 + wave;
+    // generated blocks: when the 4 frames lie in one block, each of their
+    // samples is generated once (frames overlap by half) and shared through LDS
+    const int64_t row0 = int64_t(blockIdx.x) * 4;
+    const int gb = int(row0 / F);
+    const int64_t gf = row0 - int64_t(gb) * F;
+    const bool shared_gen = !src.x && row0 + 3 < total && gf + 3 < F;    // uniform
+    if (shared_gen)
+        for (int j = tid; j < kShared; j += 256) smp[j] = synth_sample(src, gb, gf * kHop + j);
+    __syncthreads();
+    const int64_t row = row0 + wave;
     const bool live = row < total;
     const int64_t rr = live ? row : total - 1;
     const int b = int(rr / F);
@@ -139,7 +149,8 @@ __global__ __launch_bounds__(256) void k_stft(BlockSource src, int nblocks, int6
     for (int r = 0; r < 4; ++r) {
         const int j = lane + 64 * r;
         const int64_t n = f * kHop + j;
-        const float2 x = src.x ? src.x[int64_t(b) * src.stride + n] : synth_sample(src, b, n);
+        const float2 x = src.x ? src.x[int64_t(b) * src.stride + n]
+                               : shared_gen ? smp[wave * kHop + j] : synth_sample(src, b, n);
         a[r] = make_float2(x.x * swin[j], x.y * swin[j]);
     }
     float2* X = buf[wave];
@@ -182,21 +193,32 @@ __global__ __launch_bounds__(256) void k_hist(const float* __restrict__ P, int64
     const int b = int(blockIdx.y);
     const uint32_t prefix = st[b].prefix;
     const float* p = P + int64_t(b) * per_block;
-    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < per_block; i += int64_t(gridDim.x) * 256) {
-        const uint32_t u = __float_as_uint(p[i]);
-        uint32_t digit;
-        bool match;
-        if (pass == 0) {
-            digit = u >> 20;
-            match = true;
-        } else if (pass == 1) {
-            digit = (u >> 10) & 1023u;
-            match = (u >> 20) == prefix;
-        } else {
-            digit = u & 1023u;
-            match = (u >> 10) == prefix;
+    // 8 loads in flight per thread before their histogram updates
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t i0 = int64_t(blockIdx.x) * 256 + threadIdx.x; i0 < per_block; i0 += 8 * stride) {
+        uint32_t u[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = i0 + k * stride;
+            u[k] = i < per_block ? __float_as_uint(p[i]) : 0u;
         }
-        if (match) atomicAdd(&h[digit], 1u);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k * stride >= per_block) break;
+            uint32_t digit;
+            bool match;
+            if (pass == 0) {
+                digit = u[k] >> 20;
+                match = true;
+            } else if (pass == 1) {
+                digit = (u[k] >> 10) & 1023u;
+                match = (u[k] >> 20) == prefix;
+            } else {
+                digit = u[k] & 1023u;
+                match = (u[k] >> 10) == prefix;
+            }
+            if (match) atomicAdd(&h[digit], 1u);
+        }
     }
     __syncthreads();
     for (int i = int(threadIdx.x); i < 2048; i += 256)
@@ -244,17 +266,32 @@ __global__ __launch_bounds__(256) void k_select(uint32_t* __restrict__ hist, int
     for (int q = 0; q < per; ++q) h[t * per + q] = 0u;
 }
 
+// four values per thread (one block's median when per_block is a multiple of 4)
 template <bool BF>
 __global__ void k_map(const float* __restrict__ P, int64_t per_block, int64_t total, const float* __restrict__ med,
                       void* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const float m = med[i / per_block];
-    const float v = m > 0.0f ? logf(fmaxf(P[i], FLT_MIN) / m) : 0.0f;
-    if constexpr (BF)
-        static_cast<uint16_t*>(out)[i] = to_bf16(v);
-    else
-        static_cast<float*>(out)[i] = v;
+    const int64_t i0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= total) return;
+    auto value = [&](float p, float m) { return m > 0.0f ? logf(fmaxf(p, FLT_MIN) / m) : 0.0f; };
+    if (per_block % 4 == 0 && i0 + 4 <= total) {
+        const float m = med[i0 / per_block];
+        const float4 p = *reinterpret_cast<const float4*>(P + i0);
+        const float v0 = value(p.x, m), v1 = value(p.y, m), v2 = value(p.z, m), v3 = value(p.w, m);
+        if constexpr (BF)
+            *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + i0) =
+                uint2{uint32_t(to_bf16(v0)) | (uint32_t(to_bf16(v1)) << 16),
+                      uint32_t(to_bf16(v2)) | (uint32_t(to_bf16(v3)) << 16)};
+        else
+            *reinterpret_cast<float4*>(static_cast<float*>(out) + i0) = float4{v0, v1, v2, v3};
+        return;
+    }
+    for (int64_t i = i0; i < i0 + 4 && i < total; ++i) {
+        const float v = value(P[i], med[i / per_block]);
+        if constexpr (BF)
+            static_cast<uint16_t*>(out)[i] = to_bf16(v);
+        else
+            static_cast<float*>(out)[i] = v;
+    }
 }
 
 __global__ void k_synth(BlockSource src, int64_t n, float2* __restrict__ out) {
@@ -930,7 +967,10 @@ hipError_t launch_median(const float* P, int nblocks, int64_t per_block, uint32_
                        int64_t(nblocks) * 2048);
     hipLaunchKernelGGL(k_median_init, dim3(blocks_for(nblocks, 64)), dim3(64), 0, st, state, nblocks,
                        uint32_t((per_block - 1) / 2));
-    const unsigned chunks = unsigned(per_block / (256 * 16) + 1 < 512 ? per_block / (256 * 16) + 1 : 512);
+    // at most 64 workgroups per block: each adds its nonzero buckets to the
+    // block's histogram with atomics, and the few buckets of the first pass
+    // are the same for all of them
+    const unsigned chunks = unsigned(per_block / (256 * 16) + 1 < 64 ? per_block / (256 * 16) + 1 : 64);
     for (int pass = 0; pass < 3; ++pass) {
         hipLaunchKernelGGL(k_hist, dim3(chunks, unsigned(nblocks)), dim3(256), 0, st, P, per_block, pass,
                            (const MedianState*)state, hist);
@@ -944,9 +984,9 @@ hipError_t launch_map(const float* P, int nblocks, int64_t F, const float* med, 
     const int64_t per = F * kWin, total = per * nblocks;
     if (total <= 0) return hipSuccess;
     if (bf16)
-        hipLaunchKernelGGL(k_map<true>, dim3(blocks_for(total, 256)), dim3(256), 0, st, P, per, total, med, map);
+        hipLaunchKernelGGL(k_map<true>, dim3(blocks_for(total, 1024)), dim3(256), 0, st, P, per, total, med, map);
     else
-        hipLaunchKernelGGL(k_map<false>, dim3(blocks_for(total, 256)), dim3(256), 0, st, P, per, total, med, map);
+        hipLaunchKernelGGL(k_map<false>, dim3(blocks_for(total, 1024)), dim3(256), 0, st, P, per, total, med, map);
     return hipGetLastError();
 }
 
