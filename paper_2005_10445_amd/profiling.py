@@ -4,6 +4,7 @@
   python -m paper_2005_10445_amd.profiling traffic <fetch_dir> <write_dir> <copy_fetch_dir>
          <copy_write_dir> <out.json> --kernel k_correlate --copy-bytes 268435456 --cmd "<command>"
   python -m paper_2005_10445_amd.profiling issue <pmc_dir> <out.txt> --kernel k_correlate --cmd "<command>"
+  python -m paper_2005_10445_amd.profiling lds <pmc_dir> <out.txt> --cmd "<command>"
 
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
 counters read for a plain device copy of known size, so that the reported
@@ -117,6 +118,43 @@ def issue_summary(pmc_dir: str, kernel: str, cmd: str, sources=KERNEL_SOURCES, l
         ms = means["SQ_INSTS_VALU"] * VALU_CLOCKS / (NUM_SIMDS * CLOCK_HZ) * 1e3
         lines += ["", f"VALU issue time at {CLOCK_HZ / 1e9:.1f} GHz, {VALU_CLOCKS} clocks per wave instruction, "
                       f"{NUM_SIMDS} SIMDs: {ms:.3f} ms per dispatch"]
+    return "\n".join(lines) + "\n"
+
+
+LDS_COUNTERS = ("SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_ADDR_CONFLICT", "SQ_LDS_UNALIGNED_STALL",
+                "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS")
+
+
+def lds_summary(pmc_dir: str, cmd: str, sources=KERNEL_SOURCES, top: int = 10) -> str:
+    """Per-dispatch means of the LDS counters of every kernel that issues LDS
+    instructions (the `top` with the most): instructions, cycles stalled on
+    bank conflicts, on address conflicts and on unaligned accesses, and the
+    cycles waves spend issuing LDS instructions, with the share of those that
+    the bank conflicts add."""
+    t = counters(pmc_dir)
+    rows = []
+    for name, cs in t.items():
+        if "SQ_INSTS_LDS" not in cs or not cs["SQ_INSTS_LDS"]:
+            continue
+        means = {c: sum(cs[c]) / len(cs[c]) for c in LDS_COUNTERS if c in cs and cs[c]}
+        if means.get("SQ_INSTS_LDS", 0.0) <= 0.0:
+            continue
+        short = _short(name).replace("(anonymous namespace)::", "").split("(")[0]
+        rows.append((short, len(cs["SQ_INSTS_LDS"]), means))
+    rows.sort(key=lambda r: -r[2]["SQ_INSTS_LDS"])
+    lines = ["# rocprofv3 LDS counters per dispatch (means over each kernel's dispatches)", f"# command: {cmd}",
+             f"# kernel source hash: {kernel_source_hash(sources)} ({', '.join(sources)})",
+             "# columns: LDS instructions; cycles stalled on bank conflicts, address conflicts and unaligned",
+             "# accesses; cycles waves spend issuing LDS instructions; bank-conflict cycles / LDS issue cycles", "",
+             f"{'kernel':40s} {'disp':>5s} {'LDS inst':>11s} {'bank cfl':>11s} {'addr cfl':>10s} {'unalgn':>8s} "
+             f"{'LDS issue':>12s} {'cfl/issue':>9s}"]
+    for name, n, m in rows[:top]:
+        act = m.get("SQ_ACTIVE_INST_LDS", 0.0)
+        bank = m.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        share = f"{bank / act:9.3f}" if act > 0 else f"{'-':>9s}"
+        lines.append(f"{name[:40]:40s} {n:5d} {m['SQ_INSTS_LDS']:11.4g} {bank:11.4g} "
+                     f"{m.get('SQ_LDS_ADDR_CONFLICT', 0.0):10.4g} {m.get('SQ_LDS_UNALIGNED_STALL', 0.0):8.4g} "
+                     f"{act:12.4g} {share}")
     return "\n".join(lines) + "\n"
 
 
@@ -277,6 +315,11 @@ def main(argv=None):
     i.add_argument("--cmd", required=True)
     i.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
     i.add_argument("--last", type=int, default=0, help="average only the kernel's last N dispatches")
+    ld = sub.add_parser("lds")
+    ld.add_argument("pmc_dir")
+    ld.add_argument("out")
+    ld.add_argument("--cmd", required=True)
+    ld.add_argument("--fsk", action="store_true", help="hash the FSK pipeline's sources")
     ls = sub.add_parser("learned")
     ls.add_argument("trace_dir")
     ls.add_argument("out")
@@ -286,6 +329,11 @@ def main(argv=None):
     ls.add_argument("--warmup", type=int, default=10)
     ls.add_argument("--steps-total", type=int, default=100)
     a = ap.parse_args(argv)
+    if a.what == "lds":
+        with open(a.out, "w") as f:
+            f.write(lds_summary(a.pmc_dir, a.cmd, sources=FSK_SOURCES if a.fsk else KERNEL_SOURCES))
+        print(open(a.out).read())
+        return
     if a.what == "learned":
         with open(a.out, "w") as f:
             f.write(learned_summary(a.trace_dir, a.cmd, a.batch, a.block_len, a.steps_total, a.warmup))

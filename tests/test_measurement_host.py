@@ -136,3 +136,20 @@ def test_committed_traffic_files_name_their_sources():
             t = json.load(f)
         assert set(t["kernel_sources"]) in (set(prof.KERNEL_SOURCES), set(prof.FSK_SOURCES)), path
         assert t["bytes_per_launch"] > 0 and math.isfinite(t["bytes_per_launch"])
+
+
+def test_lds_summary(tmp_path):
+    kern = "void acq::(anonymous namespace)::k_correlate<acq::Fft14, 0, 0>(acq::CorrArgs)"
+    other = "void acq::(anonymous namespace)::k_refine(acq::RefineArgs)"
+    rows = []
+    for i, (k, inst, bank, act) in enumerate([(kern, 100.0, 10.0, 400.0), (kern, 300.0, 30.0, 400.0),
+                                              (other, 5.0, 0.0, 20.0)]):
+        rows += [(i + 1, k, "SQ_INSTS_LDS", inst), (i + 1, k, "SQ_LDS_BANK_CONFLICT", bank),
+                 (i + 1, k, "SQ_ACTIVE_INST_LDS", act)]
+    _write_counters(tmp_path, rows)
+    s = prof.lds_summary(str(tmp_path), "cmd")
+    lines = [l for l in s.splitlines() if l.startswith("k_")]
+    assert lines[0].split()[0] == "k_correlate<Fft14," and lines[1].split()[0] == "k_refine"
+    f = lines[0].split()
+    # 2 dispatches; means 200 instructions, 20 conflict cycles, 400 issue cycles, share 0.05
+    assert f[-7] == "2" and float(f[-6]) == 200.0 and float(f[-5]) == 20.0 and float(f[-1]) == 0.05
