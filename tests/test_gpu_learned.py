@@ -170,6 +170,13 @@ def test_forward_gradients_bf16_against_oracle(dev, nblocks, F):
         y = net.forward(ti, nblocks).cpu().numpy()
         loss, grad = net.gradients(ti, tl, pw, nblocks)
         grad = grad.cpu().numpy()
+        _, grad2 = net.gradients(ti, tl, pw, nblocks)
+        grad2 = grad2.cpu().numpy()
+    # the conv layers' gradients are summed in a fixed order: the same batch
+    # gives them bit for bit (the head's sums use atomics)
+    for name, sl in _segments(net_o, cin):
+        if name[0] in "Wb" and name[1:].isdigit():
+            assert np.array_equal(grad[sl], grad2[sl]), name
 
     def rel(a, b):
         return np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
