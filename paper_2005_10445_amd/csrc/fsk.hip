@@ -24,7 +24,7 @@
 //                     so the product is (Z[i] (B_a + B_b) + conj Z[-i]
 //                     (B_a - B_b)) / 2 for the conjugate spectra B of the two
 //                     templates.  The peak search uses |c|.  An M-point inverse
-//                     transform (M up to 2^17) runs as P = M / Msub phases of
+//                     transform (M up to 2^18) runs as P = M / Msub phases of
 //                     an Msub-point transform: for output lag tau = P u + rho,
 //                       G_rho[i'] = exp(+j 2 pi i' rho / M)
 //                                   sum_a Y[i' + Msub a] exp(+j 2 pi a rho / P),
@@ -390,20 +390,22 @@ __global__ __launch_bounds__(E::NT) void k_fsk_correlate(FskCorrArgs a) {
                 asm volatile("" ::: "memory");    // one input index at a time: no hoisting of later loads
             }
         } else {
-            // two input indices per pass, so that their 4P loads are in flight
-            // together; the P-point DFT over q is a radix-P butterfly, and the
-            // twiddle of phase rho is the rho-th power of exp(+j 2 pi i' / M)
+            // two input indices per pass (one for P = 16), so that their 4P
+            // loads are in flight together; the P-point DFT over q is a
+            // radix-P butterfly, and the twiddle of phase rho is the rho-th
+            // power of exp(+j 2 pi i' / M)
+            constexpr int IPP = PP > 8 ? 1 : 2;
 #pragma unroll 1
-            for (int m = 0; m < 16; m += 2) {
-                float2 y[2][PP];
-                int ipv[2];
+            for (int m = 0; m < 16; m += IPP) {
+                float2 y[IPP][PP];
+                int ipv[IPP];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < IPP; ++h) {
                     ipv[h] = eng.in_index(m + h);
                     products(ipv[h], y[h]);
                 }
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < IPP; ++h) {
                     const int ip = ipv[h];
                     if constexpr (PP > 1) dev::dft_r<PP, +1>(y[h]);
                     G[ip] = y[h][0];
@@ -725,12 +727,14 @@ __global__ __launch_bounds__(1024) void k_fsk_compact(const acq_fsk_detection* _
 template <class E, int PP>
 void launch_fsk_corr_ep(const FskCorrArgs& a, int grid, hipStream_t st) {
     const bool track = a.tasks.track != 0;
+    // one phase per work item (split) is built for P <= 8 (eighth roots of unity)
+    constexpr bool can_split = PP > 1 && PP <= 8;
     if (a.dump)                                          // searching only
         hipLaunchKernelGGL((k_fsk_correlate<E, PP, true, false, false>), dim3(grid), dim3(E::NT), 0, st, a);
-    else if (PP > 1 && a.split && track)
-        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, PP != 1, true>), dim3(grid), dim3(E::NT), 0, st, a);
-    else if (PP > 1 && a.split)
-        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, PP != 1, false>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (can_split && a.split && track)
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, can_split, true>), dim3(grid), dim3(E::NT), 0, st, a);
+    else if (can_split && a.split)
+        hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, can_split, false>), dim3(grid), dim3(E::NT), 0, st, a);
     else if (track)
         hipLaunchKernelGGL((k_fsk_correlate<E, PP, false, false, true>), dim3(grid), dim3(E::NT), 0, st, a);
     else
@@ -753,6 +757,7 @@ hipError_t launch_fsk_correlate(const FskCorrArgs& a, int grid, int log2_sub, hi
                 case 2: launch_fsk_corr_ep<Fft14, 2>(a, grid, st); break;
                 case 4: launch_fsk_corr_ep<Fft14, 4>(a, grid, st); break;
                 case 8: launch_fsk_corr_ep<Fft14, 8>(a, grid, st); break;
+                case 16: launch_fsk_corr_ep<Fft14, 16>(a, grid, st); break;
                 default: return hipErrorInvalidValue;
             }
             break;
@@ -783,15 +788,29 @@ int fsk_geometry(const acq_fsk_config* c, FskGeometry* g) {
     g->lg = int64_t(c->bp_len) + c->mf_len - 1;
     g->nt = int64_t(c->num_bits) * c->mf_len + g->lg - 1;
     g->vf = kFrontN - g->lg + 1;
+    constexpr int64_t kMaxM = int64_t(1) << 18;
     int64_t M = c->fft_len;
     if (M == 0) {
         M = 1024;
-        while (M <= g->nt) M <<= 1;                   // smallest power of two > n_t ...
-        if (M < (int64_t(1) << 17) && M - g->nt + 1 < g->nt / 2) M <<= 1;   // ... doubled when few lags remain
+        while (M <= g->nt && M < kMaxM) M <<= 1;      // smallest power of two > n_t ...
+        if (M < kMaxM && M - g->nt + 1 < g->nt / 2) M <<= 1;   // ... doubled when few lags remain
+        // ... or, from 2^17 (templates of the paper's length), doubled when
+        // that needs fewer transform points for the plan's blocks: one window
+        // of max_block_len samples, or, when the plan is sized for tracking
+        // tasks, max_track_tasks blocks of equal length
+        if (M >= (int64_t(1) << 17) && M > g->nt && 2 * M <= kMaxM) {
+            const int64_t tasks = c->max_track_tasks > 0 ? c->max_track_tasks : 1;
+            const int64_t len = (c->max_block_len + tasks - 1) / tasks;
+            auto points = [&](int64_t m) {
+                const int64_t lags = std::max<int64_t>(len - g->nt + 1, 1), v = m - g->nt + 1;
+                return tasks * ((lags + v - 1) / v + 1) / 2 * m;       // segments two to a transform
+            };
+            if (points(2 * M) < points(M)) M *= 2;
+        }
     }
-    if (M < 1024 || M > (int64_t(1) << 17) || (M & (M - 1)))
-        return fail(ACQ_ERR_UNSUPPORTED, "fft_len must be a power of two in [2^10, 2^17]");
-    if (M <= g->nt) return fail(ACQ_ERR_UNSUPPORTED, "template longer than the correlation segment (at most 2^17 - 1)");
+    if (M < 1024 || M > kMaxM || (M & (M - 1)))
+        return fail(ACQ_ERR_UNSUPPORTED, "fft_len must be a power of two in [2^10, 2^18]");
+    if (M <= g->nt) return fail(ACQ_ERR_UNSUPPORTED, "template longer than the correlation segment (at most 2^18 - 1)");
     g->M = M;
     g->Msub = std::min<int64_t>(M, int64_t(1) << 14);
     g->P = int(M / g->Msub);
@@ -1264,7 +1283,7 @@ int enqueue_fsk(acq_fsk_plan_s* p, int nblocks, bool track, float* dump, int* it
     ca.units = units;
     int64_t work = track ? int64_t(slots) : int64_t(T) * slots;
     int grid = int(std::min<int64_t>(work, p->corr_grid));
-    if (!dump && g.P > 1 && work < acq::kFskMaxGrid) {   // fewer items than CUs: one phase per workgroup
+    if (!dump && g.P > 1 && g.P <= 8 && work < acq::kFskMaxGrid) {   // fewer items than CUs: one phase per workgroup
         ca.split = 1;
         work *= g.P;
         grid = int(std::min<int64_t>(work, acq::kFskSplitMaxGrid));

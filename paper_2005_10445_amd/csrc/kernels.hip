@@ -586,6 +586,12 @@ static hipError_t fwd_e(const FwdArgs& a, int grid, hipStream_t st) {
 
 template <int PREC>
 static hipError_t combine_p(const FwdArgs& a, dim3 grid, hipStream_t st) {
+    if constexpr (PREC == ACQ_FP32) {
+        if (a.spc == 16) {                  // the FSK path's 2^18-point segments (16 phases of 2^14)
+            hipLaunchKernelGGL((k_forward_combine<PREC, 16>), grid, dim3(256), 0, st, a);
+            return hipSuccess;
+        }
+    }
     switch (a.spc) {
         case 1: hipLaunchKernelGGL((k_forward_combine<PREC, 1>), grid, dim3(256), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_forward_combine<PREC, 2>), grid, dim3(256), 0, st, a); break;
@@ -602,7 +608,8 @@ static hipError_t combine_p(const FwdArgs& a, dim3 grid, hipStream_t st) {
 
 hipError_t launch_forward(const FwdArgs& a, int grid, int combine_slots, int log2_sub, int prec, hipStream_t st) {
     if (grid <= 0 || combine_slots <= 0) return hipSuccess;
-    if ((1 << log2_sub) != a.Msub || a.Msub % 256 || a.spc < 1 || a.spc > 8) return hipErrorInvalidValue;
+    if ((1 << log2_sub) != a.Msub || a.Msub % 256 || a.spc < 1 || (a.spc > 8 && !(a.spc == 16 && prec == ACQ_FP32)))
+        return hipErrorInvalidValue;
     if (a.xpad < 0 || a.xpad > a.M / 2 || a.xstride < int64_t(a.M) + 2 * int64_t(a.xpad)) return hipErrorInvalidValue;
     hipError_t e;
     switch (log2_sub) {

@@ -210,7 +210,8 @@ def test_threshold_edges_and_errors(dev):
 
 
 @pytest.mark.timeout(600)
-def test_paper_shaped_window(dev):
+@pytest.mark.parametrize("fft_len", [0, 1 << 17])
+def test_paper_shaped_window(dev, fft_len):
     """The paper's searching task at full size: 100 ms at 8 Msps, 128 codes of
     8192 bits at 8 samples per bit, a 200-tap band-pass, six packets at
     -10..0 dB: every packet found at its delay, and every code's peak compared
@@ -223,8 +224,9 @@ def test_paper_shaped_window(dev):
     iq, txs = siggen.make_fsk_block(w["seeds"][0] + 1, w["block_len"], bits, w["sps"], FS, w["f1_hz"], w["f0_hz"],
                                     w["lo_hz"], w["n_tx"], snr_db=w["snr_db"], noise_rms=w["noise_rms"])
     from paper_2005_10445_amd.fsk import FskPlan
-    with FskPlan(bits, FS, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], w["block_len"]) as plan:
-        assert plan.geometry["fft_len"] == 1 << 17
+    with FskPlan(bits, FS, w["lo_hz"], w["f1_hz"], w["f0_hz"], bp, w["sps"], w["block_len"], fft_len=fft_len) as plan:
+        # by default 16 phases of 2^14 points (4 segments), else 8 (12 segments)
+        assert plan.geometry["fft_len"] == (fft_len or 1 << 18)
         dets = plan.detect(torch.from_numpy(iq).to(dev))
     assert len(dets) == T
     for tag, D, snr in txs:
