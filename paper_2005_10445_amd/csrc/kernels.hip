@@ -237,11 +237,25 @@ __global__ __launch_bounds__(256) void k_forward_combine(FwdArgs a) {
     float2 F[SPC];
 #pragma unroll
     for (int r = 0; r < SPC; ++r) F[r] = X[r * a.Msub + i];
+    // 16 phases (the FSK path's 2^18-point segments): X[i + q Msub] is the
+    // 16-point DFT over r of F_r[i] exp(-j 2 pi i r / M)
+    if constexpr (SPC == 16) {
+        const float2 w1 = a.rootsM[i];
+        float2 w = w1;
+#pragma unroll
+        for (int r = 1; r < SPC; ++r) {
+            F[r] = cmulc(F[r], w);
+            if (r + 1 < SPC) w = cmul(w, w1);
+        }
+        dev::dft16<-1>(F);
+    }
 #pragma unroll
     for (int q = 0; q < SPC; ++q) {
         const int io = i + q * a.Msub;
         float2 c = F[0];
-        if constexpr (SPC > 1) {
+        if constexpr (SPC == 16) {
+            c = F[q];
+        } else if constexpr (SPC > 1) {
             const float2 w1 = a.rootsM[io];
             float2 w = w1;
 #pragma unroll

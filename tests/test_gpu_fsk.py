@@ -24,6 +24,7 @@ CASES = [  # name, T, bits, sps, bp taps, cutoff, f1, f0, lo, N, fft_len, n_tx
     ("mid_p2", 4, 700, 8, 61, 600e3, 250e3, -250e3, -0.5e6, 60000, 16384 * 2, 3),
     ("odd_sps_p8", 3, 1500, 5, 200, 900e3, 400e3, -300e3, 2.0e6, 300000, 1 << 17, 2),
     ("three_segments_p4", 2, 1000, 8, 100, 600e3, 250e3, -250e3, 0.3e6, 150000, 1 << 16, 2),
+    ("sixteen_phases_p16", 2, 1500, 5, 200, 900e3, 400e3, -300e3, 2.0e6, 600000, 1 << 18, 2),
 ]
 
 
