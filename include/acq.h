@@ -576,7 +576,12 @@ typedef struct acq_fsk_config {
     int32_t        num_tags;        /* >= 1                                               */
     int32_t        num_bits;        /* >= 1                                               */
     int32_t        fft_len;         /* correlation segment M: power of two in
-                                       [2^10, 2^17], > template length; 0 = choice      */
+                                       [2^10, 2^18], > template length; 0 = the
+                                       library's choice (the smallest such power,
+                                       doubled from 2^17 when the blocks -- one of
+                                       max_block_len, or max_track_tasks of equal
+                                       length when that is set -- need fewer
+                                       transform points)                              */
     int32_t        max_track_tasks; /* tasks per acq_fsk_track call; 0 -> 16             */
 } acq_fsk_config;
 
